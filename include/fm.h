@@ -1,0 +1,239 @@
+/*
+ * fm.h -- C ABI of the structured linear operator library (MI355X, gfx950).
+ *
+ * A linear operator A (m x n) is applied forward, y = A x (the forward
+ * transform of eq. (3)), or backward, x = A^H y (the backward transform of
+ * eq. (4)), to a block of column vectors at once, as in the paper's section
+ * "Software description" (operators act on arrays of several vectors, and the
+ * number of vectors processed together is a calibration parameter there).
+ *
+ * Conventions that hold for every entry point:
+ *
+ *  - Blocks are column-major: column j of a block with leading dimension ld
+ *    starts at ptr + j*ld elements; ld >= rows. In PyTorch terms a block is a
+ *    contiguous tensor of shape (ncols, rows).
+ *  - Data pointers are DEVICE pointers on the current HIP device, in the
+ *    operator's element type: FM_C64 = interleaved float (re, im),
+ *    FM_C128 = interleaved double, FM_I32 = int32_t, FM_I64 = int64_t.
+ *  - Operators are immutable once created (section "General Matrix-free
+ *    Representations": precomputations stay valid only because instances never
+ *    change). Handles are reference counted; fm_op_compose and fm_op_adjoint
+ *    retain their children, so callers may release children afterwards.
+ *  - Creation copies every parameter array (the caller may free it on return)
+ *    and performs the precomputation (spectra, twiddle tables) on `stream`;
+ *    creation synchronises that stream before it returns.
+ *  - fm_apply enqueues kernels on `stream` and returns without synchronising.
+ *    It allocates nothing when a large enough workspace is passed.
+ *  - Every entry point validates its arguments first and returns a status
+ *    before anything is enqueued. On error, fm_last_error() describes it.
+ *    Device faults surface as FM_E_DEVICE at the next synchronising call.
+ *  - Streams are passed as `void*` holding a hipStream_t (NULL: the null
+ *    stream), so this header does not depend on the HIP headers.
+ */
+#ifndef FM_H
+#define FM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fm_op_s* fm_op;
+typedef struct fm_batch_s* fm_batch;
+
+typedef enum { FM_C64 = 1, FM_C128 = 2, FM_I32 = 3, FM_I64 = 4 } fm_dtype;
+
+/* FM_FWD: y = A x (eq. 3).  FM_ADJ: y = A^H x (eq. 4). */
+typedef enum { FM_FWD = 0, FM_ADJ = 1 } fm_dir;
+
+typedef enum { FM_PRODUCT = 0, FM_SUM = 1, FM_KRON = 2, FM_BLKDIAG = 3 } fm_compose_kind;
+
+typedef enum {
+  FM_OK = 0,
+  FM_E_INVALID = 1,     /* NULL handle/pointer, non-positive size, bad enum  */
+  FM_E_SHAPE = 2,       /* inconsistent shapes, ld < rows, index out of range */
+  FM_E_DTYPE = 3,       /* dtype mismatch or not supported by this operator  */
+  FM_E_ALIAS = 4,       /* x and y overlap                                    */
+  FM_E_UNSUPPORTED = 5, /* valid request this build does not implement        */
+  FM_E_WORKSPACE = 6,   /* workspace given but smaller than fm_workspace_size */
+  FM_E_NOMEM = 7,       /* device allocation failed                           */
+  FM_E_DEVICE = 8,      /* HIP runtime error (launch failure, device fault)   */
+  FM_E_RELEASED = 9     /* handle already released                            */
+} fm_status;
+
+/* ------------------------------------------------------------------ creation
+ * Parameter arrays are device pointers in dtype `dt`.
+ */
+
+/* Unnormalised DFT matrix F_n, F[i,k] = exp(-2 pi j i k / n), eq. (1) read with
+ * 0-based indices. n must be a power of two, 1 <= n <= 2^20. Complex dtypes. */
+fm_status fm_op_create_fourier(fm_op* out, int64_t n, fm_dtype dt);
+
+/* Walsh-Hadamard matrix H_n in natural (Sylvester) order, entries +-1,
+ * H[i,j] = (-1)^popcount(i AND j); n a power of two. All four dtypes; integer
+ * results wrap modulo 2^32 / 2^64 (two's complement), so they are exact and
+ * independent of the order of additions. */
+fm_status fm_op_create_hadamard(fm_op* out, int64_t n, fm_dtype dt);
+
+/* Diag(d), n x n with d on the diagonal (the Diag factor of eq. (7)).
+ * Complex dtypes. */
+fm_status fm_op_create_diag(fm_op* out, int64_t n, const void* d, fm_dtype dt, void* stream);
+
+/* Dense m x n matrix, column-major with leading dimension lda >= m (the plain
+ * product of eq. (2)); used mainly as a Kronecker factor. Complex dtypes. */
+fm_status fm_op_create_dense(fm_op* out, int64_t m, int64_t n, const void* a, int64_t lda,
+                             fm_dtype dt, void* stream);
+
+/* Circulant C(c): y = c cyclically convolved with x (eq. (5)), c = first column,
+ * C[i,j] = c[(i-j) mod n]. The spectrum DFT(c) is computed once here in FP64
+ * (section "General Matrix-free Representations": FFT(c) is precomputed at
+ * initialisation). n a power of two, 1 <= n <= 2^20. Complex dtypes. */
+fm_status fm_op_create_circulant(fm_op* out, int64_t n, const void* c, fm_dtype dt, void* stream);
+
+/* Toeplitz m x n (a non-circular convolution): T[i,j] = col[i-j] for i >= j,
+ * row[j-i] for i < j. col has m entries and defines the diagonal; row has n
+ * entries and row[0] is ignored. Applied through a cyclic convolution of length
+ * L = the smallest power of two >= m + n - 1 with zero padding and cropping
+ * (the embedding described for eq. (7)); L <= 2^20. Complex dtypes. */
+fm_status fm_op_create_toeplitz(fm_op* out, int64_t m, int64_t n, const void* col,
+                                const void* row, fm_dtype dt, void* stream);
+
+/* Multilevel (block-) Toeplitz of `levels` levels with n_per_level[l] entries
+ * per level (square, size prod n_l), the 2-level structure of the blocks H_ij
+ * of eq. (7). t holds prod(2 n_l - 1) values, row-major (last level fastest),
+ * offset o_l at index o_l + n_l - 1:
+ *   T[(i_1..i_d),(j_1..j_d)] = t[i_1-j_1, ..., i_d-j_d].
+ * 1 <= levels <= 3. Complex dtypes. */
+fm_status fm_op_create_mltoeplitz(fm_op* out, int32_t levels, const int64_t* n_per_level,
+                                  const void* t, fm_dtype dt, void* stream);
+
+/* Row selection S (m x n_in), S[r, idx[r]] = 1 (the Partial operator, and the
+ * row selections of Psi in eq. (9)). idx: DEVICE int32 array of m distinct
+ * indices in [0, n_in); validated here (FM_E_SHAPE on a duplicate or an index
+ * out of range). Forward gathers, adjoint scatters into zeros. All dtypes. */
+fm_status fm_op_create_select_rows(fm_op* out, int64_t n_in, int64_t m, const int32_t* idx,
+                                   fm_dtype dt, void* stream);
+
+/* Composite of `nterms` operators, all of one dtype (section "General
+ * Matrix-free Representations": composites are applied only through their
+ * terms' transforms):
+ *   FM_PRODUCT  terms[0] * terms[1] * ... (applied right to left),
+ *   FM_SUM      terms[0] + terms[1] + ... (equal shapes),
+ *   FM_KRON     terms[0] (x) terms[1] (x) ... (first factor slowest, eq. (7)),
+ *   FM_BLKDIAG  block diagonal of the terms (the BlkDiag of eq. (9)).
+ * Retains the terms. */
+fm_status fm_op_compose(fm_op* out, fm_compose_kind kind, int32_t nterms, const fm_op* terms);
+
+/* Hermitian transpose A^H as an operator (shares A's storage, retains A). */
+fm_status fm_op_adjoint(fm_op* out, fm_op a);
+
+/* Shape (m rows, n columns) and dtype of an operator. Any pointer may be NULL. */
+fm_status fm_op_shape(fm_op a, int64_t* m, int64_t* n, fm_dtype* dt);
+
+/* Drops one reference; storage is freed when the last reference goes. */
+fm_status fm_op_release(fm_op a);
+
+/* ------------------------------------------------------------------ application */
+
+/* Workspace bytes fm_apply needs for (a, dir, ncols). */
+fm_status fm_workspace_size(fm_op a, fm_dir dir, int64_t ncols, size_t* bytes);
+
+/* y = A x (FM_FWD) or y = A^H x (FM_ADJ) for ncols columns.
+ * FWD: x is n x ncols (ldx >= n), y is m x ncols (ldy >= m); ADJ swaps m, n.
+ * ws/ws_bytes: device workspace of at least fm_workspace_size bytes; with
+ * ws == NULL and ws_bytes == 0 the library takes stream-ordered memory
+ * (hipMallocAsync/hipFreeAsync) itself. x and y must not overlap (FM_E_ALIAS).
+ * ncols == 0 is a no-op. */
+fm_status fm_apply(fm_op a, fm_dir dir, int64_t ncols, const void* x, int64_t ldx, void* y,
+                   int64_t ldy, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------ FISTA / ISTA
+ * Per column j of b (each column is its own problem), minimise
+ *   1/2 ||A x_j - b_j||_2^2 + lambda_j ||x_j||_1
+ * (eq. (8) with the conventional factor 1/2, i.e. tau = 2 lambda), by the
+ * constant-step proximal-gradient iteration the paper runs (ISTA) and its
+ * accelerated form it cites (FISTA, Beck-Teboulle):
+ *   g = A^H (A y_k - b); x_{k+1} = soft(y_k - g/L, lambda/L);
+ *   t_{k+1} = (1 + sqrt(1 + 4 t_k^2))/2;
+ *   y_{k+1} = x_{k+1} + ((t_k - 1)/t_{k+1}) (x_{k+1} - x_k)   (ISTA: y = x).
+ * soft() shrinks the complex modulus (|z| <= s gives exactly 0).
+ */
+typedef struct {
+  int32_t max_iters;       /* iterations K (>= 0)                               */
+  int32_t momentum;        /* 1 FISTA, 0 ISTA                                   */
+  int32_t x0_given;        /* 1: x holds the start x_0 on entry; 0: x_0 = 0     */
+  int32_t power_max_iters; /* power iteration cap when L <= 0 (e.g. 500)        */
+  double lambda_abs;       /* > 0: lambda_j = lambda_abs for every column       */
+  double lambda_rel;       /* used when lambda_abs <= 0:
+                              lambda_j = lambda_rel * ||A^H b_j||_inf           */
+  double L;                /* > 0: step constant; <= 0: FP64 power iteration    */
+  double stop_tol;         /* > 0: freeze column j after the first k with
+                              ||x_k - x_{k-1}|| <= stop_tol * ||x_k||; 0: fixed K */
+  double power_tol;        /* relative change that ends the power iteration     */
+  uint64_t seed;           /* start vector of the power iteration (SplitMix64)  */
+} fm_fista_opts;
+
+typedef struct {
+  int32_t iters_done;  /* iterations applied to this column                     */
+  int32_t status;      /* 0 ok, 1 non-finite values met (column frozen)         */
+  double L_used;       /* step constant used                                    */
+  double lambda_used;  /* lambda_j used                                         */
+} fm_fista_stat;
+
+/* Runs the iteration on `stream`; b is m x ncols, x is n x ncols (output; also
+ * the start when x0_given). stats: HOST array of ncols entries, filled after the
+ * single synchronisation at the end (may be NULL). Workspace as in fm_apply
+ * (size from fm_fista_workspace_size). Complex dtypes. */
+fm_status fm_fista(fm_op a, int64_t ncols, const void* b, int64_t ldb, void* x, int64_t ldx,
+                   const fm_fista_opts* opts, fm_fista_stat* stats, void* ws, size_t ws_bytes,
+                   void* stream);
+fm_status fm_fista_workspace_size(fm_op a, int64_t ncols, const fm_fista_opts* opts, size_t* bytes);
+
+/* L = ||A||_2^2 by power iteration on A^H A in complex128 (FP64) whatever the
+ * operator's dtype: v <- v/||v||, repeat w = A^H A v, L_k = ||A v||^2,
+ * v <- w/||w|| until |L_k - L_{k-1}| <= tol * L_k or max_iters. v0: DEVICE
+ * complex128 start vector of n entries, or NULL for the SplitMix64 vector of
+ * `seed` (entry i = (u(2i) - 1/2) + j (u(2i+1) - 1/2), u(k) the k-th SplitMix64
+ * output of `seed` scaled to [0,1) by its top 53 bits). Synchronises `stream`.
+ * iters_out may be NULL. */
+fm_status fm_power_iteration(fm_op a, const void* v0, uint64_t seed, int32_t max_iters, double tol,
+                             double* L_out, int32_t* iters_out, void* stream);
+
+/* ------------------------------------------------------------------ batching
+ * Many independent operators applied in one persistent launch: the library
+ * builds a work queue over (operator, column tile) items once, at creation. */
+fm_status fm_batch_create(fm_batch* out, int32_t nops, const fm_op* ops, const int64_t* ncols);
+/* x[i], y[i]: device blocks of operator i with leading dimensions ldx[i], ldy[i]
+ * (host arrays of nops entries). */
+fm_status fm_batch_apply(fm_batch b, fm_dir dir, const void* const* x, const int64_t* ldx,
+                         void* const* y, const int64_t* ldy, void* stream);
+/* FISTA for every operator of the batch (opts shared); stats: host array with
+ * one entry per column of every operator, in batch order. */
+fm_status fm_batch_fista(fm_batch b, const void* const* bvec, const int64_t* ldb, void* const* x,
+                         const int64_t* ldx, const fm_fista_opts* opts, fm_fista_stat* stats,
+                         void* stream);
+fm_status fm_batch_release(fm_batch b);
+
+/* ------------------------------------------------------------------ differentiation
+ * Gradient of a real loss with respect to the generator c of C(c) (n x n):
+ *   use = FM_FWD, y = C(c) in:    grad_c[k] += sum_j sum_i g_j[i] conj(in_j[(i-k) mod n])
+ *   use = FM_ADJ, w = C(c)^H in:  grad_c[k] += sum_j sum_i in_j[i] conj(g_j[(i-k) mod n])
+ * i.e. the circular cross-correlations (PyTorch's convention: grad = dL/d conj(c)),
+ * summed over the ncols columns. `accumulate` = 0 overwrites grad_c. Complex dtypes. */
+fm_status fm_circulant_grad_generator(int64_t n, int64_t ncols, fm_dir use, const void* in,
+                                      int64_t ld_in, const void* g, int64_t ld_g, void* grad_c,
+                                      int32_t accumulate, fm_dtype dt, void* stream);
+
+/* ------------------------------------------------------------------ misc */
+/* Thread-local description of the last error; valid until the next fm_* call
+ * on this thread. */
+const char* fm_last_error(void);
+/* Library version, e.g. "0.1.0". */
+const char* fm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FM_H */

@@ -90,6 +90,30 @@ def kron_apply(factors, x, adjoint_dir: bool = False):
     return np.stack(out)
 
 
+def kron_apply_int(factors, x, bits: int):
+    """Integer Kronecker product by mode products in int64, then wrapped to a
+    signed ``bits``-bit result. Exact only while no partial sum leaves int64:
+    the caller bounds the inputs (checked here)."""
+    mats = [np.asarray(f, dtype=np.int64) for f in factors]
+    x = np.asarray(x, dtype=np.int64)
+    bound = float(np.max(np.abs(x.astype(np.float64)))) if x.size else 0.0
+    for m in mats:
+        bound *= float(np.max(np.sum(np.abs(m), axis=1)))
+    assert bound < 2.0 ** 62, "int64 partial sums could overflow"
+    dims = [m.shape[1] for m in mats]
+    out = []
+    for j in range(x.shape[0]):
+        t = x[j].reshape(dims)
+        for k, m in enumerate(mats):
+            t = np.moveaxis(np.tensordot(m, t, axes=([1], [k])), 0, k)
+        out.append(t.reshape(-1))
+    y = np.stack(out)
+    if bits == 64:
+        return y
+    mod, half = 1 << bits, 1 << (bits - 1)
+    return (((y + half) % mod) - half).astype(np.int32)
+
+
 def circulant_apply_fft64(c, x, adjoint_dir: bool = False):
     """Eq. (5) in complex128: y = IFFT(FFT(c) * FFT(x)); adjoint uses conj."""
     c = np.asarray(c, dtype=C128)

@@ -1,0 +1,25 @@
+"""Structured linear operators and FISTA on MI355X (gfx950).
+
+The compute path is the HIP library ``libfm.so`` (C ABI in ``include/fm.h``);
+``capi`` binds it entry point by entry point, ``operators`` offers the
+paper's notation on top (``Circulant(c) @ x``, ``A.H``, ``Product``, ...).
+"""
+
+from .capi import FmError, load  # noqa: F401
+from .operators import (  # noqa: F401
+    BlkDiag,
+    Circulant,
+    Dense,
+    Diag,
+    Fourier,
+    Hadamard,
+    Kron,
+    MLToeplitz,
+    Operator,
+    Product,
+    SelectRows,
+    Sum,
+    Toeplitz,
+)
+
+__version__ = "0.1.0"

@@ -1,0 +1,286 @@
+"""ctypes binding of the C ABI in ``include/fm.h``, one Python function per C
+entry point and with the same name.
+
+Arguments are marshalled only: device pointers are passed as integers (or
+torch tensors, whose ``data_ptr()`` is taken), streams as integers holding a
+``hipStream_t``. A non-zero status raises ``FmError`` with the library's own
+error text. The shared library must have been built (``build()``); loading
+fails loudly otherwise -- there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfm.so")
+
+FM_C64, FM_C128, FM_I32, FM_I64 = 1, 2, 3, 4
+FM_FWD, FM_ADJ = 0, 1
+FM_PRODUCT, FM_SUM, FM_KRON, FM_BLKDIAG = 0, 1, 2, 3
+
+STATUS = {
+    0: "FM_OK",
+    1: "FM_E_INVALID",
+    2: "FM_E_SHAPE",
+    3: "FM_E_DTYPE",
+    4: "FM_E_ALIAS",
+    5: "FM_E_UNSUPPORTED",
+    6: "FM_E_WORKSPACE",
+    7: "FM_E_NOMEM",
+    8: "FM_E_DEVICE",
+    9: "FM_E_RELEASED",
+}
+
+
+class FmError(RuntimeError):
+    """A library call returned a non-zero fm_status."""
+
+    def __init__(self, func: str, status: int, text: str):
+        self.status = status
+        self.code = STATUS.get(status, str(status))
+        super().__init__(f"{func}: {self.code}: {text}")
+
+
+class fm_fista_opts(C.Structure):
+    _fields_ = [
+        ("max_iters", C.c_int32),
+        ("momentum", C.c_int32),
+        ("x0_given", C.c_int32),
+        ("power_max_iters", C.c_int32),
+        ("lambda_abs", C.c_double),
+        ("lambda_rel", C.c_double),
+        ("L", C.c_double),
+        ("stop_tol", C.c_double),
+        ("power_tol", C.c_double),
+        ("seed", C.c_uint64),
+    ]
+
+
+class fm_fista_stat(C.Structure):
+    _fields_ = [
+        ("iters_done", C.c_int32),
+        ("status", C.c_int32),
+        ("L_used", C.c_double),
+        ("lambda_used", C.c_double),
+    ]
+
+
+P = C.c_void_p
+I64 = C.c_int64
+I32 = C.c_int32
+ST = C.c_int
+
+# name: (restype, argtypes)
+SIGNATURES = {
+    "fm_op_create_fourier": (ST, [C.POINTER(P), I64, C.c_int]),
+    "fm_op_create_hadamard": (ST, [C.POINTER(P), I64, C.c_int]),
+    "fm_op_create_diag": (ST, [C.POINTER(P), I64, P, C.c_int, P]),
+    "fm_op_create_dense": (ST, [C.POINTER(P), I64, I64, P, I64, C.c_int, P]),
+    "fm_op_create_circulant": (ST, [C.POINTER(P), I64, P, C.c_int, P]),
+    "fm_op_create_toeplitz": (ST, [C.POINTER(P), I64, I64, P, P, C.c_int, P]),
+    "fm_op_create_mltoeplitz": (ST, [C.POINTER(P), I32, C.POINTER(I64), P, C.c_int, P]),
+    "fm_op_create_select_rows": (ST, [C.POINTER(P), I64, I64, P, C.c_int, P]),
+    "fm_op_compose": (ST, [C.POINTER(P), C.c_int, I32, C.POINTER(P)]),
+    "fm_op_adjoint": (ST, [C.POINTER(P), P]),
+    "fm_op_shape": (ST, [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(C.c_int)]),
+    "fm_op_release": (ST, [P]),
+    "fm_workspace_size": (ST, [P, C.c_int, I64, C.POINTER(C.c_size_t)]),
+    "fm_apply": (ST, [P, C.c_int, I64, P, I64, P, I64, P, C.c_size_t, P]),
+    "fm_fista": (ST, [P, I64, P, I64, P, I64, C.POINTER(fm_fista_opts), C.POINTER(fm_fista_stat),
+                      P, C.c_size_t, P]),
+    "fm_fista_workspace_size": (ST, [P, I64, C.POINTER(fm_fista_opts), C.POINTER(C.c_size_t)]),
+    "fm_power_iteration": (ST, [P, P, C.c_uint64, I32, C.c_double, C.POINTER(C.c_double),
+                                C.POINTER(I32), P]),
+    "fm_batch_create": (ST, [C.POINTER(P), I32, C.POINTER(P), C.POINTER(I64)]),
+    "fm_batch_apply": (ST, [P, C.c_int, C.POINTER(P), C.POINTER(I64), C.POINTER(P), C.POINTER(I64), P]),
+    "fm_batch_fista": (ST, [P, C.POINTER(P), C.POINTER(I64), C.POINTER(P), C.POINTER(I64),
+                            C.POINTER(fm_fista_opts), C.POINTER(fm_fista_stat), P]),
+    "fm_batch_release": (ST, [P]),
+    "fm_circulant_grad_generator": (ST, [I64, I64, C.c_int, P, I64, P, I64, P, I32, C.c_int, P]),
+    "fm_last_error": (C.c_char_p, []),
+    "fm_version": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+def load(path: str | None = None):
+    """Loads libfm.so (after torch, so both share torch's HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  (HIP runtime of torch first)
+
+    path = path or os.environ.get("FM_LIB", LIB_PATH)
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"HIP library {path} is missing: build it with "
+            "`python -m paper_1710_09578_amd.build` (there is no fallback path)")
+    lib = C.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(v):
+    """Device/host pointer of a tensor, an int, or None."""
+    if v is None:
+        return None
+    if hasattr(v, "data_ptr"):
+        return v.data_ptr()
+    return int(v)
+
+
+def _call(name, *args):
+    lib = load()
+    st = getattr(lib, name)(*args)
+    if st != 0:
+        raise FmError(name, st, lib.fm_last_error().decode(errors="replace"))
+    return st
+
+
+def fm_last_error() -> str:
+    return load().fm_last_error().decode(errors="replace")
+
+
+def fm_version() -> str:
+    return load().fm_version().decode()
+
+
+def fm_op_create_fourier(n, dt):
+    h = P()
+    _call("fm_op_create_fourier", C.byref(h), n, dt)
+    return h
+
+
+def fm_op_create_hadamard(n, dt):
+    h = P()
+    _call("fm_op_create_hadamard", C.byref(h), n, dt)
+    return h
+
+
+def fm_op_create_diag(n, d, dt, stream):
+    h = P()
+    _call("fm_op_create_diag", C.byref(h), n, _ptr(d), dt, _ptr(stream))
+    return h
+
+
+def fm_op_create_dense(m, n, a, lda, dt, stream):
+    h = P()
+    _call("fm_op_create_dense", C.byref(h), m, n, _ptr(a), lda, dt, _ptr(stream))
+    return h
+
+
+def fm_op_create_circulant(n, c, dt, stream):
+    h = P()
+    _call("fm_op_create_circulant", C.byref(h), n, _ptr(c), dt, _ptr(stream))
+    return h
+
+
+def fm_op_create_toeplitz(m, n, col, row, dt, stream):
+    h = P()
+    _call("fm_op_create_toeplitz", C.byref(h), m, n, _ptr(col), _ptr(row), dt, _ptr(stream))
+    return h
+
+
+def fm_op_create_mltoeplitz(levels, n_per_level, t, dt, stream):
+    h = P()
+    arr = (I64 * len(n_per_level))(*n_per_level)
+    _call("fm_op_create_mltoeplitz", C.byref(h), levels, arr, _ptr(t), dt, _ptr(stream))
+    return h
+
+
+def fm_op_create_select_rows(n_in, m, idx, dt, stream):
+    h = P()
+    _call("fm_op_create_select_rows", C.byref(h), n_in, m, _ptr(idx), dt, _ptr(stream))
+    return h
+
+
+def fm_op_compose(kind, terms):
+    h = P()
+    arr = (P * len(terms))(*[t.value if isinstance(t, P) else t for t in terms])
+    _call("fm_op_compose", C.byref(h), kind, len(terms), arr)
+    return h
+
+
+def fm_op_adjoint(a):
+    h = P()
+    _call("fm_op_adjoint", C.byref(h), a)
+    return h
+
+
+def fm_op_shape(a):
+    m, n, dt = I64(), I64(), C.c_int()
+    _call("fm_op_shape", a, C.byref(m), C.byref(n), C.byref(dt))
+    return m.value, n.value, dt.value
+
+
+def fm_op_release(a):
+    _call("fm_op_release", a)
+
+
+def fm_workspace_size(a, direction, ncols):
+    b = C.c_size_t()
+    _call("fm_workspace_size", a, direction, ncols, C.byref(b))
+    return b.value
+
+
+def fm_apply(a, direction, ncols, x, ldx, y, ldy, ws, ws_bytes, stream):
+    _call("fm_apply", a, direction, ncols, _ptr(x), ldx, _ptr(y), ldy, _ptr(ws), ws_bytes, _ptr(stream))
+
+
+def fm_fista_workspace_size(a, ncols, opts):
+    b = C.c_size_t()
+    _call("fm_fista_workspace_size", a, ncols, C.byref(opts), C.byref(b))
+    return b.value
+
+
+def fm_fista(a, ncols, b, ldb, x, ldx, opts, stats, ws, ws_bytes, stream):
+    _call("fm_fista", a, ncols, _ptr(b), ldb, _ptr(x), ldx, C.byref(opts),
+          stats if stats is not None else None, _ptr(ws), ws_bytes, _ptr(stream))
+
+
+def fm_power_iteration(a, v0, seed, max_iters, tol, stream):
+    L = C.c_double()
+    its = I32()
+    _call("fm_power_iteration", a, _ptr(v0), seed, max_iters, tol, C.byref(L), C.byref(its), _ptr(stream))
+    return L.value, its.value
+
+
+def fm_batch_create(ops, ncols):
+    h = P()
+    oa = (P * len(ops))(*[o.value if isinstance(o, P) else o for o in ops])
+    na = (I64 * len(ncols))(*ncols)
+    _call("fm_batch_create", C.byref(h), len(ops), oa, na)
+    return h
+
+
+def _parr(vals):
+    return (P * len(vals))(*[_ptr(v) for v in vals])
+
+
+def _iarr(vals):
+    return (I64 * len(vals))(*vals)
+
+
+def fm_batch_apply(b, direction, xs, ldx, ys, ldy, stream):
+    _call("fm_batch_apply", b, direction, _parr(xs), _iarr(ldx), _parr(ys), _iarr(ldy), _ptr(stream))
+
+
+def fm_batch_fista(b, bvecs, ldb, xs, ldx, opts, stats, stream):
+    _call("fm_batch_fista", b, _parr(bvecs), _iarr(ldb), _parr(xs), _iarr(ldx), C.byref(opts),
+          stats, _ptr(stream))
+
+
+def fm_batch_release(b):
+    _call("fm_batch_release", b)
+
+
+def fm_circulant_grad_generator(n, ncols, use, inp, ld_in, g, ld_g, grad_c, accumulate, dt, stream):
+    _call("fm_circulant_grad_generator", n, ncols, use, _ptr(inp), ld_in, _ptr(g), ld_g, _ptr(grad_c),
+          accumulate, dt, _ptr(stream))

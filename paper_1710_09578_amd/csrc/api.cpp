@@ -1,0 +1,546 @@
+// C ABI: operator creation (with the one-time precomputation of spectra),
+// composition, validation at every entry point, and fm_apply.
+#include <cstring>
+#include <vector>
+
+#include "runtime.h"
+
+namespace fm {
+void register_op(const fm_op_s* op);
+void unregister_op(const fm_op_s* op);
+}  // namespace fm
+
+using namespace fm;
+
+namespace {
+
+constexpr int kMaxLog = 20;
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+fm_status current_device(int* dev) {
+  FM_HIP(hipGetDevice(dev));
+  return FM_OK;
+}
+
+fm_status new_op(Kind k, fm_dtype dt, int64_t m, int64_t n, fm_op_s** out) {
+  fm_op_s* op = new (std::nothrow) fm_op_s();
+  FM_CHECK_ARG(op != nullptr, FM_E_NOMEM, "out of host memory");
+  op->kind = k;
+  op->dt = dt;
+  op->m = m;
+  op->n = n;
+  fm_status st = current_device(&op->device);
+  if (st != FM_OK) {
+    delete op;
+    return st;
+  }
+  *out = op;
+  return FM_OK;
+}
+
+void destroy(fm_op_s* op);
+
+void drop(fm_op_s* op) {
+  if (op->refs.fetch_sub(1) == 1) destroy(op);
+}
+
+void destroy(fm_op_s* op) {
+  unregister_op(op);
+  for (fm_op t : op->terms) drop(t);
+  op->magic = 0;
+  delete op;
+}
+
+fm_status publish(fm_op_s* op, fm_op* out) {
+  register_op(op);
+  *out = op;
+  return FM_OK;
+}
+
+// Guard that deletes a half-built operator on an error path.
+struct Building {
+  fm_op_s* op;
+  ~Building() {
+    if (op) {
+      for (fm_op t : op->terms) drop(t);
+      delete op;
+    }
+  }
+  fm_op_s* release() {
+    fm_op_s* o = op;
+    op = nullptr;
+    return o;
+  }
+};
+
+bool valid_dtype(fm_dtype dt) { return dt == FM_C64 || dt == FM_C128 || dt == FM_I32 || dt == FM_I64; }
+
+// Copies n complex values of dtype dt from src into the operator's complex128
+// store (exact upcast) and, for FM_C64, its complex64 store.
+fm_status store_params(fm_op_s* op, const void* src, int64_t count, hipStream_t s) {
+  FM_TRY(op->p64.alloc(size_t(count) * 16));
+  if (op->dt == FM_C64) {
+    FM_TRY(op->p32.alloc(size_t(count) * 8));
+    FM_HIP(hipMemcpyAsync(op->p32.p, src, size_t(count) * 8, hipMemcpyDeviceToDevice, s));
+    FM_TRY(launch_c64_to_c128(count, src, op->p64.p, s));
+  } else {
+    FM_HIP(hipMemcpyAsync(op->p64.p, src, size_t(count) * 16, hipMemcpyDeviceToDevice, s));
+  }
+  return FM_OK;
+}
+
+// Turns a natural-order complex128 spectrum g_hat (length L, already scaled)
+// into the operator's stores, in the order each precision's split expects.
+fm_status store_spectrum(fm_op_s* op, const void* ghat, hipStream_t s) {
+  const int64_t L = op->L;
+  FM_TRY(op->p64.alloc(size_t(L) * 16));
+  if (op->s64.four_step())
+    FM_TRY(launch_fourstep_permute(int64_t(1) << op->s64.log1, int64_t(1) << op->s64.log2, ghat,
+                                   op->p64.p, s));
+  else
+    FM_HIP(hipMemcpyAsync(op->p64.p, ghat, size_t(L) * 16, hipMemcpyDeviceToDevice, s));
+  if (op->dt == FM_C64) {
+    FM_TRY(op->p32.alloc(size_t(L) * 8));
+    DevBuf tmp;
+    const void* src = ghat;
+    if (op->s32.four_step()) {
+      FM_TRY(tmp.alloc(size_t(L) * 16));
+      FM_TRY(launch_fourstep_permute(int64_t(1) << op->s32.log1, int64_t(1) << op->s32.log2, ghat,
+                                     tmp.p, s));
+      src = tmp.p;
+    }
+    FM_TRY(launch_c128_to_c64(L, src, op->p32.p, s));
+    FM_HIP(hipStreamSynchronize(s));  // tmp is freed on return
+  }
+  return FM_OK;
+}
+
+// DFT in complex128 of `count` contiguous vectors of length L (natural order),
+// scaled by `scale`, through the library's own transform.
+fm_status dft128(int64_t L, const void* in, void* out, double scale, hipStream_t s) {
+  fm_op_s f;
+  f.kind = Kind::Fourier;
+  f.dt = FM_C128;
+  f.m = f.n = f.L = L;
+  f.s32 = split_for(Elem::C64, ilog2(L));
+  f.s64 = split_for(Elem::C128, ilog2(L));
+  Batch b{1, 1, 1, L, L, L, L};
+  Workspace ws;
+  ws.sizing = true;
+  FM_TRY(exec(&f, false, Elem::C128, b, in, out, false, ws, s));
+  DevBuf wbuf;
+  FM_TRY(wbuf.alloc(ws.peak));
+  Workspace run;
+  run.base = static_cast<char*>(wbuf.p);
+  run.cap = wbuf.bytes;
+  FM_TRY(exec(&f, false, Elem::C128, b, in, out, false, run, s));
+  if (scale != 1.0) FM_TRY(launch_scale_copy(Elem::C128, L, scale, out, out, s));
+  FM_HIP(hipStreamSynchronize(s));
+  return FM_OK;
+}
+
+// Largest workspace fm_apply needs (contiguous blocks).
+fm_status size_of(const fm_op_s* op, bool adj, int64_t ncols, size_t* bytes) {
+  Batch b{ncols, 1, 1, in_rows(op, adj), in_rows(op, adj), out_rows(op, adj), out_rows(op, adj)};
+  Workspace ws;
+  ws.sizing = true;
+  FM_TRY(exec(op, adj, elem_of(op->dt), b, nullptr, nullptr, false, ws, nullptr));
+  *bytes = ws.peak;
+  return FM_OK;
+}
+
+#define CHECK_OUT(out) FM_CHECK_ARG((out) != nullptr, FM_E_INVALID, "output handle pointer is NULL")
+#define CHECK_LIVE(a)                                                                  \
+  do {                                                                                 \
+    FM_CHECK_ARG((a) != nullptr, FM_E_INVALID, "operator handle is NULL");             \
+    FM_CHECK_ARG(op_alive(a), FM_E_RELEASED, "operator handle was released");          \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+const char* fm_last_error(void) { return last_error(); }
+const char* fm_version(void) { return "0.1.0"; }
+
+fm_status fm_op_create_fourier(fm_op* out, int64_t n, fm_dtype dt) {
+  set_error("");
+  CHECK_OUT(out);
+  FM_CHECK_ARG(valid_dtype(dt), FM_E_INVALID, "unknown dtype %d", int(dt));
+  FM_CHECK_ARG(is_complex(dt), FM_E_DTYPE, "Fourier needs a complex dtype");
+  FM_CHECK_ARG(n >= 1 && is_pow2(n) && ilog2(n) <= kMaxLog, FM_E_UNSUPPORTED,
+               "Fourier size %lld: powers of two up to 2^20 are supported", (long long)n);
+  fm_op_s* op;
+  FM_TRY(new_op(Kind::Fourier, dt, n, n, &op));
+  op->L = n;
+  op->s32 = split_for(Elem::C64, ilog2(n));
+  op->s64 = split_for(Elem::C128, ilog2(n));
+  return publish(op, out);
+}
+
+fm_status fm_op_create_hadamard(fm_op* out, int64_t n, fm_dtype dt) {
+  set_error("");
+  CHECK_OUT(out);
+  FM_CHECK_ARG(valid_dtype(dt), FM_E_INVALID, "unknown dtype %d", int(dt));
+  FM_CHECK_ARG(n >= 1 && is_pow2(n) && ilog2(n) <= 26, FM_E_UNSUPPORTED,
+               "Hadamard size %lld: powers of two up to 2^26 are supported", (long long)n);
+  fm_op_s* op;
+  FM_TRY(new_op(Kind::Hadamard, dt, n, n, &op));
+  return publish(op, out);
+}
+
+fm_status fm_op_create_diag(fm_op* out, int64_t n, const void* d, fm_dtype dt, void* stream) {
+  set_error("");
+  CHECK_OUT(out);
+  FM_CHECK_ARG(valid_dtype(dt), FM_E_INVALID, "unknown dtype %d", int(dt));
+  FM_CHECK_ARG(is_complex(dt), FM_E_DTYPE, "Diag needs a complex dtype");
+  FM_CHECK_ARG(n >= 1, FM_E_INVALID, "Diag size must be positive");
+  FM_CHECK_ARG(d != nullptr, FM_E_INVALID, "Diag: NULL diagonal");
+  hipStream_t s = as_stream(stream);
+  fm_op_s* op;
+  FM_TRY(new_op(Kind::Diag, dt, n, n, &op));
+  Building g{op};
+  FM_TRY(store_params(op, d, n, s));
+  FM_HIP(hipStreamSynchronize(s));
+  return publish(g.release(), out);
+}
+
+fm_status fm_op_create_dense(fm_op* out, int64_t m, int64_t n, const void* a, int64_t lda,
+                             fm_dtype dt, void* stream) {
+  set_error("");
+  CHECK_OUT(out);
+  FM_CHECK_ARG(valid_dtype(dt), FM_E_INVALID, "unknown dtype %d", int(dt));
+  FM_CHECK_ARG(is_complex(dt), FM_E_DTYPE, "Dense needs a complex dtype");
+  FM_CHECK_ARG(m >= 1 && n >= 1, FM_E_INVALID, "Dense shape must be positive");
+  FM_CHECK_ARG(lda >= m, FM_E_SHAPE, "Dense: lda %lld < m %lld", (long long)lda, (long long)m);
+  FM_CHECK_ARG(a != nullptr, FM_E_INVALID, "Dense: NULL matrix");
+  hipStream_t s = as_stream(stream);
+  fm_op_s* op;
+  FM_TRY(new_op(Kind::Dense, dt, m, n, &op));
+  Building g{op};
+  const size_t es = elem_size(dt);
+  DevBuf packed;
+  FM_TRY(packed.alloc(size_t(m * n) * es));
+  FM_HIP(hipMemcpy2DAsync(packed.p, size_t(m) * es, a, size_t(lda) * es, size_t(m) * es, size_t(n),
+                          hipMemcpyDeviceToDevice, s));
+  FM_TRY(store_params(op, packed.p, m * n, s));
+  op->lda = m;
+  FM_HIP(hipStreamSynchronize(s));
+  return publish(g.release(), out);
+}
+
+fm_status fm_op_create_circulant(fm_op* out, int64_t n, const void* c, fm_dtype dt, void* stream) {
+  set_error("");
+  CHECK_OUT(out);
+  FM_CHECK_ARG(valid_dtype(dt), FM_E_INVALID, "unknown dtype %d", int(dt));
+  FM_CHECK_ARG(is_complex(dt), FM_E_DTYPE, "Circulant needs a complex dtype");
+  FM_CHECK_ARG(n >= 1 && is_pow2(n) && ilog2(n) <= kMaxLog, FM_E_UNSUPPORTED,
+               "Circulant size %lld: powers of two up to 2^20 are supported", (long long)n);
+  FM_CHECK_ARG(c != nullptr, FM_E_INVALID, "Circulant: NULL generator");
+  hipStream_t s = as_stream(stream);
+  fm_op_s* op;
+  FM_TRY(new_op(Kind::Circulant, dt, n, n, &op));
+  Building g{op};
+  op->L = n;
+  op->s32 = split_for(Elem::C64, ilog2(n));
+  op->s64 = split_for(Elem::C128, ilog2(n));
+  DevBuf c128, ghat;
+  FM_TRY(c128.alloc(size_t(n) * 16));
+  FM_TRY(ghat.alloc(size_t(n) * 16));
+  if (dt == FM_C64)
+    FM_TRY(launch_c64_to_c128(n, c, c128.p, s));
+  else
+    FM_HIP(hipMemcpyAsync(c128.p, c, size_t(n) * 16, hipMemcpyDeviceToDevice, s));
+  // C = F^-1 diag(F c) F: spectrum F c with the 1/n of the inverse folded in
+  FM_TRY(dft128(n, c128.p, ghat.p, 1.0 / double(n), s));
+  FM_TRY(store_spectrum(op, ghat.p, s));
+  FM_HIP(hipStreamSynchronize(s));
+  return publish(g.release(), out);
+}
+
+fm_status fm_op_create_toeplitz(fm_op* out, int64_t m, int64_t n, const void* col, const void* row,
+                                fm_dtype dt, void* stream) {
+  set_error("");
+  CHECK_OUT(out);
+  FM_CHECK_ARG(valid_dtype(dt), FM_E_INVALID, "unknown dtype %d", int(dt));
+  FM_CHECK_ARG(is_complex(dt), FM_E_DTYPE, "Toeplitz needs a complex dtype");
+  FM_CHECK_ARG(m >= 1 && n >= 1, FM_E_INVALID, "Toeplitz shape must be positive");
+  FM_CHECK_ARG(col != nullptr && (row != nullptr || n == 1), FM_E_INVALID, "Toeplitz: NULL generator");
+  const int64_t L = next_pow2(m + n - 1);
+  FM_CHECK_ARG(ilog2(L) <= kMaxLog, FM_E_UNSUPPORTED,
+               "Toeplitz %lld x %lld: embedding length above 2^20", (long long)m, (long long)n);
+  hipStream_t s = as_stream(stream);
+  fm_op_s* op;
+  FM_TRY(new_op(Kind::Toeplitz, dt, m, n, &op));
+  Building g{op};
+  op->L = L;
+  op->s32 = split_for(Elem::C64, ilog2(L));
+  op->s64 = split_for(Elem::C128, ilog2(L));
+  DevBuf emb, ghat;
+  FM_TRY(emb.alloc(size_t(L) * 16));
+  FM_TRY(ghat.alloc(size_t(L) * 16));
+  FM_TRY(launch_toeplitz_embed(m, n, L, col, row != nullptr ? row : col, dt == FM_C64, emb.p, s));
+  FM_TRY(dft128(L, emb.p, ghat.p, 1.0 / double(L), s));
+  FM_TRY(store_spectrum(op, ghat.p, s));
+  FM_HIP(hipStreamSynchronize(s));
+  return publish(g.release(), out);
+}
+
+fm_status fm_op_create_mltoeplitz(fm_op* out, int32_t levels, const int64_t* n_per_level,
+                                  const void* t, fm_dtype dt, void* stream) {
+  set_error("");
+  CHECK_OUT(out);
+  FM_CHECK_ARG(valid_dtype(dt), FM_E_INVALID, "unknown dtype %d", int(dt));
+  FM_CHECK_ARG(is_complex(dt), FM_E_DTYPE, "multilevel Toeplitz needs a complex dtype");
+  FM_CHECK_ARG(levels >= 1 && levels <= 3, FM_E_UNSUPPORTED, "multilevel Toeplitz: 1..3 levels");
+  FM_CHECK_ARG(n_per_level != nullptr && t != nullptr, FM_E_INVALID, "multilevel Toeplitz: NULL argument");
+  std::vector<int64_t> lv(levels), lL(levels);
+  int64_t size = 1, tsize = 1, total = 1;
+  for (int l = 0; l < levels; ++l) {
+    FM_CHECK_ARG(n_per_level[l] >= 1, FM_E_INVALID, "multilevel Toeplitz: level sizes must be positive");
+    lv[l] = n_per_level[l];
+    lL[l] = next_pow2(2 * lv[l] - 1);
+    FM_CHECK_ARG(ilog2(lL[l]) <= fft_lds_max_log(Elem::C128), FM_E_UNSUPPORTED,
+                 "multilevel Toeplitz: level %d too long", l);
+    size *= lv[l];
+    tsize *= 2 * lv[l] - 1;
+    total *= lL[l];
+  }
+  hipStream_t s = as_stream(stream);
+  fm_op_s* op;
+  FM_TRY(new_op(Kind::MLToeplitz, dt, size, size, &op));
+  Building g{op};
+  op->lv = lv;
+  op->lL = lL;
+  // Kron of the per-level Fourier matrices: the multi-dimensional DFT
+  std::vector<fm_op> fs(levels);
+  for (int l = 0; l < levels; ++l) {
+    fm_status st = fm_op_create_fourier(&fs[l], lL[l], dt);
+    if (st != FM_OK) {
+      for (int k = 0; k < l; ++k) fm_op_release(fs[k]);
+      return st;
+    }
+  }
+  fm_op kf;
+  fm_status st = fm_op_compose(&kf, FM_KRON, levels, fs.data());
+  for (int l = 0; l < levels; ++l) fm_op_release(fs[l]);
+  FM_TRY(st);
+  op->terms.push_back(kf);
+  // embed the generator on the host in FP64: offset o_l lands at o_l mod L_l
+  const size_t es = elem_size(dt);
+  std::vector<unsigned char> th(size_t(tsize) * es);
+  FM_HIP(hipMemcpyAsync(th.data(), t, th.size(), hipMemcpyDeviceToHost, s));
+  FM_HIP(hipStreamSynchronize(s));
+  std::vector<double> gh(size_t(total) * 2, 0.0);
+  for (int64_t k = 0; k < tsize; ++k) {
+    int64_t rem = k, pos = 0, stride = 1;
+    for (int l = levels - 1; l >= 0; --l) {
+      const int64_t w = 2 * lv[l] - 1;
+      const int64_t idx = rem % w;
+      rem /= w;
+      const int64_t off = idx - (lv[l] - 1);
+      pos += ((off % lL[l] + lL[l]) % lL[l]) * stride;
+      stride *= lL[l];
+    }
+    double re, im;
+    if (dt == FM_C64) {
+      const float* f = reinterpret_cast<const float*>(th.data()) + 2 * k;
+      re = f[0];
+      im = f[1];
+    } else {
+      const double* f = reinterpret_cast<const double*>(th.data()) + 2 * k;
+      re = f[0];
+      im = f[1];
+    }
+    gh[2 * pos] = re;
+    gh[2 * pos + 1] = im;
+  }
+  DevBuf gd, ghat, wsb;
+  FM_TRY(gd.alloc(size_t(total) * 16));
+  FM_TRY(ghat.alloc(size_t(total) * 16));
+  FM_HIP(hipMemcpyAsync(gd.p, gh.data(), size_t(total) * 16, hipMemcpyHostToDevice, s));
+  {
+    Batch b{1, 1, 1, total, total, total, total};
+    Workspace ws;
+    ws.sizing = true;
+    FM_TRY(exec(kf, false, Elem::C128, b, gd.p, ghat.p, false, ws, s));
+    FM_TRY(wsb.alloc(ws.peak));
+    Workspace run;
+    run.base = static_cast<char*>(wsb.p);
+    run.cap = wsb.bytes;
+    FM_TRY(exec(kf, false, Elem::C128, b, gd.p, ghat.p, false, run, s));
+  }
+  FM_TRY(op->p64.alloc(size_t(total) * 16));
+  FM_TRY(launch_scale_copy(Elem::C128, total, 1.0 / double(total), ghat.p, op->p64.p, s));
+  if (dt == FM_C64) {
+    FM_TRY(op->p32.alloc(size_t(total) * 8));
+    FM_TRY(launch_c128_to_c64(total, op->p64.p, op->p32.p, s));
+  }
+  FM_HIP(hipStreamSynchronize(s));
+  return publish(g.release(), out);
+}
+
+fm_status fm_op_create_select_rows(fm_op* out, int64_t n_in, int64_t m, const int32_t* idx,
+                                   fm_dtype dt, void* stream) {
+  set_error("");
+  CHECK_OUT(out);
+  FM_CHECK_ARG(valid_dtype(dt), FM_E_INVALID, "unknown dtype %d", int(dt));
+  FM_CHECK_ARG(n_in >= 1 && m >= 0 && m <= n_in, FM_E_SHAPE, "selection: need 0 <= m <= n_in");
+  FM_CHECK_ARG(n_in < (int64_t(1) << 31), FM_E_UNSUPPORTED, "selection: n_in must fit int32");
+  FM_CHECK_ARG(idx != nullptr || m == 0, FM_E_INVALID, "selection: NULL indices");
+  hipStream_t s = as_stream(stream);
+  fm_op_s* op;
+  FM_TRY(new_op(Kind::Select, dt, m, n_in, &op));
+  Building g{op};
+  FM_TRY(op->idx.alloc(size_t(m > 0 ? m : 1) * 4));
+  if (m > 0) {
+    FM_HIP(hipMemcpyAsync(op->idx.p, idx, size_t(m) * 4, hipMemcpyDeviceToDevice, s));
+    DevBuf flags;
+    FM_TRY(flags.alloc(size_t(n_in + 1) * 4));
+    FM_HIP(hipMemsetAsync(flags.p, 0, flags.bytes, s));
+    FM_TRY(launch_check_indices(n_in, m, static_cast<const int32_t*>(op->idx.p),
+                                static_cast<int*>(flags.p), s));
+    int bad = 0;
+    FM_HIP(hipMemcpyAsync(&bad, static_cast<int*>(flags.p) + n_in, 4, hipMemcpyDeviceToHost, s));
+    FM_HIP(hipStreamSynchronize(s));
+    FM_CHECK_ARG(bad == 0, FM_E_SHAPE, "selection: indices must be distinct and in [0, n_in)");
+  }
+  return publish(g.release(), out);
+}
+
+fm_status fm_op_compose(fm_op* out, fm_compose_kind kind, int32_t nterms, const fm_op* terms) {
+  set_error("");
+  CHECK_OUT(out);
+  FM_CHECK_ARG(nterms >= 1 && terms != nullptr, FM_E_INVALID, "compose: need at least one term");
+  FM_CHECK_ARG(kind >= FM_PRODUCT && kind <= FM_BLKDIAG, FM_E_INVALID, "compose: unknown kind");
+  for (int i = 0; i < nterms; ++i) {
+    CHECK_LIVE(terms[i]);
+    FM_CHECK_ARG(terms[i]->dt == terms[0]->dt, FM_E_DTYPE, "compose: terms have different dtypes");
+  }
+  int64_t m = 0, n = 0;
+  Kind k = Kind::Product;
+  switch (kind) {
+    case FM_PRODUCT:
+      k = Kind::Product;
+      for (int i = 0; i + 1 < nterms; ++i)
+        FM_CHECK_ARG(terms[i]->n == terms[i + 1]->m, FM_E_SHAPE,
+                     "product: term %d has %lld columns, term %d has %lld rows", i,
+                     (long long)terms[i]->n, i + 1, (long long)terms[i + 1]->m);
+      m = terms[0]->m;
+      n = terms[nterms - 1]->n;
+      break;
+    case FM_SUM:
+      k = Kind::Sum;
+      for (int i = 1; i < nterms; ++i)
+        FM_CHECK_ARG(terms[i]->m == terms[0]->m && terms[i]->n == terms[0]->n, FM_E_SHAPE,
+                     "sum: terms differ in shape");
+      m = terms[0]->m;
+      n = terms[0]->n;
+      break;
+    case FM_KRON:
+      k = Kind::Kron;
+      m = n = 1;
+      for (int i = 0; i < nterms; ++i) {
+        m *= terms[i]->m;
+        n *= terms[i]->n;
+      }
+      break;
+    case FM_BLKDIAG:
+      k = Kind::BlkDiag;
+      for (int i = 0; i < nterms; ++i) {
+        m += terms[i]->m;
+        n += terms[i]->n;
+      }
+      break;
+  }
+  fm_op_s* op;
+  FM_TRY(new_op(k, terms[0]->dt, m, n, &op));
+  for (int i = 0; i < nterms; ++i) {
+    terms[i]->refs.fetch_add(1);
+    op->terms.push_back(terms[i]);
+  }
+  return publish(op, out);
+}
+
+fm_status fm_op_adjoint(fm_op* out, fm_op a) {
+  set_error("");
+  CHECK_OUT(out);
+  CHECK_LIVE(a);
+  fm_op_s* op;
+  FM_TRY(new_op(Kind::Adjoint, a->dt, a->n, a->m, &op));
+  a->refs.fetch_add(1);
+  op->terms.push_back(a);
+  return publish(op, out);
+}
+
+fm_status fm_op_shape(fm_op a, int64_t* m, int64_t* n, fm_dtype* dt) {
+  set_error("");
+  CHECK_LIVE(a);
+  if (m) *m = a->m;
+  if (n) *n = a->n;
+  if (dt) *dt = a->dt;
+  return FM_OK;
+}
+
+fm_status fm_op_release(fm_op a) {
+  set_error("");
+  CHECK_LIVE(a);
+  drop(a);
+  return FM_OK;
+}
+
+fm_status fm_workspace_size(fm_op a, fm_dir dir, int64_t ncols, size_t* bytes) {
+  set_error("");
+  CHECK_LIVE(a);
+  FM_CHECK_ARG(bytes != nullptr, FM_E_INVALID, "NULL output");
+  FM_CHECK_ARG(dir == FM_FWD || dir == FM_ADJ, FM_E_INVALID, "unknown direction");
+  FM_CHECK_ARG(ncols >= 0, FM_E_INVALID, "negative column count");
+  return size_of(a, dir == FM_ADJ, ncols, bytes);
+}
+
+fm_status fm_apply(fm_op a, fm_dir dir, int64_t ncols, const void* x, int64_t ldx, void* y,
+                   int64_t ldy, void* ws, size_t ws_bytes, void* stream) {
+  set_error("");
+  CHECK_LIVE(a);
+  FM_CHECK_ARG(dir == FM_FWD || dir == FM_ADJ, FM_E_INVALID, "unknown direction");
+  FM_CHECK_ARG(ncols >= 0, FM_E_INVALID, "negative column count");
+  if (ncols == 0) return FM_OK;
+  const bool adj = dir == FM_ADJ;
+  const int64_t rin = in_rows(a, adj), rout = out_rows(a, adj);
+  FM_CHECK_ARG(x != nullptr && y != nullptr, FM_E_INVALID, "NULL data pointer");
+  FM_CHECK_ARG(ldx >= rin && ldy >= rout, FM_E_SHAPE,
+               "leading dimensions too small: ldx %lld (need %lld), ldy %lld (need %lld)",
+               (long long)ldx, (long long)rin, (long long)ldy, (long long)rout);
+  const size_t es = elem_size(a->dt);
+  const char* xb = static_cast<const char*>(x);
+  const char* yb = static_cast<const char*>(y);
+  const size_t xlen = size_t((ncols - 1) * ldx + rin) * es, ylen = size_t((ncols - 1) * ldy + rout) * es;
+  FM_CHECK_ARG(xb + xlen <= yb || yb + ylen <= xb, FM_E_ALIAS, "x and y overlap");
+  int dev = 0;
+  FM_TRY(current_device(&dev));
+  FM_CHECK_ARG(dev == a->device, FM_E_DEVICE, "operator lives on device %d, current is %d", a->device, dev);
+  size_t need = 0;
+  FM_TRY(size_of(a, adj, ncols, &need));
+  hipStream_t s = as_stream(stream);
+  void* wsp = ws;
+  bool own = false;
+  if (need > 0) {
+    if (ws == nullptr && ws_bytes == 0) {
+      FM_HIP(hipMallocAsync(&wsp, need, s));
+      own = true;
+    } else {
+      FM_CHECK_ARG(ws != nullptr && ws_bytes >= need, FM_E_WORKSPACE,
+                   "workspace of %zu bytes given, %zu needed", ws_bytes, need);
+    }
+  }
+  Batch b{ncols, 1, 1, ldx, rin, ldy, rout};
+  Workspace w;
+  w.base = static_cast<char*>(wsp);
+  w.cap = own ? need : ws_bytes;
+  fm_status st = exec(a, adj, elem_of(a->dt), b, x, y, false, w, s);
+  if (own) (void)hipFreeAsync(wsp, s);
+  return st;
+}
+
+}  // extern "C"

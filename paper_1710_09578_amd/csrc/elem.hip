@@ -1,0 +1,413 @@
+// Elementwise and data-movement kernels: Diag, row selection (gather /
+// scatter), the generic dense mode product, zero-pad / crop boxes, precision
+// conversions, spectrum permutation, Toeplitz embedding and index checks.
+#include "kernels.h"
+
+namespace fm {
+namespace {
+
+template <typename V>
+struct Ops;
+template <>
+struct Ops<c64> {
+  using R = float;
+  static __device__ __forceinline__ c64 add(c64 a, c64 b) { return cadd(a, b); }
+  static __device__ __forceinline__ c64 zero() { return {0.f, 0.f}; }
+};
+template <>
+struct Ops<c128> {
+  using R = double;
+  static __device__ __forceinline__ c128 add(c128 a, c128 b) { return cadd(a, b); }
+  static __device__ __forceinline__ c128 zero() { return {0.0, 0.0}; }
+};
+template <>
+struct Ops<int32_t> {
+  static __device__ __forceinline__ int32_t add(int32_t a, int32_t b) {
+    return int32_t(uint32_t(a) + uint32_t(b));
+  }
+  static __device__ __forceinline__ int32_t zero() { return 0; }
+};
+template <>
+struct Ops<int64_t> {
+  static __device__ __forceinline__ int64_t add(int64_t a, int64_t b) {
+    return int64_t(uint64_t(a) + uint64_t(b));
+  }
+  static __device__ __forceinline__ int64_t zero() { return 0; }
+};
+
+template <typename V>
+__device__ __forceinline__ void store(V* p, V v, int acc) {
+  *p = acc ? Ops<V>::add(*p, v) : v;
+}
+
+// Grid: x over the flat (row, inner) positions of one vector, y over
+// (column, outer) pairs (grid-strided).
+struct VecGrid {
+  int64_t pairs;   // ncols * outer
+  int64_t flat;    // positions per output vector
+};
+
+inline dim3 vec_grid(int64_t pairs, int64_t flat, int threads) {
+  const int64_t gx = cdiv(flat, threads);
+  const int64_t gy = pairs < 65535 ? pairs : 65535;
+  return dim3(unsigned(gx), unsigned(gy));
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void diag_kernel(int64_t n, Batch b, const V* __restrict__ d,
+                                                   int conj, const V* __restrict__ x, V* y, int acc) {
+  const int64_t flat_n = n * b.inner;
+  const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (f >= flat_n) return;
+  const int64_t r = b.inner == 1 ? f : f / b.inner;
+  const V dv = d[r];
+  for (int64_t p = blockIdx.y; p < b.ncols * b.outer; p += gridDim.y) {
+    const int64_t c = p / b.outer, o = p - c * b.outer;
+    const V xv = x[c * b.ldx + o * b.xvs + f];
+    store(y + c * b.ldy + o * b.yvs + f, conj ? cmulc(xv, dv) : cmul(xv, dv), acc);
+  }
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void gather_kernel(int64_t m, Batch b, const int32_t* __restrict__ idx,
+                                                     const V* __restrict__ x, V* y, int acc) {
+  const int64_t flat_m = m * b.inner;
+  const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (f >= flat_m) return;
+  const int64_t r = b.inner == 1 ? f : f / b.inner;
+  const int64_t i = f - r * b.inner;
+  const int64_t src = int64_t(idx[r]) * b.inner + i;
+  for (int64_t p = blockIdx.y; p < b.ncols * b.outer; p += gridDim.y) {
+    const int64_t c = p / b.outer, o = p - c * b.outer;
+    store(y + c * b.ldy + o * b.yvs + f, x[c * b.ldx + o * b.xvs + src], acc);
+  }
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void scatter_kernel(int64_t m, Batch b, const int32_t* __restrict__ idx,
+                                                      const V* __restrict__ x, V* y, int acc) {
+  const int64_t flat_m = m * b.inner;
+  const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (f >= flat_m) return;
+  const int64_t r = b.inner == 1 ? f : f / b.inner;
+  const int64_t i = f - r * b.inner;
+  const int64_t dst = int64_t(idx[r]) * b.inner + i;
+  for (int64_t p = blockIdx.y; p < b.ncols * b.outer; p += gridDim.y) {
+    const int64_t c = p / b.outer, o = p - c * b.outer;
+    store(y + c * b.ldy + o * b.yvs + dst, x[c * b.ldx + o * b.xvs + f], acc);
+  }
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void copy_kernel(int64_t flat_n, Batch b, const V* __restrict__ x, V* y,
+                                                   int acc) {
+  const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (f >= flat_n) return;
+  for (int64_t p = blockIdx.y; p < b.ncols * b.outer; p += gridDim.y) {
+    const int64_t c = p / b.outer, o = p - c * b.outer;
+    store(y + c * b.ldy + o * b.yvs + f, x[c * b.ldx + o * b.xvs + f], acc);
+  }
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void zero_kernel(int64_t flat_n, Batch b, V* y) {
+  const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (f >= flat_n) return;
+  for (int64_t p = blockIdx.y; p < b.ncols * b.outer; p += gridDim.y) {
+    const int64_t c = p / b.outer, o = p - c * b.outer;
+    y[c * b.ldy + o * b.yvs + f] = Ops<V>::zero();
+  }
+}
+
+// y[c,o,r,i] (+)= sum_k A[r,k] x[c,o,k,i]      (forward, r < m, k < n)
+// y[c,o,r,i] (+)= sum_k conj(A[k,r]) x[c,o,k,i] (adjoint, r < n, k < m)
+template <typename V>
+__global__ __launch_bounds__(256) void dense_kernel(int64_t m, int64_t n, const V* __restrict__ a,
+                                                    int64_t lda, int adj, Batch b,
+                                                    const V* __restrict__ x, V* y, int acc) {
+  const int64_t rows_out = adj ? n : m, rows_in = adj ? m : n;
+  const int64_t flat_n = rows_out * b.inner;
+  const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (f >= flat_n) return;
+  const int64_t r = b.inner == 1 ? f : f / b.inner;
+  const int64_t i = f - r * b.inner;
+  for (int64_t p = blockIdx.y; p < b.ncols * b.outer; p += gridDim.y) {
+    const int64_t c = p / b.outer, o = p - c * b.outer;
+    const V* X = x + c * b.ldx + o * b.xvs + i;
+    V s = Ops<V>::zero();
+    for (int64_t k = 0; k < rows_in; ++k) {
+      const V xv = X[k * b.inner];
+      s = adj ? cadd(s, cmulc(xv, a[k + r * lda])) : cadd(s, cmul(a[r + k * lda], xv));
+    }
+    store(y + c * b.ldy + o * b.yvs + f, s, acc);
+  }
+}
+
+struct Box {
+  int ndim;
+  int64_t box[3], src[3], dst[3];
+};
+
+template <typename V>
+__global__ __launch_bounds__(256) void box_kernel(Box bx, int64_t ncols, const V* __restrict__ x,
+                                                  int64_t ldx, V* y, int64_t ldy, int acc) {
+  int64_t total = 1;
+  for (int d = 0; d < bx.ndim; ++d) total *= bx.dst[d];
+  const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (f >= total) return;
+  int64_t rem = f, src = 0, stride = 1;
+  bool inside = true;
+  int64_t idx[3];
+  for (int d = bx.ndim - 1; d >= 0; --d) {
+    idx[d] = rem % bx.dst[d];
+    rem /= bx.dst[d];
+  }
+  for (int d = bx.ndim - 1; d >= 0; --d) {
+    if (idx[d] >= bx.box[d]) inside = false;
+    src += idx[d] * stride;
+    stride *= bx.src[d];
+  }
+  for (int64_t c = blockIdx.y; c < ncols; c += gridDim.y) {
+    const V v = inside ? x[c * ldx + src] : Ops<V>::zero();
+    if (acc) {
+      if (inside) store(y + c * ldy + f, v, 1);
+    } else {
+      y[c * ldy + f] = v;
+    }
+  }
+}
+
+template <typename V, typename R>
+__global__ __launch_bounds__(256) void scale_kernel(int64_t count, R alpha, const V* __restrict__ x, V* y) {
+  const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (f < count) y[f] = cscale(x[f], alpha);
+}
+
+__global__ __launch_bounds__(256) void up_kernel(int64_t count, const c64* __restrict__ x, c128* y) {
+  const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (f < count) y[f] = {double(x[f].x), double(x[f].y)};
+}
+__global__ __launch_bounds__(256) void down_kernel(int64_t count, const c128* __restrict__ x, c64* y) {
+  const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (f < count) y[f] = {float(x[f].x), float(x[f].y)};
+}
+
+__global__ __launch_bounds__(256) void permute_kernel(int64_t n1, int64_t n2, const c128* __restrict__ x,
+                                                      c128* y) {
+  const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;  // f = k1 + n1 * k2
+  if (f >= n1 * n2) return;
+  const int64_t k1 = f % n1, k2 = f / n1;
+  y[f] = x[k2 + n2 * k1];
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void embed_kernel(int64_t m, int64_t n, int64_t L, const V* __restrict__ col,
+                                                    const V* __restrict__ row, c128* g) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= L) return;
+  c128 v = {0.0, 0.0};
+  if (k < m) {
+    v = {double(col[k].x), double(col[k].y)};
+  } else if (k > L - n) {
+    const V r = row[L - k];
+    v = {double(r.x), double(r.y)};
+  }
+  g[k] = v;
+}
+
+__global__ __launch_bounds__(256) void check_idx_kernel(int64_t n, int64_t m, const int32_t* __restrict__ idx,
+                                                        int* flags, int* bad) {
+  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r >= m) return;
+  const int32_t v = idx[r];
+  if (v < 0 || int64_t(v) >= n) {
+    atomicOr(bad, 1);
+    return;
+  }
+  if (atomicAdd(flags + v, 1) != 0) atomicOr(bad, 1);
+}
+
+}  // namespace
+
+#define FM_ELEM_SWITCH(e, V, ...)        \
+  switch (e) {                           \
+    case Elem::C64: {                    \
+      using V = c64;                     \
+      __VA_ARGS__;                       \
+      break;                             \
+    }                                    \
+    case Elem::C128: {                   \
+      using V = c128;                    \
+      __VA_ARGS__;                       \
+      break;                             \
+    }                                    \
+    case Elem::I32: {                    \
+      using V = int32_t;                 \
+      __VA_ARGS__;                       \
+      break;                             \
+    }                                    \
+    case Elem::I64: {                    \
+      using V = int64_t;                 \
+      __VA_ARGS__;                       \
+      break;                             \
+    }                                    \
+  }
+
+fm_status launch_diag(Elem e, int64_t n, const Batch& b, const void* d, int conj, const void* x,
+                      void* y, int acc, hipStream_t s) {
+  if (b.ncols == 0 || n == 0) return FM_OK;
+  dim3 g = vec_grid(b.ncols * b.outer, n * b.inner, 256);
+  if (e == Elem::C64)
+    hipLaunchKernelGGL(diag_kernel<c64>, g, dim3(256), 0, s, n, b, (const c64*)d, conj, (const c64*)x,
+                       (c64*)y, acc);
+  else if (e == Elem::C128)
+    hipLaunchKernelGGL(diag_kernel<c128>, g, dim3(256), 0, s, n, b, (const c128*)d, conj,
+                       (const c128*)x, (c128*)y, acc);
+  else {
+    set_error("diag: integer element type");
+    return FM_E_DTYPE;
+  }
+  FM_LAUNCHED();
+  return FM_OK;
+}
+
+fm_status launch_select(Elem e, int64_t n_in, int64_t m, const int32_t* idx, int adjoint,
+                        const Batch& b, const void* x, void* y, int acc, hipStream_t s) {
+  if (b.ncols == 0) return FM_OK;
+  if (!adjoint) {
+    if (m == 0) return FM_OK;
+    dim3 g = vec_grid(b.ncols * b.outer, m * b.inner, 256);
+    FM_ELEM_SWITCH(e, V, hipLaunchKernelGGL(gather_kernel<V>, g, dim3(256), 0, s, m, b, idx,
+                                            (const V*)x, (V*)y, acc));
+  } else {
+    if (!acc && n_in > 0) {
+      dim3 gz = vec_grid(b.ncols * b.outer, n_in * b.inner, 256);
+      FM_ELEM_SWITCH(e, V, hipLaunchKernelGGL(zero_kernel<V>, gz, dim3(256), 0, s, n_in * b.inner, b,
+                                              (V*)y));
+      FM_LAUNCHED();
+    }
+    if (m == 0) return FM_OK;
+    dim3 g = vec_grid(b.ncols * b.outer, m * b.inner, 256);
+    FM_ELEM_SWITCH(e, V, hipLaunchKernelGGL(scatter_kernel<V>, g, dim3(256), 0, s, m, b, idx,
+                                            (const V*)x, (V*)y, 1));
+  }
+  FM_LAUNCHED();
+  return FM_OK;
+}
+
+fm_status launch_copy(Elem e, int64_t n, const Batch& b, const void* x, void* y, int acc,
+                      hipStream_t s) {
+  if (b.ncols == 0 || n == 0) return FM_OK;
+  dim3 g = vec_grid(b.ncols * b.outer, n * b.inner, 256);
+  FM_ELEM_SWITCH(e, V, hipLaunchKernelGGL(copy_kernel<V>, g, dim3(256), 0, s, n * b.inner, b,
+                                          (const V*)x, (V*)y, acc));
+  FM_LAUNCHED();
+  return FM_OK;
+}
+
+fm_status launch_dense(Elem e, int64_t m, int64_t n, const void* a, int64_t lda, int adjoint,
+                       const Batch& b, const void* x, void* y, int acc, hipStream_t s) {
+  if (b.ncols == 0) return FM_OK;
+  const int64_t rows_out = adjoint ? n : m;
+  if (rows_out == 0) return FM_OK;
+  dim3 g = vec_grid(b.ncols * b.outer, rows_out * b.inner, 256);
+  if (e == Elem::C64)
+    hipLaunchKernelGGL(dense_kernel<c64>, g, dim3(256), 0, s, m, n, (const c64*)a, lda, adjoint, b,
+                       (const c64*)x, (c64*)y, acc);
+  else if (e == Elem::C128)
+    hipLaunchKernelGGL(dense_kernel<c128>, g, dim3(256), 0, s, m, n, (const c128*)a, lda, adjoint, b,
+                       (const c128*)x, (c128*)y, acc);
+  else {
+    set_error("dense: integer element type");
+    return FM_E_DTYPE;
+  }
+  FM_LAUNCHED();
+  return FM_OK;
+}
+
+fm_status launch_box_copy(Elem e, int ndim, const int64_t* box, const int64_t* src_dims,
+                          const int64_t* dst_dims, int64_t ncols, const void* x, int64_t ldx,
+                          void* y, int64_t ldy, int acc, hipStream_t s) {
+  if (ncols == 0) return FM_OK;
+  FM_CHECK_ARG(ndim >= 1 && ndim <= 3, FM_E_UNSUPPORTED, "box copy: 1..3 dimensions");
+  Box bx{};
+  bx.ndim = ndim;
+  int64_t total = 1;
+  for (int d = 0; d < ndim; ++d) {
+    bx.box[d] = box[d];
+    bx.src[d] = src_dims[d];
+    bx.dst[d] = dst_dims[d];
+    total *= dst_dims[d];
+  }
+  dim3 g(unsigned(cdiv(total, 256)), unsigned(ncols < 65535 ? ncols : 65535));
+  FM_ELEM_SWITCH(e, V, hipLaunchKernelGGL(box_kernel<V>, g, dim3(256), 0, s, bx, ncols, (const V*)x,
+                                          ldx, (V*)y, ldy, acc));
+  FM_LAUNCHED();
+  return FM_OK;
+}
+
+fm_status launch_scale_copy(Elem e, int64_t count, double alpha, const void* x, void* y,
+                            hipStream_t s) {
+  if (count == 0) return FM_OK;
+  dim3 g(unsigned(cdiv(count, 256)));
+  if (e == Elem::C64)
+    hipLaunchKernelGGL((scale_kernel<c64, float>), g, dim3(256), 0, s, count, float(alpha),
+                       (const c64*)x, (c64*)y);
+  else if (e == Elem::C128)
+    hipLaunchKernelGGL((scale_kernel<c128, double>), g, dim3(256), 0, s, count, alpha,
+                       (const c128*)x, (c128*)y);
+  else {
+    set_error("scale: integer element type");
+    return FM_E_DTYPE;
+  }
+  FM_LAUNCHED();
+  return FM_OK;
+}
+
+fm_status launch_c64_to_c128(int64_t count, const void* x, void* y, hipStream_t s) {
+  if (count == 0) return FM_OK;
+  hipLaunchKernelGGL(up_kernel, dim3(unsigned(cdiv(count, 256))), dim3(256), 0, s, count,
+                     (const c64*)x, (c128*)y);
+  FM_LAUNCHED();
+  return FM_OK;
+}
+
+fm_status launch_c128_to_c64(int64_t count, const void* x, void* y, hipStream_t s) {
+  if (count == 0) return FM_OK;
+  hipLaunchKernelGGL(down_kernel, dim3(unsigned(cdiv(count, 256))), dim3(256), 0, s, count,
+                     (const c128*)x, (c64*)y);
+  FM_LAUNCHED();
+  return FM_OK;
+}
+
+fm_status launch_fourstep_permute(int64_t n1, int64_t n2, const void* x, void* y, hipStream_t s) {
+  hipLaunchKernelGGL(permute_kernel, dim3(unsigned(cdiv(n1 * n2, 256))), dim3(256), 0, s, n1, n2,
+                     (const c128*)x, (c128*)y);
+  FM_LAUNCHED();
+  return FM_OK;
+}
+
+fm_status launch_toeplitz_embed(int64_t m, int64_t n, int64_t L, const void* col, const void* row,
+                                int elem_c64, void* g, hipStream_t s) {
+  dim3 gr(unsigned(cdiv(L, 256)));
+  if (elem_c64)
+    hipLaunchKernelGGL(embed_kernel<c64>, gr, dim3(256), 0, s, m, n, L, (const c64*)col,
+                       (const c64*)row, (c128*)g);
+  else
+    hipLaunchKernelGGL(embed_kernel<c128>, gr, dim3(256), 0, s, m, n, L, (const c128*)col,
+                       (const c128*)row, (c128*)g);
+  FM_LAUNCHED();
+  return FM_OK;
+}
+
+fm_status launch_check_indices(int64_t n, int64_t m, const int32_t* idx, int* flags_and_bad,
+                               hipStream_t s) {
+  // flags_and_bad: n + 1 zeroed ints; the last one receives the verdict
+  if (m == 0) return FM_OK;
+  hipLaunchKernelGGL(check_idx_kernel, dim3(unsigned(cdiv(m, 256))), dim3(256), 0, s, n, m, idx,
+                     flags_and_bad, flags_and_bad + n);
+  FM_LAUNCHED();
+  return FM_OK;
+}
+
+}  // namespace fm

@@ -1,0 +1,385 @@
+// Executor: applies an operator tree to a strided batch of vectors.
+//
+// Composite operators are applied only through their terms' transforms
+// (section "General Matrix-free Representations"): a Product applies its terms
+// right to left (forward) or its term adjoints left to right (adjoint); a Sum
+// accumulates its terms; a Kronecker product applies each factor as a mode
+// product along its own axis (eq. (7) structure, first factor slowest); a
+// block-diagonal operator applies each block to its slice of rows. Leaves
+// launch the HIP kernels. Temporaries come from a stack over the workspace.
+#include <cstring>
+
+#include "runtime.h"
+
+namespace fm {
+
+#define LAUNCH(expr)                     \
+  do {                                   \
+    if (!ws.sizing) FM_TRY(expr);        \
+  } while (0)
+
+namespace {
+
+// (ncols, outer) pairs folded into one column index when the strides allow it.
+bool fold_outer(const Batch& b, int64_t rows_in, int64_t rows_out, Batch* out) {
+  *out = b;
+  if (b.outer == 1) return true;
+  if (b.inner != 1) return false;
+  if ((b.ncols == 1 || b.ldx == b.outer * b.xvs) && (b.ncols == 1 || b.ldy == b.outer * b.yvs)) {
+    out->ncols = b.ncols * b.outer;
+    out->outer = 1;
+    out->ldx = b.xvs;
+    out->ldy = b.yvs;
+    out->xvs = rows_in;
+    out->yvs = rows_out;
+    (void)rows_in;
+    return true;
+  }
+  return false;
+}
+
+bool packed(const Batch& b, int64_t rows_in, int64_t rows_out) {
+  return b.outer == 1 || (b.xvs == rows_in * b.inner && b.yvs == rows_out * b.inner);
+}
+
+const void* param(const fm_op_s* op, Elem e) { return e == Elem::C64 ? op->p32.p : op->p64.p; }
+const Split& split(const fm_op_s* op, Elem e) { return e == Elem::C64 ? op->s32 : op->s64; }
+
+// Plain DFT (or its unnormalised inverse) of length L along the vector axis.
+fm_status exec_fourier(const fm_op_s* op, bool adj, Elem e, const Batch& b, const void* x, void* y,
+                       bool acc, Workspace& ws, hipStream_t s) {
+  const Split& sp = split(op, e);
+  const int64_t L = op->L;
+  if (!sp.four_step()) {
+    FftLaunch f;
+    f.elem = e;
+    f.logn = sp.logL;
+    f.mode = adj ? FFT_INV : FFT_FWD;
+    f.b = b;
+    f.x = x;
+    f.y = y;
+    f.in_limit = f.out_limit = L * b.inner;
+    f.accumulate = acc;
+    LAUNCH(launch_fft(f, s));
+    return FM_OK;
+  }
+  Batch fb;
+  FM_CHECK_ARG(b.inner == 1 && fold_outer(b, L, L, &fb), FM_E_UNSUPPORTED,
+               "Fourier of length %lld along a strided axis", (long long)L);
+  const int64_t n1 = int64_t(1) << sp.log1, n2 = int64_t(1) << sp.log2;
+  const size_t mk = ws.mark();
+  void* w = ws.take(size_t(fb.ncols * L) * elem_bytes(e));
+  // step 1: length-n2 transforms at stride n1, then twiddles W_L^(k2 n1)
+  FftLaunch f1;
+  f1.elem = e;
+  f1.logn = sp.log2;
+  f1.mode = adj ? FFT_INV : FFT_FWD;
+  f1.b = Batch{fb.ncols, 1, n1, fb.ldx, 0, L, 0};
+  f1.x = x;
+  f1.y = w;
+  f1.in_limit = f1.out_limit = L;
+  f1.tw_log = sp.logL;
+  f1.tw_inv = adj;
+  LAUNCH(launch_fft(f1, s));
+  // step 2: contiguous length-n1 transforms in place; result X[k2 + n2 k1] at k1 + n1 k2
+  FftLaunch f2;
+  f2.elem = e;
+  f2.logn = sp.log1;
+  f2.mode = adj ? FFT_INV : FFT_FWD;
+  f2.b = Batch{fb.ncols, n2, 1, L, n1, L, n1};
+  f2.x = w;
+  f2.y = w;
+  f2.in_limit = f2.out_limit = n1;
+  LAUNCH(launch_fft(f2, s));
+  // step 3: into natural order
+  LAUNCH(launch_transpose(e, fb.ncols, n2, n1, w, L, y, fb.ldy, acc, s));
+  ws.release(mk);
+  return FM_OK;
+}
+
+// Cyclic convolution of length L with pad / crop (Circulant, Toeplitz):
+// y = crop(IFFT(spec .* FFT(pad(x)))), spec conj'ed for the adjoint.
+fm_status exec_conv(const fm_op_s* op, bool adj, Elem e, const Batch& b, const void* x, void* y,
+                    bool acc, Workspace& ws, hipStream_t s) {
+  const Split& sp = split(op, e);
+  const int64_t L = op->L;
+  const int64_t nin = in_rows(op, adj), nout = out_rows(op, adj);
+  const void* spec = param(op, e);
+  if (!sp.four_step()) {
+    FftLaunch f;
+    f.elem = e;
+    f.logn = sp.logL;
+    f.mode = FFT_CONV;
+    f.b = b;
+    f.x = x;
+    f.y = y;
+    f.in_limit = nin * b.inner;
+    f.out_limit = nout * b.inner;
+    f.spec = spec;
+    f.spec_conj = adj;
+    f.accumulate = acc;
+    LAUNCH(launch_fft(f, s));
+    return FM_OK;
+  }
+  FM_CHECK_ARG(b.inner == 1, FM_E_UNSUPPORTED, "convolution of length %lld along a strided axis",
+               (long long)L);
+  const int64_t n1 = int64_t(1) << sp.log1, n2 = int64_t(1) << sp.log2;
+  const size_t mk = ws.mark();
+  void* w = ws.take(size_t(b.ncols * b.outer * L) * elem_bytes(e));
+  // step 1: forward length-n2 transforms at stride n1 of the zero-padded input,
+  // then twiddles W_L^(k2 n1)
+  FftLaunch f1;
+  f1.elem = e;
+  f1.logn = sp.log2;
+  f1.mode = FFT_FWD;
+  f1.b = Batch{b.ncols, b.outer, n1, b.ldx, b.xvs, b.outer * L, L};
+  f1.x = x;
+  f1.y = w;
+  f1.in_limit = nin;
+  f1.out_limit = L;
+  f1.tw_log = sp.logL;
+  LAUNCH(launch_fft(f1, s));
+  // step 2: contiguous length-n1 forward transform, spectral product (spectrum
+  // stored in the same transposed order), inverse transform, twiddles W_L^-(n1 k2)
+  FftLaunch f2;
+  f2.elem = e;
+  f2.logn = sp.log1;
+  f2.mode = FFT_CONV;
+  f2.b = Batch{b.ncols * b.outer, n2, 1, L, n1, L, n1};
+  f2.x = w;
+  f2.y = w;
+  f2.in_limit = f2.out_limit = n1;
+  f2.spec = spec;
+  f2.spec_ostride = n1;
+  f2.spec_conj = adj;
+  f2.tw_log = sp.logL;
+  f2.tw_inv = 1;
+  LAUNCH(launch_fft(f2, s));
+  // step 3: inverse length-n2 transforms at stride n1, cropped store
+  FftLaunch f3;
+  f3.elem = e;
+  f3.logn = sp.log2;
+  f3.mode = FFT_INV;
+  f3.b = Batch{b.ncols, b.outer, n1, b.outer * L, L, b.ldy, b.yvs};
+  f3.x = w;
+  f3.y = y;
+  f3.in_limit = L;
+  f3.out_limit = nout;
+  f3.accumulate = acc;
+  LAUNCH(launch_fft(f3, s));
+  ws.release(mk);
+  return FM_OK;
+}
+
+fm_status exec_hadamard(const fm_op_s* op, Elem e, const Batch& b, const void* x, void* y, bool acc,
+                        Workspace& ws, hipStream_t s) {
+  const int logn = ilog2(op->n);
+  if (logn <= fwht_lds_max_log(e)) {
+    LAUNCH(launch_fwht(e, logn, b, x, y, acc, s));
+    return FM_OK;
+  }
+  // H_N = H_N1 (x) H_N2: two mode products, the second in place.
+  FM_CHECK_ARG(packed(b, op->n, op->n), FM_E_UNSUPPORTED, "Hadamard: unpacked outer batch");
+  const int log2n = logn / 2, log1n = logn - log2n;
+  const int64_t n1 = int64_t(1) << log1n, n2 = int64_t(1) << log2n;
+  const size_t mk = ws.mark();
+  void* dst = y;
+  Batch bd = b;
+  if (acc) {
+    dst = ws.take(size_t(b.ncols * b.outer * op->n * b.inner) * elem_bytes(e));
+    bd.ldy = b.outer * op->n * b.inner;
+    bd.yvs = op->n * b.inner;
+  }
+  Batch pa{b.ncols, b.outer * n1, b.inner, b.ldx, n2 * b.inner, bd.ldy, n2 * b.inner};
+  LAUNCH(launch_fwht(e, log2n, pa, x, dst, 0, s));
+  Batch pb{b.ncols, b.outer, n2 * b.inner, bd.ldy, bd.yvs, bd.ldy, bd.yvs};
+  LAUNCH(launch_fwht(e, log1n, pb, dst, dst, 0, s));
+  if (acc) {
+    Batch cb{b.ncols, b.outer, b.inner, bd.ldy, bd.yvs, b.ldy, b.yvs};
+    LAUNCH(launch_copy(e, op->n, cb, dst, y, 1, s));
+  }
+  ws.release(mk);
+  return FM_OK;
+}
+
+fm_status exec_mltoeplitz(const fm_op_s* op, bool adj, Elem e, const Batch& b, const void* x, void* y,
+                          bool acc, Workspace& ws, hipStream_t s) {
+  Batch fb;
+  FM_CHECK_ARG(b.inner == 1 && fold_outer(b, op->n, op->m, &fb), FM_E_UNSUPPORTED,
+               "multilevel Toeplitz along a strided axis");
+  const int d = int(op->lv.size());
+  int64_t total = 1;
+  for (int l = 0; l < d; ++l) total *= op->lL[l];
+  const size_t mk = ws.mark();
+  const size_t bytes = size_t(fb.ncols * total) * elem_bytes(e);
+  void* w1 = ws.take(bytes);
+  void* w2 = ws.take(bytes);
+  const fm_op_s* kf = op->terms[0];  // Kron of Fourier(L_l)
+  // zero-pad into the embedding grid
+  LAUNCH(launch_box_copy(e, d, op->lv.data(), op->lv.data(), op->lL.data(), fb.ncols, x, fb.ldx, w1,
+                         total, 0, s));
+  Batch kb{fb.ncols, 1, 1, total, total, total, total};
+  FM_TRY(exec(kf, false, e, kb, w1, w2, false, ws, s));
+  Batch db{fb.ncols, 1, 1, total, total, total, total};
+  LAUNCH(launch_diag(e, total, db, param(op, e), adj, w2, w2, 0, s));
+  FM_TRY(exec(kf, true, e, kb, w2, w1, false, ws, s));
+  LAUNCH(launch_box_copy(e, d, op->lv.data(), op->lL.data(), op->lv.data(), fb.ncols, w1, total, y,
+                         fb.ldy, acc, s));
+  ws.release(mk);
+  return FM_OK;
+}
+
+fm_status exec_product(const fm_op_s* op, bool adj, Elem e, const Batch& b, const void* x, void* y,
+                       bool acc, Workspace& ws, hipStream_t s) {
+  const int k = int(op->terms.size());
+  // application order
+  std::vector<const fm_op_s*> seq;
+  for (int j = 0; j < k; ++j) seq.push_back(op->terms[adj ? j : k - 1 - j]);
+  if (k == 1) return exec(seq[0], adj, e, b, x, y, acc, ws, s);
+  int64_t maxrows = 0;
+  for (int j = 0; j + 1 < k; ++j) {
+    const int64_t r = out_rows(seq[j], adj);
+    if (r > maxrows) maxrows = r;
+  }
+  const size_t mk = ws.mark();
+  const size_t bytes = size_t(b.ncols * b.outer * maxrows * b.inner) * elem_bytes(e);
+  char* bufs[2] = {static_cast<char*>(ws.take(bytes)), static_cast<char*>(ws.take(bytes))};
+  const void* cur = x;
+  int64_t cur_ld = b.ldx, cur_vs = b.xvs;
+  for (int j = 0; j < k; ++j) {
+    const bool last = j == k - 1;
+    const int64_t rows = out_rows(seq[j], adj);
+    Batch sb{b.ncols, b.outer, b.inner, cur_ld, cur_vs, 0, 0};
+    void* dst;
+    if (last) {
+      dst = y;
+      sb.ldy = b.ldy;
+      sb.yvs = b.yvs;
+    } else {
+      dst = bufs[j & 1];
+      sb.ldy = b.outer * rows * b.inner;
+      sb.yvs = rows * b.inner;
+    }
+    FM_TRY(exec(seq[j], adj, e, sb, cur, dst, last ? acc : false, ws, s));
+    cur = dst;
+    cur_ld = sb.ldy;
+    cur_vs = sb.yvs;
+  }
+  ws.release(mk);
+  return FM_OK;
+}
+
+fm_status exec_kron(const fm_op_s* op, bool adj, Elem e, const Batch& b, const void* x, void* y,
+                    bool acc, Workspace& ws, hipStream_t s) {
+  const int d = int(op->terms.size());
+  FM_CHECK_ARG(packed(b, in_rows(op, adj), out_rows(op, adj)), FM_E_UNSUPPORTED,
+               "Kron: unpacked outer batch");
+  std::vector<int64_t> cur(d);
+  for (int l = 0; l < d; ++l) cur[l] = in_rows(op->terms[l], adj);
+  // largest intermediate
+  int64_t maxsz = 0;
+  {
+    std::vector<int64_t> c2 = cur;
+    for (int k = d - 1; k > 0; --k) {
+      c2[k] = out_rows(op->terms[k], adj);
+      int64_t sz = 1;
+      for (int l = 0; l < d; ++l) sz *= c2[l];
+      if (sz > maxsz) maxsz = sz;
+    }
+  }
+  const size_t mk = ws.mark();
+  const size_t bytes = size_t(b.ncols * b.outer * maxsz * b.inner) * elem_bytes(e);
+  char* bufs[2] = {nullptr, nullptr};
+  if (d > 1) {
+    bufs[0] = static_cast<char*>(ws.take(bytes));
+    bufs[1] = static_cast<char*>(ws.take(bytes));
+  }
+  const void* src = x;
+  int64_t src_ld = b.ldx, src_vs = b.xvs;
+  int stage = 0;
+  for (int k = d - 1; k >= 0; --k, ++stage) {
+    const fm_op_s* f = op->terms[k];
+    int64_t outer = 1, inner = 1;
+    for (int l = 0; l < k; ++l) outer *= cur[l];
+    for (int l = k + 1; l < d; ++l) inner *= cur[l];
+    const int64_t rin = in_rows(f, adj), rout = out_rows(f, adj);
+    const bool last = k == 0;
+    void* dst;
+    Batch sb;
+    sb.ncols = b.ncols;
+    sb.outer = b.outer * outer;
+    sb.inner = inner * b.inner;
+    sb.ldx = src_ld;
+    sb.xvs = rin * sb.inner;
+    if (last) {
+      dst = y;
+      sb.ldy = b.ldy;
+    } else {
+      dst = bufs[stage & 1];
+      int64_t total = rout * sb.inner * outer;
+      sb.ldy = b.outer * total;
+    }
+    sb.yvs = rout * sb.inner;
+    FM_TRY(exec(f, adj, e, sb, src, dst, last ? acc : false, ws, s));
+    cur[k] = rout;
+    src = dst;
+    src_ld = sb.ldy;
+    (void)src_vs;
+  }
+  ws.release(mk);
+  return FM_OK;
+}
+
+}  // namespace
+
+fm_status exec(const fm_op_s* op, bool adj, Elem e, const Batch& b, const void* x, void* y,
+               bool acc, Workspace& ws, hipStream_t s) {
+  if (b.ncols == 0 || b.outer == 0) return FM_OK;
+  switch (op->kind) {
+    case Kind::Adjoint:
+      return exec(op->terms[0], !adj, e, b, x, y, acc, ws, s);
+    case Kind::Fourier:
+      return exec_fourier(op, adj, e, b, x, y, acc, ws, s);
+    case Kind::Circulant:
+    case Kind::Toeplitz:
+      return exec_conv(op, adj, e, b, x, y, acc, ws, s);
+    case Kind::Hadamard:
+      return exec_hadamard(op, e, b, x, y, acc, ws, s);
+    case Kind::Diag:
+      LAUNCH(launch_diag(e, op->n, b, param(op, e), adj, x, y, acc, s));
+      return FM_OK;
+    case Kind::Dense:
+      LAUNCH(launch_dense(e, op->m, op->n, param(op, e), op->lda, adj, b, x, y, acc, s));
+      return FM_OK;
+    case Kind::Select:
+      LAUNCH(launch_select(e, op->n, op->m, static_cast<const int32_t*>(op->idx.p), adj, b, x, y,
+                           acc, s));
+      return FM_OK;
+    case Kind::MLToeplitz:
+      return exec_mltoeplitz(op, adj, e, b, x, y, acc, ws, s);
+    case Kind::Product:
+      return exec_product(op, adj, e, b, x, y, acc, ws, s);
+    case Kind::Sum: {
+      for (size_t j = 0; j < op->terms.size(); ++j)
+        FM_TRY(exec(op->terms[j], adj, e, b, x, y, j == 0 ? acc : true, ws, s));
+      return FM_OK;
+    }
+    case Kind::Kron:
+      return exec_kron(op, adj, e, b, x, y, acc, ws, s);
+    case Kind::BlkDiag: {
+      int64_t oi = 0, oo = 0;
+      for (const fm_op_s* t : op->terms) {
+        const char* xs = static_cast<const char*>(x) + size_t(oi * b.inner) * elem_bytes(e);
+        char* ys = static_cast<char*>(y) + size_t(oo * b.inner) * elem_bytes(e);
+        FM_TRY(exec(t, adj, e, b, xs, ys, acc, ws, s));
+        oi += in_rows(t, adj);
+        oo += out_rows(t, adj);
+      }
+      return FM_OK;
+    }
+  }
+  set_error("exec: unknown operator kind");
+  return FM_E_INVALID;
+}
+
+}  // namespace fm

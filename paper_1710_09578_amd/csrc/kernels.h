@@ -1,0 +1,94 @@
+// Launch interfaces of the device kernels (implemented in the *.hip files).
+#pragma once
+
+#include "common.h"
+
+namespace fm {
+
+// A strided batch of vectors. Vector (c, o, i) -- column c < ncols, outer
+// index o < outer, inner index i < inner -- has its element r at
+//   base + c*ld + o*vs + r*inner + i
+// for x (ldx, xvs) and y (ldy, yvs). Contiguous vectors have outer = inner = 1.
+struct Batch {
+  int64_t ncols = 0, outer = 1, inner = 1;
+  int64_t ldx = 0, xvs = 0, ldy = 0, yvs = 0;
+};
+
+enum class Elem { C64, C128, I32, I64 };
+inline size_t elem_bytes(Elem e) {
+  return e == Elem::C64 ? 8 : e == Elem::C128 ? 16 : e == Elem::I32 ? 4 : 8;
+}
+
+// ---------------------------------------------------------------- FFT
+// Largest transform length held in one work-group's LDS.
+inline int fft_lds_max_log(Elem e) { return e == Elem::C64 ? 13 : 13; }
+
+enum FftMode { FFT_FWD = 0, FFT_INV = 1, FFT_CONV = 2 };
+
+struct FftLaunch {
+  Elem elem = Elem::C64;
+  int logn = 0;            // transform length 2^logn (<= fft_lds_max_log)
+  int mode = FFT_FWD;
+  Batch b;
+  const void* x = nullptr;
+  void* y = nullptr;
+  int64_t in_limit = 0;    // element (r, i) is read only when r*inner + i < in_limit
+  int64_t out_limit = 0;   // and stored only when r*inner + i < out_limit
+  const void* spec = nullptr;  // FFT_CONV: spectrum, entry r (+ o*spec_ostride)
+  int64_t spec_ostride = 0;
+  int spec_conj = 0;
+  int tw_log = 0;          // > 0: multiply result r by W^(r*q), W = exp(-+2 pi j / 2^tw_log),
+  int tw_inv = 0;          //      q = i (strided) or o (contiguous); tw_inv picks the + sign
+  int accumulate = 0;      // y += result
+};
+fm_status launch_fft(const FftLaunch& L, hipStream_t s);
+
+// Column-wise transpose of a row-major rows x cols matrix per column block:
+// y[c*ldy + j*rows + i] (+)= x[c*ldx + i*cols + j].
+fm_status launch_transpose(Elem e, int64_t ncols, int64_t rows, int64_t cols, const void* x,
+                           int64_t ldx, void* y, int64_t ldy, int accumulate, hipStream_t s);
+
+// ---------------------------------------------------------------- Walsh-Hadamard
+inline int fwht_lds_max_log(Elem e) { return e == Elem::C128 ? 13 : 14; }
+fm_status launch_fwht(Elem e, int logn, const Batch& b, const void* x, void* y, int accumulate,
+                      hipStream_t s);
+
+// ---------------------------------------------------------------- elementwise
+// y (+)= d .* x  (d conj'ed when conj) along the vector axis of the batch.
+fm_status launch_diag(Elem e, int64_t n, const Batch& b, const void* d, int conj, const void* x,
+                      void* y, int accumulate, hipStream_t s);
+// Row selection: forward y[r] (+)= x[idx[r]] (m outputs); adjoint y = 0 except
+// y[idx[r]] (+)= x[r] (n outputs).
+fm_status launch_select(Elem e, int64_t n_in, int64_t m, const int32_t* idx, int adjoint,
+                        const Batch& b, const void* x, void* y, int accumulate, hipStream_t s);
+// Dense mode product y[:, o, :, i] (+)= op(A) x[:, o, :, i], A m x n col-major.
+fm_status launch_dense(Elem e, int64_t m, int64_t n, const void* a, int64_t lda, int adjoint,
+                       const Batch& b, const void* x, void* y, int accumulate, hipStream_t s);
+// Zero-pad / crop copy between multi-dimensional grids (multilevel Toeplitz):
+// copies the box [0, nbox) of the source grid (dims src_dims) into the
+// destination grid (dims dst_dims), zero-filling the rest of the destination.
+fm_status launch_box_copy(Elem e, int ndim, const int64_t* box, const int64_t* src_dims,
+                          const int64_t* dst_dims, int64_t ncols, const void* x, int64_t ldx,
+                          void* y, int64_t ldy, int accumulate, hipStream_t s);
+// y = alpha * x (contiguous, count elements of type e); alpha real.
+fm_status launch_scale_copy(Elem e, int64_t count, double alpha, const void* x, void* y,
+                            hipStream_t s);
+// Upcast complex64 -> complex128 (count entries, contiguous).
+fm_status launch_c64_to_c128(int64_t count, const void* x, void* y, hipStream_t s);
+// Round complex128 -> complex64 (count entries, contiguous).
+fm_status launch_c128_to_c64(int64_t count, const void* x, void* y, hipStream_t s);
+// Permute a length N1*N2 spectrum from natural order X[k2 + N2 k1] into the
+// four-step order P[k1 + N1 k2] (complex128).
+fm_status launch_fourstep_permute(int64_t n1, int64_t n2, const void* x, void* y, hipStream_t s);
+// Toeplitz generator embedded into a cyclic length-L vector (complex128):
+// g[0..m-1] = col, g[L-k] = row[k] for k = 1..n-1, zero elsewhere.
+fm_status launch_toeplitz_embed(int64_t m, int64_t n, int64_t L, const void* col, const void* row,
+                                int elem_c64, void* g, hipStream_t s);
+// Check indices. flags: n + 1 zeroed ints; flags[n] becomes nonzero if any
+// idx is outside [0, n) or repeated.
+fm_status launch_check_indices(int64_t n, int64_t m, const int32_t* idx, int* flags, hipStream_t s);
+// y (+)= x over the vectors of a batch (n rows each).
+fm_status launch_copy(Elem e, int64_t n, const Batch& b, const void* x, void* y, int accumulate,
+                      hipStream_t s);
+
+}  // namespace fm

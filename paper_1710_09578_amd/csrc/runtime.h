@@ -1,0 +1,109 @@
+// Runtime pieces shared by the kernels and the C ABI: per-device twiddle
+// tables, device buffers, the operator tree and the executor interface.
+#pragma once
+
+#include <atomic>
+#include <memory>
+#include <mutex>
+#include <vector>
+
+#include "kernels.h"
+
+namespace fm {
+
+// Twiddle tables of every power-of-two size up to 2^logmax on the current
+// device: entry [size + k] = exp(-2 pi j k / size), 0 <= k < size. Generated
+// in FP64 on the host with exact octant reduction and rounded once for
+// complex64. Returns nullptr on failure (error text set).
+const void* twiddle_table(Elem e, int logmax);
+
+// Owned device allocation.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { reset(); }
+  fm_status alloc(size_t n);
+  void reset();
+};
+
+enum class Kind {
+  Fourier,
+  Hadamard,
+  Diag,
+  Dense,
+  Circulant,
+  Toeplitz,
+  MLToeplitz,
+  Select,
+  Product,
+  Sum,
+  Kron,
+  BlkDiag,
+  Adjoint
+};
+
+// Split of a cyclic length L for one element type: L <= LDS limit runs in one
+// work-group (n2 == 0); otherwise L = n1 * n2 (four-step, n1 contiguous).
+struct Split {
+  int logL = 0;
+  int log1 = 0, log2 = 0;
+  bool four_step() const { return log2 > 0; }
+};
+Split split_for(Elem e, int logL);
+
+}  // namespace fm
+
+struct fm_op_s {
+  std::atomic<int> refs{1};
+  uint32_t magic = 0x464d4f50u;  // "FMOP" while alive
+  fm::Kind kind;
+  fm_dtype dt;
+  int64_t m = 0, n = 0;
+  int device = 0;
+  // leaf parameters: complex64 copy (for FM_C64 operators) and complex128 copy
+  // (always, for the FP64 power iteration)
+  fm::DevBuf p32, p64;
+  fm::DevBuf idx;          // selection indices
+  int64_t lda = 0;         // dense: leading dimension of the stored copy (= m)
+  int64_t L = 0;           // cyclic length (Fourier/Circulant/Toeplitz)
+  fm::Split s32, s64;      // splits of L for complex64 / complex128
+  std::vector<int64_t> lv, lL;  // multilevel: entries per level, embedding per level
+  std::vector<fm_op> terms;     // composites (retained) / adjoint child
+};
+
+namespace fm {
+
+// Stack allocator over a caller workspace; in sizing mode it only records the
+// high-water mark.
+struct Workspace {
+  char* base = nullptr;
+  size_t cap = 0, top = 0, peak = 0;
+  bool sizing = false;
+  void* take(size_t bytes) {
+    bytes = (bytes + 255) & ~size_t(255);
+    void* p = sizing ? nullptr : base + top;
+    top += bytes;
+    if (top > peak) peak = top;
+    return p;
+  }
+  size_t mark() const { return top; }
+  void release(size_t m) { top = m; }
+};
+
+Elem elem_of(fm_dtype dt);
+
+// Applies op (or op^H when adj) to a batch: y (+)= op(x). In sizing mode no
+// kernel is launched; the workspace records what the call would take.
+fm_status exec(const fm_op_s* op, bool adj, Elem e, const Batch& b, const void* x, void* y,
+               bool accumulate, Workspace& ws, hipStream_t s);
+
+// Rows of op^H / op in the given direction.
+inline int64_t out_rows(const fm_op_s* op, bool adj) { return adj ? op->n : op->m; }
+inline int64_t in_rows(const fm_op_s* op, bool adj) { return adj ? op->m : op->n; }
+
+bool op_alive(const fm_op_s* op);
+
+}  // namespace fm

@@ -1,0 +1,190 @@
+"""Operator objects in the paper's notation over the C ABI.
+
+``A @ x`` is the forward transform y = A x (eq. (3)) and ``A.H @ y`` the
+backward transform A^H y (eq. (4)); composites are built with ``Product``
+(also ``A @ B`` for two operators), ``Sum``, ``Kron`` and ``BlkDiag``. Blocks of
+vectors are torch tensors of shape (ncols, rows) on the GPU (a 1-D tensor is
+one vector). Torch provides the device memory and the current stream; every
+operation itself runs in the HIP library.
+"""
+
+from __future__ import annotations
+
+import torch
+
+from . import capi
+
+_DT = {
+    torch.complex64: capi.FM_C64,
+    torch.complex128: capi.FM_C128,
+    torch.int32: capi.FM_I32,
+    torch.int64: capi.FM_I64,
+}
+_TORCH = {v: k for k, v in _DT.items()}
+
+
+def _stream():
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dt(dtype) -> int:
+    try:
+        return _DT[dtype]
+    except KeyError:
+        raise TypeError(f"unsupported dtype {dtype}") from None
+
+
+def _dev(t: torch.Tensor, dtype=None) -> torch.Tensor:
+    if not t.is_cuda:
+        raise ValueError("parameter arrays must be GPU tensors")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    return t.contiguous()
+
+
+class Operator:
+    """An immutable structured linear operator (a handle of the library)."""
+
+    def __init__(self, handle, keep=()):
+        self._h = handle
+        self._keep = keep  # Python objects that must outlive the handle
+        m, n, dt = capi.fm_op_shape(handle)
+        self.shape = (m, n)
+        self.dtype = _TORCH[dt]
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None:
+            try:
+                capi.fm_op_release(h)
+            except Exception:
+                pass
+            self._h = None
+
+    # ------------------------------------------------------------ views
+    @property
+    def H(self) -> "Operator":
+        """Hermitian transpose (shares storage)."""
+        return Operator(capi.fm_op_adjoint(self._h), keep=(self,))
+
+    # ------------------------------------------------------------ application
+    def _block(self, x: torch.Tensor, rows: int):
+        if x.dtype != self.dtype:
+            raise TypeError(f"operator is {self.dtype}, input is {x.dtype}")
+        if not x.is_cuda:
+            raise ValueError("input must be a GPU tensor")
+        vec = x.dim() == 1
+        xb = x.unsqueeze(0) if vec else x
+        if xb.dim() != 2 or xb.shape[1] != rows:
+            raise ValueError(f"expected a block of shape (ncols, {rows}), got {tuple(x.shape)}")
+        if xb.stride(1) != 1:
+            xb = xb.contiguous()
+        return xb, vec
+
+    def apply(self, x: torch.Tensor, adjoint: bool = False, out: torch.Tensor | None = None,
+              workspace: torch.Tensor | None = None) -> torch.Tensor:
+        m, n = self.shape
+        rin, rout = (m, n) if adjoint else (n, m)
+        xb, vec = self._block(x, rin)
+        ncols = xb.shape[0]
+        if out is None:
+            y = torch.empty((ncols, rout), dtype=self.dtype, device=xb.device)
+        else:
+            y = out.unsqueeze(0) if out.dim() == 1 else out
+            if y.shape != (ncols, rout) or y.stride(1) != 1 or y.dtype != self.dtype:
+                raise ValueError("out has the wrong shape, layout or dtype")
+        d = capi.FM_ADJ if adjoint else capi.FM_FWD
+        need = capi.fm_workspace_size(self._h, d, ncols)
+        if workspace is None and need:
+            workspace = torch.empty(need, dtype=torch.uint8, device=xb.device)
+        wsb = 0 if workspace is None else workspace.numel()
+        capi.fm_apply(self._h, d, ncols, xb, max(xb.stride(0), rin), y, max(y.stride(0), rout),
+                      workspace, wsb, _stream())
+        return y.squeeze(0) if vec and out is None else (out if out is not None else y)
+
+    def forward(self, x):
+        return self.apply(x, False)
+
+    def backward(self, x):
+        return self.apply(x, True)
+
+    def __matmul__(self, other):
+        if isinstance(other, Operator):
+            return Product(self, other)
+        return self.apply(other, False)
+
+    def __add__(self, other):
+        return Sum(self, other)
+
+    def __repr__(self):
+        return f"<Operator {self.shape[0]}x{self.shape[1]} {self.dtype}>"
+
+
+# ---------------------------------------------------------------- elementary
+def Fourier(n: int, dtype=torch.complex64) -> Operator:
+    return Operator(capi.fm_op_create_fourier(n, _dt(dtype)))
+
+
+def Hadamard(n: int, dtype=torch.complex64) -> Operator:
+    return Operator(capi.fm_op_create_hadamard(n, _dt(dtype)))
+
+
+def Diag(d: torch.Tensor) -> Operator:
+    d = _dev(d)
+    return Operator(capi.fm_op_create_diag(d.numel(), d, _dt(d.dtype), _stream()))
+
+
+def Dense(a: torch.Tensor) -> Operator:
+    """Dense (m, n) matrix given as a torch tensor indexed [row, col]."""
+    a = _dev(a)
+    m, n = a.shape
+    colmajor = a.t().contiguous()  # element (i, j) at i + j*m
+    return Operator(capi.fm_op_create_dense(m, n, colmajor, m, _dt(a.dtype), _stream()))
+
+
+def Circulant(c: torch.Tensor) -> Operator:
+    c = _dev(c)
+    return Operator(capi.fm_op_create_circulant(c.numel(), c, _dt(c.dtype), _stream()))
+
+
+def Toeplitz(col: torch.Tensor, row: torch.Tensor) -> Operator:
+    col, row = _dev(col), _dev(row, col.dtype)
+    return Operator(capi.fm_op_create_toeplitz(col.numel(), row.numel(), col, row, _dt(col.dtype),
+                                               _stream()))
+
+
+def MLToeplitz(n_levels, t: torch.Tensor) -> Operator:
+    t = _dev(t)
+    return Operator(capi.fm_op_create_mltoeplitz(len(n_levels), list(n_levels), t, _dt(t.dtype),
+                                                 _stream()))
+
+
+def SelectRows(n_in: int, rows: torch.Tensor, dtype=torch.complex64) -> Operator:
+    rows = _dev(rows, torch.int32)
+    return Operator(capi.fm_op_create_select_rows(n_in, rows.numel(), rows, _dt(dtype), _stream()))
+
+
+# ---------------------------------------------------------------- composites
+def _compose(kind, ops):
+    ops = list(ops)
+    return Operator(capi.fm_op_compose(kind, [o.handle for o in ops]), keep=tuple(ops))
+
+
+def Product(*ops) -> Operator:
+    return _compose(capi.FM_PRODUCT, ops)
+
+
+def Sum(*ops) -> Operator:
+    return _compose(capi.FM_SUM, ops)
+
+
+def Kron(*ops) -> Operator:
+    return _compose(capi.FM_KRON, ops)
+
+
+def BlkDiag(*ops) -> Operator:
+    return _compose(capi.FM_BLKDIAG, ops)

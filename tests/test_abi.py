@@ -1,0 +1,80 @@
+"""The C-ABI library: it loads, exports every entry point the header
+declares, and rejects invalid arguments with the documented status before
+touching the device (these checks need no GPU)."""
+
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fm.h")
+
+
+def declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fm_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1710_09578_amd import capi
+
+    if not os.path.exists(capi.LIB_PATH):
+        pytest.fail("libfm.so is not built (run __graft_entry__.build())")
+    return capi.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(lib, name), f"{name} declared in fm.h but not exported"
+    from paper_1710_09578_amd import capi
+
+    assert set(names) == set(capi.SIGNATURES), "binding and header disagree"
+
+
+def test_version(lib):
+    from paper_1710_09578_amd import capi
+
+    assert capi.fm_version() == "0.1.0"
+
+
+def st(lib, name, *args):
+    return getattr(lib, name)(*args)
+
+
+def test_invalid_arguments_return_status(lib):
+    h = C.c_void_p()
+    assert st(lib, "fm_op_create_fourier", None, 8, 1) == 1          # NULL out
+    assert st(lib, "fm_op_create_fourier", C.byref(h), 8, 99) == 1   # bad dtype
+    assert st(lib, "fm_op_create_fourier", C.byref(h), 8, 3) == 3    # integer Fourier
+    assert st(lib, "fm_op_create_fourier", C.byref(h), 12, 1) == 5   # not a power of two
+    assert st(lib, "fm_op_create_fourier", C.byref(h), 0, 1) == 5
+    assert st(lib, "fm_op_create_circulant", C.byref(h), 8, None, 1, None) == 1
+    assert st(lib, "fm_op_create_toeplitz", C.byref(h), 0, 4, None, None, 1, None) == 1
+    assert st(lib, "fm_op_create_dense", C.byref(h), 4, 4, C.c_void_p(16), 3, 1, None) == 2  # lda < m
+    assert st(lib, "fm_op_create_select_rows", C.byref(h), 4, 5, C.c_void_p(16), 1, None) == 2  # m > n
+    assert st(lib, "fm_op_create_mltoeplitz", C.byref(h), 4, None, None, 1, None) == 5
+    assert st(lib, "fm_op_compose", C.byref(h), 0, 0, None) == 1
+    assert st(lib, "fm_op_release", None) == 1
+    # a pointer that was never a handle
+    bogus = C.c_void_p(0x1000)
+    assert st(lib, "fm_op_release", bogus) == 9
+    assert st(lib, "fm_op_shape", bogus, None, None, None) == 9
+    assert st(lib, "fm_apply", None, 0, 1, None, 1, None, 1, None, 0, None) == 1
+    size = C.c_size_t()
+    assert st(lib, "fm_workspace_size", bogus, 0, 1, C.byref(size)) == 9
+    msg = lib.fm_last_error().decode()
+    assert "released" in msg
+
+
+def test_binding_raises(lib):
+    from paper_1710_09578_amd import capi
+
+    with pytest.raises(capi.FmError) as e:
+        capi.fm_op_create_fourier(12, capi.FM_C64)
+    assert e.value.code == "FM_E_UNSUPPORTED"

@@ -1,0 +1,302 @@
+"""GPU parity of fm_apply (forward and adjoint) against the FP64 oracle.
+
+Every operator is built through the C ABI from seeded inputs, applied on the
+GPU, and compared column by column with the dense oracle (or, where the dense
+matrix is too large, with the oracle's dense-free evaluations, which are
+themselves pinned against the dense ones). Tolerance: relative L2 per column
+<= 2e-5 (complex64) and <= 1e-12 (complex128); integer Hadamard and index
+selection are compared bit for bit.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import dense, structured
+from tests.gpu_util import TOL, crandn, rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+NP = {"c64": np.complex64, "c128": np.complex128}
+
+
+def torch_dt(name):
+    import torch
+
+    return {"c64": torch.complex64, "c128": torch.complex128}[name]
+
+
+def check(op, a_dense, rng, prec, ncols=3, exact=False):
+    m, n = a_dense.shape
+    for adj in (False, True):
+        x = crandn(rng, (ncols, m if adj else n), NP[prec])
+        y = to_host(op.apply(to_dev(x), adjoint=adj))
+        ref = dense.apply(a_dense, x, adj)
+        err = rel_err(y, ref)
+        assert err <= TOL[prec], f"adj={adj}: rel err {err:.3e}"
+
+
+# ---------------------------------------------------------------- Fourier
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+@pytest.mark.parametrize("n", [1, 2, 4, 8, 16, 32, 128, 512, 1024, 4096, 8192])
+def test_fourier_dense(gpu, prec, n):
+    rng = np.random.default_rng(n)
+    op = gpu.Fourier(n, torch_dt(prec))
+    if n <= 2048:
+        check(op, dense.fourier(n), rng, prec, ncols=5)
+    else:
+        for adj in (False, True):
+            x = crandn(rng, (3, n), NP[prec])
+            y = to_host(op.apply(to_dev(x), adjoint=adj))
+            ref = np.fft.ifft(x, axis=1) * n if adj else np.fft.fft(x, axis=1)
+            assert rel_err(y, ref) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+@pytest.mark.parametrize("n", [16384, 65536, 131072])
+def test_fourier_four_step(gpu, prec, n):
+    """Lengths above one work-group's LDS (two transform passes + transpose);
+    reference: numpy.fft in complex128 (pinned to the dense DFT in the oracle
+    tests)."""
+    rng = np.random.default_rng(n + 1)
+    op = gpu.Fourier(n, torch_dt(prec))
+    for adj in (False, True):
+        x = crandn(rng, (2, n), NP[prec])
+        y = to_host(op.apply(to_dev(x), adjoint=adj))
+        ref = np.fft.ifft(x.astype(np.complex128), axis=1) * n if adj else np.fft.fft(x.astype(np.complex128), axis=1)
+        assert rel_err(y, ref) <= TOL[prec]
+
+
+# ---------------------------------------------------------------- Circulant
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+@pytest.mark.parametrize("n", [1, 2, 8, 16, 64, 256, 1024, 2048])
+def test_circulant_dense(gpu, prec, n):
+    rng = np.random.default_rng(100 + n)
+    c = crandn(rng, n, NP[prec])
+    op = gpu.Circulant(to_dev(c))
+    check(op, dense.circulant(c), rng, prec, ncols=7)
+
+
+def test_circulant_1024_x16_config(gpu):
+    """Circulant N=1024, CN(0,1) generator (seed 0), 16 CN(0,1) columns."""
+    from workloads import circulant_1024
+
+    c, x = circulant_1024()
+    op = gpu.Circulant(to_dev(c))
+    a = dense.circulant(c)
+    y = to_host(op @ to_dev(x))
+    assert rel_err(y, dense.apply(a, x)) <= TOL["c64"]
+    z = to_host(op.H @ to_dev(x))
+    assert rel_err(z, dense.apply(a, x, True)) <= TOL["c64"]
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+@pytest.mark.parametrize("n", [4096, 8192, 16384, 65536, 131072])
+def test_circulant_large(gpu, prec, n):
+    rng = np.random.default_rng(200 + n)
+    c = crandn(rng, n, NP[prec])
+    op = gpu.Circulant(to_dev(c))
+    for adj in (False, True):
+        x = crandn(rng, (3, n), NP[prec])
+        y = to_host(op.apply(to_dev(x), adjoint=adj))
+        ref = structured.circulant_apply_fft64(c, x, adj)
+        assert rel_err(y, ref) <= TOL[prec]
+
+
+# ---------------------------------------------------------------- Toeplitz
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+@pytest.mark.parametrize("m,n", [(1, 1), (1, 7), (9, 1), (5, 5), (100, 37), (37, 100), (1000, 1000),
+                                 (1500, 700), (2049, 2048)])
+def test_toeplitz_dense(gpu, prec, m, n):
+    rng = np.random.default_rng(m * 7 + n)
+    col, row = crandn(rng, m, NP[prec]), crandn(rng, n, NP[prec])
+    op = gpu.Toeplitz(to_dev(col), to_dev(row))
+    check(op, dense.toeplitz(col, row), rng, prec, ncols=4)
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+@pytest.mark.parametrize("m,n", [(4097, 4097), (9000, 6000), (20000, 20000), (40000, 40000), (65536, 65536)])
+def test_toeplitz_large(gpu, prec, m, n):
+    rng = np.random.default_rng(m + 3 * n)
+    col, row = crandn(rng, m, NP[prec]), crandn(rng, n, NP[prec])
+    op = gpu.Toeplitz(to_dev(col), to_dev(row))
+    for adj in (False, True):
+        x = crandn(rng, (2, m if adj else n), NP[prec])
+        y = to_host(op.apply(to_dev(x), adjoint=adj))
+        ref = structured.toeplitz_apply_fft64(col, row, x, adj)
+        assert rel_err(y, ref) <= TOL[prec]
+    # sampled rows straight from the definition (no FFT in the reference)
+    x = crandn(rng, (1, n), NP[prec])
+    y = to_host(op @ to_dev(x))[0]
+    rows = rng.choice(m, size=8, replace=False)
+    for i in rows:
+        trow = np.where(np.arange(n) <= i, col[np.clip(i - np.arange(n), 0, m - 1)],
+                        row[np.clip(np.arange(n) - i, 0, n - 1)]).astype(np.complex128)
+        ref_i = np.dot(trow, x[0].astype(np.complex128))
+        assert abs(y[i] - ref_i) <= 1e-4 * np.linalg.norm(trow) * np.linalg.norm(x[0])
+
+
+# ---------------------------------------------------------------- multilevel Toeplitz
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+@pytest.mark.parametrize("levels", [[5], [3, 4], [7, 9], [2, 3, 4]])
+def test_ml_toeplitz(gpu, prec, levels):
+    rng = np.random.default_rng(sum(levels))
+    t = crandn(rng, tuple(2 * v - 1 for v in levels), NP[prec])
+    op = gpu.MLToeplitz(levels, to_dev(t))
+    check(op, dense.ml_toeplitz(levels, t), rng, prec, ncols=3)
+
+
+# ---------------------------------------------------------------- Hadamard
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+@pytest.mark.parametrize("n", [1, 2, 8, 16, 32, 1024, 2048])
+def test_hadamard_complex(gpu, prec, n):
+    rng = np.random.default_rng(n + 5)
+    op = gpu.Hadamard(n, torch_dt(prec))
+    check(op, dense.hadamard(n).astype(np.complex128), rng, prec, ncols=5)
+
+
+@pytest.mark.parametrize("bits", [32, 64])
+@pytest.mark.parametrize("n", [1, 4, 16, 64, 512, 4096, 32768, 65536])
+def test_hadamard_integer_bit_exact(gpu, bits, n):
+    import torch
+
+    from oracle import structured
+
+    rng = np.random.default_rng(bits + n)
+    npdt = np.int32 if bits == 32 else np.int64
+    if n <= 512:
+        info = np.iinfo(npdt)
+        x = rng.integers(info.min, info.max, size=(3, n), dtype=npdt, endpoint=True)
+        ref = dense.apply_int(dense.hadamard(n), x, bits)
+    else:
+        # int32: full range (the sums wrap); int64: |x| < 2^40 so the int64
+        # reference sums stay exact
+        lim = 2**31 if bits == 32 else 2**40
+        x = rng.integers(-lim, lim - 1, size=(3, n), dtype=np.int64).astype(npdt)
+        a = 1 << (n.bit_length() - 1) // 2
+        ref = structured.kron_apply_int([dense.hadamard(n // a), dense.hadamard(a)], x, bits)
+    op = gpu.Hadamard(n, torch.int32 if bits == 32 else torch.int64)
+    y = to_host(op @ to_dev(x))
+    assert np.array_equal(y, ref)
+    # H is its own adjoint
+    z = to_host(op.H @ to_dev(x))
+    assert np.array_equal(z, y)
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_hadamard_two_pass(gpu, prec):
+    n = 32768
+    rng = np.random.default_rng(7)
+    x = crandn(rng, (2, n), NP[prec])
+    op = gpu.Hadamard(n, torch_dt(prec))
+    y = to_host(op @ to_dev(x)).astype(np.complex128)
+    # reference by the Kronecker identity H_n = H_a (x) H_b with dense factors
+    ref = structured.kron_apply([dense.hadamard(256), dense.hadamard(128)], x)
+    assert rel_err(y, ref) <= TOL[prec]
+
+
+# ---------------------------------------------------------------- Diag, Dense, selection
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_diag_dense_select(gpu, prec):
+    rng = np.random.default_rng(11)
+    d = crandn(rng, 300, NP[prec])
+    check(gpu.Diag(to_dev(d)), dense.diag(d), rng, prec)
+    a = crandn(rng, (37, 53), NP[prec])
+    check(gpu.Dense(to_dev(a)), a.astype(np.complex128), rng, prec)
+    import torch
+
+    rows = np.sort(rng.choice(500, 77, replace=False)).astype(np.int32)
+    s = gpu.SelectRows(500, to_dev(rows), torch_dt(prec))
+    for adj in (False, True):
+        x = crandn(rng, (4, 77 if adj else 500), NP[prec])
+        y = to_host(s.apply(to_dev(x), adjoint=adj))
+        ref = dense.apply(dense.select_rows(500, rows), x, adj)
+        assert np.array_equal(y.astype(np.complex128), ref)
+
+
+@pytest.mark.parametrize("bits", [32, 64])
+def test_select_integer_bit_exact(gpu, bits):
+    import torch
+
+    rng = np.random.default_rng(bits)
+    npdt = np.int32 if bits == 32 else np.int64
+    rows = rng.permutation(1000)[:333].astype(np.int32)  # unsorted, distinct
+    s = gpu.SelectRows(1000, to_dev(rows), torch.int32 if bits == 32 else torch.int64)
+    x = rng.integers(-1000, 1000, size=(2, 1000)).astype(npdt)
+    assert np.array_equal(to_host(s @ to_dev(x)), x[:, rows])
+    u = rng.integers(-1000, 1000, size=(2, 333)).astype(npdt)
+    z = np.zeros((2, 1000), npdt)
+    z[:, rows] = u
+    assert np.array_equal(to_host(s.H @ to_dev(u)), z)
+
+
+# ---------------------------------------------------------------- composites
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_composites(gpu, prec):
+    import torch
+
+    rng = np.random.default_rng(21)
+    dt = torch_dt(prec)
+    c = crandn(rng, 64, NP[prec])
+    col, row = crandn(rng, 40, NP[prec]), crandn(rng, 64, NP[prec])
+    d = crandn(rng, 64, NP[prec])
+    g = crandn(rng, (5, 3), NP[prec])
+    C = gpu.Circulant(to_dev(c))
+    T = gpu.Toeplitz(to_dev(col), to_dev(row))
+    D = gpu.Diag(to_dev(d))
+    G = gpu.Dense(to_dev(g))
+    F = gpu.Fourier(8, dt)
+    H = gpu.Hadamard(4, dt)
+    rows = np.array([1, 5, 9, 30, 63], np.int32)
+    S = gpu.SelectRows(64, to_dev(rows), dt)
+    cd, td, dd, gd = dense.circulant(c), dense.toeplitz(col, row), dense.diag(d), g.astype(np.complex128)
+    fd, hd, sd = dense.fourier(8), dense.hadamard(4).astype(complex), dense.select_rows(64, rows)
+    check(gpu.Product(T, C, D), td @ cd @ dd, rng, prec)
+    check(S @ C, sd @ cd, rng, prec)
+    check(gpu.Sum(C, D, C.H), cd + dd + cd.conj().T, rng, prec)
+    check(gpu.Kron(F, G), dense.kron(fd, gd), rng, prec)
+    check(gpu.Kron(G, F, H), dense.kron(gd, fd, hd), rng, prec)
+    check(gpu.Kron(H, gpu.Product(G, G.H), F), dense.kron(hd, gd @ gd.conj().T, fd), rng, prec)
+    check(gpu.BlkDiag(C, G, F), dense.blkdiag(cd, gd, fd), rng, prec)
+    check(gpu.Kron(gpu.BlkDiag(F, H), G), dense.kron(dense.blkdiag(fd, hd), gd), rng, prec)
+    check(gpu.Product(gpu.Kron(F, H), gpu.BlkDiag(gpu.Diag(to_dev(d[:8])), F, H, H, F)),
+          dense.kron(fd, hd) @ dense.blkdiag(dense.diag(d[:8]), fd, hd, hd, fd), rng, prec)
+    check(T.H, td.conj().T, rng, prec)
+    check(gpu.Product(S, C).H, (sd @ cd).conj().T, rng, prec)
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_adjoint_identity(gpu, prec):
+    """<A x, y> = <x, A^H y> for a composed operator, on the GPU."""
+    import torch
+
+    rng = np.random.default_rng(5)
+    c = crandn(rng, 4096, NP[prec])
+    rows = np.sort(rng.choice(4096, 1000, replace=False)).astype(np.int32)
+    A = gpu.Product(gpu.SelectRows(4096, to_dev(rows), torch_dt(prec)), gpu.Circulant(to_dev(c)))
+    x = crandn(rng, (4, 4096), NP[prec])
+    y = crandn(rng, (4, 1000), NP[prec])
+    ax = to_host(A @ to_dev(x)).astype(np.complex128)
+    ahy = to_host(A.H @ to_dev(y)).astype(np.complex128)
+    lhs = np.sum(np.conj(y.astype(np.complex128)) * ax, axis=1)
+    rhs = np.sum(np.conj(ahy) * x.astype(np.complex128), axis=1)
+    nrm = np.max(np.abs(np.fft.fft(c.astype(np.complex128))))
+    scale = nrm * np.linalg.norm(x, axis=1) * np.linalg.norm(y, axis=1)
+    tol = 1e-5 if prec == "c64" else 1e-13
+    assert np.all(np.abs(lhs - rhs) <= tol * scale)
+
+
+def test_leading_dimension_and_views(gpu):
+    """Blocks with ld > rows (column views of a wider buffer)."""
+    import torch
+
+    rng = np.random.default_rng(3)
+    c = crandn(rng, 256, np.complex64)
+    op = gpu.Circulant(to_dev(c))
+    big = to_dev(crandn(rng, (5, 300), np.complex64))
+    x = big[:, :256]
+    assert x.stride(0) == 300
+    y = torch.zeros((5, 400), dtype=torch.complex64, device="cuda")
+    op.apply(x, out=y[:, :256])
+    ref = dense.apply(dense.circulant(c), to_host(x))
+    assert rel_err(to_host(y[:, :256]), ref) <= TOL["c64"]
+    assert np.all(to_host(y[:, 256:]) == 0)

@@ -173,6 +173,15 @@ def test_integer_product_wraps():
     assert y.dtype == np.int32
 
 
+def test_kron_apply_int_matches_exact_dense():
+    r = np.random.default_rng(5)
+    x = r.integers(-2**31, 2**31 - 1, size=(3, 64), dtype=np.int64)
+    y = structured.kron_apply_int([dense.hadamard(8), dense.hadamard(8)], x, 32)
+    assert np.array_equal(y, dense.apply_int(dense.hadamard(64), x, 32))
+    y64 = structured.kron_apply_int([dense.hadamard(16), dense.hadamard(4)], x, 64)
+    assert np.array_equal(y64, dense.apply_int(dense.hadamard(64), x, 64))
+
+
 # ---------------------------------------------------------------- Kron
 def test_kron_golden():
     k = dense.kron(np.array([[1, 2], [3, 4]]), np.array([[0, 5], [6, 7]]))
