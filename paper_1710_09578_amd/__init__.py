@@ -7,6 +7,7 @@ paper's notation on top (``Circulant(c) @ x``, ``A.H``, ``Product``, ...).
 
 from .capi import FmError, load  # noqa: F401
 from .operators import (  # noqa: F401
+    Batch,
     BlkDiag,
     Circulant,
     Dense,

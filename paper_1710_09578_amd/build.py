@@ -33,6 +33,9 @@ CFLAGS = [
     # packed FP32 instructions stay off: hipcc would otherwise form them from
     # plain float code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # contraction into FMA decided per source expression, so one transform gives
+    # the same bits in every kernel that inlines it
+    "-ffp-contract=on",
     "-Wall",
     "-Wno-unused-function",
     "-Wno-unused-variable",

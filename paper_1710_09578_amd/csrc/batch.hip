@@ -1,0 +1,416 @@
+// Batched application of many circulant / Toeplitz operators.
+//
+// Work is cut into items of 4096 complex values each (one work-group):
+//   SINGLE  a whole zero-padded convolution (length <= 4096) for up to
+//           4096/L columns of one operator
+//   FS1     four-step pass 1 of one column: strided 2^lg-point transforms of
+//           4096/2^lg neighbouring inner indices, twiddles, into the column's
+//           intermediate slot
+//   FS2     pass 2: one 4096-point row, spectral product, inverse row, twiddles
+//   FS3     pass 3: strided inverse transforms, cropped store into y
+// The four-step columns are grouped into chunks whose intermediates fit a
+// region sized for the memory-side cache, and the passes are software
+// pipelined over the chunks: stage k runs pass 1 of chunk k, pass 2 of chunk
+// k-1 and pass 3 of chunk k-2 (three regions in rotation), plus a share of the
+// single-pass items. Each stage is one launch of a single kernel that maps
+// work-group g to item g of the stage; launch boundaries order the passes, so
+// no work-group ever waits for another.
+#include <cstring>
+#include <unordered_set>
+
+#include "runtime.h"
+#include "xform.h"
+
+namespace fm {
+namespace {
+
+using namespace xf;
+
+constexpr int kLog1 = 12;  // contiguous factor of the four-step split
+constexpr size_t kRegionBytes = size_t(48) << 20;  // intermediates of one chunk
+
+enum ItemKind : int { IT_SINGLE = 0, IT_FS1 = 1, IT_FS2 = 2, IT_FS3 = 3 };
+
+struct Item {
+  int32_t kind_log;  // kind | (log2 of the transform length << 8)
+  int32_t op;
+  int32_t col;  // SINGLE: first column; FS*: four-step column index
+  int32_t sub;  // SINGLE: columns in this item; FS1/FS3: inner tile; FS2: row
+};
+
+struct OpDev {
+  const c64* spec;  // spectrum in the order of the operator's split, 1/L folded in
+  int32_t m, n;
+  int32_t logL;
+  int32_t ncols;
+};
+
+struct FsCol {
+  int32_t op, col;
+  int64_t woff;  // element offset of the column's slot in the intermediate pool
+};
+
+struct Ptrs {
+  const c64* x;
+  c64* y;
+  int64_t ldx, ldy;
+};
+
+struct BArgs {
+  const Item* items;  // this stage's items
+  const OpDev* ops;
+  const FsCol* cols;
+  const Ptrs* ptrs;
+  c64* wpool;
+  const c64* tw;
+  int32_t adj;
+};
+
+// A whole zero-padded convolution (length 2^lg <= 4096) of up to 4096/2^lg columns.
+__device__ __forceinline__ void run_single(const BArgs& a, const Item& it, int lg, c64* smem) {
+  const OpDev op = a.ops[it.op];
+  const Ptrs pt = a.ptrs[it.op];
+  Job<float> jb;
+  jb.x = pt.x + int64_t(it.col) * pt.ldx;
+  jb.y = pt.y + int64_t(it.col) * pt.ldy;
+  jb.xbstride = pt.ldx;
+  jb.ybstride = pt.ldy;
+  jb.inner = 1;
+  jb.nvalid = it.sub;
+  jb.in_limit = a.adj ? op.m : op.n;
+  jb.out_limit = a.adj ? op.n : op.m;
+  jb.i0 = 0;
+  jb.S = op.spec;
+  jb.sbstride = 0;
+  jb.q0 = 0;
+  const Mode md{FFT_CONV, a.adj, 0, 0, 0};
+  run_job<float, false, false, false>(jb, md, lg, smem, a.tw);
+}
+
+// Pass 1 (first) or pass 3 of the four-step convolution: strided transforms of
+// length 2^lg at stride 4096 over 4096/2^lg neighbouring inner indices.
+__device__ __forceinline__ void run_strided(const BArgs& a, const Item& it, const FsCol& fc, int lg, bool first,
+                                            c64* smem) {
+  const OpDev op = a.ops[fc.op];
+  const Ptrs pt = a.ptrs[fc.op];
+  const int tpw = 1 << (kLog1 - lg);
+  const int i0 = it.sub * tpw;
+  c64* w = a.wpool + fc.woff;
+  Job<float> jb;
+  jb.xbstride = jb.ybstride = 1;
+  jb.inner = 1 << kLog1;
+  jb.nvalid = tpw;
+  jb.i0 = i0;
+  jb.S = nullptr;
+  jb.sbstride = 0;
+  jb.q0 = i0;
+  const int L = 1 << op.logL;
+  if (first) {
+    jb.x = pt.x + int64_t(fc.col) * pt.ldx + i0;
+    jb.y = w + i0;
+    jb.in_limit = a.adj ? op.m : op.n;
+    jb.out_limit = L;
+    const Mode md{FFT_FWD, 0, op.logL, 0, 0};
+    run_job<float, true, false, false>(jb, md, lg, smem, a.tw);
+  } else {
+    jb.x = w + i0;
+    jb.y = pt.y + int64_t(fc.col) * pt.ldy + i0;
+    jb.in_limit = L;
+    jb.out_limit = a.adj ? op.n : op.m;
+    const Mode md{FFT_INV, 0, 0, 0, 0};
+    run_job<float, true, false, false>(jb, md, lg, smem, a.tw);
+  }
+}
+
+// Pass 2: one contiguous 4096-point row k2: transform, spectral product,
+// inverse transform, twiddles W_L^-(n1 k2), in place in the slot.
+__device__ __forceinline__ void run_row(const BArgs& a, const Item& it, const FsCol& fc, c64* smem) {
+  const OpDev op = a.ops[fc.op];
+  c64* row = a.wpool + fc.woff + (int64_t(it.sub) << kLog1);
+  Job<float> jb;
+  jb.x = row;
+  jb.y = row;
+  jb.xbstride = jb.ybstride = 0;
+  jb.inner = 1;
+  jb.nvalid = 1;
+  jb.in_limit = jb.out_limit = 1 << kLog1;
+  jb.i0 = 0;
+  jb.S = op.spec + (int64_t(it.sub) << kLog1);
+  jb.sbstride = 0;
+  jb.q0 = it.sub;
+  const Mode md{FFT_CONV, a.adj, op.logL, 1, 0};
+  run_job<float, false, false, false>(jb, md, kLog1, smem, a.tw);
+}
+
+__global__ __launch_bounds__(kWG) void stage_kernel(BArgs a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  c64* smem = reinterpret_cast<c64*>(smem_raw);
+  const Item it = a.items[blockIdx.x];
+  const int kind = it.kind_log & 0xff;
+  const int lg = it.kind_log >> 8;
+  if (kind == IT_SINGLE) {
+    run_single(a, it, lg, smem);
+    return;
+  }
+  const FsCol fc = a.cols[it.col];
+  if (kind == IT_FS2)
+    run_row(a, it, fc, smem);
+  else
+    run_strided(a, it, fc, lg, kind == IT_FS1, smem);
+}
+
+}  // namespace
+}  // namespace fm
+
+using namespace fm;
+
+struct fm_batch_s {
+  uint32_t magic = 0x464d4254u;
+  int device = 0;
+  std::vector<fm_op> ops;
+  std::vector<int64_t> ncols;
+  DevBuf d_items, d_ops, d_cols, d_ptrs, d_wpool;
+  std::vector<int64_t> stage_off;  // stage s: items [stage_off[s], stage_off[s+1])
+  // pointer tables: kTables device copies, each with a pinned staging buffer,
+  // the event after its last upload and the pointers it holds
+  static constexpr int kTables = 4;
+  Ptrs* staging = nullptr;
+  hipEvent_t uploaded[kTables] = {};
+  std::vector<Ptrs> held[kTables];
+  uint64_t used[kTables] = {};
+  uint64_t clock = 0;
+  std::vector<Ptrs> cur;
+};
+
+namespace {
+std::mutex g_batch_mu;
+std::unordered_set<const fm_batch_s*>& live_batches() {
+  static std::unordered_set<const fm_batch_s*> s;
+  return s;
+}
+bool batch_alive(const fm_batch_s* b) {
+  std::lock_guard<std::mutex> lock(g_batch_mu);
+  return live_batches().count(b) != 0;
+}
+void destroy_batch(fm_batch_s* b) {
+  {
+    std::lock_guard<std::mutex> lock(g_batch_mu);
+    live_batches().erase(b);
+  }
+  for (int k = 0; k < fm_batch_s::kTables; ++k)
+    if (b->uploaded[k]) (void)hipEventSynchronize(b->uploaded[k]), (void)hipEventDestroy(b->uploaded[k]);
+  if (b->staging) (void)hipHostFree(b->staging);
+  for (fm_op o : b->ops) fm_op_release(o);
+  b->magic = 0;
+  delete b;
+}
+}  // namespace
+
+extern "C" {
+
+fm_status fm_batch_create(fm_batch* out, int32_t nops, const fm_op* ops, const int64_t* ncols) {
+  set_error("");
+  FM_CHECK_ARG(out != nullptr, FM_E_INVALID, "output handle pointer is NULL");
+  FM_CHECK_ARG(nops >= 1 && ops != nullptr && ncols != nullptr, FM_E_INVALID, "batch: need operators");
+  int dev = 0;
+  FM_HIP(hipGetDevice(&dev));
+  for (int i = 0; i < nops; ++i) {
+    FM_CHECK_ARG(ops[i] != nullptr, FM_E_INVALID, "batch: operator %d is NULL", i);
+    FM_CHECK_ARG(op_alive(ops[i]), FM_E_RELEASED, "batch: operator %d was released", i);
+    const fm_op_s* o = ops[i];
+    FM_CHECK_ARG(o->kind == Kind::Circulant || o->kind == Kind::Toeplitz, FM_E_UNSUPPORTED,
+                 "batch: operator %d is not a circulant or Toeplitz operator", i);
+    FM_CHECK_ARG(o->dt == FM_C64, FM_E_DTYPE, "batch: operator %d is not complex64", i);
+    FM_CHECK_ARG(o->device == dev, FM_E_DEVICE, "batch: operator %d lives on another device", i);
+    FM_CHECK_ARG(ncols[i] >= 0 && ncols[i] < (int64_t(1) << 24), FM_E_INVALID, "batch: bad column count");
+    FM_CHECK_ARG(!o->s32.four_step() || o->s32.log1 == kLog1, FM_E_UNSUPPORTED, "batch: unexpected transform split");
+  }
+  fm_batch_s* b = new (std::nothrow) fm_batch_s();
+  FM_CHECK_ARG(b != nullptr, FM_E_NOMEM, "out of host memory");
+  b->device = dev;
+  std::vector<OpDev> hops(nops);
+  std::vector<Item> singles;
+  std::vector<FsCol> cols;
+  std::vector<int> col_log2;
+  for (int i = 0; i < nops; ++i) {
+    fm_op_s* o = ops[i];
+    o->refs.fetch_add(1);
+    b->ops.push_back(o);
+    b->ncols.push_back(ncols[i]);
+    const int logL = ilog2(o->L);
+    hops[i] = OpDev{static_cast<const c64*>(o->p32.p), int32_t(o->m), int32_t(o->n), logL, int32_t(ncols[i])};
+    if (logL <= kLog1) {
+      const int B = 1 << (kLog1 - logL);  // transforms per work-group
+      for (int64_t c0 = 0; c0 < ncols[i]; c0 += B) {
+        const int cnt = int(std::min<int64_t>(B, ncols[i] - c0));
+        singles.push_back(Item{IT_SINGLE | (logL << 8), i, int32_t(c0), cnt});
+      }
+    } else {
+      for (int64_t c = 0; c < ncols[i]; ++c) {
+        cols.push_back(FsCol{i, int32_t(c), 0});
+        col_log2.push_back(logL - kLog1);
+      }
+    }
+  }
+  // chunks of columns whose intermediates fit one region; three regions rotate
+  const size_t region_elems = kRegionBytes / sizeof(c64);
+  std::vector<std::vector<int>> chunks;
+  {
+    size_t used = region_elems;  // forces a first chunk
+    for (int j = 0; j < int(cols.size()); ++j) {
+      const size_t L = size_t(1) << (col_log2[j] + kLog1);
+      if (used + L > region_elems) {
+        chunks.emplace_back();
+        used = 0;
+      }
+      cols[j].woff = int64_t(used);  // offset inside the chunk's region
+      used += L;
+      chunks.back().push_back(j);
+    }
+  }
+  const int nchunks = int(chunks.size());
+  for (int c = 0; c < nchunks; ++c)
+    for (int j : chunks[c]) cols[j].woff += int64_t(c % 3) * int64_t(region_elems);
+  const int nstages = nchunks > 0 ? nchunks + 2 : (singles.empty() ? 0 : 1);
+  std::vector<Item> items;
+  size_t si = 0;
+  b->stage_off.push_back(0);
+  for (int s = 0; s < nstages; ++s) {
+    if (s < nchunks)  // pass 1 of chunk s
+      for (int j : chunks[s])
+        for (int t = 0; t < (1 << col_log2[j]); ++t)
+          items.push_back(Item{IT_FS1 | (col_log2[j] << 8), cols[j].op, j, t});
+    if (s - 1 >= 0 && s - 1 < nchunks)  // pass 2 of chunk s-1
+      for (int j : chunks[s - 1])
+        for (int r = 0; r < (1 << col_log2[j]); ++r)
+          items.push_back(Item{IT_FS2 | (kLog1 << 8), cols[j].op, j, r});
+    if (s - 2 >= 0 && s - 2 < nchunks)  // pass 3 of chunk s-2
+      for (int j : chunks[s - 2])
+        for (int t = 0; t < (1 << col_log2[j]); ++t)
+          items.push_back(Item{IT_FS3 | (col_log2[j] << 8), cols[j].op, j, t});
+    const size_t want = size_t(double(s + 1) / nstages * singles.size());
+    while (si < want) items.push_back(singles[si++]);
+    if (s == nstages - 1)
+      while (si < singles.size()) items.push_back(singles[si++]);
+    b->stage_off.push_back(int64_t(items.size()));
+  }
+  fm_status st = FM_OK;
+  auto fail = [&](fm_status s) {
+    destroy_batch(b);
+    return s;
+  };
+  if ((st = b->d_items.alloc(std::max<size_t>(1, items.size()) * sizeof(Item))) != FM_OK) return fail(st);
+  if ((st = b->d_ops.alloc(hops.size() * sizeof(OpDev))) != FM_OK) return fail(st);
+  if ((st = b->d_cols.alloc(std::max<size_t>(1, cols.size()) * sizeof(FsCol))) != FM_OK) return fail(st);
+  if ((st = b->d_ptrs.alloc(size_t(fm_batch_s::kTables) * nops * sizeof(Ptrs))) != FM_OK) return fail(st);
+  if (nchunks > 0 && (st = b->d_wpool.alloc(size_t(std::min(3, nchunks)) * kRegionBytes)) != FM_OK)
+    return fail(st);
+  if (hipHostMalloc(reinterpret_cast<void**>(&b->staging), size_t(fm_batch_s::kTables) * nops * sizeof(Ptrs)) !=
+      hipSuccess) {
+    set_error("batch: pinned staging allocation failed");
+    return fail(FM_E_NOMEM);
+  }
+  for (int k = 0; k < fm_batch_s::kTables; ++k) {
+    if (hipEventCreateWithFlags(&b->uploaded[k], hipEventDisableTiming) != hipSuccess) {
+      set_error("batch: event creation failed");
+      return fail(FM_E_DEVICE);
+    }
+  }
+  if ((!items.empty() &&
+       hipMemcpy(b->d_items.p, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice) != hipSuccess) ||
+      hipMemcpy(b->d_ops.p, hops.data(), hops.size() * sizeof(OpDev), hipMemcpyHostToDevice) != hipSuccess ||
+      (!cols.empty() &&
+       hipMemcpy(b->d_cols.p, cols.data(), cols.size() * sizeof(FsCol), hipMemcpyHostToDevice) != hipSuccess)) {
+    set_error("batch: upload of the work list failed");
+    return fail(FM_E_DEVICE);
+  }
+  {
+    std::lock_guard<std::mutex> lock(g_batch_mu);
+    live_batches().insert(b);
+  }
+  *out = b;
+  return FM_OK;
+}
+
+fm_status fm_batch_apply(fm_batch b, fm_dir dir, const void* const* x, const int64_t* ldx, void* const* y,
+                         const int64_t* ldy, void* stream) {
+  set_error("");
+  FM_CHECK_ARG(b != nullptr, FM_E_INVALID, "batch handle is NULL");
+  FM_CHECK_ARG(batch_alive(b), FM_E_RELEASED, "batch handle was released");
+  FM_CHECK_ARG(dir == FM_FWD || dir == FM_ADJ, FM_E_INVALID, "unknown direction");
+  FM_CHECK_ARG(x != nullptr && y != nullptr && ldx != nullptr && ldy != nullptr, FM_E_INVALID,
+               "batch: NULL pointer array");
+  const bool adj = dir == FM_ADJ;
+  const int nops = int(b->ops.size());
+  b->cur.resize(nops);
+  for (int i = 0; i < nops; ++i) {
+    const fm_op_s* o = b->ops[i];
+    const int64_t rin = adj ? o->m : o->n, rout = adj ? o->n : o->m;
+    const int64_t nc = b->ncols[i];
+    if (nc > 0) {
+      FM_CHECK_ARG(x[i] != nullptr && y[i] != nullptr, FM_E_INVALID, "batch: NULL block for operator %d", i);
+      FM_CHECK_ARG(ldx[i] >= rin && ldy[i] >= rout, FM_E_SHAPE, "batch: leading dimension of operator %d", i);
+      const char* xb = static_cast<const char*>(x[i]);
+      const char* yb = static_cast<const char*>(y[i]);
+      const size_t xl = size_t((nc - 1) * ldx[i] + rin) * 8, yl = size_t((nc - 1) * ldy[i] + rout) * 8;
+      FM_CHECK_ARG(xb + xl <= yb || yb + yl <= xb, FM_E_ALIAS, "batch: x and y of operator %d overlap", i);
+    }
+    b->cur[i] = Ptrs{static_cast<const c64*>(x[i]), static_cast<c64*>(y[i]), ldx[i], ldy[i]};
+  }
+  int dev = 0;
+  FM_HIP(hipGetDevice(&dev));
+  FM_CHECK_ARG(dev == b->device, FM_E_DEVICE, "batch lives on device %d, current is %d", b->device, dev);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const void* tw = twiddle_table(Elem::C64, 20);
+  FM_CHECK_ARG(tw != nullptr, FM_E_DEVICE, "twiddle table unavailable");
+  // find (or refresh the least recently used) device copy of this pointer table;
+  // an upload is ordered on the stream after every earlier launch that read it
+  int slot = -1;
+  for (int k = 0; k < fm_batch_s::kTables && slot < 0; ++k) {
+    if (b->held[k].size() != b->cur.size()) continue;
+    bool same = true;
+    for (int i = 0; same && i < nops; ++i)
+      same = b->held[k][i].x == b->cur[i].x && b->held[k][i].y == b->cur[i].y &&
+             b->held[k][i].ldx == b->cur[i].ldx && b->held[k][i].ldy == b->cur[i].ldy;
+    if (same) slot = k;
+  }
+  Ptrs* dptrs = static_cast<Ptrs*>(b->d_ptrs.p);
+  if (slot < 0) {
+    slot = 0;
+    for (int k = 1; k < fm_batch_s::kTables; ++k)
+      if (b->used[k] < b->used[slot]) slot = k;
+    FM_HIP(hipEventSynchronize(b->uploaded[slot]));  // its staging buffer may still be read
+    Ptrs* stg = b->staging + size_t(slot) * nops;
+    std::memcpy(stg, b->cur.data(), size_t(nops) * sizeof(Ptrs));
+    FM_HIP(hipMemcpyAsync(dptrs + size_t(slot) * nops, stg, size_t(nops) * sizeof(Ptrs), hipMemcpyHostToDevice, s));
+    FM_HIP(hipEventRecord(b->uploaded[slot], s));
+    b->held[slot] = b->cur;
+  }
+  b->used[slot] = ++b->clock;
+  BArgs a{};
+  a.ops = static_cast<const OpDev*>(b->d_ops.p);
+  a.cols = static_cast<const FsCol*>(b->d_cols.p);
+  a.ptrs = dptrs + size_t(slot) * nops;
+  a.wpool = static_cast<c64*>(b->d_wpool.p);
+  a.tw = static_cast<const c64*>(tw);
+  a.adj = adj;
+  const Item* items = static_cast<const Item*>(b->d_items.p);
+  for (size_t st = 0; st + 1 < b->stage_off.size(); ++st) {
+    const int64_t n = b->stage_off[st + 1] - b->stage_off[st];
+    if (n == 0) continue;
+    a.items = items + b->stage_off[st];
+    hipLaunchKernelGGL(stage_kernel, dim3(unsigned(n)), dim3(kWG), job_lds_bytes<float>(), s, a);
+    FM_LAUNCHED();
+  }
+  return FM_OK;
+}
+
+fm_status fm_batch_release(fm_batch b) {
+  set_error("");
+  FM_CHECK_ARG(b != nullptr, FM_E_INVALID, "batch handle is NULL");
+  FM_CHECK_ARG(batch_alive(b), FM_E_RELEASED, "batch handle was released");
+  destroy_batch(b);
+  return FM_OK;
+}
+
+}  // extern "C"

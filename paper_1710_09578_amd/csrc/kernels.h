@@ -21,7 +21,7 @@ inline size_t elem_bytes(Elem e) {
 
 // ---------------------------------------------------------------- FFT
 // Largest transform length held in one work-group's LDS.
-inline int fft_lds_max_log(Elem e) { return e == Elem::C64 ? 13 : 13; }
+inline int fft_lds_max_log(Elem) { return 12; }
 
 enum FftMode { FFT_FWD = 0, FFT_INV = 1, FFT_CONV = 2 };
 

@@ -58,8 +58,11 @@ Split split_for(Elem e, int logL) {
     s.log1 = logL;
     s.log2 = 0;
   } else {
-    s.log2 = logL / 2;       // strided length (shorter)
-    s.log1 = logL - s.log2;  // contiguous length
+    // the contiguous factor takes the full single-pass length; the strided
+    // factor (2^1 .. 2^8 for L up to 2^20) lets a strided pass cover many
+    // neighbouring vectors per work-group, i.e. long contiguous runs
+    s.log1 = lim;
+    s.log2 = logL - lim;
   }
   return s;
 }

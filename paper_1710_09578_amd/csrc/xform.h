@@ -1,0 +1,404 @@
+// Device-side FFT engine shared by the per-operator kernels and the batched
+// work-queue kernel (the fast transform behind the DFT of eq. (1) and the
+// cyclic convolution of eq. (5)).
+//
+// A work-group of 256 threads always holds 4096 complex values: 16 per thread
+// in registers.
+//
+// Transforms of N = 2^n >= 16 points (n <= 12) are held by T = N/16 threads,
+// thread t holding positions t + T*k (k = 0..15), and the work-group holds
+// 4096/N of them. The transform is a sequence of Stockham steps: one short
+// radix-2/4/8 step first when n is not a multiple of 4, then radix-16 steps.
+// Butterfly j of a step with radix R and span Ns reads positions j + r*N/R --
+// in the thread's own registers -- multiplies by W_{Ns R}^{(j mod Ns) r}, runs
+// a radix-R DFT in registers and writes result q to position
+// (j div Ns)*Ns*R + (j mod Ns) + q*Ns. Between steps the values go through LDS
+// (one padding slot every 16 spreads the banks); after the last step they are
+// back in the natural layout, so global loads and stores are coalesced and the
+// spectral product between a forward and an inverse transform needs no
+// exchange. The number of steps is a run-time value, so one code path serves
+// every length.
+//
+// Shorter transforms (N < 16) run without LDS: each thread holds 16/N of them.
+//
+// The inverse (unnormalised) transform is conj(F(conj(x))), so only forward
+// butterflies exist.
+#pragma once
+
+#include "kernels.h"
+
+namespace fm {
+namespace xf {
+
+constexpr int kWG = 256;   // threads per work-group
+constexpr int kE = 16;     // values per thread
+constexpr int kMaxLog = 12;
+
+// cos of 2 pi m / 16, m = 0..4 (sin by symmetry)
+__device__ constexpr double kCos16[5] = {1.0, 0.92387953251128675613, 0.70710678118654752440,
+                                         0.38268343236508977173, 0.0};
+
+// a * exp(-2 pi j e / 16)
+template <typename R>
+__device__ __forceinline__ Cx<R> rot16(Cx<R> a, int e) {
+  e &= 15;
+  if (e == 0) return a;
+  if (e == 8) return {-a.x, -a.y};
+  if (e == 4) return {a.y, -a.x};
+  if (e == 12) return {-a.y, a.x};
+  const int q = e >> 2, r = e & 3;
+  R c = R(kCos16[r]), sn = R(kCos16[4 - r]);
+  for (int k = 0; k < q; ++k) {  // a quarter turn: (c, s) -> (-s, c)
+    R t = c;
+    c = -sn;
+    sn = t;
+  }
+  sn = -sn;
+  return {a.x * c - a.y * sn, a.x * sn + a.y * c};
+}
+
+// In-register forward DFT of RAD points (natural order in and out).
+template <int RAD, typename R>
+__device__ __forceinline__ void dft(Cx<R>* a) {
+  if constexpr (RAD == 2) {
+    Cx<R> t = a[0];
+    a[0] = cadd(t, a[1]);
+    a[1] = csub(t, a[1]);
+  } else if constexpr (RAD == 4) {
+    Cx<R> t0 = cadd(a[0], a[2]), t1 = csub(a[0], a[2]);
+    Cx<R> t2 = cadd(a[1], a[3]), d = csub(a[1], a[3]);
+    Cx<R> t3 = {d.y, -d.x};  // d * (-j)
+    a[0] = cadd(t0, t2);
+    a[2] = csub(t0, t2);
+    a[1] = cadd(t1, t3);
+    a[3] = csub(t1, t3);
+  } else if constexpr (RAD == 8 || RAD == 16) {
+    // RAD = P*Q, n = Q*n1 + n2, k = k1 + P*k2:
+    // X[k1 + P k2] = sum_n2 W_Q^{n2 k2} W_RAD^{n2 k1} sum_n1 x[Q n1 + n2] W_P^{n1 k1}
+    constexpr int P = RAD == 8 ? 2 : 4;
+    constexpr int Q = RAD / P;
+    Cx<R> b[RAD];
+#pragma unroll
+    for (int n2 = 0; n2 < Q; ++n2) {
+      Cx<R> t[P];
+#pragma unroll
+      for (int n1 = 0; n1 < P; ++n1) t[n1] = a[Q * n1 + n2];
+      dft<P>(t);
+#pragma unroll
+      for (int k1 = 0; k1 < P; ++k1) b[n2 * P + k1] = rot16(t[k1], n2 * k1 * (16 / RAD));
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < P; ++k1) {
+      Cx<R> t[Q];
+#pragma unroll
+      for (int n2 = 0; n2 < Q; ++n2) t[n2] = b[n2 * P + k1];
+      dft<Q>(t);
+#pragma unroll
+      for (int k2 = 0; k2 < Q; ++k2) a[k1 + P * k2] = t[k2];
+    }
+  }
+}
+
+__device__ __forceinline__ int pad16(int pos) { return pos + (pos >> 4); }
+
+// Twiddles W^(jj r), r = 1..15, from the table entries W^(jj), W^(2jj),
+// W^(4jj), W^(8jj) (products of at most three of them).
+template <typename R>
+__device__ __forceinline__ void twiddles16(const Cx<R>* __restrict__ tab, int jj, Cx<R>* w) {
+  w[1] = tab[jj];
+  w[2] = tab[2 * jj];
+  w[3] = cmul(w[1], w[2]);
+  w[4] = tab[4 * jj];
+  w[5] = cmul(w[1], w[4]);
+  w[6] = cmul(w[2], w[4]);
+  w[7] = cmul(w[3], w[4]);
+  w[8] = tab[8 * jj];
+#pragma unroll
+  for (int r = 9; r < 16; ++r) w[r] = cmul(w[r - 8], w[8]);
+}
+
+// Short first step (radix RR = 2, 4, 8, span 1, no twiddles) into LDS.
+template <int RR, typename R>
+__device__ __forceinline__ void first_step(Cx<R>* v, Cx<R>* lds, int t, int T) {
+  constexpr int M = kE / RR;
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const int j = t + T * m;
+    Cx<R> a[RR];
+#pragma unroll
+    for (int r = 0; r < RR; ++r) a[r] = v[m + r * M];
+    dft<RR>(a);
+#pragma unroll
+    for (int q = 0; q < RR; ++q) lds[pad16(j * RR + q)] = a[q];
+  }
+}
+
+// Forward transform of 2^logn points (4 <= logn <= 12) held as described above.
+template <typename R>
+__device__ __forceinline__ void forward(Cx<R>* v, int logn, int t, Cx<R>* lds, const Cx<R>* __restrict__ tw) {
+  const int T = 1 << (logn - 4);
+  const int first = logn & 3;
+  const int nsteps = (logn >> 2) + (first ? 1 : 0);
+  int lns = 0;
+  int step = 0;
+  if (first) {
+    if (first == 1)
+      first_step<2>(v, lds, t, T);
+    else if (first == 2)
+      first_step<4>(v, lds, t, T);
+    else
+      first_step<8>(v, lds, t, T);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kE; ++k) v[k] = lds[pad16(t + T * k)];
+    __syncthreads();
+    lns = first;
+    step = 1;
+  }
+  for (; step < nsteps; ++step) {
+    const int ns = 1 << lns;
+    if (lns > 0) {
+      Cx<R> w[16];
+      twiddles16(tw + (ns << 4), t & (ns - 1), w);  // table of W_{16 Ns}
+#pragma unroll
+      for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], w[r]);
+    }
+    dft<16>(v);
+    if (step == nsteps - 1) break;
+    const int idxd = ((t >> lns) << (lns + 4)) | (t & (ns - 1));
+#pragma unroll
+    for (int q = 0; q < 16; ++q) lds[pad16(idxd + q * ns)] = v[q];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kE; ++k) v[k] = lds[pad16(t + T * k)];
+    __syncthreads();
+    lns += 4;
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void conj_all(Cx<R>* v) {
+#pragma unroll
+  for (int k = 0; k < kE; ++k) v[k].y = -v[k].y;
+}
+
+// Forward DFT of G = 16/N independent transforms of N = 2^logn < 16 points
+// held by one thread (transform g at v[g*N .. g*N + N)).
+template <typename R>
+__device__ __forceinline__ void forward_tiny(Cx<R>* v, int logn) {
+  if (logn == 1) {
+#pragma unroll
+    for (int g = 0; g < 8; ++g) dft<2>(v + 2 * g);
+  } else if (logn == 2) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g) dft<4>(v + 4 * g);
+  } else if (logn == 3) {
+#pragma unroll
+    for (int g = 0; g < 2; ++g) dft<8>(v + 8 * g);
+  }
+}
+
+// ---------------------------------------------------------------- global access
+// Device-scope loads and stores (coherent across the L2 slices of the chip),
+// for intermediates handed between work-groups inside one launch.
+template <typename R>
+__device__ __forceinline__ Cx<R> load_coherent(const Cx<R>* p) {
+  unsigned long long* q = reinterpret_cast<unsigned long long*>(const_cast<Cx<R>*>(p));
+  if constexpr (sizeof(R) == 4) {
+    unsigned long long u = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    Cx<R> v;
+    __builtin_memcpy(&v, &u, 8);
+    return v;
+  } else {
+    unsigned long long u0 = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned long long u1 = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    Cx<R> v;
+    __builtin_memcpy(&v.x, &u0, 8);
+    __builtin_memcpy(&v.y, &u1, 8);
+    return v;
+  }
+}
+template <typename R>
+__device__ __forceinline__ void store_coherent(Cx<R>* p, Cx<R> v) {
+  unsigned long long* q = reinterpret_cast<unsigned long long*>(p);
+  if constexpr (sizeof(R) == 4) {
+    unsigned long long u;
+    __builtin_memcpy(&u, &v, 8);
+    __hip_atomic_store(q, u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    unsigned long long u0, u1;
+    __builtin_memcpy(&u0, &v.x, 8);
+    __builtin_memcpy(&u1, &v.y, 8);
+    __hip_atomic_store(q, u0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(q + 1, u1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// ---------------------------------------------------------------- one work-group's job
+// A work-group's 4096 values are 4096/N transforms. Transform b (0 <= b <
+// 4096/N) starts at base + b*bstride (contiguous vectors) or at base + b
+// (strided vectors, element r at r*inner); its spectrum row starts at
+// S + b*sbstride; its twiddle-epilogue index is q0 + b. Transforms with
+// b >= nvalid are computed on zeros and not stored.
+template <typename R>
+struct Job {
+  const Cx<R>* x;
+  Cx<R>* y;
+  int64_t xbstride, ybstride;  // contiguous: element offset between transforms
+  int inner;                   // strided: element stride of the points (1: contiguous)
+  int nvalid;
+  int in_limit, out_limit;     // point r of transform b is read if r*inner + i_b < in_limit,
+                               // stored if < out_limit (i_b = i0 + b when strided, else 0)
+  int i0;
+  const Cx<R>* S;
+  int64_t sbstride;
+  int q0;
+};
+struct Mode {
+  int mode, spec_conj, tw_log, tw_inv, accumulate;
+};
+
+// Loads, transforms and stores one job. Every thread of the work-group calls it.
+template <typename R, bool STRIDED, bool COH_IN, bool COH_OUT>
+__device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int logn, Cx<R>* lds,
+                                        const Cx<R>* __restrict__ tw) {
+  const int tid = threadIdx.x;
+  Cx<R> v[kE];
+  if (logn >= 4) {
+    const int T = 1 << (logn - 4);
+    const int B = kWG / T;
+    const int b = STRIDED ? (tid % B) : (tid / T);
+    const int t = STRIDED ? (tid / B) : (tid % T);
+    const bool valid = b < jb.nvalid;
+    const int inner = STRIDED ? jb.inner : 1;
+    const int ii = STRIDED ? jb.i0 + b : 0;
+    const Cx<R>* X = STRIDED ? jb.x + b : jb.x + b * jb.xbstride;
+    Cx<R>* Y = STRIDED ? jb.y + b : jb.y + b * jb.ybstride;
+#pragma unroll
+    for (int k = 0; k < kE; ++k) {
+      const int p = t + T * k;
+      const bool in = valid && p * inner + ii < jb.in_limit;
+      if constexpr (COH_IN)
+        v[k] = in ? load_coherent(X + p * inner) : Cx<R>{R(0), R(0)};
+      else
+        v[k] = in ? X[p * inner] : Cx<R>{R(0), R(0)};
+    }
+    Cx<R>* my = lds + b * ((1 << logn) + (1 << (logn - 4)));
+    if (md.mode == FFT_INV) conj_all(v);
+    forward(v, logn, t, my, tw);
+    if (md.mode == FFT_CONV) {
+      const Cx<R>* S = jb.S + b * jb.sbstride;
+#pragma unroll
+      for (int k = 0; k < kE; ++k) {
+        const Cx<R> s = S[t + T * k];
+        // inverse follows: keep conj(X s) (or conj(X conj s)) for the conj trick
+        const Cx<R> p = md.spec_conj ? cmulc(v[k], s) : cmul(v[k], s);
+        v[k] = {p.x, -p.y};
+      }
+      forward(v, logn, t, my, tw);
+      conj_all(v);
+    } else if (md.mode == FFT_INV) {
+      conj_all(v);
+    }
+    if (md.tw_log > 0) {
+      const int twn = 1 << md.tw_log;
+      const Cx<R>* tab = tw + twn;
+      const int qq = jb.q0 + b;
+#pragma unroll
+      for (int k = 0; k < kE; ++k) {
+        const int p = t + T * k;
+        const Cx<R> w = tab[(p * qq) & (twn - 1)];
+        v[k] = md.tw_inv ? cmulc(v[k], w) : cmul(v[k], w);
+      }
+    }
+    if (valid) {
+#pragma unroll
+      for (int k = 0; k < kE; ++k) {
+        const int p = t + T * k;
+        if (p * inner + ii < jb.out_limit) {
+          Cx<R>* dst = Y + p * inner;
+          if constexpr (COH_OUT) {
+            store_coherent(dst, v[k]);
+          } else if (md.accumulate) {
+            const Cx<R> old = *dst;
+            *dst = cadd(old, v[k]);
+          } else {
+            *dst = v[k];
+          }
+        }
+      }
+    }
+    return;
+  }
+  // ---- N < 16: G = 16/N transforms per thread, no LDS
+  const int N = 1 << logn;
+  const int G = kE >> logn;
+  // transform of (thread, g): contiguous b = tid*G + g; strided b = tid + 256*g
+#pragma unroll
+  for (int k = 0; k < kE; ++k) {
+    const int g = k >> logn, r = k & (N - 1);
+    const int b = STRIDED ? tid + kWG * g : tid * G + g;
+    const int inner = STRIDED ? jb.inner : 1;
+    const int ii = STRIDED ? jb.i0 + b : 0;
+    const bool in = b < jb.nvalid && r * inner + ii < jb.in_limit;
+    const Cx<R>* src = STRIDED ? jb.x + b + r * inner : jb.x + b * jb.xbstride + r;
+    if constexpr (COH_IN)
+      v[k] = in ? load_coherent(src) : Cx<R>{R(0), R(0)};
+    else
+      v[k] = in ? *src : Cx<R>{R(0), R(0)};
+  }
+  if (md.mode == FFT_INV) conj_all(v);
+  forward_tiny(v, logn);
+  if (md.mode == FFT_CONV) {
+#pragma unroll
+    for (int k = 0; k < kE; ++k) {
+      const int g = k >> logn, r = k & (N - 1);
+      const int b = STRIDED ? tid + kWG * g : tid * G + g;
+      const Cx<R> s = jb.S[b * jb.sbstride + r];
+      const Cx<R> p = md.spec_conj ? cmulc(v[k], s) : cmul(v[k], s);
+      v[k] = {p.x, -p.y};
+    }
+    forward_tiny(v, logn);
+    conj_all(v);
+  } else if (md.mode == FFT_INV) {
+    conj_all(v);
+  }
+  if (md.tw_log > 0) {
+    const int twn = 1 << md.tw_log;
+    const Cx<R>* tab = tw + twn;
+#pragma unroll
+    for (int k = 0; k < kE; ++k) {
+      const int g = k >> logn, r = k & (N - 1);
+      const int b = STRIDED ? tid + kWG * g : tid * G + g;
+      const Cx<R> w = tab[(r * (jb.q0 + b)) & (twn - 1)];
+      v[k] = md.tw_inv ? cmulc(v[k], w) : cmul(v[k], w);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kE; ++k) {
+    const int g = k >> logn, r = k & (N - 1);
+    const int b = STRIDED ? tid + kWG * g : tid * G + g;
+    const int inner = STRIDED ? jb.inner : 1;
+    const int ii = STRIDED ? jb.i0 + b : 0;
+    if (b < jb.nvalid && r * inner + ii < jb.out_limit) {
+      Cx<R>* dst = STRIDED ? jb.y + b + r * inner : jb.y + b * jb.ybstride + r;
+      if constexpr (COH_OUT) {
+        store_coherent(dst, v[k]);
+      } else if (md.accumulate) {
+        const Cx<R> old = *dst;
+        *dst = cadd(old, v[k]);
+      } else {
+        *dst = v[k];
+      }
+    }
+  }
+}
+
+// LDS bytes of one work-group.
+template <typename R>
+constexpr size_t job_lds_bytes() {
+  return size_t(4096 + 256) * sizeof(Cx<R>);
+}
+
+}  // namespace xf
+}  // namespace fm

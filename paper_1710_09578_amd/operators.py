@@ -188,3 +188,42 @@ def Kron(*ops) -> Operator:
 
 def BlkDiag(*ops) -> Operator:
     return _compose(capi.FM_BLKDIAG, ops)
+
+
+# ---------------------------------------------------------------- batching
+class Batch:
+    """Many circulant / Toeplitz operators applied in one persistent launch.
+
+    ``ncols[i]`` is the number of columns operator i is applied to; blocks are
+    passed per call as lists of tensors of shape (ncols[i], rows).
+    """
+
+    def __init__(self, ops, ncols):
+        self.ops = list(ops)
+        self.ncols = [int(v) for v in ncols]
+        if len(self.ops) != len(self.ncols):
+            raise ValueError("one column count per operator")
+        self._h = capi.fm_batch_create([o.handle for o in self.ops], self.ncols)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None:
+            try:
+                capi.fm_batch_release(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def apply(self, xs, adjoint: bool = False, outs=None):
+        if len(xs) != len(self.ops):
+            raise ValueError("one block per operator")
+        if outs is None:
+            outs = []
+            for op, x, nc in zip(self.ops, xs, self.ncols):
+                m, n = op.shape
+                outs.append(torch.empty((nc, n if adjoint else m), dtype=op.dtype, device=x.device))
+        ldx = [max(x.stride(0), 1) if x.dim() == 2 else x.shape[-1] for x in xs]
+        ldy = [max(y.stride(0), 1) if y.dim() == 2 else y.shape[-1] for y in outs]
+        capi.fm_batch_apply(self._h, capi.FM_ADJ if adjoint else capi.FM_FWD, xs, ldx, outs, ldy,
+                            _stream())
+        return outs

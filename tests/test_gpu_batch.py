@@ -1,0 +1,110 @@
+"""GPU parity of the batched persistent launch (fm_batch_apply).
+
+The batched launch runs the same per-transform code, splits, spectra and
+twiddles as one fm_apply per operator, so its results must equal the plain
+path bit for bit; both are also compared with the FP64 oracle.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import structured
+from tests.gpu_util import TOL, crandn, rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def build_batch(gpu, sizes, ncols, seed, square=True):
+    rng = np.random.default_rng(seed)
+    ops, data = [], []
+    for n, nc in zip(sizes, ncols):
+        m = n if square else max(1, int(n * 0.75))
+        col, row = crandn(rng, m), crandn(rng, n)
+        x = crandn(rng, (nc, n))
+        u = crandn(rng, (nc, m))
+        ops.append(gpu.Toeplitz(to_dev(col), to_dev(row)))
+        data.append((col, row, x, u))
+    return ops, data
+
+
+@pytest.mark.parametrize("square", [True, False])
+def test_batch_equals_plain_and_oracle(gpu, square):
+    # lengths on both sides of the single-pass limit (embedding 2^12 vs 2^13+),
+    # ragged column counts, including a zero-column operator
+    sizes = [3, 100, 1000, 2047, 2049, 3000, 5000, 17000, 40000, 65536, 300, 9000]
+    ncols = [1, 5, 3, 2, 4, 0, 2, 3, 1, 2, 17, 6]
+    ops, data = build_batch(gpu, sizes, ncols, seed=1, square=square)
+    batch = gpu.Batch(ops, ncols)
+    xs = [to_dev(d[2]) for d in data]
+    us = [to_dev(d[3]) for d in data]
+    ys = batch.apply(xs)
+    zs = batch.apply(us, adjoint=True)
+    for i, (op, (col, row, x, u)) in enumerate(zip(ops, data)):
+        if ncols[i] == 0:
+            continue
+        y_plain = to_host(op @ xs[i])
+        z_plain = to_host(op.H @ us[i])
+        y_b, z_b = to_host(ys[i]), to_host(zs[i])
+        assert np.array_equal(y_b, y_plain), f"op {i}: batched forward differs from plain"
+        assert np.array_equal(z_b, z_plain), f"op {i}: batched adjoint differs from plain"
+        assert rel_err(y_b, structured.toeplitz_apply_fft64(col, row, x)) <= TOL["c64"]
+        assert rel_err(z_b, structured.toeplitz_apply_fft64(col, row, u, True)) <= TOL["c64"]
+
+
+def test_batch_repeated_calls_and_pointer_tables(gpu):
+    """Alternating pointer tables (more than the cached copies) and repeated
+    launches give the same bits every time."""
+    import torch
+
+    sizes = [700, 6000, 33000]
+    ncols = [3, 2, 2]
+    ops, data = build_batch(gpu, sizes, ncols, seed=2)
+    batch = gpu.Batch(ops, ncols)
+    xs = [to_dev(d[2]) for d in data]
+    ref = [to_host(y) for y in batch.apply(xs)]
+    outs = [[torch.empty_like(x) for x in xs] for _ in range(6)]
+    for rep in range(3):
+        for k in range(6):
+            batch.apply(xs, outs=outs[k])
+        for k in range(6):
+            for i in range(3):
+                assert np.array_equal(to_host(outs[k][i]), ref[i])
+
+
+def test_batch_circulant_ops(gpu):
+    rng = np.random.default_rng(4)
+    cs = [crandn(rng, n) for n in (1024, 16384, 131072)]
+    ops = [gpu.Circulant(to_dev(c)) for c in cs]
+    ncols = [4, 3, 2]
+    xs = [to_dev(crandn(rng, (nc, c.size))) for nc, c in zip(ncols, cs)]
+    batch = gpu.Batch(ops, ncols)
+    for adj in (False, True):
+        ys = batch.apply(xs, adjoint=adj)
+        for c, x, y in zip(cs, xs, ys):
+            assert rel_err(to_host(y), structured.circulant_apply_fft64(c, to_host(x), adj)) <= TOL["c64"]
+
+
+def test_batch_toeplitz_workload_sample(gpu):
+    """The 512-operator Toeplitz workload in one launch; a seeded sample of
+    operators (all small ones and a few large) is checked against the oracle."""
+    from workloads import toeplitz_batch
+
+    full = toeplitz_batch()
+    sizes, ncols = full["sizes"], full["ncols"]
+    ops, xs = [], []
+    for i in range(len(sizes)):
+        d = full["ops"][i]
+        ops.append(gpu.Toeplitz(to_dev(d["col"]), to_dev(d["row"])))
+        xs.append(to_dev(d["x"]))
+    batch = gpu.Batch(ops, list(ncols))
+    ys = batch.apply(xs)
+    zs = batch.apply(ys, adjoint=True)
+    rng = np.random.default_rng(0)
+    small = [i for i in range(len(sizes)) if sizes[i] <= 1024]
+    large = list(rng.choice([i for i in range(len(sizes)) if sizes[i] > 1024], 12, replace=False))
+    for i in small[:40] + large:
+        d = full["ops"][i]
+        y = to_host(ys[i])
+        assert rel_err(y, structured.toeplitz_apply_fft64(d["col"], d["row"], d["x"])) <= TOL["c64"]
+        z = to_host(zs[i])
+        assert rel_err(z, structured.toeplitz_apply_fft64(d["col"], d["row"], y, True)) <= TOL["c64"]
