@@ -69,17 +69,30 @@ def objective(a, b, x, lam) -> np.ndarray:
 
 def fista(a, b, lam, L: float, iters: int, momentum: bool = True, x0=None,
           stop_tol: float = 0.0, history: bool = False):
-    """Constant-step FISTA (momentum=True) or ISTA (False), column by column.
+    """Constant-step FISTA (momentum=True) or ISTA (False) with a dense A.
 
     a: dense (m, n); b: (ncols, m); lam: scalar or (ncols,); L: step constant.
+    See ``fista_op`` for the iteration; this form supplies the dense products
+    of eq. (2).
+    """
+    a = np.asarray(a, dtype=C128)
+    ah = a.conj().T
+    return fista_op(lambda v: (a @ v.T).T, lambda v: (ah @ v.T).T, a.shape[1], b, lam, L, iters,
+                    momentum=momentum, x0=x0, stop_tol=stop_tol, history=history)
+
+
+def fista_op(apply, adjoint, n: int, b, lam, L: float, iters: int, momentum: bool = True,
+             x0=None, stop_tol: float = 0.0, history: bool = False):
+    """FISTA / ISTA with the operator given by its forward and backward
+    transforms (``apply(v)`` = A v, ``adjoint(v)`` = A^H v on blocks of shape
+    (ncols, rows)), column by column.
+
     With stop_tol > 0 a column is frozen after the first iteration k at which
     ||x_k - x_{k-1}||_2 <= stop_tol * max(||x_k||_2, 1e-30); its iterate count
     is then k. Returns (x, iters_done) and, with history, the list of iterates.
     """
-    a = np.asarray(a, dtype=C128)
     b = np.asarray(b, dtype=C128)
     ncols = b.shape[0]
-    n = a.shape[1]
     lam = np.broadcast_to(np.asarray(lam, dtype=np.float64), (ncols,))
     x_prev = np.zeros((ncols, n), dtype=C128) if x0 is None else np.asarray(x0, dtype=C128).copy()
     y = x_prev.copy()
@@ -87,9 +100,8 @@ def fista(a, b, lam, L: float, iters: int, momentum: bool = True, x0=None,
     done = np.full(ncols, iters, dtype=np.int64)
     active = np.ones(ncols, dtype=bool)
     hist = []
-    ah = a.conj().T
     for k in range(iters):
-        g = (ah @ ((a @ y.T) - b.T)).T
+        g = adjoint(apply(y) - b)
         z = y - g / L
         x = soft(z, (lam / L)[:, None])
         y_new = x + (beta[k] * (x - x_prev) if momentum else 0.0)
@@ -111,22 +123,56 @@ def fista(a, b, lam, L: float, iters: int, momentum: bool = True, x0=None,
     return x_prev, done
 
 
+def lambda_rule_op(adjoint, b, rel: float) -> np.ndarray:
+    """lam_j = rel * ||A^H b_j||_inf with A^H given as a function."""
+    return rel * np.max(np.abs(adjoint(np.asarray(b, dtype=C128))), axis=1)
+
+
+def splitmix64_outputs(seed: int, count: int):
+    """The first ``count`` 64-bit outputs of SplitMix64 seeded with ``seed``."""
+    mask = (1 << 64) - 1
+    out = []
+    for k in range(count):
+        z = (seed + (k + 1) * 0x9E3779B97F4A7C15) & mask
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & mask
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & mask
+        out.append(z ^ (z >> 31))
+    return out
+
+
+def splitmix64_start(n: int, seed: int) -> np.ndarray:
+    """Start vector of the power iteration drawn from SplitMix64 (Steele, Lea
+    and Flood, 2014): output k of the generator seeded with ``seed`` is the
+    finaliser applied to seed + (k+1) * 0x9E3779B97F4A7C15 (mod 2^64); entry i
+    is (u(2i) - 1/2) + j (u(2i+1) - 1/2) with u(k) = (output k >> 11) / 2^53."""
+    raw = splitmix64_outputs(seed, 2 * n)
+    u = np.array([(z >> 11) / float(1 << 53) for z in raw])
+    return (u[0::2] - 0.5) + 1j * (u[1::2] - 0.5)
+
+
 def power_iteration(a, v0, max_iters: int = 500, tol: float = 1e-13):
-    """Estimate L = ||A||_2^2 by power iteration on A^H A in FP64.
+    """Estimate L = ||A||_2^2 by power iteration on A^H A in FP64 (dense A).
 
     v <- v0 / ||v0||; repeat: w = A^H (A v); L_k = <v, w> (the Rayleigh
     quotient, = ||A v||^2); v <- w / ||w||; stop when |L_k - L_{k-1}| <=
     tol * L_k or after max_iters. Returns (L, iterations).
     """
     a = np.asarray(a, dtype=C128)
+    ah = a.conj().T
+    return power_iteration_op(lambda v: a @ v, lambda v: ah @ v, v0, max_iters, tol)
+
+
+def power_iteration_op(apply, adjoint, v0, max_iters: int = 500, tol: float = 1e-13):
+    """The power iteration of ``power_iteration`` with A given by functions
+    on single vectors."""
     v = np.asarray(v0, dtype=C128)
     v = v / np.linalg.norm(v)
     prev = None
     lk = 0.0
     for it in range(1, max_iters + 1):
-        av = a @ v
+        av = apply(v)
         lk = float(np.vdot(av, av).real)
-        w = a.conj().T @ av
+        w = adjoint(av)
         nw = np.linalg.norm(w)
         if nw == 0.0:
             return 0.0, it

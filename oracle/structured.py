@@ -148,35 +148,30 @@ def toeplitz_apply_fft64(col, row, x, adjoint_dir: bool = False, L: int | None =
 
 
 def toeplitz_fista_fft64(col, row, b, lam, L, iters, momentum=True, stop_tol=0.0):
-    """FISTA (same steps as ``fista.fista``) with the Toeplitz product done by
+    """FISTA of ``fista.fista_op`` with the Toeplitz products done by
     ``toeplitz_apply_fft64``; for batches too large for dense products."""
-    from .fista import momentum_sequence, soft
+    from .fista import fista_op
 
-    b = np.asarray(b, dtype=C128)
-    ncols = b.shape[0]
     n = np.asarray(row).shape[0]
-    lam = np.broadcast_to(np.asarray(lam, dtype=np.float64), (ncols,))
-    x_prev = np.zeros((ncols, n), dtype=C128)
-    y = x_prev.copy()
-    _, beta = momentum_sequence(iters)
-    done = np.full(ncols, iters, dtype=np.int64)
-    active = np.ones(ncols, dtype=bool)
-    for k in range(iters):
-        r = toeplitz_apply_fft64(col, row, y) - b
-        g = toeplitz_apply_fft64(col, row, r, adjoint_dir=True)
-        x = soft(y - g / L, (lam / L)[:, None])
-        y_new = x + (beta[k] * (x - x_prev) if momentum else 0.0)
-        if stop_tol > 0.0:
-            dx = np.linalg.norm(x - x_prev, axis=1)
-            nx = np.maximum(np.linalg.norm(x, axis=1), 1e-30)
-            stop_now = active & (dx <= stop_tol * nx)
-        x = np.where(active[:, None], x, x_prev)
-        y = np.where(active[:, None], y_new, y)
-        x_prev = x
-        if stop_tol > 0.0:
-            done[stop_now] = k + 1
-            active = active & ~stop_now
-    return x_prev, done
+    return fista_op(lambda v: toeplitz_apply_fft64(col, row, v),
+                    lambda v: toeplitz_apply_fft64(col, row, v, adjoint_dir=True),
+                    n, b, lam, L, iters, momentum=momentum, stop_tol=stop_tol)
+
+
+def select_circulant_fft64(c, rows):
+    """(apply, adjoint) of A = S_rows C(c) through the FFT64 circulant product."""
+    rows = np.asarray(rows, dtype=np.int64)
+    n = np.asarray(c).shape[0]
+
+    def apply(v):
+        return circulant_apply_fft64(c, v)[:, rows]
+
+    def adjoint(u):
+        z = np.zeros((u.shape[0], n), dtype=C128)
+        z[:, rows] = u
+        return circulant_apply_fft64(c, z, adjoint_dir=True)
+
+    return apply, adjoint
 
 
 def ml_toeplitz_apply_fft64(n_levels, t, x, adjoint_dir: bool = False):

@@ -21,6 +21,9 @@ from .operators import (  # noqa: F401
     SelectRows,
     Sum,
     Toeplitz,
+    fista,
+    fista_options,
+    power_iteration,
 )
 
 __version__ = "0.1.0"

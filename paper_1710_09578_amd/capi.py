@@ -242,7 +242,8 @@ def fm_fista_workspace_size(a, ncols, opts):
 
 def fm_fista(a, ncols, b, ldb, x, ldx, opts, stats, ws, ws_bytes, stream):
     _call("fm_fista", a, ncols, _ptr(b), ldb, _ptr(x), ldx, C.byref(opts),
-          stats if stats is not None else None, _ptr(ws), ws_bytes, _ptr(stream))
+          C.cast(stats, C.POINTER(fm_fista_stat)) if stats is not None else None, _ptr(ws), ws_bytes,
+          _ptr(stream))
 
 
 def fm_power_iteration(a, v0, seed, max_iters, tol, stream):
@@ -274,7 +275,7 @@ def fm_batch_apply(b, direction, xs, ldx, ys, ldy, stream):
 
 def fm_batch_fista(b, bvecs, ldb, xs, ldx, opts, stats, stream):
     _call("fm_batch_fista", b, _parr(bvecs), _iarr(ldb), _parr(xs), _iarr(ldx), C.byref(opts),
-          stats, _ptr(stream))
+          C.cast(stats, C.POINTER(fm_fista_stat)) if stats is not None else None, _ptr(stream))
 
 
 def fm_batch_release(b):

@@ -1,0 +1,42 @@
+// Launch interfaces of the solver kernels (solve.hip).
+#pragma once
+
+#include "kernels.h"
+
+namespace fm {
+
+struct UpdateArgs {
+  void* x;        // iterate x_k (overwritten by x_{k+1})
+  void* y;        // extrapolated point y_k (overwritten by y_{k+1})
+  const void* g;  // gradient A^H (A y_k - b)
+  int64_t ldx, ldy, ldg;
+  int64_t rows;
+  double invL;
+  const double* lam;  // per column
+  double beta;        // momentum weight (t_k - 1)/t_{k+1}
+  int momentum;
+  const int* active;  // per column, NULL: all active
+  int* status;        // per column, set to 1 on a non-finite value
+  double* partial;    // per column and tile: sum |dx|^2, sum |x|^2 (NULL: not needed)
+  int64_t ntiles;
+  int per_thread;
+};
+
+int64_t update_tiles(int64_t rows, int* per_thread);
+fm_status launch_update(Elem e, const UpdateArgs& a, int64_t ncols, hipStream_t s);
+fm_status launch_stop(const double* partial, int64_t ntiles, int64_t ncols, double tol, int k, int* active,
+                      int* iters, const int* status, hipStream_t s);
+fm_status launch_sub(Elem e, int64_t rows, int64_t ncols, const void* b, int64_t ldb, void* r, int64_t ldr,
+                     const int* active, hipStream_t s);
+fm_status launch_colmax(Elem e, int64_t rows, int64_t ncols, const void* g, int64_t ldg, double rel, double* out,
+                        hipStream_t s);
+fm_status launch_norm2(int64_t n, const void* v, double* partial, int nparts, double* out, hipStream_t s);
+fm_status launch_normalize(int64_t n, void* v, const double* nrm2, hipStream_t s);
+fm_status launch_start_vector(int64_t n, uint64_t seed, void* v, hipStream_t s);
+fm_status launch_fill_int(int64_t n, int* p, int v, hipStream_t s);
+fm_status launch_fill_double(int64_t n, double* p, double v, hipStream_t s);
+fm_status launch_zero2d(Elem e, int64_t rows, int64_t ncols, void* p, int64_t ld, hipStream_t s);
+fm_status launch_copy2d(Elem e, int64_t rows, int64_t ncols, const void* src, int64_t lds, void* dst, int64_t ldd,
+                        hipStream_t s);
+
+}  // namespace fm

@@ -190,6 +190,57 @@ def BlkDiag(*ops) -> Operator:
     return _compose(capi.FM_BLKDIAG, ops)
 
 
+# ---------------------------------------------------------------- solver
+def fista_options(iters=200, momentum=True, lam=None, lam_rel=None, L=None, stop_tol=0.0,
+                  x0_given=False, power_iters=500, power_tol=1e-13, seed=0):
+    o = capi.fm_fista_opts()
+    o.max_iters = int(iters)
+    o.momentum = 1 if momentum else 0
+    o.x0_given = 1 if x0_given else 0
+    o.power_max_iters = int(power_iters)
+    o.lambda_abs = float(lam) if lam is not None else 0.0
+    o.lambda_rel = float(lam_rel) if lam_rel is not None else 0.0
+    o.L = float(L) if L is not None else 0.0
+    o.stop_tol = float(stop_tol)
+    o.power_tol = float(power_tol)
+    o.seed = int(seed)
+    return o
+
+
+def fista(A: Operator, b: torch.Tensor, iters=200, momentum=True, lam=None, lam_rel=None, L=None,
+          stop_tol=0.0, x0=None, power_iters=500, power_tol=1e-13, seed=0):
+    """FISTA (momentum=True) or ISTA for min 1/2||A x - b||^2 + lam ||x||_1 per
+    column of b (shape (ncols, m)); lam absolute, or lam_rel * ||A^H b||_inf.
+    Returns (x, stats) with stats a list of dicts per column."""
+    import ctypes as C
+
+    m, n = A.shape
+    bb = b.unsqueeze(0) if b.dim() == 1 else b
+    if bb.stride(1) != 1:
+        bb = bb.contiguous()
+    ncols = bb.shape[0]
+    if x0 is not None:
+        x = (x0.unsqueeze(0) if x0.dim() == 1 else x0).clone().contiguous()
+    else:
+        x = torch.empty((ncols, n), dtype=A.dtype, device=bb.device)
+    o = fista_options(iters, momentum, lam, lam_rel, L, stop_tol, x0 is not None, power_iters, power_tol, seed)
+    need = capi.fm_fista_workspace_size(A.handle, ncols, o)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=bb.device)
+    stats = (capi.fm_fista_stat * max(ncols, 1))()
+    capi.fm_fista(A.handle, ncols, bb, max(bb.stride(0), m), x, n, o, stats, ws, ws.numel(), _stream())
+    st = [{"iters": stats[j].iters_done, "status": stats[j].status, "L": stats[j].L_used,
+           "lam": stats[j].lambda_used} for j in range(ncols)]
+    return (x.squeeze(0) if b.dim() == 1 else x), st
+
+
+def power_iteration(A: Operator, v0: torch.Tensor | None = None, seed=0, max_iters=500, tol=1e-13):
+    """L = ||A||_2^2 in FP64; v0: complex128 GPU start vector (default:
+    SplitMix64 vector of ``seed``). Returns (L, iterations)."""
+    if v0 is not None:
+        v0 = _dev(v0, torch.complex128)
+    return capi.fm_power_iteration(A.handle, v0, seed, max_iters, tol, _stream())
+
+
 # ---------------------------------------------------------------- batching
 class Batch:
     """Many circulant / Toeplitz operators applied in one persistent launch.

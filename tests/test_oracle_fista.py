@@ -194,3 +194,31 @@ def test_power_iteration_closed_forms(kind):
     assert L <= expect * (1 + 1e-12)
     tol = 1e-12 if kind in ("fourier", "hadamard") else 1e-9
     assert abs(L - expect) <= tol * expect
+
+
+def test_splitmix64_reference_values():
+    expect = [int(r[0], 16) for r in golden_rows("splitmix64.txt")]
+    assert fista.splitmix64_outputs(0, 3) == expect
+    v = fista.splitmix64_start(3, 0)
+    assert v.shape == (3,) and np.all(np.abs(v.real) <= 0.5) and np.all(np.abs(v.imag) <= 0.5)
+    assert v[0].real == (expect[0] >> 11) / 2**53 - 0.5
+
+
+def test_fista_op_matches_dense_form():
+    from oracle import structured
+
+    rng = np.random.default_rng(3)
+    c = crand(64)
+    rows = np.sort(rng.choice(64, 20, replace=False))
+    a = dense.product(dense.select_rows(64, rows), dense.circulant(c))
+    b = crand(2, 20)
+    L = fista.spectral_norm_sq(a)
+    lam = fista.lambda_rule(a, b, 0.1)
+    ap, ad = structured.select_circulant_fft64(c, rows)
+    assert np.allclose(fista.lambda_rule_op(ad, b, 0.1), lam)
+    x1, _ = fista.fista(a, b, lam, L, 30)
+    x2, _ = fista.fista_op(ap, ad, 64, b, lam, L, 30)
+    assert np.allclose(x1, x2, atol=1e-12)
+    L2, _ = fista.power_iteration_op(lambda v: ap(v[None])[0], lambda u: ad(u[None])[0],
+                                     crand(64), 5000, 1e-15)
+    assert abs(L2 - L) <= 1e-9 * L
