@@ -209,8 +209,13 @@ fm_status fm_batch_create(fm_batch* out, int32_t nops, const fm_op* ops, const i
  * (host arrays of nops entries). */
 fm_status fm_batch_apply(fm_batch b, fm_dir dir, const void* const* x, const int64_t* ldx,
                          void* const* y, const int64_t* ldy, void* stream);
-/* FISTA for every operator of the batch (opts shared); stats: host array with
- * one entry per column of every operator, in batch order. */
+/* FISTA / ISTA for every column of every operator of the batch (opts shared;
+ * b[i] is m_i x ncols[i], x[i] is n_i x ncols[i]). With opts->L <= 0 each
+ * operator uses max_k |DFT_L(g)_k|^2 of its cyclic embedding, an upper bound
+ * of its ||A||_2^2. Columns meeting the stopping rule are frozen and their work
+ * is skipped from then on. stats: host array with one entry per column of
+ * every operator, in batch order (may be NULL). Synchronises the stream once at
+ * the end. */
 fm_status fm_batch_fista(fm_batch b, const void* const* bvec, const int64_t* ldb, void* const* x,
                          const int64_t* ldx, const fm_fista_opts* opts, fm_fista_stat* stats,
                          void* stream);

@@ -1,0 +1,88 @@
+// Internals of the batched path shared by the batched apply and the batched
+// solver.
+#pragma once
+
+#include <vector>
+
+#include "runtime.h"
+
+namespace fm {
+
+constexpr int kLog1 = 12;  // contiguous factor of the four-step split
+constexpr size_t kRegionBytes = size_t(48) << 20;  // intermediates of one chunk
+
+enum ItemKind : int { IT_SINGLE = 0, IT_FS1 = 1, IT_FS2 = 2, IT_FS3 = 3 };
+
+struct Item {
+  int32_t kind_log;  // kind | (log2 of the transform length << 8)
+  int32_t op;
+  int32_t col;  // SINGLE: first column; FS*: four-step column index
+  int32_t sub;  // SINGLE: columns in this item; FS1/FS3: inner tile; FS2: row
+};
+
+struct OpDev {
+  const c64* spec;  // spectrum in the order of the operator's split, 1/L folded in
+  int32_t m, n;
+  int32_t logL;
+  int32_t ncols;
+  int64_t col_base;  // index of the operator's first column among all columns of the batch
+};
+
+struct FsCol {
+  int32_t op, col;
+  int64_t woff;  // element offset of the column's slot in the intermediate pool
+};
+
+struct Ptrs {
+  const c64* x;
+  c64* y;
+  int64_t ldx, ldy;
+};
+
+struct BArgs {
+  const Item* items;  // this stage's items
+  const OpDev* ops;
+  const FsCol* cols;
+  const Ptrs* ptrs;
+  c64* wpool;
+  const c64* tw;
+  int32_t adj;
+  const int* active;  // per batch column; NULL: every column is active
+};
+
+
+}  // namespace fm
+
+struct fm_batch_s {
+  uint32_t magic = 0x464d4254u;
+  int device = 0;
+  std::vector<fm_op> ops;
+  std::vector<int64_t> ncols;
+  std::vector<int64_t> col_base;  // first batch column of each operator
+  int64_t total_cols = 0;
+  fm::DevBuf d_items, d_ops, d_cols, d_ptrs, d_wpool;
+  std::vector<int64_t> stage_off;  // stage s: items [stage_off[s], stage_off[s+1])
+  // pointer tables: kTables device copies, each with a pinned staging buffer,
+  // the event after its last upload and the pointers it holds
+  static constexpr int kTables = 6;
+  fm::Ptrs* staging = nullptr;
+  hipEvent_t uploaded[kTables] = {};
+  std::vector<fm::Ptrs> held[kTables];
+  uint64_t used[kTables] = {};
+  uint64_t clock = 0;
+  std::vector<fm::Ptrs> cur;
+  // solver state, allocated on the first fm_batch_fista call
+  fm::DevBuf s_y, s_r, s_g, s_lam, s_L, s_active, s_status, s_iters, s_partial, s_cols, s_utiles, s_stiles,
+      s_user;
+  std::vector<int64_t> s_yoff, s_roff;  // per operator: first element in the packed n- / m-sized buffers
+  int64_t s_nutiles = 0, s_nstiles = 0;
+  std::vector<double> s_bound;  // per operator: max |DFT_L(g)|^2 (empty until computed)
+};
+
+namespace fm {
+bool batch_alive(const fm_batch_s* b);
+// Uploads (or finds) the device pointer table for b->cur; returns its address.
+fm_status batch_pointer_table(fm_batch_s* b, hipStream_t s, const Ptrs** table);
+// Launches every stage of one direction; active: per batch column or NULL.
+fm_status batch_launch(fm_batch_s* b, bool adj, const Ptrs* table, const int* active, hipStream_t s);
+}  // namespace fm

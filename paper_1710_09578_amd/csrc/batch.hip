@@ -18,53 +18,13 @@
 #include <cstring>
 #include <unordered_set>
 
-#include "runtime.h"
+#include "batch.h"
 #include "xform.h"
 
 namespace fm {
 namespace {
 
 using namespace xf;
-
-constexpr int kLog1 = 12;  // contiguous factor of the four-step split
-constexpr size_t kRegionBytes = size_t(48) << 20;  // intermediates of one chunk
-
-enum ItemKind : int { IT_SINGLE = 0, IT_FS1 = 1, IT_FS2 = 2, IT_FS3 = 3 };
-
-struct Item {
-  int32_t kind_log;  // kind | (log2 of the transform length << 8)
-  int32_t op;
-  int32_t col;  // SINGLE: first column; FS*: four-step column index
-  int32_t sub;  // SINGLE: columns in this item; FS1/FS3: inner tile; FS2: row
-};
-
-struct OpDev {
-  const c64* spec;  // spectrum in the order of the operator's split, 1/L folded in
-  int32_t m, n;
-  int32_t logL;
-  int32_t ncols;
-};
-
-struct FsCol {
-  int32_t op, col;
-  int64_t woff;  // element offset of the column's slot in the intermediate pool
-};
-
-struct Ptrs {
-  const c64* x;
-  c64* y;
-  int64_t ldx, ldy;
-};
-
-struct BArgs {
-  const Item* items;  // this stage's items
-  const OpDev* ops;
-  const FsCol* cols;
-  const Ptrs* ptrs;
-  c64* wpool;
-  const c64* tw;
-  int32_t adj;
-};
 
 // A whole zero-padded convolution (length 2^lg <= 4096) of up to 4096/2^lg columns.
 __device__ __forceinline__ void run_single(const BArgs& a, const Item& it, int lg, c64* smem) {
@@ -149,10 +109,17 @@ __global__ __launch_bounds__(kWG) void stage_kernel(BArgs a) {
   const int kind = it.kind_log & 0xff;
   const int lg = it.kind_log >> 8;
   if (kind == IT_SINGLE) {
+    if (a.active) {  // skip the item when every one of its columns is frozen
+      const int64_t g0 = a.ops[it.op].col_base + it.col;
+      bool any = false;
+      for (int c = 0; c < it.sub; ++c) any |= a.active[g0 + c] != 0;
+      if (!any) return;
+    }
     run_single(a, it, lg, smem);
     return;
   }
   const FsCol fc = a.cols[it.col];
+  if (a.active && !a.active[a.ops[fc.op].col_base + fc.col]) return;
   if (kind == IT_FS2)
     run_row(a, it, fc, smem);
   else
@@ -164,34 +131,20 @@ __global__ __launch_bounds__(kWG) void stage_kernel(BArgs a) {
 
 using namespace fm;
 
-struct fm_batch_s {
-  uint32_t magic = 0x464d4254u;
-  int device = 0;
-  std::vector<fm_op> ops;
-  std::vector<int64_t> ncols;
-  DevBuf d_items, d_ops, d_cols, d_ptrs, d_wpool;
-  std::vector<int64_t> stage_off;  // stage s: items [stage_off[s], stage_off[s+1])
-  // pointer tables: kTables device copies, each with a pinned staging buffer,
-  // the event after its last upload and the pointers it holds
-  static constexpr int kTables = 4;
-  Ptrs* staging = nullptr;
-  hipEvent_t uploaded[kTables] = {};
-  std::vector<Ptrs> held[kTables];
-  uint64_t used[kTables] = {};
-  uint64_t clock = 0;
-  std::vector<Ptrs> cur;
-};
-
 namespace {
 std::mutex g_batch_mu;
 std::unordered_set<const fm_batch_s*>& live_batches() {
   static std::unordered_set<const fm_batch_s*> s;
   return s;
 }
-bool batch_alive(const fm_batch_s* b) {
+}  // namespace
+
+bool fm::batch_alive(const fm_batch_s* b) {
   std::lock_guard<std::mutex> lock(g_batch_mu);
   return live_batches().count(b) != 0;
 }
+
+namespace {
 void destroy_batch(fm_batch_s* b) {
   {
     std::lock_guard<std::mutex> lock(g_batch_mu);
@@ -205,6 +158,58 @@ void destroy_batch(fm_batch_s* b) {
   delete b;
 }
 }  // namespace
+
+fm_status fm::batch_pointer_table(fm_batch_s* b, hipStream_t s, const Ptrs** table) {
+  const int nops = int(b->ops.size());
+  int slot = -1;
+  for (int k = 0; k < fm_batch_s::kTables && slot < 0; ++k) {
+    if (b->held[k].size() != b->cur.size()) continue;
+    bool same = true;
+    for (int i = 0; same && i < nops; ++i)
+      same = b->held[k][i].x == b->cur[i].x && b->held[k][i].y == b->cur[i].y &&
+             b->held[k][i].ldx == b->cur[i].ldx && b->held[k][i].ldy == b->cur[i].ldy;
+    if (same) slot = k;
+  }
+  Ptrs* dptrs = static_cast<Ptrs*>(b->d_ptrs.p);
+  if (slot < 0) {
+    // refresh the least recently used copy; the upload is ordered on the
+    // stream after every earlier launch that read it
+    slot = 0;
+    for (int k = 1; k < fm_batch_s::kTables; ++k)
+      if (b->used[k] < b->used[slot]) slot = k;
+    FM_HIP(hipEventSynchronize(b->uploaded[slot]));  // its staging buffer may still be read
+    Ptrs* stg = b->staging + size_t(slot) * nops;
+    std::memcpy(stg, b->cur.data(), size_t(nops) * sizeof(Ptrs));
+    FM_HIP(hipMemcpyAsync(dptrs + size_t(slot) * nops, stg, size_t(nops) * sizeof(Ptrs), hipMemcpyHostToDevice, s));
+    FM_HIP(hipEventRecord(b->uploaded[slot], s));
+    b->held[slot] = b->cur;
+  }
+  b->used[slot] = ++b->clock;
+  *table = dptrs + size_t(slot) * nops;
+  return FM_OK;
+}
+
+fm_status fm::batch_launch(fm_batch_s* b, bool adj, const Ptrs* table, const int* active, hipStream_t s) {
+  const void* tw = twiddle_table(Elem::C64, 20);
+  FM_CHECK_ARG(tw != nullptr, FM_E_DEVICE, "twiddle table unavailable");
+  BArgs a{};
+  a.ops = static_cast<const OpDev*>(b->d_ops.p);
+  a.cols = static_cast<const FsCol*>(b->d_cols.p);
+  a.ptrs = table;
+  a.wpool = static_cast<c64*>(b->d_wpool.p);
+  a.tw = static_cast<const c64*>(tw);
+  a.adj = adj;
+  a.active = active;
+  const Item* items = static_cast<const Item*>(b->d_items.p);
+  for (size_t st = 0; st + 1 < b->stage_off.size(); ++st) {
+    const int64_t n = b->stage_off[st + 1] - b->stage_off[st];
+    if (n == 0) continue;
+    a.items = items + b->stage_off[st];
+    hipLaunchKernelGGL(stage_kernel, dim3(unsigned(n)), dim3(kWG), job_lds_bytes<float>(), s, a);
+    FM_LAUNCHED();
+  }
+  return FM_OK;
+}
 
 extern "C" {
 
@@ -238,7 +243,10 @@ fm_status fm_batch_create(fm_batch* out, int32_t nops, const fm_op* ops, const i
     b->ops.push_back(o);
     b->ncols.push_back(ncols[i]);
     const int logL = ilog2(o->L);
-    hops[i] = OpDev{static_cast<const c64*>(o->p32.p), int32_t(o->m), int32_t(o->n), logL, int32_t(ncols[i])};
+    hops[i] = OpDev{static_cast<const c64*>(o->p32.p), int32_t(o->m), int32_t(o->n), logL, int32_t(ncols[i]),
+                    b->total_cols};
+    b->col_base.push_back(b->total_cols);
+    b->total_cols += ncols[i];
     if (logL <= kLog1) {
       const int B = 1 << (kLog1 - logL);  // transforms per work-group
       for (int64_t c0 = 0; c0 < ncols[i]; c0 += B) {
@@ -361,48 +369,9 @@ fm_status fm_batch_apply(fm_batch b, fm_dir dir, const void* const* x, const int
   FM_HIP(hipGetDevice(&dev));
   FM_CHECK_ARG(dev == b->device, FM_E_DEVICE, "batch lives on device %d, current is %d", b->device, dev);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  const void* tw = twiddle_table(Elem::C64, 20);
-  FM_CHECK_ARG(tw != nullptr, FM_E_DEVICE, "twiddle table unavailable");
-  // find (or refresh the least recently used) device copy of this pointer table;
-  // an upload is ordered on the stream after every earlier launch that read it
-  int slot = -1;
-  for (int k = 0; k < fm_batch_s::kTables && slot < 0; ++k) {
-    if (b->held[k].size() != b->cur.size()) continue;
-    bool same = true;
-    for (int i = 0; same && i < nops; ++i)
-      same = b->held[k][i].x == b->cur[i].x && b->held[k][i].y == b->cur[i].y &&
-             b->held[k][i].ldx == b->cur[i].ldx && b->held[k][i].ldy == b->cur[i].ldy;
-    if (same) slot = k;
-  }
-  Ptrs* dptrs = static_cast<Ptrs*>(b->d_ptrs.p);
-  if (slot < 0) {
-    slot = 0;
-    for (int k = 1; k < fm_batch_s::kTables; ++k)
-      if (b->used[k] < b->used[slot]) slot = k;
-    FM_HIP(hipEventSynchronize(b->uploaded[slot]));  // its staging buffer may still be read
-    Ptrs* stg = b->staging + size_t(slot) * nops;
-    std::memcpy(stg, b->cur.data(), size_t(nops) * sizeof(Ptrs));
-    FM_HIP(hipMemcpyAsync(dptrs + size_t(slot) * nops, stg, size_t(nops) * sizeof(Ptrs), hipMemcpyHostToDevice, s));
-    FM_HIP(hipEventRecord(b->uploaded[slot], s));
-    b->held[slot] = b->cur;
-  }
-  b->used[slot] = ++b->clock;
-  BArgs a{};
-  a.ops = static_cast<const OpDev*>(b->d_ops.p);
-  a.cols = static_cast<const FsCol*>(b->d_cols.p);
-  a.ptrs = dptrs + size_t(slot) * nops;
-  a.wpool = static_cast<c64*>(b->d_wpool.p);
-  a.tw = static_cast<const c64*>(tw);
-  a.adj = adj;
-  const Item* items = static_cast<const Item*>(b->d_items.p);
-  for (size_t st = 0; st + 1 < b->stage_off.size(); ++st) {
-    const int64_t n = b->stage_off[st + 1] - b->stage_off[st];
-    if (n == 0) continue;
-    a.items = items + b->stage_off[st];
-    hipLaunchKernelGGL(stage_kernel, dim3(unsigned(n)), dim3(kWG), job_lds_bytes<float>(), s, a);
-    FM_LAUNCHED();
-  }
-  return FM_OK;
+  const Ptrs* table = nullptr;
+  FM_TRY(batch_pointer_table(b, s, &table));
+  return batch_launch(b, adj, table, nullptr, s);
 }
 
 fm_status fm_batch_release(fm_batch b) {

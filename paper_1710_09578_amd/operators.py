@@ -278,3 +278,22 @@ class Batch:
         capi.fm_batch_apply(self._h, capi.FM_ADJ if adjoint else capi.FM_FWD, xs, ldx, outs, ldy,
                             _stream())
         return outs
+
+    def fista(self, bs, iters=100, momentum=True, lam=None, lam_rel=None, L=None, stop_tol=0.0, x0s=None):
+        """FISTA for every column of every operator; bs[i] has shape
+        (ncols[i], m_i). Returns (xs, stats) with stats per batch column."""
+        xs = []
+        for op, b, nc in zip(self.ops, bs, self.ncols):
+            xs.append(torch.empty((nc, op.shape[1]), dtype=op.dtype, device=b.device))
+        if x0s is not None:
+            for x, x0 in zip(xs, x0s):
+                x.copy_(x0)
+        o = fista_options(iters, momentum, lam, lam_rel, L, stop_tol, x0s is not None)
+        total = sum(self.ncols)
+        stats = (capi.fm_fista_stat * max(total, 1))()
+        ldb = [max(b.stride(0), 1) if b.dim() == 2 else b.shape[-1] for b in bs]
+        ldx = [op.shape[1] for op in self.ops]
+        capi.fm_batch_fista(self._h, bs, ldb, xs, ldx, o, stats, _stream())
+        st = [{"iters": stats[j].iters_done, "status": stats[j].status, "L": stats[j].L_used,
+               "lam": stats[j].lambda_used} for j in range(total)]
+        return xs, st

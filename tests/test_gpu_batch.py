@@ -108,3 +108,69 @@ def test_batch_toeplitz_workload_sample(gpu):
         assert rel_err(y, structured.toeplitz_apply_fft64(d["col"], d["row"], d["x"])) <= TOL["c64"]
         z = to_host(zs[i])
         assert rel_err(z, structured.toeplitz_apply_fft64(d["col"], d["row"], y, True)) <= TOL["c64"]
+
+
+def fista_batch_problem(gpu, sizes, ncols, seed):
+    rng = np.random.default_rng(seed)
+    ops, data = [], []
+    for n, nc in zip(sizes, ncols):
+        col, row = crandn(rng, n), crandn(rng, n)
+        xt = np.zeros((nc, n), np.complex128)
+        for j in range(nc):
+            k = max(n // 256, 1)
+            xt[j, rng.choice(n, k, replace=False)] = rng.standard_normal(k)
+        b = (structured.toeplitz_apply_fft64(col, row, xt) + 1e-3 * crandn(rng, (nc, n), np.complex128))
+        ops.append(gpu.Toeplitz(to_dev(col), to_dev(row)))
+        data.append((col, row, b.astype(np.complex64)))
+    return ops, data
+
+
+def test_batch_fista_equals_plain_and_oracle(gpu):
+    sizes = [300, 1000, 3000, 5000, 20000]
+    ncols = [3, 2, 0, 2, 2]
+    ops, data = fista_batch_problem(gpu, sizes, ncols, seed=11)
+    batch = gpu.Batch(ops, ncols)
+    bs = [to_dev(d[2]) for d in data]
+    xs, st = batch.fista(bs, iters=30, lam_rel=0.05)
+    gi = 0
+    for i, (op, (col, row, b)) in enumerate(zip(ops, data)):
+        if ncols[i] == 0:
+            continue
+        L = st[gi]["L"]
+        lam = np.array([st[gi + j]["lam"] for j in range(ncols[i])])
+        # the bound max |DFT(g)|^2 is at least ||T||^2 (here compared to the
+        # spectrum of the embedding computed by the oracle)
+        m = col.size
+        Lemb = 1 << int(np.ceil(np.log2(m + row.size - 1)))
+        g = np.zeros(Lemb, np.complex128)
+        g[:m] = col
+        g[Lemb - row.size + 1:] = row[1:][::-1]
+        assert abs(L - np.max(np.abs(np.fft.fft(g))) ** 2) <= 1e-12 * L
+        x_plain, _ = gpu.fista(op, bs[i], iters=30, lam_rel=0.05, L=L)
+        assert np.array_equal(to_host(xs[i]), to_host(x_plain)), f"op {i}: batched solve differs from plain"
+        x_ref, _ = structured.toeplitz_fista_fft64(col, row, b, lam, L, 30)
+        assert rel_err(to_host(xs[i]), x_ref) <= TOL["c64"]
+        gi += ncols[i]
+
+
+def test_batch_fista_stopping(gpu):
+    sizes = [500, 2500, 9000]
+    ncols = [4, 3, 2]
+    ops, data = fista_batch_problem(gpu, sizes, ncols, seed=12)
+    batch = gpu.Batch(ops, ncols)
+    bs = [to_dev(d[2]) for d in data]
+    xs, st = batch.fista(bs, iters=150, lam_rel=0.05, stop_tol=1e-4)
+    counts = [s["iters"] for s in st]
+    assert min(counts) < 150
+    gi = 0
+    for i, (col, row, b) in enumerate(data):
+        L = st[gi]["L"]
+        lam = np.array([st[gi + j]["lam"] for j in range(ncols[i])])
+        x_ref, done = structured.toeplitz_fista_fft64(col, row, b, lam, L, 150, stop_tol=1e-4)
+        got = np.array(counts[gi:gi + ncols[i]])
+        assert np.all(np.abs(got - done) <= 1)
+        # each column equals the oracle run stopped at the GPU's own count
+        for j in range(ncols[i]):
+            xj, _ = structured.toeplitz_fista_fft64(col, row, b[j:j + 1], lam[j], L, int(got[j]))
+            assert rel_err(to_host(xs[i])[j:j + 1], xj) <= TOL["c64"]
+        gi += ncols[i]
