@@ -28,6 +28,32 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+STAGE_SOURCES = ("batch.hip", "batch.h", "xform.h", "kernels.h", "common.h")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "stage_kernel_toeplitz512_fwd_adj.md")
+
+
+def stage_source_hash():
+    """sha256 (16 hex digits) over the sources of the batched stage kernel."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in STAGE_SOURCES:
+        with open(os.path.join(ROOT, "paper_1710_09578_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per direction from the committed FETCH_SIZE / WRITE_SIZE
+    summary, or None when the kernel sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_PROFILE) as fh:
+            kv = dict(line.split(": ", 1) for line in fh.read().splitlines() if ": " in line)
+    except OSError:
+        return None
+    if kv.get("source_hash", "").strip() != stage_source_hash():
+        return None
+    return int(kv["traffic_bytes_per_direction"])
 
 
 def log(msg):
@@ -100,7 +126,7 @@ def plain_step_factory(w):
 
 
 def batched_step_factory(w):
-    """The whole batch in one persistent launch per direction."""
+    """The whole batch as one pipelined sequence of stage launches per direction."""
     import paper_1710_09578_amd as fm
     from paper_1710_09578_amd import capi
 
@@ -288,7 +314,7 @@ def main():
     achieved = per_launch / (launch_ms * 1e-3) / 1e9
     log(f"one direction (all its stage launches): {launch_ms:.3f} ms avg, {achieved:.1f} GB/s")
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
             "kernel": "stage_kernel: all stage launches of one direction (fm_batch_apply)",
             "alg_bytes_per_launch": int(per_launch), "launch_ms": round(launch_ms, 4)}
     fres = None if args.no_fista else fista_solves(w)

@@ -202,8 +202,18 @@ fm_status fm_power_iteration(fm_op a, const void* v0, uint64_t seed, int32_t max
                              double* L_out, int32_t* iters_out, void* stream);
 
 /* ------------------------------------------------------------------ batching
- * Many independent operators applied in one persistent launch: the library
- * builds a work queue over (operator, column tile) items once, at creation. */
+ * Many independent Circulant / Toeplitz operators of uneven sizes applied
+ * together (the batch-of-operators extension of the per-column evaluation of
+ * Sec. 2). At creation the library cuts every transform into 4096-value work
+ * items and lays them out in a software-pipelined sequence of kernel launches
+ * ("stages"): operators whose embedding length is <= 4096 take one item per
+ * column; longer ones take three passes of a four-step split, chunked so
+ * that the intermediate buffers of three chunks in flight stay in a fixed
+ * device pool. One direction is a few stage launches on `stream`, with no
+ * host synchronisation and no waits between workgroups. ops: composite-free
+ * Circulant or Toeplitz operators of one complex dtype on the current device;
+ * ncols[i] >= 1 columns of operator i. The batch holds references to its
+ * operators until fm_batch_release. */
 fm_status fm_batch_create(fm_batch* out, int32_t nops, const fm_op* ops, const int64_t* ncols);
 /* x[i], y[i]: device blocks of operator i with leading dimensions ldx[i], ldy[i]
  * (host arrays of nops entries). */

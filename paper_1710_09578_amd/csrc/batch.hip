@@ -44,7 +44,7 @@ __device__ __forceinline__ void run_single(const BArgs& a, const Item& it, int l
   jb.sbstride = 0;
   jb.q0 = 0;
   const Mode md{FFT_CONV, a.adj, 0, 0, 0};
-  run_job<float, false, false, false>(jb, md, lg, smem, a.tw);
+  run_job<float, false>(jb, md, lg, smem, a.tw);
 }
 
 // Pass 1 (first) or pass 3 of the four-step convolution: strided transforms of
@@ -71,14 +71,14 @@ __device__ __forceinline__ void run_strided(const BArgs& a, const Item& it, cons
     jb.in_limit = a.adj ? op.m : op.n;
     jb.out_limit = L;
     const Mode md{FFT_FWD, 0, op.logL, 0, 0};
-    run_job<float, true, false, false>(jb, md, lg, smem, a.tw);
+    run_job<float, true>(jb, md, lg, smem, a.tw);
   } else {
     jb.x = w + i0;
     jb.y = pt.y + int64_t(fc.col) * pt.ldy + i0;
     jb.in_limit = L;
     jb.out_limit = a.adj ? op.n : op.m;
     const Mode md{FFT_INV, 0, 0, 0, 0};
-    run_job<float, true, false, false>(jb, md, lg, smem, a.tw);
+    run_job<float, true>(jb, md, lg, smem, a.tw);
   }
 }
 
@@ -99,7 +99,7 @@ __device__ __forceinline__ void run_row(const BArgs& a, const Item& it, const Fs
   jb.sbstride = 0;
   jb.q0 = it.sub;
   const Mode md{FFT_CONV, a.adj, op.logL, 1, 0};
-  run_job<float, false, false, false>(jb, md, kLog1, smem, a.tw);
+  run_job<float, false>(jb, md, kLog1, smem, a.tw);
 }
 
 __global__ __launch_bounds__(kWG) void stage_kernel(BArgs a) {

@@ -87,7 +87,7 @@ __global__ __launch_bounds__(kWG) void fft_kernel(KArgs a) {
     }
   }
   const Mode md{a.mode, a.spec_conj, a.tw_log, a.tw_inv, a.accumulate};
-  run_job<R, STRIDED, false, false>(jb, md, a.logn, lds, reinterpret_cast<const Cx<R>*>(a.tw));
+  run_job<R, STRIDED>(jb, md, a.logn, lds, reinterpret_cast<const Cx<R>*>(a.tw));
 }
 
 template <typename R>

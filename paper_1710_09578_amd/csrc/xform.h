@@ -1,5 +1,5 @@
 // Device-side FFT engine shared by the per-operator kernels and the batched
-// work-queue kernel (the fast transform behind the DFT of eq. (1) and the
+// stage kernel (the fast transform behind the DFT of eq. (1) and the
 // cyclic convolution of eq. (5)).
 //
 // A work-group of 256 threads always holds 4096 complex values: 16 per thread
@@ -198,42 +198,6 @@ __device__ __forceinline__ void forward_tiny(Cx<R>* v, int logn) {
   }
 }
 
-// ---------------------------------------------------------------- global access
-// Device-scope loads and stores (coherent across the L2 slices of the chip),
-// for intermediates handed between work-groups inside one launch.
-template <typename R>
-__device__ __forceinline__ Cx<R> load_coherent(const Cx<R>* p) {
-  unsigned long long* q = reinterpret_cast<unsigned long long*>(const_cast<Cx<R>*>(p));
-  if constexpr (sizeof(R) == 4) {
-    unsigned long long u = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    Cx<R> v;
-    __builtin_memcpy(&v, &u, 8);
-    return v;
-  } else {
-    unsigned long long u0 = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    unsigned long long u1 = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    Cx<R> v;
-    __builtin_memcpy(&v.x, &u0, 8);
-    __builtin_memcpy(&v.y, &u1, 8);
-    return v;
-  }
-}
-template <typename R>
-__device__ __forceinline__ void store_coherent(Cx<R>* p, Cx<R> v) {
-  unsigned long long* q = reinterpret_cast<unsigned long long*>(p);
-  if constexpr (sizeof(R) == 4) {
-    unsigned long long u;
-    __builtin_memcpy(&u, &v, 8);
-    __hip_atomic_store(q, u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  } else {
-    unsigned long long u0, u1;
-    __builtin_memcpy(&u0, &v.x, 8);
-    __builtin_memcpy(&u1, &v.y, 8);
-    __hip_atomic_store(q, u0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(q + 1, u1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-}
-
 // ---------------------------------------------------------------- one work-group's job
 // A work-group's 4096 values are 4096/N transforms. Transform b (0 <= b <
 // 4096/N) starts at base + b*bstride (contiguous vectors) or at base + b
@@ -259,7 +223,7 @@ struct Mode {
 };
 
 // Loads, transforms and stores one job. Every thread of the work-group calls it.
-template <typename R, bool STRIDED, bool COH_IN, bool COH_OUT>
+template <typename R, bool STRIDED>
 __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int logn, Cx<R>* lds,
                                         const Cx<R>* __restrict__ tw) {
   const int tid = threadIdx.x;
@@ -278,10 +242,7 @@ __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int lo
     for (int k = 0; k < kE; ++k) {
       const int p = t + T * k;
       const bool in = valid && p * inner + ii < jb.in_limit;
-      if constexpr (COH_IN)
-        v[k] = in ? load_coherent(X + p * inner) : Cx<R>{R(0), R(0)};
-      else
-        v[k] = in ? X[p * inner] : Cx<R>{R(0), R(0)};
+      v[k] = in ? X[p * inner] : Cx<R>{R(0), R(0)};
     }
     Cx<R>* my = lds + b * ((1 << logn) + (1 << (logn - 4)));
     if (md.mode == FFT_INV) conj_all(v);
@@ -317,9 +278,7 @@ __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int lo
         const int p = t + T * k;
         if (p * inner + ii < jb.out_limit) {
           Cx<R>* dst = Y + p * inner;
-          if constexpr (COH_OUT) {
-            store_coherent(dst, v[k]);
-          } else if (md.accumulate) {
+          if (md.accumulate) {
             const Cx<R> old = *dst;
             *dst = cadd(old, v[k]);
           } else {
@@ -342,10 +301,7 @@ __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int lo
     const int ii = STRIDED ? jb.i0 + b : 0;
     const bool in = b < jb.nvalid && r * inner + ii < jb.in_limit;
     const Cx<R>* src = STRIDED ? jb.x + b + r * inner : jb.x + b * jb.xbstride + r;
-    if constexpr (COH_IN)
-      v[k] = in ? load_coherent(src) : Cx<R>{R(0), R(0)};
-    else
-      v[k] = in ? *src : Cx<R>{R(0), R(0)};
+    v[k] = in ? *src : Cx<R>{R(0), R(0)};
   }
   if (md.mode == FFT_INV) conj_all(v);
   forward_tiny(v, logn);
@@ -382,9 +338,7 @@ __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int lo
     const int ii = STRIDED ? jb.i0 + b : 0;
     if (b < jb.nvalid && r * inner + ii < jb.out_limit) {
       Cx<R>* dst = STRIDED ? jb.y + b + r * inner : jb.y + b * jb.ybstride + r;
-      if constexpr (COH_OUT) {
-        store_coherent(dst, v[k]);
-      } else if (md.accumulate) {
+      if (md.accumulate) {
         const Cx<R> old = *dst;
         *dst = cadd(old, v[k]);
       } else {

@@ -243,7 +243,7 @@ def power_iteration(A: Operator, v0: torch.Tensor | None = None, seed=0, max_ite
 
 # ---------------------------------------------------------------- batching
 class Batch:
-    """Many circulant / Toeplitz operators applied in one persistent launch.
+    """Many circulant / Toeplitz operators applied together in pipelined stage launches.
 
     ``ncols[i]`` is the number of columns operator i is applied to; blocks are
     passed per call as lists of tensors of shape (ncols[i], rows).

@@ -1,4 +1,4 @@
-"""GPU parity of the batched persistent launch (fm_batch_apply).
+"""GPU parity of the batched stage launches (fm_batch_apply, fm_batch_fista).
 
 The batched launch runs the same per-transform code, splits, spectra and
 twiddles as one fm_apply per operator, so its results must equal the plain
