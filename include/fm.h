@@ -232,14 +232,67 @@ fm_status fm_batch_fista(fm_batch b, const void* const* bvec, const int64_t* ldb
 fm_status fm_batch_release(fm_batch b);
 
 /* ------------------------------------------------------------------ differentiation
- * Gradient of a real loss with respect to the generator c of C(c) (n x n):
- *   use = FM_FWD, y = C(c) in:    grad_c[k] += sum_j sum_i g_j[i] conj(in_j[(i-k) mod n])
- *   use = FM_ADJ, w = C(c)^H in:  grad_c[k] += sum_j sum_i in_j[i] conj(g_j[(i-k) mod n])
- * i.e. the circular cross-correlations (PyTorch's convention: grad = dL/d conj(c)),
- * summed over the ncols columns. `accumulate` = 0 overwrites grad_c. Complex dtypes. */
+ * Building blocks of reverse-mode differentiation through operator
+ * applications and unrolled FISTA (an extension; the paper has no autodiff).
+ * Gradients follow PyTorch's convention for complex tensors: for a real loss
+ * and an upstream gradient G of an output s, the gradient of an input z is
+ * G conj(ds/dz) + conj(G) ds/dz*. The gradient of x for y = A x is A^H G, so
+ * fm_apply in the other direction serves it.
+ *
+ * Generator of a circulant C(c) (n x n, c its first column; the cyclic
+ * convolution y = c (*) x of eq. (5)), summed over the ncols columns:
+ *   use = FM_FWD, y = C(c) in:    grad_c[k] (+)= sum_j sum_i g_j[i] conj(in_j[(i-k) mod n])
+ *   use = FM_ADJ, w = C(c)^H in:  grad_c[k] (+)= sum_j sum_i in_j[i] conj(g_j[(i-k) mod n])
+ * (circular cross-correlations, computed through length-n DFTs and summed over
+ * the columns in the frequency domain). in, g: DEVICE blocks of ncols columns
+ * of n entries (leading dimensions ld_in, ld_g >= n); grad_c: DEVICE vector of
+ * n entries, overwritten (accumulate = 0) or added to; it must not overlap the
+ * inputs. n: power of two <= 2^20; complex dtypes. ncols = 0 leaves grad_c
+ * unchanged (accumulate) or zeroes it. Allocates its own device workspace and
+ * synchronises the stream before returning. */
 fm_status fm_circulant_grad_generator(int64_t n, int64_t ncols, fm_dir use, const void* in,
                                       int64_t ld_in, const void* g, int64_t ld_g, void* grad_c,
                                       int32_t accumulate, fm_dtype dt, void* stream);
+
+/* One proximal-gradient step of the solver of eq. (8) on DEVICE blocks of
+ * ncols columns of n entries (all with leading dimension ld), given the
+ * gradient g = A^H (A y - b):
+ *   z = y - g / L,  x_new = soft(z, lam[j] / L),  y_new = x_new + beta (x_new - x_old)
+ * soft(z, s) = z (|z| - s)/|z| for |z| > s, else 0 (complex modulus). lam:
+ * DEVICE array of ncols doubles. z_out (may be NULL) receives z. x_new may be
+ * x_old and y_new may be y (elementwise in place); x_new, y_new and z_out must
+ * not overlap each other. The arithmetic is that of fm_fista's update, so a
+ * step recomputed from the same inputs gives the same bits. Stream-ordered. */
+fm_status fm_fista_step(int64_t n, int64_t ncols, const void* y, const void* g, const void* x_old,
+                        void* x_new, void* y_new, void* z_out, int64_t ld, const double* lam,
+                        double L, double beta, fm_dtype dt, void* stream);
+
+/* Vector-Jacobian product of fm_fista_step. Given z of the forward step and
+ * the upstream gradients gx_new, gy_new of x_new, y_new, with
+ * xt = gx_new + (1 + beta) gy_new and s = lam[j]/L:
+ *   gz     = xt (1 - s/(2|z|)) + conj(xt) s z^2 / (2 |z|^3)   if |z| > s, else 0
+ *   gg     = -gz / L               (gradient of g; may be NULL)
+ *   gx_old = -beta gy_new          (gradient of x_old; may be NULL)
+ * and the gradient of y is gz (z = y - g/L). gz may be gx_new or gy_new,
+ * gg and gx_old may be gx_new or gy_new (elementwise in place); other overlaps
+ * are rejected. Same layout rules as fm_fista_step. Stream-ordered. */
+fm_status fm_fista_step_vjp(int64_t n, int64_t ncols, const void* z, const void* gx_new,
+                            const void* gy_new, void* gz, void* gg, void* gx_old, int64_t ld,
+                            const double* lam, double L, double beta, fm_dtype dt, void* stream);
+
+/* out = alpha x + beta y on DEVICE blocks (real alpha, beta; complex dtypes).
+ * out may be x or y with the same leading dimension. Stream-ordered. */
+fm_status fm_axpby(int64_t n, int64_t ncols, double alpha, const void* x, int64_t ldx, double beta,
+                   const void* y, int64_t ldy, void* out, int64_t ldo, fm_dtype dt, void* stream);
+
+/* Upper bound of ||A||_2^2 from the operator's structure, in FP64: n for
+ * Fourier and Hadamard, 1 for a row selection, max |d|^2 for Diag, the
+ * squared Frobenius norm for a dense matrix, max_k |DFT_L(g)_k|^2 for
+ * Circulant / Toeplitz / multilevel Toeplitz (g the cyclic embedding), the
+ * product over the terms of a Product or Kronecker product, (sum of square
+ * roots)^2 for a Sum, the maximum over the blocks of BlkDiag. A valid FISTA
+ * step constant. Synchronises the stream. */
+fm_status fm_op_norm_bound(fm_op a, double* bound, void* stream);
 
 /* ------------------------------------------------------------------ misc */
 /* Thread-local description of the last error; valid until the next fm_* call

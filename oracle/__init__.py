@@ -27,4 +27,4 @@ Parity status of every function is stated in its docstring; functions without
 an independent pin say "parity unpinned".
 """
 
-from . import dense, fista, structured  # noqa: F401
+from . import dense, fista, grad, structured  # noqa: F401

@@ -2,9 +2,11 @@
 
 The compute path is the HIP library ``libfm.so`` (C ABI in ``include/fm.h``);
 ``capi`` binds it entry point by entry point, ``operators`` offers the
-paper's notation on top (``Circulant(c) @ x``, ``A.H``, ``Product``, ...).
+paper's notation on top (``Circulant(c) @ x``, ``A.H``, ``Product``, ...),
+``autograd`` the differentiable applications and unrolled FISTA.
 """
 
+from . import autograd  # noqa: F401
 from .capi import FmError, load  # noqa: F401
 from .operators import (  # noqa: F401
     Batch,

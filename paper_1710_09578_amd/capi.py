@@ -99,6 +99,10 @@ SIGNATURES = {
                             C.POINTER(fm_fista_opts), C.POINTER(fm_fista_stat), P]),
     "fm_batch_release": (ST, [P]),
     "fm_circulant_grad_generator": (ST, [I64, I64, C.c_int, P, I64, P, I64, P, I32, C.c_int, P]),
+    "fm_fista_step": (ST, [I64, I64, P, P, P, P, P, P, I64, P, C.c_double, C.c_double, C.c_int, P]),
+    "fm_fista_step_vjp": (ST, [I64, I64, P, P, P, P, P, P, I64, P, C.c_double, C.c_double, C.c_int, P]),
+    "fm_axpby": (ST, [I64, I64, C.c_double, P, I64, C.c_double, P, I64, P, I64, C.c_int, P]),
+    "fm_op_norm_bound": (ST, [P, C.POINTER(C.c_double), P]),
     "fm_last_error": (C.c_char_p, []),
     "fm_version": (C.c_char_p, []),
 }
@@ -285,3 +289,23 @@ def fm_batch_release(b):
 def fm_circulant_grad_generator(n, ncols, use, inp, ld_in, g, ld_g, grad_c, accumulate, dt, stream):
     _call("fm_circulant_grad_generator", n, ncols, use, _ptr(inp), ld_in, _ptr(g), ld_g, _ptr(grad_c),
           accumulate, dt, _ptr(stream))
+
+
+def fm_fista_step(n, ncols, y, g, x_old, x_new, y_new, z_out, ld, lam, L, beta, dt, stream):
+    _call("fm_fista_step", n, ncols, _ptr(y), _ptr(g), _ptr(x_old), _ptr(x_new), _ptr(y_new), _ptr(z_out),
+          ld, _ptr(lam), L, beta, dt, _ptr(stream))
+
+
+def fm_fista_step_vjp(n, ncols, z, gx_new, gy_new, gz, gg, gx_old, ld, lam, L, beta, dt, stream):
+    _call("fm_fista_step_vjp", n, ncols, _ptr(z), _ptr(gx_new), _ptr(gy_new), _ptr(gz), _ptr(gg), _ptr(gx_old),
+          ld, _ptr(lam), L, beta, dt, _ptr(stream))
+
+
+def fm_axpby(n, ncols, alpha, x, ldx, beta, y, ldy, out, ldo, dt, stream):
+    _call("fm_axpby", n, ncols, alpha, _ptr(x), ldx, beta, _ptr(y), ldy, _ptr(out), ldo, dt, _ptr(stream))
+
+
+def fm_op_norm_bound(a, stream):
+    v = C.c_double()
+    _call("fm_op_norm_bound", a, C.byref(v), _ptr(stream))
+    return v.value

@@ -1,0 +1,447 @@
+// Differentiation support: the generator gradient of a circulant operator,
+// one proximal-gradient (FISTA) step and its vector-Jacobian product, a block
+// axpby, and an upper bound of ||A||_2^2 from an operator's structure.
+//
+// Gradients follow PyTorch's convention for complex tensors: for a real loss
+// f and an upstream gradient G of an output s, the gradient of an input z is
+// G conj(ds/dz) + conj(G) ds/dz* (Wirtinger derivatives).
+//
+// Circulant generator (the cyclic convolution y = c (*) x of eq. (5)): y is
+// linear in c with matrix C(x), so dL/dc = C(x)^H G, a circular
+// cross-correlation, computed as IDFT(DFT(G) . conj(DFT(x))) / n and summed
+// over the columns in the frequency domain. For w = C(c)^H u, w is linear in
+// conj(c), and the gradient is the cross-correlation of u with G.
+#include <algorithm>
+#include <cmath>
+
+#include "runtime.h"
+#include "solve.h"
+
+namespace fm {
+namespace {
+
+constexpr int kTPB = 256;
+
+template <typename R>
+__device__ __forceinline__ Cx<R> soft(Cx<R> z, R s) {
+  const R mag = sqrt(z.x * z.x + z.y * z.y);
+  if (!(mag > s)) return {R(0), R(0)};
+  const R f = (mag - s) / mag;
+  return {z.x * f, z.y * f};
+}
+
+// P[f] (+)= scale * sum_j A_j[f] conj(B_j[f]) over the columns of one chunk,
+// in column order (deterministic).
+template <typename R>
+__global__ __launch_bounds__(kTPB) void corr_reduce_kernel(int64_t n, int64_t ncols, const Cx<R>* __restrict__ A,
+                                                           const Cx<R>* __restrict__ B, R scale, Cx<R>* P,
+                                                           int accumulate) {
+  const int64_t f = int64_t(blockIdx.x) * kTPB + threadIdx.x;
+  if (f >= n) return;
+  Cx<R> acc = {R(0), R(0)};
+  for (int64_t j = 0; j < ncols; ++j) acc = cadd(acc, cmulc(A[j * n + f], B[j * n + f]));
+  acc = cscale(acc, scale);
+  P[f] = accumulate ? cadd(P[f], acc) : acc;
+}
+
+struct StepArgs {
+  int64_t n, ncols, ld;
+  const void* y;
+  const void* g;
+  const void* xo;
+  void* xn;
+  void* yn;
+  void* z;
+  const double* lam;
+  double invL, beta;
+};
+
+// z = y - g/L; x_new = soft(z, lam_c/L); y_new = x_new + beta (x_new - x_old).
+// The arithmetic is the solver's update, so a recomputed step reproduces the
+// forward step bit for bit.
+template <typename R>
+__global__ __launch_bounds__(kTPB) void step_kernel(StepArgs a) {
+  const R invL = R(a.invL);
+  const R beta = R(a.beta);
+  for (int64_t c = blockIdx.y; c < a.ncols; c += gridDim.y) {
+    const int64_t i = int64_t(blockIdx.x) * kTPB + threadIdx.x;
+    if (i >= a.n) continue;
+    const int64_t o = c * a.ld + i;
+    const R s = R(a.lam[c] * a.invL);
+    const Cx<R> yv = static_cast<const Cx<R>*>(a.y)[o];
+    const Cx<R> gv = static_cast<const Cx<R>*>(a.g)[o];
+    const Cx<R> xo = static_cast<const Cx<R>*>(a.xo)[o];
+    const Cx<R> z = {yv.x - gv.x * invL, yv.y - gv.y * invL};
+    const Cx<R> xn = soft(z, s);
+    const Cx<R> d = {xn.x - xo.x, xn.y - xo.y};
+    static_cast<Cx<R>*>(a.xn)[o] = xn;
+    static_cast<Cx<R>*>(a.yn)[o] = {xn.x + beta * d.x, xn.y + beta * d.y};
+    if (a.z) static_cast<Cx<R>*>(a.z)[o] = z;
+  }
+}
+
+struct VjpArgs {
+  int64_t n, ncols, ld;
+  const void* z;
+  const void* gxn;
+  const void* gyn;
+  void* gz;
+  void* gg;
+  void* gxo;
+  const double* lam;
+  double invL, beta;
+};
+
+// Reverse of step_kernel. With xt = gx_new + (1 + beta) gy_new (the whole
+// gradient reaching x_new) and s = lam_c/L:
+//   |z| > s: gz = xt (1 - s/(2|z|)) + conj(xt) s z^2 / (2|z|^3);  else 0
+//   gg = -gz/L,  gx_old = -beta gy_new.
+template <typename R>
+__global__ __launch_bounds__(kTPB) void step_vjp_kernel(VjpArgs a) {
+  const R invL = R(a.invL);
+  const R beta = R(a.beta);
+  for (int64_t c = blockIdx.y; c < a.ncols; c += gridDim.y) {
+    const int64_t i = int64_t(blockIdx.x) * kTPB + threadIdx.x;
+    if (i >= a.n) continue;
+    const int64_t o = c * a.ld + i;
+    const R s = R(a.lam[c] * a.invL);
+    const Cx<R> z = static_cast<const Cx<R>*>(a.z)[o];
+    const Cx<R> gx = static_cast<const Cx<R>*>(a.gxn)[o];
+    const Cx<R> gy = static_cast<const Cx<R>*>(a.gyn)[o];
+    const Cx<R> xt = {gx.x + (R(1) + beta) * gy.x, gx.y + (R(1) + beta) * gy.y};
+    Cx<R> gz = {R(0), R(0)};
+    const R m2 = z.x * z.x + z.y * z.y;
+    const R m = sqrt(m2);
+    if (m > s) {
+      const R a1 = R(1) - s / (R(2) * m);
+      const R a2 = s / (R(2) * m * m2);
+      const Cx<R> z2 = {z.x * z.x - z.y * z.y, R(2) * z.x * z.y};
+      const Cx<R> cz = cmul(cconj(xt), z2);
+      gz = {a1 * xt.x + a2 * cz.x, a1 * xt.y + a2 * cz.y};
+    }
+    if (a.gxo) static_cast<Cx<R>*>(a.gxo)[o] = {-beta * gy.x, -beta * gy.y};
+    static_cast<Cx<R>*>(a.gz)[o] = gz;
+    if (a.gg) static_cast<Cx<R>*>(a.gg)[o] = {-gz.x * invL, -gz.y * invL};
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kTPB) void axpby_kernel(int64_t n, int64_t ncols, R alpha, const Cx<R>* x, int64_t ldx,
+                                                     R beta, const Cx<R>* y, int64_t ldy, Cx<R>* out, int64_t ldo) {
+  for (int64_t c = blockIdx.y; c < ncols; c += gridDim.y) {
+    const int64_t i = int64_t(blockIdx.x) * kTPB + threadIdx.x;
+    if (i >= n) continue;
+    const Cx<R> xv = x[c * ldx + i], yv = y[c * ldy + i];
+    out[c * ldo + i] = {alpha * xv.x + beta * yv.x, alpha * xv.y + beta * yv.y};
+  }
+}
+
+// Per-block maximum of |v|^2 (mode 0) or sum of |v|^2 (mode 1) over a
+// complex128 array, then one work-group reduces the partials in a fixed order.
+__device__ __forceinline__ double combine(double a, double b, int mode) {
+  return mode == 0 ? (a > b ? a : b) : a + b;
+}
+
+__device__ __forceinline__ double block_reduce(double acc, int mode, double* sm) {
+  sm[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = kTPB / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sm[threadIdx.x] = combine(sm[threadIdx.x], sm[threadIdx.x + w], mode);
+    __syncthreads();
+  }
+  return sm[0];
+}
+
+__global__ __launch_bounds__(kTPB) void mag2_partial_kernel(int64_t count, const c128* __restrict__ v, int mode,
+                                                            double* part) {
+  __shared__ double sm[kTPB];
+  double acc = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * kTPB + threadIdx.x; i < count; i += int64_t(gridDim.x) * kTPB)
+    acc = combine(acc, v[i].x * v[i].x + v[i].y * v[i].y, mode);
+  const double r = block_reduce(acc, mode, sm);
+  if (threadIdx.x == 0) part[blockIdx.x] = r;
+}
+
+__global__ __launch_bounds__(kTPB) void mag2_final_kernel(int nparts, const double* __restrict__ part, int mode,
+                                                          double* out) {
+  __shared__ double sm[kTPB];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += kTPB) acc = combine(acc, part[i], mode);
+  const double r = block_reduce(acc, mode, sm);
+  if (threadIdx.x == 0) *out = r;
+}
+
+dim3 grid2(int64_t n, int64_t ncols) {
+  return dim3(unsigned(cdiv(n, kTPB)), unsigned(std::min<int64_t>(ncols, 65535)));
+}
+
+// max (mode 0) or sum (mode 1) of |v_i|^2 over count complex128 values;
+// synchronises the stream.
+fm_status mag2(const void* v, int64_t count, int mode, double* out, hipStream_t s) {
+  const int nb = int(std::min<int64_t>(256, std::max<int64_t>(1, cdiv(count, kTPB))));
+  DevBuf part;
+  FM_TRY(part.alloc(size_t(nb + 1) * sizeof(double)));
+  double* pp = static_cast<double*>(part.p);
+  hipLaunchKernelGGL(mag2_partial_kernel, dim3(nb), dim3(kTPB), 0, s, count, static_cast<const c128*>(v), mode, pp);
+  FM_LAUNCHED();
+  hipLaunchKernelGGL(mag2_final_kernel, dim3(1), dim3(kTPB), 0, s, nb, pp, mode, pp + nb);
+  FM_LAUNCHED();
+  double h = 0.0;
+  FM_HIP(hipMemcpyAsync(&h, pp + nb, sizeof(double), hipMemcpyDeviceToHost, s));
+  FM_HIP(hipStreamSynchronize(s));
+  *out = h;
+  return FM_OK;
+}
+
+// Upper bound of ||op||_2^2 from the operator's structure.
+fm_status norm_bound(const fm_op_s* op, hipStream_t s, double* out) {
+  double v = 0.0;
+  switch (op->kind) {
+    case Kind::Fourier:
+    case Kind::Hadamard:
+      *out = double(op->n);  // F^H F = n I, H^T H = n I
+      return FM_OK;
+    case Kind::Select:
+      *out = 1.0;
+      return FM_OK;
+    case Kind::Diag:
+      FM_TRY(mag2(op->p64.p, op->n, 0, &v, s));
+      *out = v;
+      return FM_OK;
+    case Kind::Dense:  // Frobenius norm squared
+      FM_TRY(mag2(op->p64.p, op->lda * op->n, 1, &v, s));
+      *out = v;
+      return FM_OK;
+    case Kind::Circulant:
+    case Kind::Toeplitz: {  // stored spectrum carries 1/L: ||T|| <= ||C_L|| = max |DFT_L(g)|
+      FM_TRY(mag2(op->p64.p, op->L, 0, &v, s));
+      *out = v * double(op->L) * double(op->L);
+      return FM_OK;
+    }
+    case Kind::MLToeplitz: {
+      int64_t total = 1;
+      for (int64_t l : op->lL) total *= l;
+      FM_TRY(mag2(op->p64.p, total, 0, &v, s));
+      *out = v * double(total) * double(total);
+      return FM_OK;
+    }
+    case Kind::Adjoint:
+      return norm_bound(op->terms[0], s, out);
+    case Kind::Product:
+    case Kind::Kron: {
+      double p = 1.0;
+      for (fm_op t : op->terms) {
+        FM_TRY(norm_bound(t, s, &v));
+        p *= v;
+      }
+      *out = p;
+      return FM_OK;
+    }
+    case Kind::Sum: {
+      double r = 0.0;
+      for (fm_op t : op->terms) {
+        FM_TRY(norm_bound(t, s, &v));
+        r += std::sqrt(v);
+      }
+      *out = r * r;
+      return FM_OK;
+    }
+    case Kind::BlkDiag: {
+      double m = 0.0;
+      for (fm_op t : op->terms) {
+        FM_TRY(norm_bound(t, s, &v));
+        m = std::max(m, v);
+      }
+      *out = m;
+      return FM_OK;
+    }
+  }
+  set_error("norm bound: unknown operator kind");
+  return FM_E_INVALID;
+}
+
+bool overlaps(const void* a, size_t alen, const void* b, size_t blen) {
+  const char* x = static_cast<const char*>(a);
+  const char* y = static_cast<const char*>(b);
+  return !(x + alen <= y || y + blen <= x);
+}
+
+size_t block_bytes(int64_t rows, int64_t ncols, int64_t ld, size_t es) {
+  return ncols > 0 ? size_t((ncols - 1) * ld + rows) * es : 0;
+}
+
+}  // namespace
+}  // namespace fm
+
+using namespace fm;
+
+extern "C" {
+
+fm_status fm_circulant_grad_generator(int64_t n, int64_t ncols, fm_dir use, const void* in, int64_t ld_in,
+                                      const void* g, int64_t ld_g, void* grad_c, int32_t accumulate, fm_dtype dt,
+                                      void* stream) {
+  set_error("");
+  FM_CHECK_ARG(dt == FM_C64 || dt == FM_C128, FM_E_DTYPE, "generator gradient needs a complex dtype");
+  FM_CHECK_ARG(use == FM_FWD || use == FM_ADJ, FM_E_INVALID, "unknown direction");
+  FM_CHECK_ARG(is_pow2(n) && ilog2(n) <= 20, FM_E_UNSUPPORTED, "circulant size %lld: powers of two up to 2^20",
+               (long long)n);
+  FM_CHECK_ARG(ncols >= 0, FM_E_INVALID, "negative column count");
+  FM_CHECK_ARG(grad_c != nullptr, FM_E_INVALID, "NULL gradient pointer");
+  const size_t es = elem_size(dt);
+  const Elem e = elem_of(dt);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (ncols == 0) {
+    if (!accumulate) FM_TRY(launch_zero2d(e, n, 1, grad_c, n, s));
+    return FM_OK;
+  }
+  FM_CHECK_ARG(in != nullptr && g != nullptr, FM_E_INVALID, "NULL data pointer");
+  FM_CHECK_ARG(ld_in >= n && ld_g >= n, FM_E_SHAPE, "leading dimensions below n");
+  FM_CHECK_ARG(!overlaps(grad_c, size_t(n) * es, in, block_bytes(n, ncols, ld_in, es)) &&
+                   !overlaps(grad_c, size_t(n) * es, g, block_bytes(n, ncols, ld_g, es)),
+               FM_E_ALIAS, "gradient overlaps an input block");
+  // correlation r[k] = sum_i a[i] conj(b[i-k]):  FWD: a = g, b = in;  ADJ: a = in, b = g
+  const void* pa = use == FM_FWD ? g : in;
+  const void* pb = use == FM_FWD ? in : g;
+  const int64_t lda = use == FM_FWD ? ld_g : ld_in, ldb = use == FM_FWD ? ld_in : ld_g;
+  fm_op F = nullptr;
+  FM_TRY(fm_op_create_fourier(&F, n, dt));
+  struct Release {
+    fm_op f;
+    ~Release() { fm_op_release(f); }
+  } rel{F};
+  // columns per chunk: two spectra blocks of at most 256 MiB together
+  const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(ncols, (int64_t(256) << 20) / (2 * n * int64_t(es))));
+  Workspace sz;
+  sz.sizing = true;
+  {
+    Batch b{chunk, 1, 1, n, n, n, n};
+    FM_TRY(exec(F, false, e, b, nullptr, nullptr, false, sz, s));
+    const size_t fft_ws = sz.peak;
+    sz = Workspace{};
+    sz.sizing = true;
+    sz.take(size_t(2 * chunk * n) * es);
+    sz.take(size_t(n) * es);
+    sz.take(fft_ws);
+  }
+  DevBuf wsb;
+  FM_TRY(wsb.alloc(sz.peak));
+  Workspace w;
+  w.base = static_cast<char*>(wsb.p);
+  w.cap = wsb.bytes;
+  void* A = w.take(size_t(chunk * n) * es);
+  void* B = w.take(size_t(chunk * n) * es);
+  void* P = w.take(size_t(n) * es);
+  for (int64_t c0 = 0; c0 < ncols; c0 += chunk) {
+    const int64_t nc = std::min(chunk, ncols - c0);
+    Batch ba{nc, 1, 1, lda, n, n, n};
+    Batch bb{nc, 1, 1, ldb, n, n, n};
+    FM_TRY(exec(F, false, e, ba, static_cast<const char*>(pa) + size_t(c0 * lda) * es, A, false, w, s));
+    FM_TRY(exec(F, false, e, bb, static_cast<const char*>(pb) + size_t(c0 * ldb) * es, B, false, w, s));
+    const dim3 grid(unsigned(cdiv(n, kTPB)));
+    if (dt == FM_C64)
+      hipLaunchKernelGGL(corr_reduce_kernel<float>, grid, dim3(kTPB), 0, s, n, nc, static_cast<const c64*>(A),
+                         static_cast<const c64*>(B), float(1.0 / double(n)), static_cast<c64*>(P), int(c0 > 0));
+    else
+      hipLaunchKernelGGL(corr_reduce_kernel<double>, grid, dim3(kTPB), 0, s, n, nc, static_cast<const c128*>(A),
+                         static_cast<const c128*>(B), 1.0 / double(n), static_cast<c128*>(P), int(c0 > 0));
+    FM_LAUNCHED();
+  }
+  // grad_c (+)= unnormalised inverse DFT of P (the 1/n is already in P)
+  Batch b1{1, 1, 1, n, n, n, n};
+  FM_TRY(exec(F, true, e, b1, P, grad_c, accumulate != 0, w, s));
+  FM_HIP(hipStreamSynchronize(s));  // the workspace is freed on return
+  return FM_OK;
+}
+
+fm_status fm_fista_step(int64_t n, int64_t ncols, const void* y, const void* g, const void* x_old, void* x_new,
+                        void* y_new, void* z_out, int64_t ld, const double* lam, double L, double beta, fm_dtype dt,
+                        void* stream) {
+  set_error("");
+  FM_CHECK_ARG(dt == FM_C64 || dt == FM_C128, FM_E_DTYPE, "FISTA step needs a complex dtype");
+  FM_CHECK_ARG(n >= 0 && ncols >= 0 && ld >= n, FM_E_SHAPE, "bad block shape");
+  FM_CHECK_ARG(L > 0.0 && std::isfinite(L), FM_E_INVALID, "step constant L must be positive");
+  if (n == 0 || ncols == 0) return FM_OK;
+  FM_CHECK_ARG(y && g && x_old && x_new && y_new && lam, FM_E_INVALID, "NULL pointer");
+  const size_t bytes = block_bytes(n, ncols, ld, elem_size(dt));
+  FM_CHECK_ARG(!overlaps(x_new, bytes, y_new, bytes), FM_E_ALIAS, "x_new and y_new overlap");
+  FM_CHECK_ARG(!z_out || (!overlaps(z_out, bytes, x_new, bytes) && !overlaps(z_out, bytes, y_new, bytes)),
+               FM_E_ALIAS, "z overlaps an output");
+  StepArgs a{n, ncols, ld, y, g, x_old, x_new, y_new, z_out, lam, 1.0 / L, beta};
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (dt == FM_C64)
+    hipLaunchKernelGGL(step_kernel<float>, grid2(n, ncols), dim3(kTPB), 0, s, a);
+  else
+    hipLaunchKernelGGL(step_kernel<double>, grid2(n, ncols), dim3(kTPB), 0, s, a);
+  FM_LAUNCHED();
+  return FM_OK;
+}
+
+fm_status fm_fista_step_vjp(int64_t n, int64_t ncols, const void* z, const void* gx_new, const void* gy_new,
+                            void* gz, void* gg, void* gx_old, int64_t ld, const double* lam, double L, double beta,
+                            fm_dtype dt, void* stream) {
+  set_error("");
+  FM_CHECK_ARG(dt == FM_C64 || dt == FM_C128, FM_E_DTYPE, "FISTA step needs a complex dtype");
+  FM_CHECK_ARG(n >= 0 && ncols >= 0 && ld >= n, FM_E_SHAPE, "bad block shape");
+  FM_CHECK_ARG(L > 0.0 && std::isfinite(L), FM_E_INVALID, "step constant L must be positive");
+  if (n == 0 || ncols == 0) return FM_OK;
+  FM_CHECK_ARG(z && gx_new && gy_new && gz && lam, FM_E_INVALID, "NULL pointer");
+  const size_t bytes = block_bytes(n, ncols, ld, elem_size(dt));
+  FM_CHECK_ARG(!overlaps(gz, bytes, z, bytes), FM_E_ALIAS, "gz overlaps z");
+  FM_CHECK_ARG(!gg || (!overlaps(gg, bytes, gz, bytes) && (gg == gx_new || !overlaps(gg, bytes, gx_new, bytes)) &&
+                       (gg == gy_new || !overlaps(gg, bytes, gy_new, bytes))),
+               FM_E_ALIAS, "gg overlaps another block");
+  FM_CHECK_ARG(!gx_old || (!overlaps(gx_old, bytes, gz, bytes) && (!gg || !overlaps(gx_old, bytes, gg, bytes)) &&
+                           (gx_old == gx_new || !overlaps(gx_old, bytes, gx_new, bytes)) &&
+                           (gx_old == gy_new || !overlaps(gx_old, bytes, gy_new, bytes))),
+               FM_E_ALIAS, "gx_old overlaps another block");
+  FM_CHECK_ARG((gz == gx_new || !overlaps(gz, bytes, gx_new, bytes)) &&
+                   (gz == gy_new || !overlaps(gz, bytes, gy_new, bytes)),
+               FM_E_ALIAS, "gz partially overlaps an upstream gradient");
+  VjpArgs a{n, ncols, ld, z, gx_new, gy_new, gz, gg, gx_old, lam, 1.0 / L, beta};
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (dt == FM_C64)
+    hipLaunchKernelGGL(step_vjp_kernel<float>, grid2(n, ncols), dim3(kTPB), 0, s, a);
+  else
+    hipLaunchKernelGGL(step_vjp_kernel<double>, grid2(n, ncols), dim3(kTPB), 0, s, a);
+  FM_LAUNCHED();
+  return FM_OK;
+}
+
+fm_status fm_axpby(int64_t n, int64_t ncols, double alpha, const void* x, int64_t ldx, double beta, const void* y,
+                   int64_t ldy, void* out, int64_t ldo, fm_dtype dt, void* stream) {
+  set_error("");
+  FM_CHECK_ARG(dt == FM_C64 || dt == FM_C128, FM_E_DTYPE, "axpby needs a complex dtype");
+  FM_CHECK_ARG(n >= 0 && ncols >= 0 && ldx >= n && ldy >= n && ldo >= n, FM_E_SHAPE, "bad block shape");
+  if (n == 0 || ncols == 0) return FM_OK;
+  FM_CHECK_ARG(x && y && out, FM_E_INVALID, "NULL pointer");
+  const size_t es = elem_size(dt);
+  const size_t ob = block_bytes(n, ncols, ldo, es);
+  FM_CHECK_ARG((out == x && ldo == ldx) || !overlaps(out, ob, x, block_bytes(n, ncols, ldx, es)), FM_E_ALIAS,
+               "out partially overlaps x");
+  FM_CHECK_ARG((out == y && ldo == ldy) || !overlaps(out, ob, y, block_bytes(n, ncols, ldy, es)), FM_E_ALIAS,
+               "out partially overlaps y");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (dt == FM_C64)
+    hipLaunchKernelGGL(axpby_kernel<float>, grid2(n, ncols), dim3(kTPB), 0, s, n, ncols, float(alpha),
+                       static_cast<const c64*>(x), ldx, float(beta), static_cast<const c64*>(y), ldy,
+                       static_cast<c64*>(out), ldo);
+  else
+    hipLaunchKernelGGL(axpby_kernel<double>, grid2(n, ncols), dim3(kTPB), 0, s, n, ncols, alpha,
+                       static_cast<const c128*>(x), ldx, beta, static_cast<const c128*>(y), ldy,
+                       static_cast<c128*>(out), ldo);
+  FM_LAUNCHED();
+  return FM_OK;
+}
+
+fm_status fm_op_norm_bound(fm_op a, double* bound, void* stream) {
+  set_error("");
+  FM_CHECK_ARG(a != nullptr, FM_E_INVALID, "operator handle is NULL");
+  FM_CHECK_ARG(op_alive(a), FM_E_RELEASED, "operator handle was released");
+  FM_CHECK_ARG(bound != nullptr, FM_E_INVALID, "NULL output");
+  int dev = 0;
+  FM_HIP(hipGetDevice(&dev));
+  FM_CHECK_ARG(dev == a->device, FM_E_DEVICE, "operator lives on device %d, current is %d", a->device, dev);
+  return norm_bound(a, reinterpret_cast<hipStream_t>(stream), bound);
+}
+
+}  // extern "C"

@@ -70,6 +70,19 @@ def test_invalid_arguments_return_status(lib):
     assert st(lib, "fm_workspace_size", bogus, 0, 1, C.byref(size)) == 9
     msg = lib.fm_last_error().decode()
     assert "released" in msg
+    # differentiation helpers
+    assert st(lib, "fm_circulant_grad_generator", 16, 1, 0, None, 16, None, 16, None, 0, 3, None) == 3  # int dtype
+    assert st(lib, "fm_circulant_grad_generator", 12, 1, 0, None, 12, None, 12, C.c_void_p(16), 0, 1, None) == 5
+    assert st(lib, "fm_circulant_grad_generator", 16, 1, 7, None, 16, None, 16, None, 0, 1, None) == 1  # direction
+    assert st(lib, "fm_fista_step", 8, 1, None, None, None, None, None, None, 4, None,
+              C.c_double(1.0), C.c_double(0.0), 1, None) == 2  # ld < n
+    assert st(lib, "fm_fista_step", 8, 1, None, None, None, None, None, None, 8, None,
+              C.c_double(0.0), C.c_double(0.0), 1, None) == 1  # L <= 0
+    assert st(lib, "fm_fista_step_vjp", 8, 1, None, None, None, None, None, None, 8, None,
+              C.c_double(1.0), C.c_double(0.0), 4, None) == 3  # integer dtype
+    assert st(lib, "fm_axpby", 8, 1, C.c_double(1.0), None, 4, C.c_double(1.0), None, 8, None, 8, 1, None) == 2
+    assert st(lib, "fm_op_norm_bound", None, None, None) == 1
+    assert st(lib, "fm_op_norm_bound", bogus, None, None) == 9
 
 
 def test_binding_raises(lib):
