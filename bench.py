@@ -222,6 +222,119 @@ def fista_solves(w, iters=100, stop_tol=1e-5):
             "mean_iters": round(float(counts.mean()), 2)}
 
 
+def learn_circulant_steps(steps=5, warmup=2, iters=20, checkpoint=5):
+    """Training steps/s of learning a circulant generator through unrolled
+    FISTA (N = 16384, M = 2048 selected rows, 256 pairs of 32-sparse vectors,
+    20 steps): the checkpointed unrolled solver (autograd.unrolled_fista)
+    against plain autograd over per-step operator applications with every
+    intermediate saved. One training step = forward, backward, Adam update of c."""
+    import torch
+
+    import paper_1710_09578_amd as fm
+    from paper_1710_09578_amd import autograd as ag
+    from workloads import learn_circulant
+
+    d = learn_circulant()
+    dev = torch.device("cuda:0")
+    c_true = torch.from_numpy(d["c_true"]).to(dev)
+    rows = torch.from_numpy(d["rows"]).to(dev)
+    x = torch.from_numpy(d["x"]).to(dev)
+    n = c_true.numel()
+    A_true = fm.Product(fm.SelectRows(n, rows), fm.Circulant(c_true))
+    b = A_true.apply(x)
+    b.add_(torch.from_numpy(d["noise"]).to(dev))
+    g = A_true.apply(b, adjoint=True)
+    lam = 0.05 * g.abs().amax(dim=1).double()
+    S = fm.SelectRows(n, rows)
+
+    def soft(z, s):
+        a = z.abs()
+        keep = a > s
+        a_safe = torch.where(keep, a, torch.ones_like(a))
+        return torch.where(keep, z * (1 - s / a_safe), torch.zeros_like(z))
+
+    def run(kind):
+        c = torch.from_numpy(d["c_init"]).to(dev).requires_grad_(True)
+        opt = torch.optim.Adam([c], lr=1e-3)
+        betas = ag.momentum_weights(iters)
+
+        def one():
+            opt.zero_grad(set_to_none=True)
+            Cc = fm.Circulant(c.detach())
+            L = fm.capi.fm_op_norm_bound(Cc.handle, 0)
+            if kind == "checkpointed":
+                xk = ag.unrolled_fista(c, b, rows, lam, L=L, iters=iters, checkpoint=checkpoint)
+            else:
+                s = (lam / L).reshape(-1, 1).to(torch.float32)
+                xp = torch.zeros_like(x)
+                y = xp
+                for k in range(iters):
+                    r = ag.apply(S, ag.circulant_apply(c, y)) - b
+                    gk = ag.circulant_apply(c, ag.apply(S, r, adjoint=True), adjoint=True)
+                    xk = soft(y - gk / L, s)
+                    y = xk + betas[k] * (xk - xp)
+                    xp = xk
+                xk = xp
+            loss = (xk - x).abs().pow(2).mean()
+            loss.backward()
+            opt.step()
+            return float(loss.detach())
+
+        for _ in range(warmup):
+            one()
+        torch.cuda.synchronize()
+        torch.cuda.reset_peak_memory_stats()
+        t0 = time.time()
+        losses = [one() for _ in range(steps)]
+        torch.cuda.synchronize()
+        dt = (time.time() - t0) / steps
+        return dt, torch.cuda.max_memory_allocated() / 2**30, losses
+
+    out = {}
+    for kind in ("checkpointed", "plain"):
+        dt, mem, losses = run(kind)
+        log(f"learn-circulant {kind}: {dt * 1e3:.1f} ms/step, peak {mem:.2f} GiB, loss {losses[0]:.4e} -> {losses[-1]:.4e}")
+        out[kind] = {"ms_per_step": round(dt * 1e3, 2), "steps_per_s": round(1 / dt, 2), "peak_gib": round(mem, 3)}
+    out["speedup"] = round(out["plain"]["ms_per_step"] / out["checkpointed"]["ms_per_step"], 2)
+    out["workload"] = "N=16384, M=2048, 256 pairs, 20 unrolled FISTA steps, checkpoints every 5, Adam"
+    return out
+
+
+def kron_hfg_bandwidth(steps=5, warmup=2):
+    """Forward + adjoint of Kron(H_1024, F_256, G_32) on 64 columns of
+    8,388,608 rows (complex64, 4 GiB per block). Algorithmic bytes per
+    direction: read the block + write the block (+ the 8 KiB factor)."""
+    import torch
+
+    import paper_1710_09578_amd as fm
+    from workloads import kron_hfg
+
+    dev = torch.device("cuda:0")
+    g, X = kron_hfg(device=dev)
+    K = fm.Kron(fm.Hadamard(1024), fm.Fourier(256), fm.Dense(torch.from_numpy(g).to(dev)))
+    Y = torch.empty_like(X)
+    Z = torch.empty_like(X)
+    from paper_1710_09578_amd import capi
+
+    ws = torch.empty(max(capi.fm_workspace_size(K.handle, capi.FM_FWD, X.shape[0]),
+                         capi.fm_workspace_size(K.handle, capi.FM_ADJ, X.shape[0]), 1),
+                     dtype=torch.uint8, device=dev)
+
+    def step():
+        K.apply(X, out=Y, workspace=ws)
+        K.apply(Y, adjoint=True, out=Z, workspace=ws)
+
+    ms, _ = time_steps(step, steps, warmup)
+    alg = 2 * (2 * X.numel() * 8 + g.size * 8)
+    gbs = alg / (ms * 1e-3) / 1e9
+    log(f"kron H1024 x F256 x G32, 64 columns: {ms:.3f} ms per fwd+adj, {gbs:.1f} GB/s")
+    del X, Y, Z, ws
+    torch.cuda.empty_cache()
+    return {"workload": "Kron(H_1024, F_256, G_32 real N(0,1/32)), 64 columns of 8388608, complex64, fwd+adj",
+            "ms_per_step": round(ms, 4), "gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "alg_bytes_per_step": int(alg)}
+
+
 def cpu_baseline_toeplitz(w, budget_s=15.0):
     """The oracle's dense-free Toeplitz product (row blocks generated from the
     definition, BLAS products) on a bounded sample of the same operators."""
@@ -258,6 +371,8 @@ def main():
     ap.add_argument("--nops", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fista", action="store_true")
+    ap.add_argument("--no-learn", action="store_true")
+    ap.add_argument("--no-kron", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 512 MiB device to device (reference for traffic counters)")
     args = ap.parse_args()
@@ -318,6 +433,8 @@ def main():
             "kernel": "stage_kernel: all stage launches of one direction (fm_batch_apply)",
             "alg_bytes_per_launch": int(per_launch), "launch_ms": round(launch_ms, 4)}
     fres = None if args.no_fista else fista_solves(w)
+    learn = None if args.no_learn else learn_circulant_steps()
+    kron = None if args.no_kron else kron_hfg_bandwidth()
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline_toeplitz(w)
@@ -344,6 +461,8 @@ def main():
                    "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)},
         "roofline": roof,
         "fista": fres,
+        "learn_circulant": learn,
+        "kron": kron,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -300,3 +300,26 @@ def test_leading_dimension_and_views(gpu):
     ref = dense.apply(dense.circulant(c), to_host(x))
     assert rel_err(to_host(y[:, :256]), ref) <= TOL["c64"]
     assert np.all(to_host(y[:, 256:]) == 0)
+
+
+# ---------------------------------------------------------------- Kronecker workload at full size
+def test_kron_hfg_full_size_sampled_columns(gpu):
+    """Kron(H_1024, F_256, G_32) on 64 columns of 8,388,608 rows (complex64,
+    4 GiB per block), forward and adjoint, in the launch configuration the
+    benchmark times. Oracle: mode products with the dense complex128 factors on
+    8 seeded columns (columns are independent, so the check is exact for them)."""
+    import torch
+
+    from workloads import kron_hfg
+
+    g, X = kron_hfg(device=torch.device("cuda:0"))
+    K = gpu.Kron(gpu.Hadamard(1024), gpu.Fourier(256), gpu.Dense(to_dev(g)))
+    Y = K @ X
+    Z = K.H @ X
+    cols = [0, 9, 17, 28, 33, 47, 52, 63]
+    xs = to_host(X[cols])
+    fs = [dense.hadamard(1024), dense.fourier(256), g]
+    ey = rel_err(to_host(Y[cols]), structured.kron_apply(fs, xs))
+    ez = rel_err(to_host(Z[cols]), structured.kron_apply(fs, xs, adjoint_dir=True))
+    print(f"kron H1024 F256 G32 full size: fwd {ey:.2e} adj {ez:.2e}")
+    assert ey <= TOL["c64"] and ez <= TOL["c64"]
