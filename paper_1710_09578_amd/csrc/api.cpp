@@ -226,6 +226,14 @@ fm_status fm_op_create_dense(fm_op* out, int64_t m, int64_t n, const void* a, in
                           hipMemcpyDeviceToDevice, s));
   FM_TRY(store_params(op, packed.p, m * n, s));
   op->lda = m;
+  if (m * n <= (int64_t(1) << 22)) {  // record a real matrix (kernels then skip the imaginary parts)
+    std::vector<double> h(size_t(m * n) * 2);
+    FM_HIP(hipMemcpyAsync(h.data(), op->p64.p, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    FM_HIP(hipStreamSynchronize(s));
+    bool real = true;
+    for (size_t i = 1; i < h.size() && real; i += 2) real = h[i] == 0.0;
+    op->real_entries = real;
+  }
   FM_HIP(hipStreamSynchronize(s));
   return publish(g.release(), out);
 }

@@ -143,6 +143,104 @@ __global__ __launch_bounds__(256) void dense_kernel(int64_t m, int64_t n, const 
   }
 }
 
+// Dense mode product along the contiguous axis (inner == 1) for small
+// factors: one vector per thread. A work-group copies op(A) into LDS (zero-
+// padded to NMAX columns, conjugate-transposed for the adjoint, real parts
+// only when A is real), stages 256 input vectors through LDS (coalesced
+// loads), keeps each thread's vector in registers and forms every output row
+// from broadcast LDS reads of the matrix; the outputs leave through LDS again
+// (coalesced stores).
+constexpr int kDV = 256;  // vectors per work-group
+
+template <typename V, int NMAX, bool REAL>
+constexpr size_t dense_vec_abytes(int nout) {
+  return (size_t(nout) * NMAX * (REAL ? 1 : 2) * sizeof(typename Ops<V>::R) + 15) & ~size_t(15);
+}
+
+template <typename V, int NMAX, bool REAL, bool ADJ>
+__global__ __launch_bounds__(kDV) void dense_vec_kernel(int64_t m, int64_t n, const V* __restrict__ a, int64_t lda,
+                                                        Batch b, const V* __restrict__ x, V* y, int acc) {
+  using R = typename Ops<V>::R;
+  constexpr int C = REAL ? 1 : 2;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int nin = int(ADJ ? m : n), nout = int(ADJ ? n : m);
+  R* amat = reinterpret_cast<R*>(smem_raw);
+  V* lds = reinterpret_cast<V*>(smem_raw + dense_vec_abytes<V, NMAX, REAL>(nout));
+  const int stride = (nin > nout ? nin : nout) + 1;  // odd padding spreads the banks
+  const int64_t P = b.ncols * b.outer;
+  const int64_t p0 = int64_t(blockIdx.x) * kDV;
+  const int nv = int(P - p0 < kDV ? P - p0 : kDV);
+  const int t = threadIdx.x;
+  // ---- op(A) row by row: amat[(r*NMAX + k)*C + {0,1}]
+  for (int idx = t; idx < nout * NMAX; idx += kDV) {
+    const int r = idx / NMAX, k = idx - r * NMAX;
+    V v = Ops<V>::zero();
+    if (k < nin) {
+      v = ADJ ? a[k + int64_t(r) * lda] : a[r + int64_t(k) * lda];
+      if (ADJ) v.y = -v.y;
+    }
+    amat[idx * C] = v.x;
+    if constexpr (!REAL) amat[idx * C + 1] = v.y;
+  }
+  const bool packed = b.outer == 1 || b.ldx == b.outer * b.xvs;
+  const bool packed_y = b.outer == 1 || b.ldy == b.outer * b.yvs;
+  // ---- stage the inputs: element e = v*nin + k of the tile
+  {
+    int v = t / nin, k = t % nin;
+    const int dv = kDV / nin, dk = kDV % nin;
+    for (int e = t; e < nv * nin; e += kDV) {
+      const int64_t p = p0 + v;
+      const int64_t off = packed ? (b.outer == 1 ? p * b.ldx : p * b.xvs)
+                                 : (p / b.outer) * b.ldx + (p % b.outer) * b.xvs;
+      lds[v * stride + k] = x[off + k];
+      v += dv;
+      k += dk;
+      if (k >= nin) {
+        k -= nin;
+        ++v;
+      }
+    }
+  }
+  __syncthreads();
+  V xv[NMAX];
+#pragma unroll
+  for (int k = 0; k < NMAX; ++k) xv[k] = (k < nin && t < nv) ? lds[t * stride + k] : Ops<V>::zero();
+  __syncthreads();
+  for (int r = 0; r < nout; ++r) {
+    const R* ar = amat + r * NMAX * C;
+    R sr = R(0), si = R(0);
+#pragma unroll
+    for (int k = 0; k < NMAX; ++k) {
+      if constexpr (REAL) {
+        sr += ar[k] * xv[k].x;
+        si += ar[k] * xv[k].y;
+      } else {
+        sr += ar[2 * k] * xv[k].x - ar[2 * k + 1] * xv[k].y;
+        si += ar[2 * k] * xv[k].y + ar[2 * k + 1] * xv[k].x;
+      }
+    }
+    lds[t * stride + r] = V{sr, si};
+  }
+  __syncthreads();
+  // ---- coalesced stores of the outputs
+  {
+    int v = t / nout, k = t % nout;
+    const int dv = kDV / nout, dk = kDV % nout;
+    for (int e = t; e < nv * nout; e += kDV) {
+      const int64_t p = p0 + v;
+      const int64_t off = packed_y ? (b.outer == 1 ? p * b.ldy : p * b.yvs)
+                                   : (p / b.outer) * b.ldy + (p % b.outer) * b.yvs;
+      store(y + off + k, lds[v * stride + k], acc);
+      v += dv;
+      k += dk;
+      if (k >= nout) {
+        k -= nout;
+        ++v;
+      }
+    }
+  }
+}
+
 struct Box {
   int ndim;
   int64_t box[3], src[3], dst[3];
@@ -305,11 +403,64 @@ fm_status launch_copy(Elem e, int64_t n, const Batch& b, const void* x, void* y,
   return FM_OK;
 }
 
-fm_status launch_dense(Elem e, int64_t m, int64_t n, const void* a, int64_t lda, int adjoint,
+// LDS bytes one work-group may allocate on the current device (cached).
+size_t max_lds_per_block() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 65536;
+  if (cached[dev] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) v = 65536;
+    cached[dev] = v;
+  }
+  return size_t(cached[dev]);
+}
+
+fm_status launch_dense(Elem e, int64_t m, int64_t n, const void* a, int64_t lda, int adjoint, int real_a,
                        const Batch& b, const void* x, void* y, int acc, hipStream_t s) {
   if (b.ncols == 0) return FM_OK;
   const int64_t rows_out = adjoint ? n : m;
   if (rows_out == 0) return FM_OK;
+  const int64_t rows_in = adjoint ? m : n;
+  const int64_t P = b.ncols * b.outer;
+  const int nmax = rows_in <= 8 ? 8 : rows_in <= 16 ? 16 : rows_in <= 32 ? 32 : 64;
+  const size_t abytes = (size_t(rows_out) * nmax * (real_a ? 1 : 2) * (e == Elem::C64 ? 4 : 8) + 15) & ~size_t(15);
+  const size_t lds = abytes + size_t(kDV) * size_t((rows_in > rows_out ? rows_in : rows_out) + 1) * elem_bytes(e);
+  if (b.inner == 1 && rows_in <= 64 && rows_out <= 64 && (e == Elem::C64 || (e == Elem::C128 && rows_in <= 32)) &&
+      P >= 4 * kDV && lds <= max_lds_per_block()) {
+    const dim3 g(unsigned(cdiv(P, kDV)));
+#define FM_DV(V, N)                                                                                        \
+  do {                                                                                                     \
+    if (real_a) {                                                                                          \
+      if (adjoint)                                                                                         \
+        hipLaunchKernelGGL((dense_vec_kernel<V, N, true, true>), g, dim3(kDV), lds, s, m, n, (const V*)a, \
+                           lda, b, (const V*)x, (V*)y, acc);                                               \
+      else                                                                                                 \
+        hipLaunchKernelGGL((dense_vec_kernel<V, N, true, false>), g, dim3(kDV), lds, s, m, n, (const V*)a, \
+                           lda, b, (const V*)x, (V*)y, acc);                                               \
+    } else {                                                                                               \
+      if (adjoint)                                                                                         \
+        hipLaunchKernelGGL((dense_vec_kernel<V, N, false, true>), g, dim3(kDV), lds, s, m, n, (const V*)a, \
+                           lda, b, (const V*)x, (V*)y, acc);                                               \
+      else                                                                                                 \
+        hipLaunchKernelGGL((dense_vec_kernel<V, N, false, false>), g, dim3(kDV), lds, s, m, n,            \
+                           (const V*)a, lda, b, (const V*)x, (V*)y, acc);                                  \
+    }                                                                                                      \
+  } while (0)
+    if (e == Elem::C64) {
+      if (nmax == 8) FM_DV(c64, 8);
+      else if (nmax == 16) FM_DV(c64, 16);
+      else if (nmax == 32) FM_DV(c64, 32);
+      else FM_DV(c64, 64);
+    } else {
+      if (nmax == 8) FM_DV(c128, 8);
+      else if (nmax == 16) FM_DV(c128, 16);
+      else FM_DV(c128, 32);
+    }
+#undef FM_DV
+    FM_LAUNCHED();
+    return FM_OK;
+  }
   dim3 g = vec_grid(b.ncols * b.outer, rows_out * b.inner, 256);
   if (e == Elem::C64)
     hipLaunchKernelGGL(dense_kernel<c64>, g, dim3(256), 0, s, m, n, (const c64*)a, lda, adjoint, b,

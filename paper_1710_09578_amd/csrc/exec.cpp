@@ -349,7 +349,7 @@ fm_status exec(const fm_op_s* op, bool adj, Elem e, const Batch& b, const void* 
       LAUNCH(launch_diag(e, op->n, b, param(op, e), adj, x, y, acc, s));
       return FM_OK;
     case Kind::Dense:
-      LAUNCH(launch_dense(e, op->m, op->n, param(op, e), op->lda, adj, b, x, y, acc, s));
+      LAUNCH(launch_dense(e, op->m, op->n, param(op, e), op->lda, adj, op->real_entries, b, x, y, acc, s));
       return FM_OK;
     case Kind::Select:
       LAUNCH(launch_select(e, op->n, op->m, static_cast<const int32_t*>(op->idx.p), adj, b, x, y,

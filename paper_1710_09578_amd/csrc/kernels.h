@@ -62,7 +62,8 @@ fm_status launch_diag(Elem e, int64_t n, const Batch& b, const void* d, int conj
 fm_status launch_select(Elem e, int64_t n_in, int64_t m, const int32_t* idx, int adjoint,
                         const Batch& b, const void* x, void* y, int accumulate, hipStream_t s);
 // Dense mode product y[:, o, :, i] (+)= op(A) x[:, o, :, i], A m x n col-major.
-fm_status launch_dense(Elem e, int64_t m, int64_t n, const void* a, int64_t lda, int adjoint,
+// real_a: every entry of A has a zero imaginary part (only real parts used).
+fm_status launch_dense(Elem e, int64_t m, int64_t n, const void* a, int64_t lda, int adjoint, int real_a,
                        const Batch& b, const void* x, void* y, int accumulate, hipStream_t s);
 // Zero-pad / crop copy between multi-dimensional grids (multilevel Toeplitz):
 // copies the box [0, nbox) of the source grid (dims src_dims) into the

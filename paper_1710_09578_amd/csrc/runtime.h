@@ -68,6 +68,7 @@ struct fm_op_s {
   fm::DevBuf p32, p64;
   fm::DevBuf idx;          // selection indices
   int64_t lda = 0;         // dense: leading dimension of the stored copy (= m)
+  bool real_entries = false;  // dense: every entry has a zero imaginary part
   int64_t L = 0;           // cyclic length (Fourier/Circulant/Toeplitz)
   fm::Split s32, s64;      // splits of L for complex64 / complex128
   std::vector<int64_t> lv, lL;  // multilevel: entries per level, embedding per level

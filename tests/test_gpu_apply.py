@@ -323,3 +323,43 @@ def test_kron_hfg_full_size_sampled_columns(gpu):
     ez = rel_err(to_host(Z[cols]), structured.kron_apply(fs, xs, adjoint_dir=True))
     print(f"kron H1024 F256 G32 full size: fwd {ey:.2e} adj {ez:.2e}")
     assert ey <= TOL["c64"] and ez <= TOL["c64"]
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+@pytest.mark.parametrize("shape", [(32, 32), (20, 12), (5, 40), (64, 64)])
+@pytest.mark.parametrize("real", [True, False])
+def test_dense_mode_product_many_vectors(gpu, prec, shape, real):
+    """A small dense factor along the contiguous axis of many vectors (the
+    register-blocked path): Kron(I_P, G) with P vectors per column, real and
+    complex G, forward and adjoint, ragged vector counts."""
+    import torch
+
+    if prec == "c128" and max(shape) > 32:
+        pytest.skip("complex128 register path covers factors up to 32")
+    rng = np.random.default_rng(shape[0] * 100 + shape[1])
+    m, n = shape
+    g = crandn(rng, shape, NP[prec])
+    if real:
+        g = g.real.astype(NP[prec])
+    P = 1300  # vectors per column: not a multiple of the 256-vector tile
+    ones = to_dev(np.ones(P, NP[prec]))
+    K = gpu.Kron(gpu.Diag(ones), gpu.Dense(to_dev(g)))
+    for adj in (False, True):
+        rin, rout = (m, n) if adj else (n, m)
+        x = crandn(rng, (3, P * rin), NP[prec])
+        y = to_host(K.apply(to_dev(x), adjoint=adj))
+        ga = g.astype(np.complex128)
+        op = ga.conj().T if adj else ga
+        ref = np.einsum("rk,cpk->cpr", op, x.astype(np.complex128).reshape(3, P, rin)).reshape(3, P * rout)
+        assert rel_err(y, ref) <= TOL[prec], (adj, rel_err(y, ref))
+    # unpacked columns (leading dimension above the rows) through the C ABI
+    from paper_1710_09578_amd import capi
+
+    x = crandn(rng, (2, P * n + 7), NP[prec])
+    y = torch.zeros((2, P * m + 5), dtype=torch_dt(prec), device="cuda")
+    capi.fm_apply(K.handle, capi.FM_FWD, 2, to_dev(x), P * n + 7, y, P * m + 5, None, 0,
+                  torch.cuda.current_stream().cuda_stream)
+    ref = np.einsum("rk,cpk->cpr", g.astype(np.complex128),
+                    x[:, :P * n].astype(np.complex128).reshape(2, P, n)).reshape(2, P * m)
+    yh = to_host(y)
+    assert rel_err(yh[:, :P * m], ref) <= TOL[prec] and np.all(yh[:, P * m:] == 0)
