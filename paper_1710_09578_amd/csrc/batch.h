@@ -8,16 +8,25 @@
 
 namespace fm {
 
-constexpr int kLog1 = 12;  // contiguous factor of the four-step split
+constexpr int kLogW = 12;   // values per work-group of the stage kernel
+constexpr int kLog1 = 12;   // contiguous factor of the four-step split (complex64)
 constexpr size_t kRegionBytes = size_t(48) << 20;  // intermediates of one chunk
 
-enum ItemKind : int { IT_SINGLE = 0, IT_FS1 = 1, IT_FS2 = 2, IT_FS3 = 3 };
+// Work items (one work-group each):
+//   SINGLE  whole zero-padded convolutions of length 2^lg for `sub` columns
+//   ROWF    row k2 = sub of a four-step column (L = 2^(12 + lg), lg <= conv_max_fuse()), the
+//           strided 2^lg-point transform folded into its load (reads x)
+//   FS1     strided 2^lg-point transforms of one column into its slot (lg not folded)
+//   FS2     row k2 = sub of a column whose FS1 pass has run (in place in the slot)
+//   FS3     strided inverse 2^lg-point transforms of one column and the cropped
+//           store into y (inner tile `sub`)
+enum ItemKind : int { IT_SINGLE = 0, IT_FS1 = 1, IT_FS2 = 2, IT_FS3 = 3, IT_ROWF = 4 };
 
 struct Item {
-  int32_t kind_log;  // kind | (log2 of the transform length << 8)
+  int32_t kind_log;  // kind | (lg << 8)
   int32_t op;
-  int32_t col;  // SINGLE: first column; FS*: four-step column index
-  int32_t sub;  // SINGLE: columns in this item; FS1/FS3: inner tile; FS2: row
+  int32_t col;  // SINGLE: first column; others: four-step column index
+  int32_t sub;  // SINGLE: columns in this item; FS1/FS3: inner tile; FS2/ROWF: row k2
 };
 
 struct OpDev {

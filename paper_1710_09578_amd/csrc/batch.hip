@@ -1,20 +1,26 @@
 // Batched application of many circulant / Toeplitz operators.
 //
-// Work is cut into items of 4096 complex values each (one work-group):
-//   SINGLE  a whole zero-padded convolution (length <= 4096) for up to
-//           4096/L columns of one operator
-//   FS1     four-step pass 1 of one column: strided 2^lg-point transforms of
-//           4096/2^lg neighbouring inner indices, twiddles, into the column's
-//           intermediate slot
-//   FS2     pass 2: one 4096-point row, spectral product, inverse row, twiddles
-//   FS3     pass 3: strided inverse transforms, cropped store into y
+// Work is cut into items of one work-group (4096 values) each (see batch.h):
+// whole convolutions of length <= 4096 (SINGLE), and for longer embeddings
+// L = 4096 * N2 the rows of the four-step split. For N2 <= 2^conv_max_fuse()
+// the strided N2-point transforms are folded into the row pass (ROWF: every
+// row work-group re-reads the column, which stays in L2 because the rows of
+// one operator are kept on one XCD), so a column costs one read of x, one
+// write and one read of the L-value intermediate and one write of y; longer
+// ones get a separate strided pass first (FS1, then FS2). The last pass (FS3)
+// applies the strided inverse transforms and the crop.
+//
 // The four-step columns are grouped into chunks whose intermediates fit a
 // region sized for the memory-side cache, and the passes are software
-// pipelined over the chunks: stage k runs pass 1 of chunk k, pass 2 of chunk
-// k-1 and pass 3 of chunk k-2 (three regions in rotation), plus a share of the
-// single-pass items. Each stage is one launch of a single kernel that maps
-// work-group g to item g of the stage; launch boundaries order the passes, so
-// no work-group ever waits for another.
+// pipelined over the chunks: chunk c runs its first pass in stage c, its
+// second in stage c+1 and (N2 >= 16) its third in stage c+2, with three
+// regions in rotation; the single-pass items are spread over the stages.
+// Each stage is one launch that maps work-group g to item g of the
+// stage; launch boundaries order the passes, so no work-group ever waits for
+// another. The rows of one column are placed at work-group indices that are
+// congruent modulo 8, i.e. on one XCD, where they share the column in L2.
+#include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <unordered_set>
 
@@ -26,7 +32,10 @@ namespace {
 
 using namespace xf;
 
-// A whole zero-padded convolution (length 2^lg <= 4096) of up to 4096/2^lg columns.
+constexpr int kXcds = 8;
+
+// Whole zero-padded convolutions of length 2^lg, it.sub columns.
+template <int LOGW>
 __device__ __forceinline__ void run_single(const BArgs& a, const Item& it, int lg, c64* smem) {
   const OpDev op = a.ops[it.op];
   const Ptrs pt = a.ptrs[it.op];
@@ -44,16 +53,16 @@ __device__ __forceinline__ void run_single(const BArgs& a, const Item& it, int l
   jb.sbstride = 0;
   jb.q0 = 0;
   const Mode md{FFT_CONV, a.adj, 0, 0, 0};
-  run_job<float, false>(jb, md, lg, smem, a.tw);
+  run_job<float, false, LOGW>(jb, md, lg, smem, a.tw);
 }
 
-// Pass 1 (first) or pass 3 of the four-step convolution: strided transforms of
-// length 2^lg at stride 4096 over 4096/2^lg neighbouring inner indices.
+// FS1 (first) or FS3: strided transforms of length 2^lg at stride 4096 over
+// 4096/2^lg neighbouring inner indices.
 __device__ __forceinline__ void run_strided(const BArgs& a, const Item& it, const FsCol& fc, int lg, bool first,
                                             c64* smem) {
   const OpDev op = a.ops[fc.op];
   const Ptrs pt = a.ptrs[fc.op];
-  const int tpw = 1 << (kLog1 - lg);
+  const int tpw = 1 << (kLogW - lg);
   const int i0 = it.sub * tpw;
   c64* w = a.wpool + fc.woff;
   Job<float> jb;
@@ -71,38 +80,48 @@ __device__ __forceinline__ void run_strided(const BArgs& a, const Item& it, cons
     jb.in_limit = a.adj ? op.m : op.n;
     jb.out_limit = L;
     const Mode md{FFT_FWD, 0, op.logL, 0, 0};
-    run_job<float, true>(jb, md, lg, smem, a.tw);
+    run_job<float, true, kLogW>(jb, md, lg, smem, a.tw);
   } else {
     jb.x = w + i0;
     jb.y = pt.y + int64_t(fc.col) * pt.ldy + i0;
     jb.in_limit = L;
     jb.out_limit = a.adj ? op.n : op.m;
     const Mode md{FFT_INV, 0, 0, 0, 0};
-    run_job<float, true>(jb, md, lg, smem, a.tw);
+    run_job<float, true, kLogW>(jb, md, lg, smem, a.tw);
   }
 }
 
-// Pass 2: one contiguous 4096-point row k2: transform, spectral product,
-// inverse transform, twiddles W_L^-(n1 k2), in place in the slot.
-__device__ __forceinline__ void run_row(const BArgs& a, const Item& it, const FsCol& fc, c64* smem) {
+// FS2 / ROWF: one contiguous 4096-point row k2: transform, spectral product,
+// inverse transform, twiddles W_L^-(n1 k2), into the column's slot. ROWF forms
+// the row from x itself (the strided 2^fuse-point transform and W_L^(n1 k2)).
+__device__ __forceinline__ void run_row(const BArgs& a, const Item& it, const FsCol& fc, int fuse, c64* smem) {
   const OpDev op = a.ops[fc.op];
   c64* row = a.wpool + fc.woff + (int64_t(it.sub) << kLog1);
   Job<float> jb;
-  jb.x = row;
+  if (fuse) {
+    const Ptrs pt = a.ptrs[fc.op];
+    jb.x = pt.x + int64_t(fc.col) * pt.ldx;
+    jb.in_limit = a.adj ? op.m : op.n;
+    jb.fuse_log2 = fuse;
+  } else {
+    jb.x = row;
+    jb.in_limit = 1 << kLog1;
+  }
   jb.y = row;
   jb.xbstride = jb.ybstride = 0;
   jb.inner = 1;
   jb.nvalid = 1;
-  jb.in_limit = jb.out_limit = 1 << kLog1;
+  jb.out_limit = 1 << kLog1;
   jb.i0 = 0;
   jb.S = op.spec + (int64_t(it.sub) << kLog1);
   jb.sbstride = 0;
   jb.q0 = it.sub;
   const Mode md{FFT_CONV, a.adj, op.logL, 1, 0};
-  run_job<float, false>(jb, md, kLog1, smem, a.tw);
+  run_job<float, false, kLogW>(jb, md, kLog1, smem, a.tw);
 }
 
-__global__ __launch_bounds__(kWG) void stage_kernel(BArgs a) {
+template <int LOGW>
+__global__ __launch_bounds__(Geo<LOGW>::kThreads) void stage_kernel(BArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   c64* smem = reinterpret_cast<c64*>(smem_raw);
   const Item it = a.items[blockIdx.x];
@@ -115,15 +134,19 @@ __global__ __launch_bounds__(kWG) void stage_kernel(BArgs a) {
       for (int c = 0; c < it.sub; ++c) any |= a.active[g0 + c] != 0;
       if (!any) return;
     }
-    run_single(a, it, lg, smem);
+    run_single<LOGW>(a, it, lg, smem);
     return;
   }
-  const FsCol fc = a.cols[it.col];
-  if (a.active && !a.active[a.ops[fc.op].col_base + fc.col]) return;
-  if (kind == IT_FS2)
-    run_row(a, it, fc, smem);
-  else
-    run_strided(a, it, fc, lg, kind == IT_FS1, smem);
+  if constexpr (LOGW == kLogW) {
+    const FsCol fc = a.cols[it.col];
+    if (a.active && !a.active[a.ops[fc.op].col_base + fc.col]) return;
+    if (kind == IT_ROWF)
+      run_row(a, it, fc, lg, smem);
+    else if (kind == IT_FS2)
+      run_row(a, it, fc, 0, smem);
+    else
+      run_strided(a, it, fc, lg, kind == IT_FS1, smem);
+  }
 }
 
 }  // namespace
@@ -205,7 +228,8 @@ fm_status fm::batch_launch(fm_batch_s* b, bool adj, const Ptrs* table, const int
     const int64_t n = b->stage_off[st + 1] - b->stage_off[st];
     if (n == 0) continue;
     a.items = items + b->stage_off[st];
-    hipLaunchKernelGGL(stage_kernel, dim3(unsigned(n)), dim3(kWG), job_lds_bytes<float>(), s, a);
+    hipLaunchKernelGGL(stage_kernel<kLogW>, dim3(unsigned(n)), dim3(Geo<kLogW>::kThreads),
+                       (job_lds_bytes<float, kLogW>()), s, a);
     FM_LAUNCHED();
   }
   return FM_OK;
@@ -234,7 +258,7 @@ fm_status fm_batch_create(fm_batch* out, int32_t nops, const fm_op* ops, const i
   FM_CHECK_ARG(b != nullptr, FM_E_NOMEM, "out of host memory");
   b->device = dev;
   std::vector<OpDev> hops(nops);
-  std::vector<Item> singles;
+  std::vector<Item> mid;  // single-pass items
   std::vector<FsCol> cols;
   std::vector<int> col_log2;
   for (int i = 0; i < nops; ++i) {
@@ -247,11 +271,11 @@ fm_status fm_batch_create(fm_batch* out, int32_t nops, const fm_op* ops, const i
                     b->total_cols};
     b->col_base.push_back(b->total_cols);
     b->total_cols += ncols[i];
-    if (logL <= kLog1) {
-      const int B = 1 << (kLog1 - logL);  // transforms per work-group
+    if (logL <= kLogW) {
+      const int B = 1 << (kLogW - logL);  // transforms per work-group
       for (int64_t c0 = 0; c0 < ncols[i]; c0 += B) {
         const int cnt = int(std::min<int64_t>(B, ncols[i] - c0));
-        singles.push_back(Item{IT_SINGLE | (logL << 8), i, int32_t(c0), cnt});
+        mid.push_back(Item{IT_SINGLE | (logL << 8), i, int32_t(c0), cnt});
       }
     } else {
       for (int64_t c = 0; c < ncols[i]; ++c) {
@@ -279,27 +303,69 @@ fm_status fm_batch_create(fm_batch* out, int32_t nops, const fm_op* ops, const i
   const int nchunks = int(chunks.size());
   for (int c = 0; c < nchunks; ++c)
     for (int j : chunks[c]) cols[j].woff += int64_t(c % 3) * int64_t(region_elems);
-  const int nstages = nchunks > 0 ? nchunks + 2 : (singles.empty() ? 0 : 1);
+  bool unfused = false;
+  const int max_fuse = conv_max_fuse();
+  for (int lg2 : col_log2) unfused |= lg2 > max_fuse;
+  const int nstages = nchunks > 0 ? nchunks + (unfused ? 2 : 1) : (mid.empty() ? 0 : 1);
+  // per stage: reuse groups (the rows of one column, which re-read its x and
+  // should share an XCD's L2)
+  std::vector<std::vector<std::vector<Item>>> groups(size_t(std::max(nstages, 0)));
+  for (int c = 0; c < nchunks; ++c) {
+    // group the columns of one operator within the chunk
+    std::vector<std::pair<int, std::vector<int>>> byop;
+    for (int j : chunks[c]) {
+      if (byop.empty() || byop.back().first != cols[j].op) byop.push_back({cols[j].op, {}});
+      byop.back().second.push_back(j);
+    }
+    for (const auto& og : byop) {
+      const int lg2 = col_log2[og.second[0]];
+      const int n2 = 1 << lg2;
+      const bool fuse = lg2 <= max_fuse;
+      const int npass = fuse ? 2 : 3;
+      for (int pass = 0; pass < npass; ++pass) {
+        std::vector<Item> g;
+        for (int j : og.second) {
+          for (int t = 0; t < n2; ++t) {
+            if (fuse && pass == 0)
+              g.push_back(Item{IT_ROWF | (lg2 << 8), cols[j].op, j, t});
+            else if (!fuse && pass == 0)
+              g.push_back(Item{IT_FS1 | (lg2 << 8), cols[j].op, j, t});
+            else if (!fuse && pass == 1)
+              g.push_back(Item{IT_FS2 | (kLog1 << 8), cols[j].op, j, t});
+            else
+              g.push_back(Item{IT_FS3 | (lg2 << 8), cols[j].op, j, t});
+          }
+        }
+        for (size_t q0 = 0; q0 < g.size(); q0 += size_t(n2))  // one reuse group per column
+          groups[size_t(c + pass)].push_back(std::vector<Item>(g.begin() + q0, g.begin() + q0 + n2));
+      }
+    }
+  }
+  // middle-length single-pass items spread evenly over the stages
+  for (size_t k = 0; k < mid.size(); ++k) {
+    const size_t st = nstages > 0 ? k * size_t(nstages) / mid.size() : 0;
+    groups[st].push_back({mid[k]});
+  }
+  // lay out each stage: each group goes to the currently shortest XCD queue,
+  // then the queues are interleaved (work-group g runs on XCD g mod 8). A
+  // column per group keeps the queues balanced; grouping whole operators
+  // measured slower.
   std::vector<Item> items;
-  size_t si = 0;
   b->stage_off.push_back(0);
-  for (int s = 0; s < nstages; ++s) {
-    if (s < nchunks)  // pass 1 of chunk s
-      for (int j : chunks[s])
-        for (int t = 0; t < (1 << col_log2[j]); ++t)
-          items.push_back(Item{IT_FS1 | (col_log2[j] << 8), cols[j].op, j, t});
-    if (s - 1 >= 0 && s - 1 < nchunks)  // pass 2 of chunk s-1
-      for (int j : chunks[s - 1])
-        for (int r = 0; r < (1 << col_log2[j]); ++r)
-          items.push_back(Item{IT_FS2 | (kLog1 << 8), cols[j].op, j, r});
-    if (s - 2 >= 0 && s - 2 < nchunks)  // pass 3 of chunk s-2
-      for (int j : chunks[s - 2])
-        for (int t = 0; t < (1 << col_log2[j]); ++t)
-          items.push_back(Item{IT_FS3 | (col_log2[j] << 8), cols[j].op, j, t});
-    const size_t want = size_t(double(s + 1) / nstages * singles.size());
-    while (si < want) items.push_back(singles[si++]);
-    if (s == nstages - 1)
-      while (si < singles.size()) items.push_back(singles[si++]);
+  for (int st = 0; st < nstages; ++st) {
+    std::vector<std::vector<Item>> q(kXcds);
+    auto& gs = groups[size_t(st)];
+    for (auto& g : gs) {
+      int best = 0;
+      for (int x = 1; x < kXcds; ++x)
+        if (q[x].size() < q[best].size()) best = x;
+      q[best].insert(q[best].end(), g.begin(), g.end());
+    }
+    size_t longest = 0;
+    for (const auto& v : q) longest = std::max(longest, v.size());
+    for (size_t r = 0; r < longest; ++r)
+      for (int x = 0; x < kXcds; ++x)
+        if (r < q[x].size()) items.push_back(q[x][r]);
     b->stage_off.push_back(int64_t(items.size()));
   }
   fm_status st = FM_OK;

@@ -126,9 +126,31 @@ fm_status exec_conv(const fm_op_s* op, bool adj, Elem e, const Batch& b, const v
   const int64_t n1 = int64_t(1) << sp.log1, n2 = int64_t(1) << sp.log2;
   const size_t mk = ws.mark();
   void* w = ws.take(size_t(b.ncols * b.outer * L) * elem_bytes(e));
-  // step 1: forward length-n2 transforms at stride n1 of the zero-padded input,
-  // then twiddles W_L^(k2 n1)
-  FftLaunch f1;
+  Batch fb;
+  if (sp.log1 == fft_lds_max_log(e) && sp.log2 <= conv_max_fuse() && fold_outer(b, nin, nout, &fb) &&
+      fb.outer == 1) {
+    // rows k2 formed from x directly (strided n2-point transform folded into
+    // the load), transform, spectral product, inverse, twiddles W_L^-(n1 k2)
+    FftLaunch fr;
+    fr.elem = e;
+    fr.logn = sp.log1;
+    fr.mode = FFT_CONV;
+    fr.b = Batch{fb.ncols, n2, 1, fb.ldx, 0, L, n1};
+    fr.x = x;
+    fr.y = w;
+    fr.in_limit = nin;
+    fr.out_limit = n1;
+    fr.spec = spec;
+    fr.spec_ostride = n1;
+    fr.spec_conj = adj;
+    fr.tw_log = sp.logL;
+    fr.tw_inv = 1;
+    fr.fuse_log2 = sp.log2;
+    LAUNCH(launch_fft(fr, s));
+  } else {
+    // step 1: forward length-n2 transforms at stride n1 of the zero-padded
+    // input, then twiddles W_L^(k2 n1)
+    FftLaunch f1;
   f1.elem = e;
   f1.logn = sp.log2;
   f1.mode = FFT_FWD;
@@ -155,6 +177,7 @@ fm_status exec_conv(const fm_op_s* op, bool adj, Elem e, const Batch& b, const v
   f2.tw_log = sp.logL;
   f2.tw_inv = 1;
   LAUNCH(launch_fft(f2, s));
+  }
   // step 3: inverse length-n2 transforms at stride n1, cropped store
   FftLaunch f3;
   f3.elem = e;

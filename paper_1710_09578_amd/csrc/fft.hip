@@ -19,16 +19,16 @@ struct KArgs {
   const void* spec;
   int64_t spec_ostride;
   const void* tw;
-  int mode, spec_conj, tw_log, tw_inv, accumulate, logn;
+  int mode, spec_conj, tw_log, tw_inv, accumulate, logn, fuse_log2;
   int layout;  // contiguous: 0 transforms = columns, 1 packed (ncols*outer), 2 per column
   int64_t tiles;  // work-groups per column (layout 2) / per vector (strided)
 };
 
-template <typename R, bool STRIDED>
-__global__ __launch_bounds__(kWG) void fft_kernel(KArgs a) {
+template <typename R, bool STRIDED, int LOGW>
+__global__ __launch_bounds__(Geo<LOGW>::kThreads) void fft_kernel(KArgs a) {
   extern __shared__ unsigned char smem_raw[];
   Cx<R>* lds = reinterpret_cast<Cx<R>*>(smem_raw);
-  const int tpw = 1 << (kMaxLog - a.logn);  // transforms per work-group
+  const int tpw = 1 << (LOGW - a.logn);  // transforms per work-group
   Job<R> jb;
   jb.in_limit = a.in_limit;
   jb.out_limit = a.out_limit;
@@ -86,13 +86,14 @@ __global__ __launch_bounds__(kWG) void fft_kernel(KArgs a) {
       jb.q0 = int(o0);
     }
   }
+  jb.fuse_log2 = a.fuse_log2;
   const Mode md{a.mode, a.spec_conj, a.tw_log, a.tw_inv, a.accumulate};
-  run_job<R, STRIDED>(jb, md, a.logn, lds, reinterpret_cast<const Cx<R>*>(a.tw));
+  run_job<R, STRIDED, LOGW>(jb, md, a.logn, lds, reinterpret_cast<const Cx<R>*>(a.tw));
 }
 
-template <typename R>
+template <typename R, int LOGW>
 fm_status launch_typed(const FftLaunch& L, KArgs ka, hipStream_t s) {
-  const int tpw = 1 << (kMaxLog - L.logn);
+  const int tpw = 1 << (LOGW - L.logn);
   const bool strided = L.b.inner > 1;
   int64_t blocks;
   if (strided) {
@@ -101,7 +102,7 @@ fm_status launch_typed(const FftLaunch& L, KArgs ka, hipStream_t s) {
   } else if (L.b.outer == 1) {
     ka.layout = 0;
     blocks = cdiv(L.b.ncols, tpw);
-  } else if (L.spec_ostride == 0 && L.tw_log == 0 &&
+  } else if (L.spec_ostride == 0 && L.tw_log == 0 && L.fuse_log2 == 0 &&
              (L.b.ncols == 1 || (L.b.ldx == L.b.outer * L.b.xvs && L.b.ldy == L.b.outer * L.b.yvs))) {
     ka.layout = 1;
     blocks = cdiv(L.b.ncols * L.b.outer, tpw);
@@ -114,18 +115,21 @@ fm_status launch_typed(const FftLaunch& L, KArgs ka, hipStream_t s) {
                "fft: grid of %lld work-groups is out of range", (long long)blocks);
   FM_CHECK_ARG((int64_t(1) << L.logn) * L.b.inner < (int64_t(1) << 30), FM_E_UNSUPPORTED,
                "fft: vector span above 2^30 elements");
+  FM_CHECK_ARG(L.fuse_log2 == 0 || (!strided && ka.layout == 2 && L.logn == LOGW && L.fuse_log2 <= 5),
+               FM_E_UNSUPPORTED, "fft: fused column transform needs a full-size row per work-group");
   static bool attr_set = false;
   if (!attr_set) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&fft_kernel<R, true>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&fft_kernel<R, true, LOGW>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&fft_kernel<R, false>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&fft_kernel<R, false, LOGW>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr_set = true;
   }
+  const dim3 wg(Geo<LOGW>::kThreads);
   if (strided)
-    hipLaunchKernelGGL((fft_kernel<R, true>), dim3(unsigned(blocks)), dim3(kWG), job_lds_bytes<R>(), s, ka);
+    hipLaunchKernelGGL((fft_kernel<R, true, LOGW>), dim3(unsigned(blocks)), wg, (job_lds_bytes<R, LOGW>()), s, ka);
   else
-    hipLaunchKernelGGL((fft_kernel<R, false>), dim3(unsigned(blocks)), dim3(kWG), job_lds_bytes<R>(), s, ka);
+    hipLaunchKernelGGL((fft_kernel<R, false, LOGW>), dim3(unsigned(blocks)), wg, (job_lds_bytes<R, LOGW>()), s, ka);
   FM_LAUNCHED();
   return FM_OK;
 }
@@ -134,9 +138,9 @@ fm_status launch_typed(const FftLaunch& L, KArgs ka, hipStream_t s) {
 
 fm_status launch_fft(const FftLaunch& L, hipStream_t s) {
   if (L.b.ncols == 0 || L.b.outer == 0 || L.b.inner == 0) return FM_OK;
-  FM_CHECK_ARG(L.logn >= 0 && L.logn <= kMaxLog, FM_E_UNSUPPORTED, "fft: length 2^%d above the single-pass limit",
-               L.logn);
   FM_CHECK_ARG(L.elem == Elem::C64 || L.elem == Elem::C128, FM_E_DTYPE, "fft: integer element type");
+  FM_CHECK_ARG(L.logn >= 0 && L.logn <= fft_lds_max_log(L.elem), FM_E_UNSUPPORTED,
+               "fft: length 2^%d above the single-pass limit", L.logn);
   KArgs ka{};
   ka.x = L.x;
   ka.y = L.y;
@@ -157,10 +161,13 @@ fm_status launch_fft(const FftLaunch& L, hipStream_t s) {
   ka.tw_inv = L.tw_inv;
   ka.accumulate = L.accumulate;
   ka.logn = L.logn;
-  const int need_log = L.tw_log > L.logn ? L.tw_log : L.logn;
+  ka.fuse_log2 = L.fuse_log2;
+  int need_log = L.tw_log > L.logn ? L.tw_log : L.logn;
+  if (L.logn + L.fuse_log2 > need_log) need_log = L.logn + L.fuse_log2;
   ka.tw = twiddle_table(L.elem, need_log);
   FM_CHECK_ARG(ka.tw != nullptr, FM_E_DEVICE, "fft: twiddle table unavailable: %s", last_error());
-  return L.elem == Elem::C64 ? launch_typed<float>(L, ka, s) : launch_typed<double>(L, ka, s);
+  if (L.elem == Elem::C128) return launch_typed<double, 12>(L, ka, s);
+  return launch_typed<float, 12>(L, ka, s);
 }
 
 // ---------------------------------------------------------------- transpose

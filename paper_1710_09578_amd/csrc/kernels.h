@@ -20,8 +20,16 @@ inline size_t elem_bytes(Elem e) {
 }
 
 // ---------------------------------------------------------------- FFT
-// Largest transform length held in one work-group's LDS.
+// Largest transform length held in one work-group's LDS (4096 values, 256
+// threads: three to four work-groups share a CU and hide each other's
+// latency; a 16384-value work-group fills a CU alone and measured slower).
 inline int fft_lds_max_log(Elem) { return 12; }
+
+// Largest strided factor 2^k of a four-step convolution that is folded into
+// the row pass (the row work-group forms its row from x directly); longer
+// ones get a separate strided pass. FM_MAX_FUSE overrides the default (0
+// disables folding).
+int conv_max_fuse();
 
 enum FftMode { FFT_FWD = 0, FFT_INV = 1, FFT_CONV = 2 };
 
@@ -40,6 +48,8 @@ struct FftLaunch {
   int tw_log = 0;          // > 0: multiply result r by W^(r*q), W = exp(-+2 pi j / 2^tw_log),
   int tw_inv = 0;          //      q = i (strided) or o (contiguous); tw_inv picks the + sign
   int accumulate = 0;      // y += result
+  int fuse_log2 = 0;       // > 0: row o = k2 of a four-step convolution formed from the column x
+                           //      (L = 2^(logn + fuse_log2), logn = 12; see xform.h)
 };
 fm_status launch_fft(const FftLaunch& L, hipStream_t s);
 

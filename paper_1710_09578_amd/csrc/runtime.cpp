@@ -1,5 +1,6 @@
 // Runtime support: error text, device buffers, twiddle tables, live-handle
 // registry and the per-precision split of long transforms.
+#include <cstdlib>
 #include "runtime.h"
 
 #include <cmath>
@@ -48,6 +49,15 @@ Elem elem_of(fm_dtype dt) {
     case FM_I32: return Elem::I32;
     default: return Elem::I64;
   }
+}
+
+int conv_max_fuse() {
+  static const int v = [] {
+    const char* e = std::getenv("FM_MAX_FUSE");
+    int k = e ? std::atoi(e) : 3;  // measured best on a log-uniform Toeplitz mix
+    return k < 0 ? 0 : (k > 5 ? 5 : k);
+  }();
+  return v;
 }
 
 Split split_for(Elem e, int logL) {

@@ -2,12 +2,13 @@
 // stage kernel (the fast transform behind the DFT of eq. (1) and the
 // cyclic convolution of eq. (5)).
 //
-// A work-group of 256 threads always holds 4096 complex values: 16 per thread
-// in registers.
+// A work-group holds 2^LOGW complex values, 16 per thread in registers
+// (256 threads for LOGW = 12).
 //
-// Transforms of N = 2^n >= 16 points (n <= 12) are held by T = N/16 threads,
-// thread t holding positions t + T*k (k = 0..15), and the work-group holds
-// 4096/N of them. The transform is a sequence of Stockham steps: one short
+// Transforms of N = 2^n >= 16 points (n <= LOGW) are held by T = N/16
+// threads, thread t holding positions t + T*k (k = 0..15), and the
+// work-group holds 2^LOGW/N of them. The arithmetic of one transform does not
+// depend on LOGW, so both engines give the same bits. The transform is a sequence of Stockham steps: one short
 // radix-2/4/8 step first when n is not a multiple of 4, then radix-16 steps.
 // Butterfly j of a step with radix R and span Ns reads positions j + r*N/R --
 // in the thread's own registers -- multiplies by W_{Ns R}^{(j mod Ns) r}, runs
@@ -30,9 +31,12 @@
 namespace fm {
 namespace xf {
 
-constexpr int kWG = 256;   // threads per work-group
-constexpr int kE = 16;     // values per thread
-constexpr int kMaxLog = 12;
+constexpr int kE = 16;  // values per thread
+template <int LOGW>
+struct Geo {
+  static constexpr int kThreads = 1 << (LOGW - 4);
+  static constexpr int kVals = 1 << LOGW;
+};
 
 // cos of 2 pi m / 16, m = 0..4 (sin by symmetry)
 __device__ constexpr double kCos16[5] = {1.0, 0.92387953251128675613, 0.70710678118654752440,
@@ -199,11 +203,16 @@ __device__ __forceinline__ void forward_tiny(Cx<R>* v, int logn) {
 }
 
 // ---------------------------------------------------------------- one work-group's job
-// A work-group's 4096 values are 4096/N transforms. Transform b (0 <= b <
-// 4096/N) starts at base + b*bstride (contiguous vectors) or at base + b
-// (strided vectors, element r at r*inner); its spectrum row starts at
-// S + b*sbstride; its twiddle-epilogue index is q0 + b. Transforms with
-// b >= nvalid are computed on zeros and not stored.
+// A work-group's 2^LOGW values are 2^LOGW/N transforms. Transform b starts at
+// base + b*bstride (contiguous vectors) or at base + b (strided vectors,
+// element r at r*inner); its spectrum row starts at S + b*sbstride; its
+// twiddle-epilogue index is q0 + b. Transforms with b >= nvalid are computed
+// on zeros and not stored.
+//
+// Fused input (fuse_log2 > 0, contiguous, one transform per work-group): the
+// row k2 = q0 of a four-step convolution with L = N * N2 (N2 = 2^fuse_log2 <=
+// 32) is formed while loading: point p is sum_n2 x[p + N n2] W_N2^(n2 k2)
+// (zero beyond in_limit), times W_L^(p k2); x is the column base.
 template <typename R>
 struct Job {
   const Cx<R>* x;
@@ -217,15 +226,17 @@ struct Job {
   const Cx<R>* S;
   int64_t sbstride;
   int q0;
+  int fuse_log2 = 0;
 };
 struct Mode {
   int mode, spec_conj, tw_log, tw_inv, accumulate;
 };
 
 // Loads, transforms and stores one job. Every thread of the work-group calls it.
-template <typename R, bool STRIDED>
+template <typename R, bool STRIDED, int LOGW>
 __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int logn, Cx<R>* lds,
                                         const Cx<R>* __restrict__ tw) {
+  constexpr int kWG = Geo<LOGW>::kThreads;
   const int tid = threadIdx.x;
   Cx<R> v[kE];
   if (logn >= 4) {
@@ -238,11 +249,39 @@ __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int lo
     const int ii = STRIDED ? jb.i0 + b : 0;
     const Cx<R>* X = STRIDED ? jb.x + b : jb.x + b * jb.xbstride;
     Cx<R>* Y = STRIDED ? jb.y + b : jb.y + b * jb.ybstride;
+    if (!STRIDED && jb.fuse_log2 > 0) {
+      // n2-outer order: the 16 loads of one n2 are in flight together and
+      // consumed only after all of them were issued
+      const int n2s = 1 << jb.fuse_log2;
+      const int k2 = jb.q0;
+      const int N = 1 << logn;
+      const int lgL = logn + jb.fuse_log2;
 #pragma unroll
-    for (int k = 0; k < kE; ++k) {
-      const int p = t + T * k;
-      const bool in = valid && p * inner + ii < jb.in_limit;
-      v[k] = in ? X[p * inner] : Cx<R>{R(0), R(0)};
+      for (int k = 0; k < kE; ++k) v[k] = Cx<R>{R(0), R(0)};
+      const int n2e = (jb.in_limit + N - 1) / N < n2s ? (jb.in_limit + N - 1) / N : n2s;  // rows holding data
+      for (int n2 = 0; n2 < n2e; ++n2) {
+        Cx<R> val[kE];
+#pragma unroll
+        for (int k = 0; k < kE; ++k) {
+          const int q = t + T * k + N * n2;
+          val[k] = q < jb.in_limit ? X[q] : Cx<R>{R(0), R(0)};
+        }
+        const Cx<R> w = tw[n2s + ((n2 * k2) & (n2s - 1))];
+#pragma unroll
+        for (int k = 0; k < kE; ++k) v[k] = cadd(v[k], cmul(val[k], w));
+      }
+#pragma unroll
+      for (int k = 0; k < kE; ++k) {
+        const int p = t + T * k;
+        v[k] = cmul(v[k], tw[(1 << lgL) + ((p * k2) & ((1 << lgL) - 1))]);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < kE; ++k) {
+        const int p = t + T * k;
+        const bool in = valid && p * inner + ii < jb.in_limit;
+        v[k] = in ? X[p * inner] : Cx<R>{R(0), R(0)};
+      }
     }
     Cx<R>* my = lds + b * ((1 << logn) + (1 << (logn - 4)));
     if (md.mode == FFT_INV) conj_all(v);
@@ -349,9 +388,9 @@ __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int lo
 }
 
 // LDS bytes of one work-group.
-template <typename R>
+template <typename R, int LOGW>
 constexpr size_t job_lds_bytes() {
-  return size_t(4096 + 256) * sizeof(Cx<R>);
+  return size_t(Geo<LOGW>::kVals + Geo<LOGW>::kVals / 16) * sizeof(Cx<R>);
 }
 
 }  // namespace xf
