@@ -373,6 +373,7 @@ def main():
     ap.add_argument("--no-fista", action="store_true")
     ap.add_argument("--no-learn", action="store_true")
     ap.add_argument("--no-kron", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default batch schedule")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 512 MiB device to device (reference for traffic counters)")
     args = ap.parse_args()
@@ -405,6 +406,10 @@ def main():
     log(f"plain (one fm_apply per operator and direction): {plain_ms:.3f} ms/step, {plain_gbs:.1f} GB/s")
 
     step, launch, _batch = batched_step_factory(w)
+    sched = _batch.schedule()
+    if not args.no_tune:
+        sched = _batch.tune(w["xs"], outs=w["ys"], reps=2)
+        log(f"tuned schedule: {sched}")
     ms, gpu_ms = time_steps(step, args.steps, args.warmup)
     gbs = alg / (ms * 1e-3) / 1e9
     log(f"batched: {ms:.3f} ms/step wall, {gpu_ms:.3f} ms/step events, {gbs:.1f} GB/s")
@@ -454,8 +459,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "512 Toeplitz operators, N log-uniform in [256, 65536], 1-32 "
                                "columns each, complex64, fwd+adj",
-                   "path": "batched (fm_batch_apply: one software-pipelined sequence of stage launches per direction)",
+                   "path": "batched (fm_batch_apply: software-pipelined stage launches replayed from a HIP graph, schedule from fm_batch_tune)",
                    "alg_bytes_per_step": w["alg_bytes"],
+                   "schedule": sched,
                    "plain_gbs": round(plain_gbs, 2),
                    "batched_over_plain": round(gbs / plain_gbs, 2),
                    "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)},

@@ -210,7 +210,9 @@ fm_status fm_power_iteration(fm_op a, const void* v0, uint64_t seed, int32_t max
  * column; longer ones take three passes of a four-step split, chunked so
  * that the intermediate buffers of three chunks in flight stay in a fixed
  * device pool. One direction is a few stage launches on `stream`, with no
- * host synchronisation and no waits between workgroups. ops: composite-free
+ * host synchronisation and no waits between workgroups; after its first use
+ * with a given set of pointers the sequence is replayed from a captured HIP
+ * graph (FM_BATCH_GRAPH=0 disables capture). ops: composite-free
  * Circulant or Toeplitz operators of one complex dtype on the current device;
  * ncols[i] >= 1 columns of operator i. The batch holds references to its
  * operators until fm_batch_release. */
@@ -230,6 +232,28 @@ fm_status fm_batch_fista(fm_batch b, const void* const* bvec, const int64_t* ldb
                          const int64_t* ldx, const fm_fista_opts* opts, fm_fista_stat* stats,
                          void* stream);
 fm_status fm_batch_release(fm_batch b);
+
+/* Schedule of a batch (see fm_batch_tune). */
+typedef struct {
+  int32_t max_fuse;    /* strided four-step factors up to 2^max_fuse are folded into the row pass */
+  int32_t region_mib;  /* slot region of one chunk of four-step columns (three rotate), MiB */
+  int32_t graphs;      /* 1: the stage sequence is replayed from captured HIP graphs */
+  double ms;           /* measured milliseconds per direction (fm_batch_tune), else 0 */
+} fm_batch_schedule;
+
+/* Autotuner, in the spirit of the paper's run-time calibration (Sec. 2.1):
+ * times fm_batch_apply(dir) on the caller's blocks for every candidate
+ * schedule (max_fuse 0..5 x slot regions of 24, 48 and 96 MiB), `reps`
+ * timed runs each after one warm-up, and keeps the fastest. y receives the
+ * correct result. Synchronises the device. A schedule whose max_fuse differs
+ * from the per-operator path's default (3, FM_MAX_FUSE) computes the same
+ * products with a different rounding order, so results then agree with
+ * fm_apply to rounding rather than bit for bit. `chosen` may be NULL. */
+fm_status fm_batch_tune(fm_batch b, fm_dir dir, const void* const* x, const int64_t* ldx,
+                        void* const* y, const int64_t* ldy, int32_t reps, fm_batch_schedule* chosen,
+                        void* stream);
+/* The batch's current schedule. */
+fm_status fm_batch_get_schedule(fm_batch b, fm_batch_schedule* out);
 
 /* ------------------------------------------------------------------ differentiation
  * Building blocks of reverse-mode differentiation through operator

@@ -67,6 +67,15 @@ class fm_fista_stat(C.Structure):
     ]
 
 
+class fm_batch_schedule(C.Structure):
+    _fields_ = [
+        ("max_fuse", C.c_int32),
+        ("region_mib", C.c_int32),
+        ("graphs", C.c_int32),
+        ("ms", C.c_double),
+    ]
+
+
 P = C.c_void_p
 I64 = C.c_int64
 I32 = C.c_int32
@@ -98,6 +107,9 @@ SIGNATURES = {
     "fm_batch_fista": (ST, [P, C.POINTER(P), C.POINTER(I64), C.POINTER(P), C.POINTER(I64),
                             C.POINTER(fm_fista_opts), C.POINTER(fm_fista_stat), P]),
     "fm_batch_release": (ST, [P]),
+    "fm_batch_tune": (ST, [P, C.c_int, C.POINTER(P), C.POINTER(I64), C.POINTER(P), C.POINTER(I64), I32,
+                           C.POINTER(fm_batch_schedule), P]),
+    "fm_batch_get_schedule": (ST, [P, C.POINTER(fm_batch_schedule)]),
     "fm_circulant_grad_generator": (ST, [I64, I64, C.c_int, P, I64, P, I64, P, I32, C.c_int, P]),
     "fm_fista_step": (ST, [I64, I64, P, P, P, P, P, P, I64, P, C.c_double, C.c_double, C.c_int, P]),
     "fm_fista_step_vjp": (ST, [I64, I64, P, P, P, P, P, P, I64, P, C.c_double, C.c_double, C.c_int, P]),
@@ -280,6 +292,19 @@ def fm_batch_apply(b, direction, xs, ldx, ys, ldy, stream):
 def fm_batch_fista(b, bvecs, ldb, xs, ldx, opts, stats, stream):
     _call("fm_batch_fista", b, _parr(bvecs), _iarr(ldb), _parr(xs), _iarr(ldx), C.byref(opts),
           C.cast(stats, C.POINTER(fm_fista_stat)) if stats is not None else None, _ptr(stream))
+
+
+def fm_batch_tune(b, direction, xs, ldx, ys, ldy, reps, stream):
+    sc = fm_batch_schedule()
+    _call("fm_batch_tune", b, direction, _parr(xs), _iarr(ldx), _parr(ys), _iarr(ldy), reps, C.byref(sc),
+          _ptr(stream))
+    return {"max_fuse": sc.max_fuse, "region_mib": sc.region_mib, "graphs": sc.graphs, "ms": sc.ms}
+
+
+def fm_batch_get_schedule(b):
+    sc = fm_batch_schedule()
+    _call("fm_batch_get_schedule", b, C.byref(sc))
+    return {"max_fuse": sc.max_fuse, "region_mib": sc.region_mib, "graphs": sc.graphs, "ms": sc.ms}
 
 
 def fm_batch_release(b):

@@ -10,7 +10,6 @@ namespace fm {
 
 constexpr int kLogW = 12;   // values per work-group of the stage kernel
 constexpr int kLog1 = 12;   // contiguous factor of the four-step split (complex64)
-constexpr size_t kRegionBytes = size_t(48) << 20;  // intermediates of one chunk
 
 // Work items (one work-group each):
 //   SINGLE  whole zero-padded convolutions of length 2^lg for `sub` columns
@@ -48,6 +47,20 @@ struct Ptrs {
   int64_t ldx, ldy;
 };
 
+// Tunable parameters of a batch's work list.
+struct Schedule {
+  int max_fuse = 3;                         // strided factors up to 2^max_fuse folded into the row pass
+  size_t region_bytes = size_t(48) << 20;   // slot region of one chunk (three rotate)
+};
+
+struct GraphEntry {
+  bool adj;
+  const void* table;
+  const int* active;
+  hipGraphExec_t exec;
+  uint64_t last_use;
+};
+
 struct BArgs {
   const Item* items;  // this stage's items
   const OpDev* ops;
@@ -71,6 +84,13 @@ struct fm_batch_s {
   int64_t total_cols = 0;
   fm::DevBuf d_items, d_ops, d_cols, d_ptrs, d_wpool;
   std::vector<int64_t> stage_off;  // stage s: items [stage_off[s], stage_off[s+1])
+  fm::Schedule sched;
+  // captured stage sequences, keyed by direction, pointer table and mask
+  bool use_graphs = true;
+  hipStream_t cap_stream = nullptr;
+  std::vector<fm::GraphEntry> graphs;
+  uint64_t graph_clock = 0;
+  double tuned_ms = 0.0;
   // pointer tables: kTables device copies, each with a pinned staging buffer,
   // the event after its last upload and the pointers it holds
   static constexpr int kTables = 6;
@@ -93,5 +113,10 @@ bool batch_alive(const fm_batch_s* b);
 // Uploads (or finds) the device pointer table for b->cur; returns its address.
 fm_status batch_pointer_table(fm_batch_s* b, hipStream_t s, const Ptrs** table);
 // Launches every stage of one direction; active: per batch column or NULL.
+// The stage sequence is replayed from a captured graph when possible.
 fm_status batch_launch(fm_batch_s* b, bool adj, const Ptrs* table, const int* active, hipStream_t s);
+// Rebuilds the work list for a schedule (synchronises the device).
+fm_status build_schedule(fm_batch_s* b, const Schedule& sc);
+// Destroys the captured graphs.
+void drop_graphs(fm_batch_s* b);
 }  // namespace fm

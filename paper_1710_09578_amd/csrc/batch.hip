@@ -173,6 +173,9 @@ void destroy_batch(fm_batch_s* b) {
     std::lock_guard<std::mutex> lock(g_batch_mu);
     live_batches().erase(b);
   }
+  if (!b->graphs.empty()) (void)hipDeviceSynchronize();
+  drop_graphs(b);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   for (int k = 0; k < fm_batch_s::kTables; ++k)
     if (b->uploaded[k]) (void)hipEventSynchronize(b->uploaded[k]), (void)hipEventDestroy(b->uploaded[k]);
   if (b->staging) (void)hipHostFree(b->staging);
@@ -212,6 +215,51 @@ fm_status fm::batch_pointer_table(fm_batch_s* b, hipStream_t s, const Ptrs** tab
   return FM_OK;
 }
 
+void fm::drop_graphs(fm_batch_s* b) {
+  for (auto& g : b->graphs) (void)hipGraphExecDestroy(g.exec);
+  b->graphs.clear();
+}
+
+namespace {
+
+fm_status launch_stages(fm_batch_s* b, const BArgs& a0, hipStream_t s) {
+  BArgs a = a0;
+  const Item* items = static_cast<const Item*>(b->d_items.p);
+  for (size_t st = 0; st + 1 < b->stage_off.size(); ++st) {
+    const int64_t n = b->stage_off[st + 1] - b->stage_off[st];
+    if (n == 0) continue;
+    a.items = items + b->stage_off[st];
+    hipLaunchKernelGGL(stage_kernel<kLogW>, dim3(unsigned(n)), dim3(Geo<kLogW>::kThreads),
+                       (job_lds_bytes<float, kLogW>()), s, a);
+    FM_LAUNCHED();
+  }
+  return FM_OK;
+}
+
+// Captures the stage sequence of one (direction, table, mask) on the batch's
+// own stream; nullptr when capture is not possible.
+hipGraphExec_t capture(fm_batch_s* b, const BArgs& a) {
+  if (hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return nullptr;
+  const fm_status st = launch_stages(b, a, b->cap_stream);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+  if (st != FM_OK || e != hipSuccess || g == nullptr) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return exec;
+}
+
+}  // namespace
+
 fm_status fm::batch_launch(fm_batch_s* b, bool adj, const Ptrs* table, const int* active, hipStream_t s) {
   const void* tw = twiddle_table(Elem::C64, 20);
   FM_CHECK_ARG(tw != nullptr, FM_E_DEVICE, "twiddle table unavailable");
@@ -223,15 +271,153 @@ fm_status fm::batch_launch(fm_batch_s* b, bool adj, const Ptrs* table, const int
   a.tw = static_cast<const c64*>(tw);
   a.adj = adj;
   a.active = active;
-  const Item* items = static_cast<const Item*>(b->d_items.p);
-  for (size_t st = 0; st + 1 < b->stage_off.size(); ++st) {
-    const int64_t n = b->stage_off[st + 1] - b->stage_off[st];
-    if (n == 0) continue;
-    a.items = items + b->stage_off[st];
-    hipLaunchKernelGGL(stage_kernel<kLogW>, dim3(unsigned(n)), dim3(Geo<kLogW>::kThreads),
-                       (job_lds_bytes<float, kLogW>()), s, a);
-    FM_LAUNCHED();
+  if (b->stage_off.size() < 2) return FM_OK;
+  if (b->use_graphs) {
+    GraphEntry* hit = nullptr;
+    for (auto& g : b->graphs)
+      if (g.adj == adj && g.table == table && g.active == active) hit = &g;
+    if (!hit) {
+      hipGraphExec_t exec = capture(b, a);
+      if (exec) {
+        constexpr size_t kMaxGraphs = 16;
+        if (b->graphs.size() >= kMaxGraphs) {  // evict the least recently used
+          size_t lru = 0;
+          for (size_t k = 1; k < b->graphs.size(); ++k)
+            if (b->graphs[k].last_use < b->graphs[lru].last_use) lru = k;
+          FM_HIP(hipStreamSynchronize(s));  // it may still be running
+          (void)hipGraphExecDestroy(b->graphs[lru].exec);
+          b->graphs.erase(b->graphs.begin() + long(lru));
+        }
+        b->graphs.push_back(GraphEntry{adj, table, active, exec, 0});
+        hit = &b->graphs.back();
+      } else {
+        b->use_graphs = false;  // this device / runtime cannot capture: launch directly from now on
+      }
+    }
+    if (hit) {
+      hit->last_use = ++b->graph_clock;
+      FM_HIP(hipGraphLaunch(hit->exec, s));
+      return FM_OK;
+    }
   }
+  return launch_stages(b, a, s);
+}
+
+// Work list of one schedule: items per stage, four-step column descriptors
+// and the slot pool. Replaces the current schedule (and drops the captured
+// graphs, which bake in its buffers).
+fm_status fm::build_schedule(fm_batch_s* b, const Schedule& sc) {
+  const int nops = int(b->ops.size());
+  std::vector<Item> mid;  // single-pass items
+  std::vector<FsCol> cols;
+  std::vector<int> col_log2;
+  for (int i = 0; i < nops; ++i) {
+    const int logL = ilog2(b->ops[i]->L);
+    const int64_t nc = b->ncols[i];
+    if (logL <= kLogW) {
+      const int B = 1 << (kLogW - logL);  // transforms per work-group
+      for (int64_t c0 = 0; c0 < nc; c0 += B) {
+        const int cnt = int(std::min<int64_t>(B, nc - c0));
+        mid.push_back(Item{IT_SINGLE | (logL << 8), i, int32_t(c0), cnt});
+      }
+    } else {
+      for (int64_t c = 0; c < nc; ++c) {
+        cols.push_back(FsCol{i, int32_t(c), 0});
+        col_log2.push_back(logL - kLog1);
+      }
+    }
+  }
+  // chunks of columns whose intermediates fit one region; three regions rotate
+  const size_t region_elems = sc.region_bytes / sizeof(c64);
+  std::vector<std::vector<int>> chunks;
+  {
+    size_t used = region_elems;  // forces a first chunk
+    for (int j = 0; j < int(cols.size()); ++j) {
+      const size_t L = size_t(1) << (col_log2[j] + kLog1);
+      FM_CHECK_ARG(L <= region_elems, FM_E_UNSUPPORTED, "batch: slot region smaller than one column");
+      if (used + L > region_elems) {
+        chunks.emplace_back();
+        used = 0;
+      }
+      cols[j].woff = int64_t(used);  // offset inside the chunk's region
+      used += L;
+      chunks.back().push_back(j);
+    }
+  }
+  const int nchunks = int(chunks.size());
+  for (int c = 0; c < nchunks; ++c)
+    for (int j : chunks[c]) cols[j].woff += int64_t(c % 3) * int64_t(region_elems);
+  bool unfused = false;
+  for (int lg2 : col_log2) unfused |= lg2 > sc.max_fuse;
+  const int nstages = nchunks > 0 ? nchunks + (unfused ? 2 : 1) : (mid.empty() ? 0 : 1);
+  // per stage: reuse groups (the rows of one column, which re-read its x and
+  // should share an XCD's L2)
+  std::vector<std::vector<std::vector<Item>>> groups(size_t(std::max(nstages, 0)));
+  for (int c = 0; c < nchunks; ++c) {
+    for (int j : chunks[c]) {
+      const int lg2 = col_log2[j];
+      const int n2 = 1 << lg2;
+      const bool fuse = lg2 <= sc.max_fuse;
+      const int npass = fuse ? 2 : 3;
+      for (int pass = 0; pass < npass; ++pass) {
+        std::vector<Item> g;
+        for (int t = 0; t < n2; ++t) {
+          if (fuse && pass == 0)
+            g.push_back(Item{IT_ROWF | (lg2 << 8), cols[j].op, j, t});
+          else if (!fuse && pass == 0)
+            g.push_back(Item{IT_FS1 | (lg2 << 8), cols[j].op, j, t});
+          else if (!fuse && pass == 1)
+            g.push_back(Item{IT_FS2 | (kLog1 << 8), cols[j].op, j, t});
+          else
+            g.push_back(Item{IT_FS3 | (lg2 << 8), cols[j].op, j, t});
+        }
+        groups[size_t(c + pass)].push_back(std::move(g));
+      }
+    }
+  }
+  // single-pass items spread evenly over the stages
+  for (size_t k = 0; k < mid.size(); ++k) {
+    const size_t st = nstages > 0 ? k * size_t(nstages) / mid.size() : 0;
+    groups[st].push_back({mid[k]});
+  }
+  // lay out each stage: each group goes to the currently shortest XCD queue,
+  // then the queues are interleaved (work-group g runs on XCD g mod 8). A
+  // column per group keeps the queues balanced; grouping whole operators
+  // measured slower.
+  std::vector<Item> items;
+  std::vector<int64_t> stage_off{0};
+  for (int st = 0; st < nstages; ++st) {
+    std::vector<std::vector<Item>> q(kXcds);
+    for (auto& g : groups[size_t(st)]) {
+      int best = 0;
+      for (int x = 1; x < kXcds; ++x)
+        if (q[x].size() < q[best].size()) best = x;
+      q[best].insert(q[best].end(), g.begin(), g.end());
+    }
+    size_t longest = 0;
+    for (const auto& v : q) longest = std::max(longest, v.size());
+    for (size_t r = 0; r < longest; ++r)
+      for (int x = 0; x < kXcds; ++x)
+        if (r < q[x].size()) items.push_back(q[x][r]);
+    stage_off.push_back(int64_t(items.size()));
+  }
+  // all work queued on the device before this call may still read the old
+  // buffers: wait for it before replacing them
+  FM_HIP(hipDeviceSynchronize());
+  drop_graphs(b);
+  FM_TRY(b->d_items.alloc(std::max<size_t>(1, items.size()) * sizeof(Item)));
+  FM_TRY(b->d_cols.alloc(std::max<size_t>(1, cols.size()) * sizeof(FsCol)));
+  const size_t pool = nchunks > 0 ? size_t(std::min(3, nchunks)) * sc.region_bytes : 0;
+  if (b->d_wpool.bytes != pool) {
+    b->d_wpool.reset();
+    if (pool > 0) FM_TRY(b->d_wpool.alloc(pool));
+  }
+  if (!items.empty())
+    FM_HIP(hipMemcpy(b->d_items.p, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice));
+  if (!cols.empty())
+    FM_HIP(hipMemcpy(b->d_cols.p, cols.data(), cols.size() * sizeof(FsCol), hipMemcpyHostToDevice));
+  b->stage_off = std::move(stage_off);
+  b->sched = sc;
   return FM_OK;
 }
 
@@ -258,127 +444,23 @@ fm_status fm_batch_create(fm_batch* out, int32_t nops, const fm_op* ops, const i
   FM_CHECK_ARG(b != nullptr, FM_E_NOMEM, "out of host memory");
   b->device = dev;
   std::vector<OpDev> hops(nops);
-  std::vector<Item> mid;  // single-pass items
-  std::vector<FsCol> cols;
-  std::vector<int> col_log2;
   for (int i = 0; i < nops; ++i) {
     fm_op_s* o = ops[i];
     o->refs.fetch_add(1);
     b->ops.push_back(o);
     b->ncols.push_back(ncols[i]);
-    const int logL = ilog2(o->L);
-    hops[i] = OpDev{static_cast<const c64*>(o->p32.p), int32_t(o->m), int32_t(o->n), logL, int32_t(ncols[i]),
+    hops[i] = OpDev{static_cast<const c64*>(o->p32.p), int32_t(o->m), int32_t(o->n), ilog2(o->L), int32_t(ncols[i]),
                     b->total_cols};
     b->col_base.push_back(b->total_cols);
     b->total_cols += ncols[i];
-    if (logL <= kLogW) {
-      const int B = 1 << (kLogW - logL);  // transforms per work-group
-      for (int64_t c0 = 0; c0 < ncols[i]; c0 += B) {
-        const int cnt = int(std::min<int64_t>(B, ncols[i] - c0));
-        mid.push_back(Item{IT_SINGLE | (logL << 8), i, int32_t(c0), cnt});
-      }
-    } else {
-      for (int64_t c = 0; c < ncols[i]; ++c) {
-        cols.push_back(FsCol{i, int32_t(c), 0});
-        col_log2.push_back(logL - kLog1);
-      }
-    }
-  }
-  // chunks of columns whose intermediates fit one region; three regions rotate
-  const size_t region_elems = kRegionBytes / sizeof(c64);
-  std::vector<std::vector<int>> chunks;
-  {
-    size_t used = region_elems;  // forces a first chunk
-    for (int j = 0; j < int(cols.size()); ++j) {
-      const size_t L = size_t(1) << (col_log2[j] + kLog1);
-      if (used + L > region_elems) {
-        chunks.emplace_back();
-        used = 0;
-      }
-      cols[j].woff = int64_t(used);  // offset inside the chunk's region
-      used += L;
-      chunks.back().push_back(j);
-    }
-  }
-  const int nchunks = int(chunks.size());
-  for (int c = 0; c < nchunks; ++c)
-    for (int j : chunks[c]) cols[j].woff += int64_t(c % 3) * int64_t(region_elems);
-  bool unfused = false;
-  const int max_fuse = conv_max_fuse();
-  for (int lg2 : col_log2) unfused |= lg2 > max_fuse;
-  const int nstages = nchunks > 0 ? nchunks + (unfused ? 2 : 1) : (mid.empty() ? 0 : 1);
-  // per stage: reuse groups (the rows of one column, which re-read its x and
-  // should share an XCD's L2)
-  std::vector<std::vector<std::vector<Item>>> groups(size_t(std::max(nstages, 0)));
-  for (int c = 0; c < nchunks; ++c) {
-    // group the columns of one operator within the chunk
-    std::vector<std::pair<int, std::vector<int>>> byop;
-    for (int j : chunks[c]) {
-      if (byop.empty() || byop.back().first != cols[j].op) byop.push_back({cols[j].op, {}});
-      byop.back().second.push_back(j);
-    }
-    for (const auto& og : byop) {
-      const int lg2 = col_log2[og.second[0]];
-      const int n2 = 1 << lg2;
-      const bool fuse = lg2 <= max_fuse;
-      const int npass = fuse ? 2 : 3;
-      for (int pass = 0; pass < npass; ++pass) {
-        std::vector<Item> g;
-        for (int j : og.second) {
-          for (int t = 0; t < n2; ++t) {
-            if (fuse && pass == 0)
-              g.push_back(Item{IT_ROWF | (lg2 << 8), cols[j].op, j, t});
-            else if (!fuse && pass == 0)
-              g.push_back(Item{IT_FS1 | (lg2 << 8), cols[j].op, j, t});
-            else if (!fuse && pass == 1)
-              g.push_back(Item{IT_FS2 | (kLog1 << 8), cols[j].op, j, t});
-            else
-              g.push_back(Item{IT_FS3 | (lg2 << 8), cols[j].op, j, t});
-          }
-        }
-        for (size_t q0 = 0; q0 < g.size(); q0 += size_t(n2))  // one reuse group per column
-          groups[size_t(c + pass)].push_back(std::vector<Item>(g.begin() + q0, g.begin() + q0 + n2));
-      }
-    }
-  }
-  // middle-length single-pass items spread evenly over the stages
-  for (size_t k = 0; k < mid.size(); ++k) {
-    const size_t st = nstages > 0 ? k * size_t(nstages) / mid.size() : 0;
-    groups[st].push_back({mid[k]});
-  }
-  // lay out each stage: each group goes to the currently shortest XCD queue,
-  // then the queues are interleaved (work-group g runs on XCD g mod 8). A
-  // column per group keeps the queues balanced; grouping whole operators
-  // measured slower.
-  std::vector<Item> items;
-  b->stage_off.push_back(0);
-  for (int st = 0; st < nstages; ++st) {
-    std::vector<std::vector<Item>> q(kXcds);
-    auto& gs = groups[size_t(st)];
-    for (auto& g : gs) {
-      int best = 0;
-      for (int x = 1; x < kXcds; ++x)
-        if (q[x].size() < q[best].size()) best = x;
-      q[best].insert(q[best].end(), g.begin(), g.end());
-    }
-    size_t longest = 0;
-    for (const auto& v : q) longest = std::max(longest, v.size());
-    for (size_t r = 0; r < longest; ++r)
-      for (int x = 0; x < kXcds; ++x)
-        if (r < q[x].size()) items.push_back(q[x][r]);
-    b->stage_off.push_back(int64_t(items.size()));
   }
   fm_status st = FM_OK;
   auto fail = [&](fm_status s) {
     destroy_batch(b);
     return s;
   };
-  if ((st = b->d_items.alloc(std::max<size_t>(1, items.size()) * sizeof(Item))) != FM_OK) return fail(st);
   if ((st = b->d_ops.alloc(hops.size() * sizeof(OpDev))) != FM_OK) return fail(st);
-  if ((st = b->d_cols.alloc(std::max<size_t>(1, cols.size()) * sizeof(FsCol))) != FM_OK) return fail(st);
   if ((st = b->d_ptrs.alloc(size_t(fm_batch_s::kTables) * nops * sizeof(Ptrs))) != FM_OK) return fail(st);
-  if (nchunks > 0 && (st = b->d_wpool.alloc(size_t(std::min(3, nchunks)) * kRegionBytes)) != FM_OK)
-    return fail(st);
   if (hipHostMalloc(reinterpret_cast<void**>(&b->staging), size_t(fm_batch_s::kTables) * nops * sizeof(Ptrs)) !=
       hipSuccess) {
     set_error("batch: pinned staging allocation failed");
@@ -390,14 +472,21 @@ fm_status fm_batch_create(fm_batch* out, int32_t nops, const fm_op* ops, const i
       return fail(FM_E_DEVICE);
     }
   }
-  if ((!items.empty() &&
-       hipMemcpy(b->d_items.p, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice) != hipSuccess) ||
-      hipMemcpy(b->d_ops.p, hops.data(), hops.size() * sizeof(OpDev), hipMemcpyHostToDevice) != hipSuccess ||
-      (!cols.empty() &&
-       hipMemcpy(b->d_cols.p, cols.data(), cols.size() * sizeof(FsCol), hipMemcpyHostToDevice) != hipSuccess)) {
-    set_error("batch: upload of the work list failed");
+  if (hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    set_error("batch: stream creation failed");
     return fail(FM_E_DEVICE);
   }
+  if (hipMemcpy(b->d_ops.p, hops.data(), hops.size() * sizeof(OpDev), hipMemcpyHostToDevice) != hipSuccess) {
+    set_error("batch: upload of the operator table failed");
+    return fail(FM_E_DEVICE);
+  }
+  {
+    const char* e = std::getenv("FM_BATCH_GRAPH");
+    b->use_graphs = !(e && std::atoi(e) == 0);
+  }
+  Schedule sc;
+  sc.max_fuse = conv_max_fuse();
+  if ((st = build_schedule(b, sc)) != FM_OK) return fail(st);
   {
     std::lock_guard<std::mutex> lock(g_batch_mu);
     live_batches().insert(b);
@@ -438,6 +527,70 @@ fm_status fm_batch_apply(fm_batch b, fm_dir dir, const void* const* x, const int
   const Ptrs* table = nullptr;
   FM_TRY(batch_pointer_table(b, s, &table));
   return batch_launch(b, adj, table, nullptr, s);
+}
+
+fm_status fm_batch_tune(fm_batch b, fm_dir dir, const void* const* x, const int64_t* ldx, void* const* y,
+                        const int64_t* ldy, int32_t reps, fm_batch_schedule* chosen, void* stream) {
+  set_error("");
+  FM_CHECK_ARG(b != nullptr, FM_E_INVALID, "batch handle is NULL");
+  FM_CHECK_ARG(batch_alive(b), FM_E_RELEASED, "batch handle was released");
+  FM_CHECK_ARG(reps >= 1 && reps <= 1000, FM_E_INVALID, "tune: reps must be in 1..1000");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  FM_TRY(fm_batch_apply(b, dir, x, ldx, y, ldy, stream));  // validates the arguments
+  hipEvent_t e0, e1;
+  FM_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    set_error("tune: event creation failed");
+    return FM_E_DEVICE;
+  }
+  Schedule best = b->sched;
+  double best_ms = -1.0;
+  fm_status st = FM_OK;
+  const int regions[3] = {24, 48, 96};
+  for (int mf = 0; mf <= 5 && st == FM_OK; ++mf) {
+    for (int r = 0; r < 3 && st == FM_OK; ++r) {
+      Schedule sc;
+      sc.max_fuse = mf;
+      sc.region_bytes = size_t(regions[r]) << 20;
+      if ((st = build_schedule(b, sc)) != FM_OK) break;
+      if ((st = fm_batch_apply(b, dir, x, ldx, y, ldy, stream)) != FM_OK) break;  // warm-up (and capture)
+      if (hipEventRecord(e0, s) != hipSuccess) st = FM_E_DEVICE;
+      for (int k = 0; k < reps && st == FM_OK; ++k) st = fm_batch_apply(b, dir, x, ldx, y, ldy, stream);
+      float ms = 0.f;
+      if (st == FM_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                          hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        st = FM_E_DEVICE;
+      if (st != FM_OK) break;
+      const double per = double(ms) / reps;
+      if (best_ms < 0 || per < best_ms) {
+        best_ms = per;
+        best = sc;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != FM_OK) {
+    (void)build_schedule(b, best);
+    return st;
+  }
+  FM_TRY(build_schedule(b, best));
+  b->tuned_ms = best_ms;
+  FM_TRY(fm_batch_apply(b, dir, x, ldx, y, ldy, stream));  // y from the chosen schedule
+  if (chosen) FM_TRY(fm_batch_get_schedule(b, chosen));
+  return FM_OK;
+}
+
+fm_status fm_batch_get_schedule(fm_batch b, fm_batch_schedule* out) {
+  set_error("");
+  FM_CHECK_ARG(b != nullptr && out != nullptr, FM_E_INVALID, "NULL argument");
+  FM_CHECK_ARG(batch_alive(b), FM_E_RELEASED, "batch handle was released");
+  out->max_fuse = b->sched.max_fuse;
+  out->region_mib = int32_t(b->sched.region_bytes >> 20);
+  out->graphs = b->use_graphs ? 1 : 0;
+  out->ms = b->tuned_ms;
+  return FM_OK;
 }
 
 fm_status fm_batch_release(fm_batch b) {

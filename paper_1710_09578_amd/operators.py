@@ -279,6 +279,20 @@ class Batch:
                             _stream())
         return outs
 
+    def tune(self, xs, adjoint: bool = False, outs=None, reps: int = 3):
+        """Times every candidate schedule on these blocks and keeps the
+        fastest (fm_batch_tune); returns the chosen schedule as a dict."""
+        if outs is None:
+            outs = [torch.empty((nc, op.shape[1] if adjoint else op.shape[0]), dtype=op.dtype, device=x.device)
+                    for op, x, nc in zip(self.ops, xs, self.ncols)]
+        ldx = [max(x.stride(0), 1) if x.dim() == 2 else x.shape[-1] for x in xs]
+        ldy = [max(y.stride(0), 1) if y.dim() == 2 else y.shape[-1] for y in outs]
+        return capi.fm_batch_tune(self._h, capi.FM_ADJ if adjoint else capi.FM_FWD, xs, ldx, outs, ldy, reps,
+                                  _stream())
+
+    def schedule(self):
+        return capi.fm_batch_get_schedule(self._h)
+
     def fista(self, bs, iters=100, momentum=True, lam=None, lam_rel=None, L=None, stop_tol=0.0, x0s=None):
         """FISTA for every column of every operator; bs[i] has shape
         (ncols[i], m_i). Returns (xs, stats) with stats per batch column."""

@@ -174,3 +174,49 @@ def test_batch_fista_stopping(gpu):
             xj, _ = structured.toeplitz_fista_fft64(col, row, b[j:j + 1], lam[j], L, int(got[j]))
             assert rel_err(to_host(xs[i])[j:j + 1], xj) <= TOL["c64"]
         gi += ncols[i]
+
+
+def test_batch_graph_replays_match_eager(gpu):
+    """The stage sequence is captured once and replayed: every replay, with
+    other library and torch work and synchronisations in between, equals the
+    per-operator (eager) path bit for bit."""
+    import torch
+
+    sizes = [500, 3000, 9000, 40000]
+    ncols = [4, 3, 2, 2]
+    ops, data = build_batch(gpu, sizes, ncols, seed=5)
+    batch = gpu.Batch(ops, ncols)
+    xs = [to_dev(d[2]) for d in data]
+    ref = [to_host(op @ x) for op, x in zip(ops, xs)]
+    ref_h = [to_host(op.H @ x) for op, x in zip(ops, xs)]
+    ys = [torch.empty_like(x) for x in xs]
+    zs = [torch.empty_like(x) for x in xs]
+    other = gpu.Circulant(to_dev(crandn(np.random.default_rng(9), 1024)))
+    w = to_dev(crandn(np.random.default_rng(10), (3, 1024)))
+    for rep in range(4):
+        for y in ys:
+            y.fill_(float("nan"))
+        batch.apply(xs, outs=ys)
+        batch.apply(xs, adjoint=True, outs=zs)
+        _ = other @ w  # eager work between the replays
+        torch.cuda.synchronize()
+        for i in range(len(ops)):
+            assert np.array_equal(to_host(ys[i]), ref[i]), f"replay {rep}, op {i}"
+            assert np.array_equal(to_host(zs[i]), ref_h[i]), f"replay {rep}, op {i} (adjoint)"
+    assert batch.schedule()["graphs"] == 1
+
+
+def test_batch_tune(gpu):
+    sizes = [300, 2500, 7000, 20000, 65536]
+    ncols = [3, 2, 4, 2, 1]
+    ops, data = build_batch(gpu, sizes, ncols, seed=6)
+    batch = gpu.Batch(ops, ncols)
+    xs = [to_dev(d[2]) for d in data]
+    ys = [to_dev(np.zeros_like(d[2])) for d in data]
+    sc = batch.tune(xs, outs=ys, reps=2)
+    assert 0 <= sc["max_fuse"] <= 5 and sc["region_mib"] in (24, 48, 96) and sc["ms"] > 0
+    assert batch.schedule() == sc
+    zs = batch.apply(xs, adjoint=True)
+    for i, (col, row, x, u) in enumerate(data):
+        assert rel_err(to_host(ys[i]), structured.toeplitz_apply_fft64(col, row, x)) <= TOL["c64"]
+        assert rel_err(to_host(zs[i]), structured.toeplitz_apply_fft64(col, row, x, True)) <= TOL["c64"]
