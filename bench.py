@@ -178,7 +178,7 @@ def time_steps(step, steps, warmup):
     return max(wall * 1e3 / steps, gpu_ms), gpu_ms
 
 
-def fista_solves(w, iters=100, stop_tol=1e-5):
+def fista_solves(w, iters=100, stop_tol=1e-5, tune=True):
     """FISTA for every column of every operator: batched (fm_batch_fista) and
     plain (one fm_fista per operator). Measurements b = T x_true + noise are
     formed on the GPU by the library's batched forward apply."""
@@ -191,6 +191,8 @@ def fista_solves(w, iters=100, stop_tol=1e-5):
     ncols = [int(v) for v in w["ncols"]]
     batch = fm.Batch(w["ops"], ncols)
     xt = [torch.from_numpy(data["ops"][i]["x_true"]).cuda() for i in range(len(ncols))]
+    if tune:
+        batch.tune(xt, reps=2)
     bs = batch.apply(xt)
     for i in range(len(ncols)):
         bs[i].add_(torch.from_numpy(data["ops"][i]["noise"]).cuda())
@@ -437,7 +439,7 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
             "kernel": "stage_kernel: all stage launches of one direction (fm_batch_apply)",
             "alg_bytes_per_launch": int(per_launch), "launch_ms": round(launch_ms, 4)}
-    fres = None if args.no_fista else fista_solves(w)
+    fres = None if args.no_fista else fista_solves(w, tune=not args.no_tune)
     learn = None if args.no_learn else learn_circulant_steps()
     kron = None if args.no_kron else kron_hfg_bandwidth()
     cpu = None

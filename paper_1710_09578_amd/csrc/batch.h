@@ -53,10 +53,43 @@ struct Schedule {
   size_t region_bytes = size_t(48) << 20;   // slot region of one chunk (three rotate)
 };
 
+
+// Caller blocks of one operator in a batched solve.
+struct User {
+  const c64* b;
+  c64* x;
+  int64_t ldb, ldx;
+};
+
+// Epilogue of the last pass of a direction inside a batched solve:
+//   kind 1 (forward):  r = A y - b        (b subtracted in the store)
+//   kind 2 (adjoint):  from g = A^H r: z = y - g/L, x+ = soft(z, lam/L),
+//                      y+ = x+ + beta (x+ - x), x and y updated in place, with
+//                      per-slot partial sums of |x+ - x|^2 and |x+|^2 for the
+//                      stopping rule and a status flag for non-finite values.
+struct EpiArgs {
+  int kind = 0;
+  const User* user = nullptr;   // per operator
+  const double* lam = nullptr;  // per batch column
+  const double* L = nullptr;    // per operator
+  const int64_t* pbase = nullptr;  // per batch column: first partial slot
+  double* partial = nullptr;    // 2 doubles per slot
+  int* status = nullptr;        // per batch column
+  const float* beta = nullptr;  // momentum weight of every iteration (device)
+  const int* iter = nullptr;    // current iteration (device; advanced by the stop check)
+  int momentum = 1;
+  bool same(const EpiArgs& o) const {
+    return kind == o.kind && user == o.user && lam == o.lam && L == o.L && pbase == o.pbase &&
+           partial == o.partial && status == o.status && beta == o.beta && iter == o.iter &&
+           momentum == o.momentum;
+  }
+};
+
 struct GraphEntry {
   bool adj;
   const void* table;
   const int* active;
+  EpiArgs epi;
   hipGraphExec_t exec;
   uint64_t last_use;
 };
@@ -70,6 +103,7 @@ struct BArgs {
   const c64* tw;
   int32_t adj;
   const int* active;  // per batch column; NULL: every column is active
+  EpiArgs epi;
 };
 
 
@@ -101,10 +135,10 @@ struct fm_batch_s {
   uint64_t clock = 0;
   std::vector<fm::Ptrs> cur;
   // solver state, allocated on the first fm_batch_fista call
-  fm::DevBuf s_y, s_r, s_g, s_lam, s_L, s_active, s_status, s_iters, s_partial, s_cols, s_utiles, s_stiles,
-      s_user;
+  fm::DevBuf s_y, s_r, s_g, s_lam, s_L, s_active, s_status, s_iters, s_partial, s_cols, s_utiles, s_pbase, s_user,
+      s_beta, s_iter;
   std::vector<int64_t> s_yoff, s_roff;  // per operator: first element in the packed n- / m-sized buffers
-  int64_t s_nutiles = 0, s_nstiles = 0;
+  int64_t s_nutiles = 0;
   std::vector<double> s_bound;  // per operator: max |DFT_L(g)|^2 (empty until computed)
 };
 
@@ -114,7 +148,8 @@ bool batch_alive(const fm_batch_s* b);
 fm_status batch_pointer_table(fm_batch_s* b, hipStream_t s, const Ptrs** table);
 // Launches every stage of one direction; active: per batch column or NULL.
 // The stage sequence is replayed from a captured graph when possible.
-fm_status batch_launch(fm_batch_s* b, bool adj, const Ptrs* table, const int* active, hipStream_t s);
+fm_status batch_launch(fm_batch_s* b, bool adj, const Ptrs* table, const int* active, hipStream_t s,
+                       const EpiArgs* epi = nullptr);
 // Rebuilds the work list for a schedule (synchronises the device).
 fm_status build_schedule(fm_batch_s* b, const Schedule& sc);
 // Destroys the captured graphs.

@@ -34,8 +34,159 @@ using namespace xf;
 
 constexpr int kXcds = 8;
 
+// ---------------------------------------------------------------- solver epilogues
+__device__ __forceinline__ c64 soft_thr(c64 z, float s) {
+  const float mag = sqrtf(z.x * z.x + z.y * z.y);
+  if (!(mag > s)) return {0.f, 0.f};
+  const float f = (mag - s) / mag;
+  return {z.x * f, z.y * f};
+}
+
+// r = A y - b: transform b of the item is column col0 + b (contiguous items,
+// bstride = ldb) or every transform belongs to one column (strided items,
+// bstride = 0; e then holds the transform's offset).
+struct ResidualEp {
+  static constexpr bool kOn = true;
+  const c64* B;
+  int64_t bstride;
+  c64 bv[16];
+  __device__ __forceinline__ void pre(int k, int b, int e, c64*) { bv[k] = B[int64_t(b) * bstride + e]; }
+  __device__ __forceinline__ void put(int k, int, int, int, c64* dst, c64 v) { *dst = csub(v, bv[k]); }
+};
+
+// FISTA update from g = A^H r (see EpiArgs). Contiguous items: transform b is
+// batch column gcol0 + b with x at X + b*xstride; strided items: one column.
+struct FistaEp {
+  static constexpr bool kOn = true;
+  c64* X;
+  int64_t xstride;
+  int64_t gcol0;
+  int colstride;  // 1: contiguous, 0: strided
+  const int* active;
+  const double* lam;
+  double invLd;
+  float invL, beta;
+  int momentum;
+  int* status;
+  // running sums of the current slot (tiny contiguous transforms flush when
+  // the slot changes: one thread holds the whole transform)
+  bool flush_per_slot;
+  const int64_t* pbase;
+  double* partial;
+  int cur = -1;
+  int64_t cur_col = -1;
+  int64_t c_gc = -1;
+  bool c_act = false;
+  float c_s = 0.f;
+  double dx = 0.0, nx = 0.0;
+
+  __device__ __forceinline__ void flush() {
+    if (cur_col >= 0) {
+      partial[2 * pbase[cur_col]] = dx;
+      partial[2 * pbase[cur_col] + 1] = nx;
+    }
+    dx = nx = 0.0;
+    cur_col = -1;
+  }
+  c64 yk[16], xk[16];
+  __device__ __forceinline__ void pre(int k, int b, int e, c64* dst) {
+    yk[k] = *dst;
+    xk[k] = X[int64_t(b) * xstride + e];
+  }
+  __device__ __forceinline__ void put(int k, int slot, int b, int e, c64* dst, c64 g) {
+    const int64_t gc = gcol0 + int64_t(b) * colstride;
+    if (flush_per_slot && slot != cur) {
+      flush();
+      cur = slot;
+    }
+    if (gc != c_gc) {  // per-column values, reloaded only when the column changes
+      c_gc = gc;
+      c_act = !active || active[gc];
+      c_s = float(lam[gc] * invLd);
+    }
+    if (!c_act) return;
+    if (flush_per_slot) cur_col = gc;
+    const float s = c_s;
+    const c64 yv = yk[k];
+    c64* xp = X + int64_t(b) * xstride + e;
+    const c64 xo = xk[k];
+    const c64 z = {yv.x - g.x * invL, yv.y - g.y * invL};
+    const c64 xn = soft_thr(z, s);
+    const c64 d = {xn.x - xo.x, xn.y - xo.y};
+    *xp = xn;
+    *dst = momentum ? c64{xn.x + beta * d.x, xn.y + beta * d.y} : xn;
+    dx += double(d.x) * d.x + double(d.y) * d.y;
+    nx += double(xn.x) * xn.x + double(xn.y) * xn.y;
+    if (!(isfinite(z.x) && isfinite(z.y))) atomicOr(status + gc, 1);
+  }
+};
+
+// Partial sums of a FistaEp after run_job: per transform (contiguous items of
+// >= 16 points: the T = 2^(lg-4) threads of transform b are tid / T == b), per
+// item (strided items: one column, slot pbase + tile), or already flushed
+// (contiguous transforms of < 16 points).
+__device__ __forceinline__ void fista_partials(FistaEp& ep, bool strided, int lg, int nvalid, int tile,
+                                               c64* smem) {
+  if (ep.flush_per_slot) {
+    ep.flush();
+    return;
+  }
+  __syncthreads();  // the transform's last LDS reads are done
+  double2* red = reinterpret_cast<double2*>(smem);
+  const int tid = threadIdx.x;
+  red[tid] = make_double2(ep.dx, ep.nx);
+  __syncthreads();
+  // tree reduction over segments of T threads (the whole work-group for a
+  // strided item), in a fixed order
+  const int T = strided ? Geo<kLogW>::kThreads : 1 << (lg - 4);
+  for (int w = T >> 1; w > 0; w >>= 1) {
+    if ((tid & (T - 1)) < w) {
+      red[tid].x += red[tid + w].x;
+      red[tid].y += red[tid + w].y;
+    }
+    __syncthreads();
+  }
+  if ((tid & (T - 1)) != 0) return;
+  if (strided) {
+    if (!ep.active || ep.active[ep.gcol0]) {
+      ep.partial[2 * (ep.pbase[ep.gcol0] + tile)] = red[0].x;
+      ep.partial[2 * (ep.pbase[ep.gcol0] + tile) + 1] = red[0].y;
+    }
+    return;
+  }
+  const int b = tid / T;
+  if (b < nvalid) {
+    const int64_t gc = ep.gcol0 + b;
+    if (!ep.active || ep.active[gc]) {
+      ep.partial[2 * ep.pbase[gc]] = red[tid].x;
+      ep.partial[2 * ep.pbase[gc] + 1] = red[tid].y;
+    }
+  }
+}
+
+template <int EPI>
+__device__ __forceinline__ FistaEp make_fista_ep(const BArgs& a, int op, int64_t col, bool strided, int lg) {
+  const User u = a.epi.user[op];
+  FistaEp ep;
+  ep.X = u.x + col * u.ldx;
+  ep.xstride = strided ? 0 : u.ldx;
+  ep.gcol0 = a.ops[op].col_base + col;
+  ep.colstride = strided ? 0 : 1;
+  ep.active = a.active;
+  ep.lam = a.epi.lam;
+  ep.invLd = 1.0 / a.epi.L[op];
+  ep.invL = float(ep.invLd);
+  ep.beta = a.epi.beta[*a.epi.iter];
+  ep.momentum = a.epi.momentum;
+  ep.status = a.epi.status;
+  ep.flush_per_slot = !strided && lg < 4;
+  ep.pbase = a.epi.pbase;
+  ep.partial = a.epi.partial;
+  return ep;
+}
+
 // Whole zero-padded convolutions of length 2^lg, it.sub columns.
-template <int LOGW>
+template <int LOGW, int EPI>
 __device__ __forceinline__ void run_single(const BArgs& a, const Item& it, int lg, c64* smem) {
   const OpDev op = a.ops[it.op];
   const Ptrs pt = a.ptrs[it.op];
@@ -53,11 +204,22 @@ __device__ __forceinline__ void run_single(const BArgs& a, const Item& it, int l
   jb.sbstride = 0;
   jb.q0 = 0;
   const Mode md{FFT_CONV, a.adj, 0, 0, 0};
-  run_job<float, false, LOGW>(jb, md, lg, smem, a.tw);
+  if constexpr (EPI == 1) {
+    const User u = a.epi.user[it.op];
+    ResidualEp ep{u.b + int64_t(it.col) * u.ldb, u.ldb};
+    run_job<float, false, LOGW>(jb, md, lg, smem, a.tw, &ep);
+  } else if constexpr (EPI == 2) {
+    FistaEp ep = make_fista_ep<EPI>(a, it.op, it.col, false, lg);
+    run_job<float, false, LOGW>(jb, md, lg, smem, a.tw, &ep);
+    fista_partials(ep, false, lg, it.sub, 0, smem);
+  } else {
+    run_job<float, false, LOGW>(jb, md, lg, smem, a.tw);
+  }
 }
 
 // FS1 (first) or FS3: strided transforms of length 2^lg at stride 4096 over
 // 4096/2^lg neighbouring inner indices.
+template <int EPI>
 __device__ __forceinline__ void run_strided(const BArgs& a, const Item& it, const FsCol& fc, int lg, bool first,
                                             c64* smem) {
   const OpDev op = a.ops[fc.op];
@@ -87,7 +249,17 @@ __device__ __forceinline__ void run_strided(const BArgs& a, const Item& it, cons
     jb.in_limit = L;
     jb.out_limit = a.adj ? op.n : op.m;
     const Mode md{FFT_INV, 0, 0, 0, 0};
-    run_job<float, true, kLogW>(jb, md, lg, smem, a.tw);
+    if constexpr (EPI == 1) {
+      const User u = a.epi.user[fc.op];
+      ResidualEp ep{u.b + int64_t(fc.col) * u.ldb, 0};
+      run_job<float, true, kLogW>(jb, md, lg, smem, a.tw, &ep);
+    } else if constexpr (EPI == 2) {
+      FistaEp ep = make_fista_ep<EPI>(a, fc.op, fc.col, true, lg);
+      run_job<float, true, kLogW>(jb, md, lg, smem, a.tw, &ep);
+      fista_partials(ep, true, lg, tpw, it.sub, smem);
+    } else {
+      run_job<float, true, kLogW>(jb, md, lg, smem, a.tw);
+    }
   }
 }
 
@@ -120,7 +292,7 @@ __device__ __forceinline__ void run_row(const BArgs& a, const Item& it, const Fs
   run_job<float, false, kLogW>(jb, md, kLog1, smem, a.tw);
 }
 
-template <int LOGW>
+template <int LOGW, int EPI>
 __global__ __launch_bounds__(Geo<LOGW>::kThreads) void stage_kernel(BArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   c64* smem = reinterpret_cast<c64*>(smem_raw);
@@ -134,19 +306,17 @@ __global__ __launch_bounds__(Geo<LOGW>::kThreads) void stage_kernel(BArgs a) {
       for (int c = 0; c < it.sub; ++c) any |= a.active[g0 + c] != 0;
       if (!any) return;
     }
-    run_single<LOGW>(a, it, lg, smem);
+    run_single<LOGW, EPI>(a, it, lg, smem);
     return;
   }
-  if constexpr (LOGW == kLogW) {
-    const FsCol fc = a.cols[it.col];
-    if (a.active && !a.active[a.ops[fc.op].col_base + fc.col]) return;
-    if (kind == IT_ROWF)
-      run_row(a, it, fc, lg, smem);
-    else if (kind == IT_FS2)
-      run_row(a, it, fc, 0, smem);
-    else
-      run_strided(a, it, fc, lg, kind == IT_FS1, smem);
-  }
+  const FsCol fc = a.cols[it.col];
+  if (a.active && !a.active[a.ops[fc.op].col_base + fc.col]) return;
+  if (kind == IT_ROWF)
+    run_row(a, it, fc, lg, smem);
+  else if (kind == IT_FS2)
+    run_row(a, it, fc, 0, smem);
+  else
+    run_strided<EPI>(a, it, fc, lg, kind == IT_FS1, smem);
 }
 
 }  // namespace
@@ -222,18 +392,25 @@ void fm::drop_graphs(fm_batch_s* b) {
 
 namespace {
 
-fm_status launch_stages(fm_batch_s* b, const BArgs& a0, hipStream_t s) {
+template <int EPI>
+fm_status launch_stages_t(fm_batch_s* b, const BArgs& a0, hipStream_t s) {
   BArgs a = a0;
   const Item* items = static_cast<const Item*>(b->d_items.p);
   for (size_t st = 0; st + 1 < b->stage_off.size(); ++st) {
     const int64_t n = b->stage_off[st + 1] - b->stage_off[st];
     if (n == 0) continue;
     a.items = items + b->stage_off[st];
-    hipLaunchKernelGGL(stage_kernel<kLogW>, dim3(unsigned(n)), dim3(Geo<kLogW>::kThreads),
+    hipLaunchKernelGGL((stage_kernel<kLogW, EPI>), dim3(unsigned(n)), dim3(Geo<kLogW>::kThreads),
                        (job_lds_bytes<float, kLogW>()), s, a);
     FM_LAUNCHED();
   }
   return FM_OK;
+}
+
+fm_status launch_stages(fm_batch_s* b, const BArgs& a, hipStream_t s) {
+  if (a.epi.kind == 1) return launch_stages_t<1>(b, a, s);
+  if (a.epi.kind == 2) return launch_stages_t<2>(b, a, s);
+  return launch_stages_t<0>(b, a, s);
 }
 
 // Captures the stage sequence of one (direction, table, mask) on the batch's
@@ -260,7 +437,8 @@ hipGraphExec_t capture(fm_batch_s* b, const BArgs& a) {
 
 }  // namespace
 
-fm_status fm::batch_launch(fm_batch_s* b, bool adj, const Ptrs* table, const int* active, hipStream_t s) {
+fm_status fm::batch_launch(fm_batch_s* b, bool adj, const Ptrs* table, const int* active, hipStream_t s,
+                           const EpiArgs* epi) {
   const void* tw = twiddle_table(Elem::C64, 20);
   FM_CHECK_ARG(tw != nullptr, FM_E_DEVICE, "twiddle table unavailable");
   BArgs a{};
@@ -271,11 +449,12 @@ fm_status fm::batch_launch(fm_batch_s* b, bool adj, const Ptrs* table, const int
   a.tw = static_cast<const c64*>(tw);
   a.adj = adj;
   a.active = active;
+  if (epi) a.epi = *epi;
   if (b->stage_off.size() < 2) return FM_OK;
   if (b->use_graphs) {
     GraphEntry* hit = nullptr;
     for (auto& g : b->graphs)
-      if (g.adj == adj && g.table == table && g.active == active) hit = &g;
+      if (g.adj == adj && g.table == table && g.active == active && g.epi.same(a.epi)) hit = &g;
     if (!hit) {
       hipGraphExec_t exec = capture(b, a);
       if (exec) {
@@ -288,7 +467,7 @@ fm_status fm::batch_launch(fm_batch_s* b, bool adj, const Ptrs* table, const int
           (void)hipGraphExecDestroy(b->graphs[lru].exec);
           b->graphs.erase(b->graphs.begin() + long(lru));
         }
-        b->graphs.push_back(GraphEntry{adj, table, active, exec, 0});
+        b->graphs.push_back(GraphEntry{adj, table, active, a.epi, exec, 0});
         hit = &b->graphs.back();
       } else {
         b->use_graphs = false;  // this device / runtime cannot capture: launch directly from now on

@@ -1,10 +1,11 @@
 // The proximal-gradient solver (FISTA / ISTA, as in fm_fista) for every column
 // of every operator of a batch at once. Each iteration is one batched forward
-// launch sequence (r = A y), one residual kernel (r -= b), one batched adjoint
-// sequence (g = A^H r), one update kernel and one stop check, all over the
-// whole batch. A column that meets the stopping rule (or a non-finite value)
-// is frozen: the update leaves it alone and the batched launches skip its
-// work items, so finished problems stop costing time.
+// launch sequence whose last pass stores r = A y - b, one batched adjoint
+// sequence whose last pass applies the update (z = y - g/L, soft threshold,
+// momentum) in place of storing g, and one stop check, all over the whole
+// batch. A column that meets the stopping rule (or a non-finite value) is
+// frozen: the epilogues leave it alone and the batched launches skip its work
+// items, so finished problems stop costing time.
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -21,91 +22,19 @@ struct SCol {  // one batch column
   int32_t op, col;
   int32_t n, m;     // rows of x (and y, g) and of b (and r)
   int64_t yoff, roff;  // offsets into the packed y/g and r buffers
-  int64_t t0;       // first update tile of the column
-  int32_t nt;       // update tiles of the column
+  int64_t pbase;    // first partial-sum slot of the column
+  int32_t nslot;    // slots: 1, or 2^k for a four-step column of length 4096 * 2^k
 };
 struct STile {
   int32_t g;     // batch column
   int32_t tile;  // tile index inside the column
 };
-struct User {  // caller blocks of one operator
-  const c64* b;
-  c64* x;
-  int64_t ldb, ldx;
-};
-
-__device__ __forceinline__ c64 soft(c64 z, float s) {
-  const float mag = sqrtf(z.x * z.x + z.y * z.y);
-  if (!(mag > s)) return {0.f, 0.f};
-  const float f = (mag - s) / mag;
-  return {z.x * f, z.y * f};
-}
-
-__global__ __launch_bounds__(kTPB) void bsub_kernel(const STile* tiles, const SCol* cols, const User* user,
-                                                    c64* r, const int* active) {
-  const STile t = tiles[blockIdx.x];
-  if (!active[t.g]) return;
-  const SCol c = cols[t.g];
-  const User u = user[c.op];
-  const c64* B = u.b + int64_t(c.col) * u.ldb;
-  c64* R = r + c.roff;
-  for (int k = threadIdx.x; k < kTile; k += kTPB) {
-    const int64_t i = int64_t(t.tile) * kTile + k;
-    if (i < c.m) R[i] = csub(R[i], B[i]);
-  }
-}
-
-__global__ __launch_bounds__(kTPB) void bupdate_kernel(const STile* tiles, const SCol* cols, const User* user,
-                                                       c64* y, const c64* g, const double* L, const double* lam,
-                                                       double beta, int momentum, const int* active, int* status,
-                                                       double* partial) {
-  __shared__ double sdx[kTPB], snx[kTPB];
-  const STile t = tiles[blockIdx.x];
-  if (!active[t.g]) return;
-  const SCol c = cols[t.g];
-  const User u = user[c.op];
-  c64* X = u.x + int64_t(c.col) * u.ldx;
-  c64* Y = y + c.yoff;
-  const c64* G = g + c.yoff;
-  const double invLd = 1.0 / L[c.op];
-  const float invL = float(invLd);
-  const float s = float(lam[t.g] * invLd);
-  const float bt = float(beta);
-  double dx = 0.0, nx = 0.0;
-  bool bad = false;
-  for (int k = threadIdx.x; k < kTile; k += kTPB) {
-    const int64_t i = int64_t(t.tile) * kTile + k;
-    if (i >= c.n) break;
-    const c64 yv = Y[i], gv = G[i], xo = X[i];
-    const c64 z = {yv.x - gv.x * invL, yv.y - gv.y * invL};
-    const c64 xn = soft(z, s);
-    const c64 d = {xn.x - xo.x, xn.y - xo.y};
-    X[i] = xn;
-    Y[i] = momentum ? c64{xn.x + bt * d.x, xn.y + bt * d.y} : xn;
-    dx += double(d.x) * d.x + double(d.y) * d.y;
-    nx += double(xn.x) * xn.x + double(xn.y) * xn.y;
-    bad |= !(isfinite(z.x) && isfinite(z.y));
-  }
-  if (bad) atomicOr(status + t.g, 1);
-  sdx[threadIdx.x] = dx;
-  snx[threadIdx.x] = nx;
-  __syncthreads();
-  for (int w = kTPB / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
-      sdx[threadIdx.x] += sdx[threadIdx.x + w];
-      snx[threadIdx.x] += snx[threadIdx.x + w];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    partial[2 * blockIdx.x] = sdx[0];
-    partial[2 * blockIdx.x + 1] = snx[0];
-  }
-}
 
 __global__ __launch_bounds__(256) void bstop_kernel(const SCol* cols, int64_t ncols, const double* partial,
-                                                    double tol, int k, int* active, int* iters, const int* status) {
+                                                    double tol, int k, int* active, int* iters, const int* status,
+                                                    int* iter) {
   const int64_t gi = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (gi == 0) *iter = k + 1;  // the next iteration's momentum weight
   if (gi >= ncols || !active[gi]) return;
   if (status[gi]) {
     active[gi] = 0;
@@ -115,9 +44,9 @@ __global__ __launch_bounds__(256) void bstop_kernel(const SCol* cols, int64_t nc
   if (tol <= 0.0) return;
   const SCol c = cols[gi];
   double dx = 0.0, nx = 0.0;
-  for (int t = 0; t < c.nt; ++t) {
-    dx += partial[2 * (c.t0 + t)];
-    nx += partial[2 * (c.t0 + t) + 1];
+  for (int t = 0; t < c.nslot; ++t) {
+    dx += partial[2 * (c.pbase + t)];
+    nx += partial[2 * (c.pbase + t) + 1];
   }
   const double nrm = sqrt(nx);
   if (sqrt(dx) <= tol * (nrm > 1e-30 ? nrm : 1e-30)) {
@@ -191,20 +120,22 @@ fm_status ensure_state(fm_batch_s* b) {
   if (b->s_cols.p) return FM_OK;
   const int nops = int(b->ops.size());
   std::vector<SCol> cols;
-  std::vector<STile> ut, st;
-  int64_t yo = 0, ro = 0;
+  std::vector<STile> ut;
+  std::vector<int64_t> pbase;
+  int64_t yo = 0, ro = 0, slots = 0;
   b->s_yoff.assign(nops, 0);
   b->s_roff.assign(nops, 0);
   for (int i = 0; i < nops; ++i) {
     const fm_op_s* o = b->ops[i];
     b->s_yoff[i] = yo;
     b->s_roff[i] = ro;
+    const int32_t nslot = o->L > (int64_t(1) << kLog1) ? int32_t(o->L >> kLog1) : 1;
     for (int64_t c = 0; c < b->ncols[i]; ++c) {
-      SCol sc{i, int32_t(c), int32_t(o->n), int32_t(o->m), yo + c * o->n, ro + c * o->m, int64_t(ut.size()),
-              int32_t(cdiv(o->n, kTile))};
+      SCol sc{i, int32_t(c), int32_t(o->n), int32_t(o->m), yo + c * o->n, ro + c * o->m, slots, nslot};
       const int32_t gidx = int32_t(cols.size());
-      for (int t = 0; t < sc.nt; ++t) ut.push_back(STile{gidx, t});
-      for (int t = 0; t < int(cdiv(o->m, kTile)); ++t) st.push_back(STile{gidx, t});
+      for (int t = 0; t < int(cdiv(o->n, kTile)); ++t) ut.push_back(STile{gidx, t});
+      pbase.push_back(slots);
+      slots += nslot;
       cols.push_back(sc);
     }
     yo += b->ncols[i] * o->n;
@@ -219,16 +150,18 @@ fm_status ensure_state(fm_batch_s* b) {
   FM_TRY(b->s_active.alloc(size_t(std::max<int64_t>(G, 1)) * 4));
   FM_TRY(b->s_status.alloc(size_t(std::max<int64_t>(G, 1)) * 4));
   FM_TRY(b->s_iters.alloc(size_t(std::max<int64_t>(G, 1)) * 4));
-  FM_TRY(b->s_partial.alloc(std::max<size_t>(ut.size(), 1) * 16));
+  FM_TRY(b->s_partial.alloc(size_t(std::max<int64_t>(slots, 1)) * 16));
+  FM_TRY(b->s_pbase.alloc(size_t(std::max<int64_t>(G, 1)) * 8));
   FM_TRY(b->s_cols.alloc(std::max<size_t>(cols.size(), 1) * sizeof(SCol)));
   FM_TRY(b->s_utiles.alloc(std::max<size_t>(ut.size(), 1) * sizeof(STile)));
-  FM_TRY(b->s_stiles.alloc(std::max<size_t>(st.size(), 1) * sizeof(STile)));
   FM_TRY(b->s_user.alloc(size_t(nops) * sizeof(User)));
-  if (!cols.empty()) FM_HIP(hipMemcpy(b->s_cols.p, cols.data(), cols.size() * sizeof(SCol), hipMemcpyHostToDevice));
+  FM_TRY(b->s_iter.alloc(sizeof(int)));
+  if (!cols.empty()) {
+    FM_HIP(hipMemcpy(b->s_cols.p, cols.data(), cols.size() * sizeof(SCol), hipMemcpyHostToDevice));
+    FM_HIP(hipMemcpy(b->s_pbase.p, pbase.data(), pbase.size() * 8, hipMemcpyHostToDevice));
+  }
   if (!ut.empty()) FM_HIP(hipMemcpy(b->s_utiles.p, ut.data(), ut.size() * sizeof(STile), hipMemcpyHostToDevice));
-  if (!st.empty()) FM_HIP(hipMemcpy(b->s_stiles.p, st.data(), st.size() * sizeof(STile), hipMemcpyHostToDevice));
   b->s_nutiles = int64_t(ut.size());
-  b->s_nstiles = int64_t(st.size());
   return FM_OK;
 }
 
@@ -297,7 +230,6 @@ extern "C" fm_status fm_batch_fista(fm_batch b, const void* const* bvec, const i
   double* partial = static_cast<double*>(b->s_partial.p);
   const SCol* cols = static_cast<const SCol*>(b->s_cols.p);
   const STile* ut = static_cast<const STile*>(b->s_utiles.p);
-  const STile* stl = static_cast<const STile*>(b->s_stiles.p);
   const User* ud = static_cast<const User*>(b->s_user.p);
   auto table = [&](bool adj_in, const c64* in_base, const std::vector<int64_t>& in_off, bool in_m, c64* out_base,
                    const std::vector<int64_t>& out_off, bool out_m, const Ptrs** t) -> fm_status {
@@ -332,27 +264,52 @@ extern "C" fm_status fm_batch_fista(fm_batch b, const void* const* bvec, const i
   hipLaunchKernelGGL(bfill_kernel<int>, dim3(unsigned(cdiv(G, kTPB))), dim3(kTPB), 0, s, G, status, 0);
   hipLaunchKernelGGL(bfill_kernel<int>, dim3(unsigned(cdiv(G, kTPB))), dim3(kTPB), 0, s, G, iters, o->max_iters);
   FM_LAUNCHED();
+  // forward: y -> r (the epilogue subtracts b); adjoint: r -> y (the epilogue
+  // reads y_k at the output position and replaces it by y_{k+1})
   const Ptrs *tf = nullptr, *ta = nullptr;
   FM_TRY(table(false, y, b->s_yoff, false, r, b->s_roff, true, &tf));
-  FM_TRY(table(true, r, b->s_roff, true, g, b->s_yoff, false, &ta));
-  double t = 1.0;
+  FM_TRY(table(true, r, b->s_roff, true, y, b->s_yoff, false, &ta));
+  // momentum weights of every iteration, read on the device through the
+  // iteration counter the stop check advances (so the launches of every
+  // iteration are the same and replay from one captured graph per direction)
+  {
+    std::vector<float> betas(size_t(std::max(o->max_iters, 1)), 0.f);
+    double t = 1.0;
+    for (int k = 0; k < o->max_iters; ++k) {
+      const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
+      betas[size_t(k)] = float((t - 1.0) / tn);
+      t = tn;
+    }
+    if (b->s_beta.bytes < betas.size() * 4) {
+      FM_HIP(hipStreamSynchronize(s));  // earlier work may still read the old array
+      b->s_beta.reset();
+      FM_TRY(b->s_beta.alloc(betas.size() * 4));
+      drop_graphs(b);
+    }
+    FM_HIP(hipMemcpyAsync(b->s_beta.p, betas.data(), betas.size() * 4, hipMemcpyHostToDevice, s));
+    FM_HIP(hipStreamSynchronize(s));  // betas is host memory of this call
+  }
+  int* iter_dev = static_cast<int*>(b->s_iter.p);
+  hipLaunchKernelGGL(bfill_kernel<int>, dim3(1), dim3(kTPB), 0, s, int64_t(1), iter_dev, 0);
+  FM_LAUNCHED();
+  EpiArgs ef, ea;
+  ef.kind = 1;
+  ef.user = ud;
+  ea.kind = 2;
+  ea.user = ud;
+  ea.lam = lam;
+  ea.L = Ld;
+  ea.pbase = static_cast<const int64_t*>(b->s_pbase.p);
+  ea.partial = partial;
+  ea.status = status;
+  ea.momentum = o->momentum != 0;
+  ea.beta = static_cast<const float*>(b->s_beta.p);
+  ea.iter = iter_dev;
   for (int k = 0; k < o->max_iters; ++k) {
-    const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
-    const double beta = (t - 1.0) / tn;
-    t = tn;
-    FM_TRY(batch_launch(b, false, tf, active, s));  // r = A y
-    if (b->s_nstiles > 0) {                         // r -= b
-      hipLaunchKernelGGL(bsub_kernel, dim3(unsigned(b->s_nstiles)), dim3(kTPB), 0, s, stl, cols, ud, r, active);
-      FM_LAUNCHED();
-    }
-    FM_TRY(batch_launch(b, true, ta, active, s));  // g = A^H r
-    if (b->s_nutiles > 0) {
-      hipLaunchKernelGGL(bupdate_kernel, dim3(unsigned(b->s_nutiles)), dim3(kTPB), 0, s, ut, cols, ud, y, g, Ld, lam,
-                         beta, o->momentum != 0, active, status, partial);
-      FM_LAUNCHED();
-    }
+    FM_TRY(batch_launch(b, false, tf, active, s, &ef));  // r = A y - b
+    FM_TRY(batch_launch(b, true, ta, active, s, &ea));   // x, y updated from A^H r
     hipLaunchKernelGGL(bstop_kernel, dim3(unsigned(cdiv(G, 256))), dim3(256), 0, s, cols, G, partial, o->stop_tol, k,
-                       active, iters, status);
+                       active, iters, status, iter_dev);
     FM_LAUNCHED();
   }
   if (stats) {

@@ -232,10 +232,22 @@ struct Mode {
   int mode, spec_conj, tw_log, tw_inv, accumulate;
 };
 
+// Store epilogue: the default stores (or adds) each result at its
+// destination. An epilogue type with kOn = true receives every result
+// instead, in two passes over the thread's values so that all of its loads
+// are in flight before the first store: pre(k, b, e, dst) for every value
+// (load operands), then put(k, slot, b, e, dst, v). k is the value's register
+// index, b the transform inside the work-group, e the element index inside
+// the output vector and slot the thread's accumulator for that transform (g
+// for contiguous transforms of fewer than 16 points, 0 otherwise).
+struct NoEp {
+  static constexpr bool kOn = false;
+};
+
 // Loads, transforms and stores one job. Every thread of the work-group calls it.
-template <typename R, bool STRIDED, int LOGW>
+template <typename R, bool STRIDED, int LOGW, class EP = NoEp>
 __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int logn, Cx<R>* lds,
-                                        const Cx<R>* __restrict__ tw) {
+                                        const Cx<R>* __restrict__ tw, EP* ep = nullptr) {
   constexpr int kWG = Geo<LOGW>::kThreads;
   const int tid = threadIdx.x;
   Cx<R> v[kE];
@@ -312,6 +324,22 @@ __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int lo
       }
     }
     if (valid) {
+      if constexpr (EP::kOn) {  // two halves of 8 values: loads of a half in flight together
+#pragma unroll
+        for (int h = 0; h < kE; h += 8) {
+#pragma unroll
+          for (int k = h; k < h + 8; ++k) {
+            const int p = t + T * k;
+            if (p * inner + ii < jb.out_limit) ep->pre(k, b, p * inner + ii, Y + p * inner);
+          }
+#pragma unroll
+          for (int k = h; k < h + 8; ++k) {
+            const int p = t + T * k;
+            if (p * inner + ii < jb.out_limit) ep->put(k, 0, b, p * inner + ii, Y + p * inner, v[k]);
+          }
+        }
+        return;
+      }
 #pragma unroll
       for (int k = 0; k < kE; ++k) {
         const int p = t + T * k;
@@ -368,6 +396,31 @@ __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int lo
       const Cx<R> w = tab[(r * (jb.q0 + b)) & (twn - 1)];
       v[k] = md.tw_inv ? cmulc(v[k], w) : cmul(v[k], w);
     }
+  }
+  if constexpr (EP::kOn) {  // two halves of 8 values, as above
+#pragma unroll
+    for (int h = 0; h < kE; h += 8) {
+#pragma unroll
+      for (int k = h; k < h + 8; ++k) {
+        const int g = k >> logn, r = k & (N - 1);
+        const int b = STRIDED ? tid + kWG * g : tid * G + g;
+        const int inner = STRIDED ? jb.inner : 1;
+        const int ii = STRIDED ? jb.i0 + b : 0;
+        if (b < jb.nvalid && r * inner + ii < jb.out_limit)
+          ep->pre(k, b, r * inner + ii, STRIDED ? jb.y + b + r * inner : jb.y + b * jb.ybstride + r);
+      }
+#pragma unroll
+      for (int k = h; k < h + 8; ++k) {
+        const int g = k >> logn, r = k & (N - 1);
+        const int b = STRIDED ? tid + kWG * g : tid * G + g;
+        const int inner = STRIDED ? jb.inner : 1;
+        const int ii = STRIDED ? jb.i0 + b : 0;
+        if (b < jb.nvalid && r * inner + ii < jb.out_limit)
+          ep->put(k, STRIDED ? 0 : g, b, r * inner + ii,
+                  STRIDED ? jb.y + b + r * inner : jb.y + b * jb.ybstride + r, v[k]);
+      }
+    }
+    return;
   }
 #pragma unroll
   for (int k = 0; k < kE; ++k) {
