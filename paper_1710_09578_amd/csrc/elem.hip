@@ -184,14 +184,32 @@ __global__ __launch_bounds__(kDV) void dense_vec_kernel(int64_t m, int64_t n, co
   }
   const bool packed = b.outer == 1 || b.ldx == b.outer * b.xvs;
   const bool packed_y = b.outer == 1 || b.ldy == b.outer * b.yvs;
-  // ---- stage the inputs: element e = v*nin + k of the tile
-  {
+  // ---- stage the inputs: element e = v*nin + k of the tile (at most NMAX per
+  // thread). When the vectors are adjacent the tile is one contiguous array
+  // and all its loads are issued before the first LDS store.
+  const int64_t vstride = b.outer == 1 ? b.ldx : b.xvs;
+  if (packed && vstride == nin) {
+    const V* src = x + p0 * nin;
+    V ld[NMAX];
+#pragma unroll
+    for (int i = 0; i < NMAX; ++i) {
+      const int e = t + kDV * i;
+      ld[i] = e < nv * nin ? src[e] : Ops<V>::zero();
+    }
+#pragma unroll
+    for (int i = 0; i < NMAX; ++i) {
+      const int e = t + kDV * i;
+      if (e < nv * nin) {
+        const int v = e / nin, k = e - v * nin;
+        lds[v * stride + k] = ld[i];
+      }
+    }
+  } else {
     int v = t / nin, k = t % nin;
     const int dv = kDV / nin, dk = kDV % nin;
     for (int e = t; e < nv * nin; e += kDV) {
       const int64_t p = p0 + v;
-      const int64_t off = packed ? (b.outer == 1 ? p * b.ldx : p * b.xvs)
-                                 : (p / b.outer) * b.ldx + (p % b.outer) * b.xvs;
+      const int64_t off = packed ? p * vstride : (p / b.outer) * b.ldx + (p % b.outer) * b.xvs;
       lds[v * stride + k] = x[off + k];
       v += dv;
       k += dk;

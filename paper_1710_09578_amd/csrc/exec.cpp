@@ -320,7 +320,30 @@ fm_status exec_kron(const fm_op_s* op, bool adj, Elem e, const Batch& b, const v
   const void* src = x;
   int64_t src_ld = b.ldx, src_vs = b.xvs;
   int stage = 0;
-  for (int k = d - 1; k >= 0; --k, ++stage) {
+  int kstart = d - 1;
+  if (d >= 2 && b.inner == 1 && op->terms[d - 1]->kind == Kind::Dense && op->terms[d - 2]->kind == Kind::Fourier) {
+    // the last two factors (Fourier, small dense) in one slab pass
+    const fm_op_s* F = op->terms[d - 2];
+    const fm_op_s* G = op->terms[d - 1];
+    const int lognf = ilog2(F->L);
+    if (kron_fg_supported(e, lognf, G->m, G->n)) {
+      int64_t slabs = b.outer;
+      for (int l = 0; l < d - 2; ++l) slabs *= cur[l];
+      const int64_t gout = out_rows(G, adj);
+      const bool last = d == 2;
+      void* dst = last ? y : bufs[0];
+      const int64_t dst_ld = last ? b.ldy : slabs * F->L * gout;
+      LAUNCH(launch_kron_fg(lognf, G->m, G->n, param(G, e), G->lda, adj, G->real_entries ? 1 : 0, b.ncols, slabs, x,
+                            b.ldx, dst, dst_ld, last ? int(acc) : 0, s));
+      cur[d - 1] = gout;
+      cur[d - 2] = F->L;
+      src = dst;
+      src_ld = dst_ld;
+      kstart = d - 3;
+      stage = 1;
+    }
+  }
+  for (int k = kstart; k >= 0; --k, ++stage) {
     const fm_op_s* f = op->terms[k];
     int64_t outer = 1, inner = 1;
     for (int l = 0; l < k; ++l) outer *= cur[l];

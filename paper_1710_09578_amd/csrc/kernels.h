@@ -63,6 +63,15 @@ inline int fwht_lds_max_log(Elem e) { return e == Elem::C128 ? 13 : 14; }
 fm_status launch_fwht(Elem e, int logn, const Batch& b, const void* x, void* y, int accumulate,
                       hipStream_t s);
 
+// ---------------------------------------------------------------- fused Kronecker slab
+// Kron(..., F_nF, G) last two factors in one pass (see kron.hip): for each of
+// the ncols * outer slabs of nF x n values (x, column stride ldx) writes the
+// nF x m slab of (F (x) G) (adjoint: (F (x) G)^H with the shapes swapped).
+bool kron_fg_supported(Elem e, int lognf, int64_t m, int64_t n);
+fm_status launch_kron_fg(int lognf, int64_t m, int64_t n, const void* g, int64_t lda, int adjoint, int real_g,
+                         int64_t ncols, int64_t outer, const void* x, int64_t ldx, void* y, int64_t ldy, int acc,
+                         hipStream_t s);
+
 // ---------------------------------------------------------------- elementwise
 // y (+)= d .* x  (d conj'ed when conj) along the vector axis of the batch.
 fm_status launch_diag(Elem e, int64_t n, const Batch& b, const void* d, int conj, const void* x,

@@ -363,3 +363,33 @@ def test_dense_mode_product_many_vectors(gpu, prec, shape, real):
                     x[:, :P * n].astype(np.complex128).reshape(2, P, n)).reshape(2, P * m)
     yh = to_host(y)
     assert rel_err(yh[:, :P * m], ref) <= TOL[prec] and np.all(yh[:, P * m:] == 0)
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+@pytest.mark.parametrize("nf,gshape,real", [(16, (32, 32), True), (64, (20, 12), False), (256, (32, 32), False),
+                                            (512, (5, 3), True), (128, (12, 20), True)])
+def test_kron_fourier_dense_slab(gpu, prec, nf, gshape, real):
+    """Kron(H_4, F_nf, G) and Kron(F_nf, G): the last two factors go through
+    the fused slab pass (complex64) or the per-factor passes (complex128);
+    forward, adjoint and accumulation (Sum of two Kronecker products)."""
+    rng = np.random.default_rng(nf + gshape[0])
+    g = crandn(rng, gshape, NP[prec])
+    if real:
+        g = g.real.astype(NP[prec])
+    gd = g.astype(np.complex128)
+    F = gpu.Fourier(nf, torch_dt(prec))
+    G = gpu.Dense(to_dev(g))
+    H = gpu.Hadamard(4, torch_dt(prec))
+    fs_full = [dense.hadamard(4).astype(complex), dense.fourier(nf), gd]
+    for op, fs in ((gpu.Kron(H, F, G), fs_full), (gpu.Kron(F, G), fs_full[1:])):
+        m, n = op.shape
+        for adj in (False, True):
+            x = crandn(rng, (3, m if adj else n), NP[prec])
+            y = to_host(op.apply(to_dev(x), adjoint=adj))
+            ref = structured.kron_apply(fs, x, adjoint_dir=adj)
+            assert rel_err(y, ref) <= TOL[prec], (adj, rel_err(y, ref))
+    K = gpu.Kron(F, G)
+    S2 = gpu.Sum(K, K)
+    x = crandn(rng, (2, K.shape[1]), NP[prec])
+    y = to_host(S2 @ to_dev(x))
+    assert rel_err(y, 2 * structured.kron_apply(fs_full[1:], x)) <= TOL[prec]
