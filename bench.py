@@ -376,6 +376,7 @@ def main():
     ap.add_argument("--no-learn", action="store_true")
     ap.add_argument("--no-kron", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="keep the default batch schedule")
+    ap.add_argument("--schedule", default="", help="MAX_FUSE,REGION_MIB: fixed batch schedule (no tuning)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 512 MiB device to device (reference for traffic counters)")
     args = ap.parse_args()
@@ -409,7 +410,12 @@ def main():
 
     step, launch, _batch = batched_step_factory(w)
     sched = _batch.schedule()
-    if not args.no_tune:
+    if args.schedule:
+        mf, rg = (int(v) for v in args.schedule.split(","))
+        _batch.set_schedule(mf, rg)
+        sched = _batch.schedule()
+        log(f"fixed schedule: {sched}")
+    elif not args.no_tune:
         sched = _batch.tune(w["xs"], outs=w["ys"], reps=2)
         log(f"tuned schedule: {sched}")
     ms, gpu_ms = time_steps(step, args.steps, args.warmup)

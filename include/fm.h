@@ -238,13 +238,15 @@ typedef struct {
   int32_t max_fuse;    /* strided four-step factors up to 2^max_fuse are folded into the row pass */
   int32_t region_mib;  /* slot region of one chunk of four-step columns (three rotate), MiB */
   int32_t graphs;      /* 1: the stage sequence is replayed from captured HIP graphs */
+  int32_t stages;      /* kernel launches per direction (output only) */
   double ms;           /* measured milliseconds per direction (fm_batch_tune), else 0 */
 } fm_batch_schedule;
 
 /* Autotuner, in the spirit of the paper's run-time calibration (Sec. 2.1):
  * times fm_batch_apply(dir) on the caller's blocks for every candidate
  * schedule (max_fuse 0..5 x slot regions of 24, 48 and 96 MiB), `reps`
- * timed runs each after one warm-up, and keeps the fastest. y receives the
+ * timed runs each after one warm-up, and keeps the fastest (a candidate
+ * replaces the best so far only when it is more than 1 % faster). y receives the
  * correct result. Synchronises the device. A schedule whose max_fuse differs
  * from the per-operator path's default (3, FM_MAX_FUSE) computes the same
  * products with a different rounding order, so results then agree with
@@ -254,6 +256,9 @@ fm_status fm_batch_tune(fm_batch b, fm_dir dir, const void* const* x, const int6
                         void* stream);
 /* The batch's current schedule. */
 fm_status fm_batch_get_schedule(fm_batch b, fm_batch_schedule* out);
+/* Sets the schedule (max_fuse 0..5, region_mib 16..1024; graphs and ms are
+ * ignored). Synchronises the device. */
+fm_status fm_batch_set_schedule(fm_batch b, const fm_batch_schedule* sc);
 
 /* ------------------------------------------------------------------ differentiation
  * Building blocks of reverse-mode differentiation through operator

@@ -72,6 +72,7 @@ class fm_batch_schedule(C.Structure):
         ("max_fuse", C.c_int32),
         ("region_mib", C.c_int32),
         ("graphs", C.c_int32),
+        ("stages", C.c_int32),
         ("ms", C.c_double),
     ]
 
@@ -110,6 +111,7 @@ SIGNATURES = {
     "fm_batch_tune": (ST, [P, C.c_int, C.POINTER(P), C.POINTER(I64), C.POINTER(P), C.POINTER(I64), I32,
                            C.POINTER(fm_batch_schedule), P]),
     "fm_batch_get_schedule": (ST, [P, C.POINTER(fm_batch_schedule)]),
+    "fm_batch_set_schedule": (ST, [P, C.POINTER(fm_batch_schedule)]),
     "fm_circulant_grad_generator": (ST, [I64, I64, C.c_int, P, I64, P, I64, P, I32, C.c_int, P]),
     "fm_fista_step": (ST, [I64, I64, P, P, P, P, P, P, I64, P, C.c_double, C.c_double, C.c_int, P]),
     "fm_fista_step_vjp": (ST, [I64, I64, P, P, P, P, P, P, I64, P, C.c_double, C.c_double, C.c_int, P]),
@@ -298,13 +300,25 @@ def fm_batch_tune(b, direction, xs, ldx, ys, ldy, reps, stream):
     sc = fm_batch_schedule()
     _call("fm_batch_tune", b, direction, _parr(xs), _iarr(ldx), _parr(ys), _iarr(ldy), reps, C.byref(sc),
           _ptr(stream))
-    return {"max_fuse": sc.max_fuse, "region_mib": sc.region_mib, "graphs": sc.graphs, "ms": sc.ms}
+    return _sched_dict(sc)
+
+
+def _sched_dict(sc):
+    return {"max_fuse": sc.max_fuse, "region_mib": sc.region_mib, "graphs": sc.graphs, "stages": sc.stages,
+            "ms": sc.ms}
 
 
 def fm_batch_get_schedule(b):
     sc = fm_batch_schedule()
     _call("fm_batch_get_schedule", b, C.byref(sc))
-    return {"max_fuse": sc.max_fuse, "region_mib": sc.region_mib, "graphs": sc.graphs, "ms": sc.ms}
+    return _sched_dict(sc)
+
+
+def fm_batch_set_schedule(b, max_fuse, region_mib):
+    sc = fm_batch_schedule()
+    sc.max_fuse = int(max_fuse)
+    sc.region_mib = int(region_mib)
+    _call("fm_batch_set_schedule", b, C.byref(sc))
 
 
 def fm_batch_release(b):

@@ -742,7 +742,7 @@ fm_status fm_batch_tune(fm_batch b, fm_dir dir, const void* const* x, const int6
         st = FM_E_DEVICE;
       if (st != FM_OK) break;
       const double per = double(ms) / reps;
-      if (best_ms < 0 || per < best_ms) {
+      if (best_ms < 0 || per < 0.99 * best_ms) {
         best_ms = per;
         best = sc;
       }
@@ -768,7 +768,24 @@ fm_status fm_batch_get_schedule(fm_batch b, fm_batch_schedule* out) {
   out->max_fuse = b->sched.max_fuse;
   out->region_mib = int32_t(b->sched.region_bytes >> 20);
   out->graphs = b->use_graphs ? 1 : 0;
+  int32_t n = 0;
+  for (size_t st = 0; st + 1 < b->stage_off.size(); ++st) n += b->stage_off[st + 1] > b->stage_off[st] ? 1 : 0;
+  out->stages = n;
   out->ms = b->tuned_ms;
+  return FM_OK;
+}
+
+fm_status fm_batch_set_schedule(fm_batch b, const fm_batch_schedule* sc) {
+  set_error("");
+  FM_CHECK_ARG(b != nullptr && sc != nullptr, FM_E_INVALID, "NULL argument");
+  FM_CHECK_ARG(batch_alive(b), FM_E_RELEASED, "batch handle was released");
+  FM_CHECK_ARG(sc->max_fuse >= 0 && sc->max_fuse <= 5, FM_E_INVALID, "max_fuse must be in 0..5");
+  FM_CHECK_ARG(sc->region_mib >= 16 && sc->region_mib <= 1024, FM_E_INVALID, "region_mib must be in 16..1024");
+  Schedule s;
+  s.max_fuse = sc->max_fuse;
+  s.region_bytes = size_t(sc->region_mib) << 20;
+  FM_TRY(build_schedule(b, s));
+  b->tuned_ms = 0.0;
   return FM_OK;
 }
 

@@ -293,6 +293,9 @@ class Batch:
     def schedule(self):
         return capi.fm_batch_get_schedule(self._h)
 
+    def set_schedule(self, max_fuse: int, region_mib: int):
+        capi.fm_batch_set_schedule(self._h, max_fuse, region_mib)
+
     def fista(self, bs, iters=100, momentum=True, lam=None, lam_rel=None, L=None, stop_tol=0.0, x0s=None):
         """FISTA for every column of every operator; bs[i] has shape
         (ncols[i], m_i). Returns (xs, stats) with stats per batch column."""
