@@ -5,10 +5,10 @@
 //   forward:  Y[o, kF, r] = sum_pF W^(pF kF) sum_k G[r, k] X[o, pF, k]
 //   adjoint:  Y[o, pF, k] = sum_kF W^-(pF kF) sum_r conj(G[r, k]) X[o, kF, r]
 // A work-group of 512 threads stages the slab in LDS (coalesced loads),
-// applies op(G) to every row in place (each row is read into registers
-// first; op(G) sits in LDS and is read by broadcast), and then runs the nF-
-// point transforms along the rows' other axis with the register/LDS engine,
-// one transform per output column, storing coalesced rows of the result.
+// applies op(G) to every row in place as a matrix product on the matrix
+// cores (MFMA, fp32), and then runs the nF-point transforms along the rows'
+// other axis with the register/LDS engine, one transform per output column,
+// storing coalesced rows of the result.
 #include <algorithm>
 
 #include "runtime.h"
@@ -36,7 +36,7 @@ struct KronArgs {
   int adj, real, acc;
 };
 
-template <int NIN>
+template <int NIN, bool REAL>
 __global__ __launch_bounds__(kKT) void kron_fg_kernel(KronArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int nF = 1 << a.lognf;
@@ -80,31 +80,106 @@ __global__ __launch_bounds__(kKT) void kron_fg_kernel(KronArgs a) {
     }
   }
   __syncthreads();
-  // op(G) along each row: tpr = 512 / nF threads per row share its outputs
+  // op(G) along each row as a matrix product on the matrix cores
+  // (v_mfma_f32_32x32x2_f32: lane l supplies A[l % 32][l / 32] and
+  // B[l / 32][l % 32]; value v of lane l is D[8 (v / 4) + 4 (l / 32) + v % 4][l % 32]).
+  //   real op(G):    rows m = 2p + part (re / im of slab row p), K = NIN, N = 32:
+  //                  D[m][r] = sum_k X_part[p][k] op(G)[r][k]
+  //   complex op(G): rows m = p, K = 2 NIN ([X_re | X_im]), N = 64 ([Y_re | Y_im]),
+  //                  B = [[Gr^T, Gi^T], [-Gi^T, Gr^T]]
   {
-    const int tpr = kKT / nF;
-    const int row = tid / tpr, part = tid % tpr;
-    c64 xr[NIN];
+    typedef float v16 __attribute__((ext_vector_type(16)));
+    const float* sf = reinterpret_cast<const float*>(slab);
+    const float* gf = reinterpret_cast<const float*>(gm);
+    const int lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 31, lk = lane >> 5;
+    const int mt_count = REAL ? (2 * nF + 31) / 32 : (nF + 31) / 32;
+    const int nt_count = REAL ? 1 : 2;
+    const int ntiles = mt_count * nt_count;
+    // operands of a tile are gathered from LDS before its products are
+    // issued; real op(G): the two tiles of a wave advance together (B is the
+    // same for both); complex op(G): one tile at a time
+    v16 acc[4];
 #pragma unroll
-    for (int k = 0; k < NIN; ++k) xr[k] = k < nin ? slab[row * S + k] : c64{0.f, 0.f};
-    __syncthreads();  // every row is read before any is overwritten
-    for (int r = part; r < nout; r += tpr) {
-      const c64* gr = gm + r * NIN;
-      float sr = 0.f, si = 0.f;
-      if (a.real) {
+    for (int j = 0; j < 4; ++j) acc[j] = v16{};
+    if constexpr (REAL) {
+      constexpr int KS = NIN / 2;
+      float bf[KS];
 #pragma unroll
-        for (int k = 0; k < NIN; ++k) {
-          sr += gr[k].x * xr[k].x;
-          si += gr[k].x * xr[k].y;
+      for (int kk = 0; kk < KS; ++kk) {
+        const int k = 2 * kk + lk;
+        bf[kk] = li < nout ? gf[2 * (li * NIN + k)] : 0.f;  // k >= nin: zero padding of op(G)
+      }
+#pragma unroll
+      for (int j0 = 0; j0 < 4; j0 += 2) {
+        if (wave + 8 * j0 >= ntiles) break;  // uniform across the wave
+        float af[2][KS];
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+          const int tile = wave + 8 * (j0 + jj);
+          const int m = tile * 32 + li;
+          const int p = m >> 1, part = m & 1;
+#pragma unroll
+          for (int kk = 0; kk < KS; ++kk) {
+            const int k = 2 * kk + lk;
+            af[jj][kk] = (tile < ntiles && p < nF && k < nin) ? sf[2 * (p * S + k) + part] : 0.f;
+          }
         }
-      } else {
 #pragma unroll
-        for (int k = 0; k < NIN; ++k) {
-          sr += gr[k].x * xr[k].x - gr[k].y * xr[k].y;
-          si += gr[k].x * xr[k].y + gr[k].y * xr[k].x;
+        for (int kk = 0; kk < KS; ++kk) {
+          acc[j0] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[0][kk], bf[kk], acc[j0], 0, 0, 0);
+          acc[j0 + 1] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[1][kk], bf[kk], acc[j0 + 1], 0, 0, 0);
         }
       }
-      slab[row * S + r] = c64{sr, si};
+    } else {
+      constexpr int KS = NIN;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int tile = wave + 8 * j;
+        if (tile < ntiles) {
+          const int mt = tile / nt_count, nt = tile % nt_count;
+          const int m = mt * 32 + li;
+          float af[KS], bf[KS];
+#pragma unroll
+          for (int kk = 0; kk < KS; ++kk) {
+            const int k = 2 * kk + lk;
+            const int kr = k < NIN ? k : k - NIN, kpart = k < NIN ? 0 : 1;
+            af[kk] = (m < nF && kr < nin) ? sf[2 * (m * S + kr) + kpart] : 0.f;
+            const int n = nt * 32 + li;
+            const int nr = n & 31, npart = n >> 5;
+            float bv = 0.f;
+            if (nr < nout) {
+              const float gr = gf[2 * (nr * NIN + kr)], gi = gf[2 * (nr * NIN + kr) + 1];
+              bv = kpart == 0 ? (npart == 0 ? gr : gi) : (npart == 0 ? -gi : gr);
+            }
+            bf[kk] = bv;
+          }
+#pragma unroll
+          for (int kk = 0; kk < KS; ++kk)
+            acc[j] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[kk], bf[kk], acc[j], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();  // every product has read the slab: write the results in place
+    float* so = reinterpret_cast<float*>(slab);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int tile = wave + 8 * j;
+      if (tile < ntiles) {
+        const int mt = tile / nt_count, nt = tile % nt_count;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int m = mt * 32 + 8 * (v / 4) + 4 * lk + (v % 4);
+          const int n = nt * 32 + li;
+          if (REAL) {
+            const int p = m >> 1, part = m & 1;
+            if (p < nF && n < nout) so[2 * (p * S + n) + part] = acc[j][v];
+          } else {
+            const int nr = n & 31, npart = n >> 5;
+            if (m < nF && nr < nout) so[2 * (m * S + nr) + npart] = acc[j][v];
+          }
+        }
+      }
     }
     __syncthreads();
   }
@@ -169,23 +244,27 @@ fm_status launch_kron_fg(int lognf, int64_t m, int64_t n, const void* g, int64_t
   const int NIN = nin <= 8 ? 8 : nin <= 16 ? 16 : 32;
   const size_t slab_vals = std::max<size_t>(size_t(nF) * S, size_t(Geo<kKW>::kVals + Geo<kKW>::kVals / 16));
   const size_t lds = (slab_vals + size_t(nout) * NIN) * sizeof(c64);
-  static bool attr = false;
-  if (!attr) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&kron_fg_kernel<8>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&kron_fg_kernel<16>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&kron_fg_kernel<32>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    attr = true;
-  }
   const dim3 grid{unsigned(blocks)};
-  if (NIN == 8)
-    hipLaunchKernelGGL(kron_fg_kernel<8>, grid, dim3(kKT), lds, s, a);
-  else if (NIN == 16)
-    hipLaunchKernelGGL(kron_fg_kernel<16>, grid, dim3(kKT), lds, s, a);
-  else
-    hipLaunchKernelGGL(kron_fg_kernel<32>, grid, dim3(kKT), lds, s, a);
+#define FM_KRON_LAUNCH(N, RL)                                                                           \
+  do {                                                                                                 \
+    static bool attr = false;                                                                          \
+    if (!attr) {                                                                                       \
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&kron_fg_kernel<N, RL>),                 \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);               \
+      attr = true;                                                                                     \
+    }                                                                                                  \
+    hipLaunchKernelGGL((kron_fg_kernel<N, RL>), grid, dim3(kKT), lds, s, a);                           \
+  } while (0)
+  if (real_g) {
+    if (NIN == 8) FM_KRON_LAUNCH(8, true);
+    else if (NIN == 16) FM_KRON_LAUNCH(16, true);
+    else FM_KRON_LAUNCH(32, true);
+  } else {
+    if (NIN == 8) FM_KRON_LAUNCH(8, false);
+    else if (NIN == 16) FM_KRON_LAUNCH(16, false);
+    else FM_KRON_LAUNCH(32, false);
+  }
+#undef FM_KRON_LAUNCH
   FM_LAUNCHED();
   return FM_OK;
 }

@@ -83,6 +83,15 @@ def test_invalid_arguments_return_status(lib):
     assert st(lib, "fm_axpby", 8, 1, C.c_double(1.0), None, 4, C.c_double(1.0), None, 8, None, 8, 1, None) == 2
     assert st(lib, "fm_op_norm_bound", None, None, None) == 1
     assert st(lib, "fm_op_norm_bound", bogus, None, None) == 9
+    # batch schedule / tuner
+    from paper_1710_09578_amd import capi
+
+    sc = capi.fm_batch_schedule()
+    assert st(lib, "fm_batch_get_schedule", None, C.byref(sc)) == 1
+    assert st(lib, "fm_batch_get_schedule", bogus, C.byref(sc)) == 9
+    assert st(lib, "fm_batch_set_schedule", bogus, C.byref(sc)) == 9
+    assert st(lib, "fm_batch_tune", None, 0, None, None, None, None, 1, None, None) == 1
+    assert st(lib, "fm_batch_apply", bogus, 0, None, None, None, None, None) == 9
 
 
 def test_binding_raises(lib):
