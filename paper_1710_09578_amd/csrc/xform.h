@@ -105,18 +105,20 @@ __device__ __forceinline__ void dft(Cx<R>* a) {
 
 __device__ __forceinline__ int pad16(int pos) { return pos + (pos >> 4); }
 
-// Twiddles W^(jj r), r = 1..15, from the table entries W^(jj), W^(2jj),
-// W^(4jj), W^(8jj) (products of at most three of them).
+// Twiddles W^(jj r), r = 1..15, from the single table entry W^(jj): W^(2jj),
+// W^(4jj), W^(8jj) by squaring, the others as products of at most three of
+// them. The transform is bound by its loads, so one load and 14 complex
+// products beat four loads and 11 products.
 template <typename R>
 __device__ __forceinline__ void twiddles16(const Cx<R>* __restrict__ tab, int jj, Cx<R>* w) {
   w[1] = tab[jj];
-  w[2] = tab[2 * jj];
+  w[2] = cmul(w[1], w[1]);
   w[3] = cmul(w[1], w[2]);
-  w[4] = tab[4 * jj];
+  w[4] = cmul(w[2], w[2]);
   w[5] = cmul(w[1], w[4]);
   w[6] = cmul(w[2], w[4]);
   w[7] = cmul(w[3], w[4]);
-  w[8] = tab[8 * jj];
+  w[8] = cmul(w[4], w[4]);
 #pragma unroll
   for (int r = 9; r < 16; ++r) w[r] = cmul(w[r - 8], w[8]);
 }
@@ -282,10 +284,15 @@ __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int lo
 #pragma unroll
         for (int k = 0; k < kE; ++k) v[k] = cadd(v[k], cmul(val[k], w));
       }
+      {  // W_L^((t + T k) k2) = W_L^(t k2) (W_L^(T k2))^k: two loads, the rest by products
+        const Cx<R>* tab = tw + (1 << lgL);
+        Cx<R> w = tab[(t * k2) & ((1 << lgL) - 1)];
+        const Cx<R> ws = tab[(T * k2) & ((1 << lgL) - 1)];
 #pragma unroll
-      for (int k = 0; k < kE; ++k) {
-        const int p = t + T * k;
-        v[k] = cmul(v[k], tw[(1 << lgL) + ((p * k2) & ((1 << lgL) - 1))]);
+        for (int k = 0; k < kE; ++k) {
+          v[k] = cmul(v[k], w);
+          w = cmul(w, ws);
+        }
       }
     } else {
 #pragma unroll
@@ -316,11 +323,13 @@ __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int lo
       const int twn = 1 << md.tw_log;
       const Cx<R>* tab = tw + twn;
       const int qq = jb.q0 + b;
+      // W^((t + T k) q) = W^(t q) (W^(T q))^k: two loads, the rest by products
+      Cx<R> w = tab[(t * qq) & (twn - 1)];
+      const Cx<R> ws = tab[(T * qq) & (twn - 1)];
 #pragma unroll
       for (int k = 0; k < kE; ++k) {
-        const int p = t + T * k;
-        const Cx<R> w = tab[(p * qq) & (twn - 1)];
         v[k] = md.tw_inv ? cmulc(v[k], w) : cmul(v[k], w);
+        w = cmul(w, ws);
       }
     }
     if (valid) {
