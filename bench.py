@@ -337,6 +337,133 @@ def kron_hfg_bandwidth(steps=5, warmup=2):
             "alg_bytes_per_step": int(alg)}
 
 
+def circulant_wide_bandwidth(steps=10, warmup=3):
+    """Forward + adjoint of the 1024-point circulant on 65,536 columns
+    (complex64, 512 MiB per block): one single-pass convolution launch per
+    direction. Algorithmic bytes per direction: read the block + write the
+    block (+ the 8 KiB spectrum)."""
+    import torch
+
+    import paper_1710_09578_amd as fm
+    from workloads import many_columns
+
+    dev = torch.device("cuda:0")
+    c, X = many_columns(device=dev)
+    C = fm.Circulant(torch.from_numpy(c).to(dev))
+    Y = torch.empty_like(X)
+    Z = torch.empty_like(X)
+
+    def step():
+        C.apply(X, out=Y)
+        C.apply(Y, adjoint=True, out=Z)
+
+    ms, _ = time_steps(step, steps, warmup)
+    alg = 2 * (2 * X.numel() * 8 + c.size * 8)
+    gbs = alg / (ms * 1e-3) / 1e9
+    log(f"circulant 1024 x 65536 columns: {ms:.3f} ms per fwd+adj, {gbs:.1f} GB/s")
+    del X, Y, Z
+    torch.cuda.empty_cache()
+    return {"workload": "Circulant N=1024, 65536 CN(0,1) columns, complex64, fwd+adj",
+            "ms_per_step": round(ms, 4), "gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "alg_bytes_per_step": int(alg)}
+
+
+def ultrasound_model(steps=5, warmup=2):
+    """The compressed ultrasound model b = Psi H x on synthetic generators:
+    H = 32 x 32 blocks of 2-level Toeplitz (levels 32, 512; embedding
+    64 x 1024), x of 524288 entries, Psi keeps one Fourier coefficient per
+    A-scan (1024 measurements). Times H fwd+adj (spectral mixing; and block by
+    block for comparison), Psi H fwd+adj and a 20-step FISTA solve.
+    Algorithmic bytes of one H direction: every block spectrum read once
+    (1024 x 65536 complex64) + x read + y written."""
+    import torch
+
+    import paper_1710_09578_amd as fm
+    from workloads import ultrasound
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    w = ultrasound()
+    n1, n2, n3, nf = w["shape"]
+    t = torch.from_numpy(w["t"]).to(dev)
+    H, Psi, PH = fm.compressed_ultrasound(t, w["psi_rows"])
+    del t
+    torch.cuda.synchronize()
+    log(f"ultrasound model built in {time.perf_counter() - t0:.1f} s")
+    n = n1 * n2 * n3
+    total = (2 * n2) * (2 * n3)
+    x = torch.from_numpy(w["x_true"]).to(dev)
+    y = torch.empty_like(x)
+    z = torch.empty_like(x)
+
+    def h_step(op):
+        def step():
+            op.apply(x, out=y)
+            op.apply(y, adjoint=True, out=z)
+        return step
+
+    ms_h, _ = time_steps(h_step(H), steps, warmup)
+    alg_dir = n1 * n1 * total * 8 + 2 * n * 8
+    gbs_h = 2 * alg_dir / (ms_h * 1e-3) / 1e9
+    log(f"ultrasound H fwd+adj (spectral mixing): {ms_h:.3f} ms, {gbs_h:.1f} GB/s")
+    blocks = H._keep
+    Hg = fm.Blocks([[fm.Product(blocks[0])] + list(blocks[1:n1])] +
+                   [list(blocks[i * n1:(i + 1) * n1]) for i in range(1, n1)])
+    ms_g, _ = time_steps(h_step(Hg), 1, 1)
+    log(f"ultrasound H fwd+adj (block by block): {ms_g:.3f} ms")
+    del Hg
+    m = PH.shape[0]
+    b = PH.apply(x) + torch.from_numpy(w["noise"]).to(dev)
+    v = torch.empty((1, m), dtype=x.dtype, device=dev)
+
+    def ph_step():
+        PH.apply(x, out=v)
+        PH.apply(v, adjoint=True, out=z)
+
+    ms_ph, _ = time_steps(ph_step, steps, warmup)
+    log(f"ultrasound Psi H fwd+adj: {ms_ph:.3f} ms")
+    L, _ = fm.power_iteration(PH)
+    torch.cuda.synchronize()
+    fm.fista(PH, b, iters=20, lam_rel=0.05, L=L)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    reps = 3
+    for _ in range(reps):
+        xr, st = fm.fista(PH, b, iters=20, lam_rel=0.05, L=L)
+    torch.cuda.synchronize()
+    fista_ms = (time.perf_counter() - t1) / reps * 1e3
+    log(f"ultrasound FISTA 20 steps on Psi H: {fista_ms:.2f} ms per solve (L = {L:.4g})")
+    del x, y, z, b, v, H, Psi, PH
+    torch.cuda.empty_cache()
+    return {"workload": "compressed ultrasound model: H = 32 x 32 blocks of 2-level Toeplitz (32 x 512), "
+                        "Psi = 1 Fourier coefficient per A-scan, complex64",
+            "h_ms_fwd_adj": round(ms_h, 4), "h_gbs": round(gbs_h, 1), "h_hbm_frac": round(gbs_h / HBM_PEAK_GBS, 4),
+            "h_block_by_block_ms": round(ms_g, 3), "mix_speedup": round(ms_g / ms_h, 1),
+            "psi_h_ms_fwd_adj": round(ms_ph, 4), "fista20_ms": round(fista_ms, 3),
+            "alg_bytes_per_direction": int(alg_dir)}
+
+
+def copy_bandwidth(nbytes=1 << 30, reps=10):
+    """Device-to-device copy rate (read + write bytes per second): the
+    practical ceiling of a streaming kernel on this device."""
+    import torch
+
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    gbs = 2 * nbytes * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def cpu_baseline_toeplitz(w, budget_s=15.0):
     """The oracle's dense-free Toeplitz product (row blocks generated from the
     definition, BLAS products) on a bounded sample of the same operators."""
@@ -375,6 +502,8 @@ def main():
     ap.add_argument("--no-fista", action="store_true")
     ap.add_argument("--no-learn", action="store_true")
     ap.add_argument("--no-kron", action="store_true")
+    ap.add_argument("--no-wide", action="store_true", help="skip the 1024-point circulant on 65536 columns")
+    ap.add_argument("--no-ultrasound", action="store_true", help="skip the compressed ultrasound model")
     ap.add_argument("--no-tune", action="store_true", help="keep the default batch schedule")
     ap.add_argument("--schedule", default="", help="MAX_FUSE,REGION_MIB: fixed batch schedule (no tuning)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -448,6 +577,12 @@ def main():
     fres = None if args.no_fista else fista_solves(w, tune=not args.no_tune)
     learn = None if args.no_learn else learn_circulant_steps()
     kron = None if args.no_kron else kron_hfg_bandwidth()
+    wide = None if args.no_wide else circulant_wide_bandwidth()
+    us = None if args.no_ultrasound else ultrasound_model()
+    copy_gbs = copy_bandwidth()
+    log(f"device copy: {copy_gbs:.1f} GB/s")
+    roof["copy_gbs"] = round(copy_gbs, 1)
+    roof["copy_frac"] = round(achieved / copy_gbs, 4)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline_toeplitz(w)
@@ -477,6 +612,8 @@ def main():
         "fista": fres,
         "learn_circulant": learn,
         "kron": kron,
+        "wide_circulant": wide,
+        "ultrasound": us,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -126,6 +126,21 @@ fm_status fm_op_create_select_rows(fm_op* out, int64_t n_in, int64_t m, const in
  * Retains the terms. */
 fm_status fm_op_compose(fm_op* out, fm_compose_kind kind, int32_t nterms, const fm_op* terms);
 
+/* Block matrix H = [A_ij], i < nbr, j < nbc: the N1 x N1 block structure of
+ * the ultrasound model (section "Application to Ultrasonic Nondestructive
+ * Testing", the block matrix of eq. (6)'s H with 2-level Toeplitz blocks of
+ * eq. (7), and the Blocks operator of the listing next to it).
+ * terms: nbr * nbc handles, row-major (terms[i * nbc + j] = A_ij), one dtype;
+ * every block of a block row has the same number of rows, every block of a
+ * block column the same number of columns (FM_E_SHAPE otherwise). A handle may
+ * appear several times. Forward y_i = sum_j A_ij x_j, adjoint
+ * x_j = sum_i A_ij^H y_i, where x_j / y_i are the row slices of the columns.
+ * When every block is a multilevel Toeplitz of one geometry, each input slice
+ * is transformed once, the blocks are mixed per frequency bin and each output
+ * slice is transformed back once (2 (nbr + nbc) transforms instead of
+ * 2 nbr nbc). Retains the terms. */
+fm_status fm_op_create_blocks(fm_op* out, int32_t nbr, int32_t nbc, const fm_op* terms);
+
 /* Hermitian transpose A^H as an operator (shares A's storage, retains A). */
 fm_status fm_op_adjoint(fm_op* out, fm_op a);
 

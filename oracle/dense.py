@@ -144,6 +144,48 @@ def blkdiag(*blocks) -> np.ndarray:
     return out
 
 
+def blocks(grid) -> np.ndarray:
+    """Block matrix [A_ij] (the block structure of the ultrasound model's H,
+    section "Application to Ultrasonic Nondestructive Testing"): block (i, j)
+    occupies rows roff_i .. roff_i + m_i and columns coff_j .. coff_j + n_j,
+    with m_i the rows of the blocks of block row i and n_j the columns of the
+    blocks of block column j."""
+    grid = [[np.asarray(a, dtype=C128) for a in r] for r in grid]
+    m_i = [r[0].shape[0] for r in grid]
+    n_j = [a.shape[1] for a in grid[0]]
+    for r in grid:
+        assert [a.shape[1] for a in r] == n_j
+        assert all(a.shape[0] == r[0].shape[0] for a in r)
+    out = np.zeros((sum(m_i), sum(n_j)), dtype=C128)
+    r0 = 0
+    for i, r in enumerate(grid):
+        c0 = 0
+        for j, a in enumerate(r):
+            out[r0:r0 + m_i[i], c0:c0 + n_j[j]] = a
+            c0 += n_j[j]
+        r0 += m_i[i]
+    return out
+
+
+def ml_toeplitz_rows(n_levels, t, rows) -> np.ndarray:
+    """Rows ``rows`` of ``ml_toeplitz(n_levels, t)``, built from the same
+    definition for those rows only (for operators too large to store)."""
+    n_levels = [int(v) for v in n_levels]
+    t = np.asarray(t, dtype=C128)
+    ri = np.unravel_index(np.asarray(rows, dtype=np.int64), n_levels)
+    cj = np.unravel_index(np.arange(int(np.prod(n_levels))), n_levels)
+    off = tuple(ri[l][:, None] - cj[l][None, :] + n_levels[l] - 1 for l in range(len(n_levels)))
+    return t[off]
+
+
+def fourier_rows(n: int, rows) -> np.ndarray:
+    """Selected rows of the DFT matrix of eq. (1): the blocks Phi of the
+    compressed model, eq. (9)."""
+    k = np.asarray(rows, dtype=np.int64)[:, None]
+    j = np.arange(n)[None, :]
+    return np.exp(-2j * np.pi * ((k * j) % n) / n)
+
+
 def adjoint(a) -> np.ndarray:
     """Hermitian transpose, the matrix of the backward transform (eq. 4)."""
     return np.asarray(a).conj().T

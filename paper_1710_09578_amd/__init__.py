@@ -11,6 +11,7 @@ from .capi import FmError, load  # noqa: F401
 from .operators import (  # noqa: F401
     Batch,
     BlkDiag,
+    Blocks,
     Circulant,
     Dense,
     Diag,
@@ -19,10 +20,12 @@ from .operators import (  # noqa: F401
     Kron,
     MLToeplitz,
     Operator,
+    Partial,
     Product,
     SelectRows,
     Sum,
     Toeplitz,
+    compressed_ultrasound,
     fista,
     fista_options,
     power_iteration,

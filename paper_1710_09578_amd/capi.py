@@ -93,6 +93,7 @@ SIGNATURES = {
     "fm_op_create_mltoeplitz": (ST, [C.POINTER(P), I32, C.POINTER(I64), P, C.c_int, P]),
     "fm_op_create_select_rows": (ST, [C.POINTER(P), I64, I64, P, C.c_int, P]),
     "fm_op_compose": (ST, [C.POINTER(P), C.c_int, I32, C.POINTER(P)]),
+    "fm_op_create_blocks": (ST, [C.POINTER(P), I32, I32, C.POINTER(P)]),
     "fm_op_adjoint": (ST, [C.POINTER(P), P]),
     "fm_op_shape": (ST, [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(C.c_int)]),
     "fm_op_release": (ST, [P]),
@@ -223,6 +224,14 @@ def fm_op_compose(kind, terms):
     h = P()
     arr = (P * len(terms))(*[t.value if isinstance(t, P) else t for t in terms])
     _call("fm_op_compose", C.byref(h), kind, len(terms), arr)
+    return h
+
+
+def fm_op_create_blocks(nbr, nbc, terms):
+    """terms: nbr * nbc handles, row-major."""
+    h = P()
+    arr = (P * len(terms))(*[t.value if isinstance(t, P) else t for t in terms])
+    _call("fm_op_create_blocks", C.byref(h), nbr, nbc, arr)
     return h
 
 

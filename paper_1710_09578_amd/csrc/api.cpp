@@ -471,6 +471,65 @@ fm_status fm_op_compose(fm_op* out, fm_compose_kind kind, int32_t nterms, const 
   return publish(op, out);
 }
 
+fm_status fm_op_create_blocks(fm_op* out, int32_t nbr, int32_t nbc, const fm_op* terms) {
+  set_error("");
+  CHECK_OUT(out);
+  FM_CHECK_ARG(nbr >= 1 && nbc >= 1 && terms != nullptr, FM_E_INVALID, "blocks: need a non-empty grid");
+  FM_CHECK_ARG(int64_t(nbr) * nbc <= (int64_t(1) << 20), FM_E_UNSUPPORTED, "blocks: more than 2^20 blocks");
+  const int64_t nb = int64_t(nbr) * nbc;
+  for (int64_t k = 0; k < nb; ++k) {
+    CHECK_LIVE(terms[k]);
+    FM_CHECK_ARG(terms[k]->dt == terms[0]->dt, FM_E_DTYPE, "blocks: blocks have different dtypes");
+  }
+  std::vector<int64_t> roff(nbr + 1, 0), coff(nbc + 1, 0);
+  for (int i = 0; i < nbr; ++i) {
+    for (int j = 1; j < nbc; ++j)
+      FM_CHECK_ARG(terms[i * nbc + j]->m == terms[i * nbc]->m, FM_E_SHAPE,
+                   "blocks: block (%d, %d) has %lld rows, block (%d, 0) has %lld", i, j,
+                   (long long)terms[i * nbc + j]->m, i, (long long)terms[i * nbc]->m);
+    roff[i + 1] = roff[i] + terms[i * nbc]->m;
+  }
+  for (int j = 0; j < nbc; ++j) {
+    for (int i = 1; i < nbr; ++i)
+      FM_CHECK_ARG(terms[i * nbc + j]->n == terms[j]->n, FM_E_SHAPE,
+                   "blocks: block (%d, %d) has %lld columns, block (0, %d) has %lld", i, j,
+                   (long long)terms[i * nbc + j]->n, j, (long long)terms[j]->n);
+    coff[j + 1] = coff[j] + terms[j]->n;
+  }
+  fm_op_s* op;
+  FM_TRY(new_op(Kind::Blocks, terms[0]->dt, roff[nbr], coff[nbc], &op));
+  Building g{op};
+  for (int64_t k = 0; k < nb; ++k) {
+    terms[k]->refs.fetch_add(1);
+    op->terms.push_back(terms[k]);
+  }
+  op->nbr = nbr;
+  op->nbc = nbc;
+  op->roff = roff;
+  op->coff = coff;
+  // spectral mixing applies when every block is a multilevel Toeplitz of one geometry
+  bool mix = true;
+  for (int64_t k = 0; k < nb && mix; ++k)
+    mix = terms[k]->kind == Kind::MLToeplitz && terms[k]->lv == terms[0]->lv && terms[k]->lL == terms[0]->lL;
+  if (mix) {
+    std::vector<const void*> t32(nb), t64(nb);
+    for (int64_t k = 0; k < nb; ++k) {
+      t32[k] = terms[k]->p32.p;
+      t64[k] = terms[k]->p64.p;
+    }
+    FM_TRY(op->p64.alloc(size_t(nb) * sizeof(void*)));
+    FM_HIP(hipMemcpy(op->p64.p, t64.data(), size_t(nb) * sizeof(void*), hipMemcpyHostToDevice));
+    if (op->dt == FM_C64) {
+      FM_TRY(op->p32.alloc(size_t(nb) * sizeof(void*)));
+      FM_HIP(hipMemcpy(op->p32.p, t32.data(), size_t(nb) * sizeof(void*), hipMemcpyHostToDevice));
+    }
+    op->lv = terms[0]->lv;
+    op->lL = terms[0]->lL;
+  }
+  op->mix = mix;
+  return publish(g.release(), out);
+}
+
 fm_status fm_op_adjoint(fm_op* out, fm_op a) {
   set_error("");
   CHECK_OUT(out);

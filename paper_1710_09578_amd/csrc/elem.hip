@@ -68,6 +68,56 @@ __global__ __launch_bounds__(256) void diag_kernel(int64_t n, Batch b, const V* 
   }
 }
 
+// Spectral mixing of a block matrix (one thread per bin and column, OB
+// outputs per work-group row): the inputs of PC blocks are held in registers
+// while the OB x PC spectrum values of the chunk stream in, all loads of a
+// chunk in flight together; the OB sums stay in registers over the chunks.
+struct MixArgs {
+  int nout, nin, ld, adjoint;
+  int64_t total, ncols;
+  const void* const* table;
+  const void* x;
+  void* y;
+};
+
+template <typename R, int OB, int PC>
+__global__ __launch_bounds__(256) void block_mix_kernel(MixArgs a) {
+  const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (f >= a.total) return;
+  const Cx<R>* X = static_cast<const Cx<R>*>(a.x);
+  Cx<R>* Y = static_cast<Cx<R>*>(a.y);
+  const Cx<R>* const* tab = reinterpret_cast<const Cx<R>* const*>(a.table);
+  const int o0 = int(blockIdx.z) * OB;
+  for (int64_t c = blockIdx.y; c < a.ncols; c += gridDim.y) {
+    Cx<R> acc[OB];
+#pragma unroll
+    for (int k = 0; k < OB; ++k) acc[k] = {R(0), R(0)};
+    for (int p0 = 0; p0 < a.nin; p0 += PC) {
+      Cx<R> xr[PC];
+#pragma unroll
+      for (int q = 0; q < PC; ++q)
+        xr[q] = p0 + q < a.nin ? X[(int64_t(p0 + q) * a.ncols + c) * a.total + f] : Cx<R>{R(0), R(0)};
+#pragma unroll
+      for (int k = 0; k < OB; ++k) {
+        const int o = o0 + k;
+        if (o >= a.nout) break;
+        Cx<R> sv[PC];
+#pragma unroll
+        for (int q = 0; q < PC; ++q) {
+          const int p = p0 + q;
+          sv[q] = p < a.nin ? (a.adjoint ? tab[int64_t(p) * a.ld + o][f] : tab[int64_t(o) * a.ld + p][f])
+                            : Cx<R>{R(0), R(0)};
+        }
+#pragma unroll
+        for (int q = 0; q < PC; ++q) acc[k] = cadd(acc[k], a.adjoint ? cmulc(xr[q], sv[q]) : cmul(xr[q], sv[q]));
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < OB; ++k)
+      if (o0 + k < a.nout) Y[(int64_t(o0 + k) * a.ncols + c) * a.total + f] = acc[k];
+  }
+}
+
 template <typename V>
 __global__ __launch_bounds__(256) void gather_kernel(int64_t m, Batch b, const int32_t* __restrict__ idx,
                                                      const V* __restrict__ x, V* y, int acc) {
@@ -511,6 +561,27 @@ fm_status launch_box_copy(Elem e, int ndim, const int64_t* box, const int64_t* s
   dim3 g(unsigned(cdiv(total, 256)), unsigned(ncols < 65535 ? ncols : 65535));
   FM_ELEM_SWITCH(e, V, hipLaunchKernelGGL(box_kernel<V>, g, dim3(256), 0, s, bx, ncols, (const V*)x,
                                           ldx, (V*)y, ldy, acc));
+  FM_LAUNCHED();
+  return FM_OK;
+}
+
+fm_status launch_block_mix(Elem e, int nout, int nin, int ld, int64_t total, int64_t ncols, const void* table,
+                           int adjoint, const void* x, void* y, hipStream_t s) {
+  if (ncols == 0 || total == 0 || nout == 0) return FM_OK;
+  MixArgs a{nout, nin, ld, adjoint, total, ncols, static_cast<const void* const*>(table), x, y};
+  const unsigned gy = unsigned(ncols < 65535 ? ncols : 65535);
+  if (e == Elem::C64) {
+    constexpr int OB = 8;
+    const dim3 g(unsigned(cdiv(total, 256)), gy, unsigned(cdiv(nout, OB)));
+    hipLaunchKernelGGL((block_mix_kernel<float, OB, 16>), g, dim3(256), 0, s, a);
+  } else if (e == Elem::C128) {
+    constexpr int OB = 4;
+    const dim3 g(unsigned(cdiv(total, 256)), gy, unsigned(cdiv(nout, OB)));
+    hipLaunchKernelGGL((block_mix_kernel<double, OB, 16>), g, dim3(256), 0, s, a);
+  } else {
+    set_error("block mix: integer element type");
+    return FM_E_DTYPE;
+  }
   FM_LAUNCHED();
   return FM_OK;
 }

@@ -5,7 +5,10 @@
 // right to left (forward) or its term adjoints left to right (adjoint); a Sum
 // accumulates its terms; a Kronecker product applies each factor as a mode
 // product along its own axis (eq. (7) structure, first factor slowest); a
-// block-diagonal operator applies each block to its slice of rows. Leaves
+// block-diagonal operator applies each block to its slice of rows (runs of one
+// repeated block in one batched call); a block matrix accumulates its blocks
+// into the output slices, or, for multilevel Toeplitz blocks of one geometry,
+// transforms each slice once and mixes the blocks per frequency bin. Leaves
 // launch the HIP kernels. Temporaries come from a stack over the workspace.
 #include <cstring>
 
@@ -376,6 +379,94 @@ fm_status exec_kron(const fm_op_s* op, bool adj, Elem e, const Batch& b, const v
   return FM_OK;
 }
 
+// Block matrix, general path: output slice o (+)= sum over input slices p of
+// block (o, p) (forward: A_op; adjoint: A_po^H).
+fm_status exec_blocks_general(const fm_op_s* op, bool adj, Elem e, const Batch& b, const void* x, void* y,
+                              bool acc, Workspace& ws, hipStream_t s) {
+  const int nout = adj ? op->nbc : op->nbr, nin = adj ? op->nbr : op->nbc;
+  const std::vector<int64_t>& ooff = adj ? op->coff : op->roff;
+  const std::vector<int64_t>& ioff = adj ? op->roff : op->coff;
+  const size_t es = elem_bytes(e);
+  for (int o = 0; o < nout; ++o) {
+    char* ys = static_cast<char*>(y) + size_t(ooff[o] * b.inner) * es;
+    for (int p = 0; p < nin; ++p) {
+      const fm_op_s* blk = adj ? op->terms[size_t(p) * op->nbc + o] : op->terms[size_t(o) * op->nbc + p];
+      const char* xs = static_cast<const char*>(x) + size_t(ioff[p] * b.inner) * es;
+      FM_TRY(exec(blk, adj, e, b, xs, ys, p == 0 ? acc : true, ws, s));
+    }
+  }
+  return FM_OK;
+}
+
+// Block matrix of multilevel Toeplitz blocks of one geometry: zero-pad every
+// input slice into the embedding grid and transform it once, form
+// Y_o = sum_p S_op .* X_p per bin (S_op = the block's spectrum, conj'ed and
+// transposed for the adjoint), transform every output back once and crop.
+fm_status exec_blocks_mix(const fm_op_s* op, bool adj, Elem e, const Batch& b, const void* x, void* y,
+                          bool acc, Workspace& ws, hipStream_t s) {
+  Batch fb;
+  FM_CHECK_ARG(b.inner == 1 && fold_outer(b, op->n, op->m, &fb) && fb.outer == 1, FM_E_UNSUPPORTED,
+               "block matrix along a strided axis");
+  const int nout = adj ? op->nbc : op->nbr, nin = adj ? op->nbr : op->nbc;
+  const std::vector<int64_t>& ooff = adj ? op->coff : op->roff;
+  const std::vector<int64_t>& ioff = adj ? op->roff : op->coff;
+  const int d = int(op->lv.size());
+  int64_t total = 1;
+  for (int l = 0; l < d; ++l) total *= op->lL[l];
+  const int64_t nc = fb.ncols;
+  const int nmax = nout > nin ? nout : nin;
+  const size_t es = elem_bytes(e);
+  const size_t mk = ws.mark();
+  char* w1 = static_cast<char*>(ws.take(size_t(nmax) * size_t(nc * total) * es));
+  char* w2 = static_cast<char*>(ws.take(size_t(nmax) * size_t(nc * total) * es));
+  const fm_op_s* kf = op->terms[0]->terms[0];  // Kron of Fourier(L_l) of the first block
+  for (int p = 0; p < nin; ++p)
+    LAUNCH(launch_box_copy(e, d, op->lv.data(), op->lv.data(), op->lL.data(), nc,
+                           static_cast<const char*>(x) + size_t(ioff[p]) * es, fb.ldx,
+                           w1 + size_t(p) * size_t(nc * total) * es, total, 0, s));
+  Batch kin{nin * nc, 1, 1, total, total, total, total};
+  FM_TRY(exec(kf, false, e, kin, w1, w2, false, ws, s));
+  LAUNCH(launch_block_mix(e, nout, nin, op->nbc, total, nc, param(op, e), adj, w2, w1, s));
+  Batch kout{nout * nc, 1, 1, total, total, total, total};
+  FM_TRY(exec(kf, true, e, kout, w1, w2, false, ws, s));
+  for (int o = 0; o < nout; ++o)
+    LAUNCH(launch_box_copy(e, d, op->lv.data(), op->lL.data(), op->lv.data(), nc,
+                           w2 + size_t(o) * size_t(nc * total) * es, total,
+                           static_cast<char*>(y) + size_t(ooff[o]) * es, fb.ldy, acc, s));
+  ws.release(mk);
+  return FM_OK;
+}
+
+// Block diagonal: each block on its slice of rows; a run of consecutive
+// identical blocks is one call batched over the run.
+fm_status exec_blkdiag(const fm_op_s* op, bool adj, Elem e, const Batch& b, const void* x, void* y,
+                       bool acc, Workspace& ws, hipStream_t s) {
+  const size_t es = elem_bytes(e);
+  int64_t oi = 0, oo = 0;
+  const size_t nt = op->terms.size();
+  for (size_t k = 0; k < nt;) {
+    const fm_op_s* t = op->terms[k];
+    size_t run = 1;
+    while (k + run < nt && op->terms[k + run] == t) ++run;
+    const int64_t ri = in_rows(t, adj), ro = out_rows(t, adj);
+    const char* xs = static_cast<const char*>(x) + size_t(oi * b.inner) * es;
+    char* ys = static_cast<char*>(y) + size_t(oo * b.inner) * es;
+    // batched only where the run's vectors are evenly strided in x and y
+    const bool even = b.ncols == 1 || (b.ldx == int64_t(run) * ri * b.inner && b.ldy == int64_t(run) * ro * b.inner);
+    if (run > 1 && b.outer == 1 && even) {
+      Batch rb{b.ncols, int64_t(run), b.inner, b.ldx, ri * b.inner, b.ldy, ro * b.inner};
+      FM_TRY(exec(t, adj, e, rb, xs, ys, acc, ws, s));
+    } else {
+      run = 1;
+      FM_TRY(exec(t, adj, e, b, xs, ys, acc, ws, s));
+    }
+    oi += int64_t(run) * ri;
+    oo += int64_t(run) * ro;
+    k += run;
+  }
+  return FM_OK;
+}
+
 }  // namespace
 
 fm_status exec(const fm_op_s* op, bool adj, Elem e, const Batch& b, const void* x, void* y,
@@ -412,17 +503,11 @@ fm_status exec(const fm_op_s* op, bool adj, Elem e, const Batch& b, const void* 
     }
     case Kind::Kron:
       return exec_kron(op, adj, e, b, x, y, acc, ws, s);
-    case Kind::BlkDiag: {
-      int64_t oi = 0, oo = 0;
-      for (const fm_op_s* t : op->terms) {
-        const char* xs = static_cast<const char*>(x) + size_t(oi * b.inner) * elem_bytes(e);
-        char* ys = static_cast<char*>(y) + size_t(oo * b.inner) * elem_bytes(e);
-        FM_TRY(exec(t, adj, e, b, xs, ys, acc, ws, s));
-        oi += in_rows(t, adj);
-        oo += out_rows(t, adj);
-      }
-      return FM_OK;
-    }
+    case Kind::BlkDiag:
+      return exec_blkdiag(op, adj, e, b, x, y, acc, ws, s);
+    case Kind::Blocks:
+      return op->mix ? exec_blocks_mix(op, adj, e, b, x, y, acc, ws, s)
+                     : exec_blocks_general(op, adj, e, b, x, y, acc, ws, s);
   }
   set_error("exec: unknown operator kind");
   return FM_E_INVALID;

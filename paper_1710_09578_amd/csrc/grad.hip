@@ -255,6 +255,17 @@ fm_status norm_bound(const fm_op_s* op, hipStream_t s, double* out) {
       *out = m;
       return FM_OK;
     }
+    case Kind::Blocks: {  // Schur test on the block norms: ||H||^2 <= max row sum * max column sum
+      std::vector<double> rs(op->nbr, 0.0), cs(op->nbc, 0.0);
+      for (int i = 0; i < op->nbr; ++i)
+        for (int j = 0; j < op->nbc; ++j) {
+          FM_TRY(norm_bound(op->terms[size_t(i) * op->nbc + j], s, &v));
+          rs[i] += std::sqrt(v);
+          cs[j] += std::sqrt(v);
+        }
+      *out = *std::max_element(rs.begin(), rs.end()) * *std::max_element(cs.begin(), cs.end());
+      return FM_OK;
+    }
   }
   set_error("norm bound: unknown operator kind");
   return FM_E_INVALID;

@@ -90,6 +90,13 @@ fm_status launch_dense(Elem e, int64_t m, int64_t n, const void* a, int64_t lda,
 fm_status launch_box_copy(Elem e, int ndim, const int64_t* box, const int64_t* src_dims,
                           const int64_t* dst_dims, int64_t ncols, const void* x, int64_t ldx,
                           void* y, int64_t ldy, int accumulate, hipStream_t s);
+// Spectral mixing of a block matrix of convolutions: for o < nout, column
+// c < ncols, bin f < total:
+//   y[(o ncols + c) total + f] = sum_{p < nin} S(o, p)[f] x[(p ncols + c) total + f]
+// with S(o, p) = table[o * ld + p] (forward) or conj(table[p * ld + o])
+// (adjoint); table: DEVICE array of spectrum pointers (complex types).
+fm_status launch_block_mix(Elem e, int nout, int nin, int ld, int64_t total, int64_t ncols, const void* table,
+                           int adjoint, const void* x, void* y, hipStream_t s);
 // y = alpha * x (contiguous, count elements of type e); alpha real.
 fm_status launch_scale_copy(Elem e, int64_t count, double alpha, const void* x, void* y,
                             hipStream_t s);

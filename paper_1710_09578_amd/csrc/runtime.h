@@ -42,6 +42,7 @@ enum class Kind {
   Sum,
   Kron,
   BlkDiag,
+  Blocks,
   Adjoint
 };
 
@@ -73,6 +74,13 @@ struct fm_op_s {
   fm::Split s32, s64;      // splits of L for complex64 / complex128
   std::vector<int64_t> lv, lL;  // multilevel: entries per level, embedding per level
   std::vector<fm_op> terms;     // composites (retained) / adjoint child
+  // Blocks: grid shape, row / column offsets of the block rows / columns
+  // (nbr + 1 and nbc + 1 entries); mix: every block is a multilevel Toeplitz
+  // of one geometry (p32 / p64 then hold device tables of the blocks'
+  // spectrum pointers, row-major)
+  int32_t nbr = 0, nbc = 0;
+  std::vector<int64_t> roff, coff;
+  bool mix = false;
 };
 
 namespace fm {

@@ -190,6 +190,50 @@ def BlkDiag(*ops) -> Operator:
     return _compose(capi.FM_BLKDIAG, ops)
 
 
+def Blocks(grid) -> Operator:
+    """Block matrix [[A_00, A_01, ...], [A_10, ...], ...] (a list of block rows).
+    Blocks of one block row share their row count, blocks of one block column
+    their column count."""
+    rows = [list(r) for r in grid]
+    if not rows or not rows[0] or any(len(r) != len(rows[0]) for r in rows):
+        raise ValueError("Blocks needs a non-empty rectangular grid")
+    flat = [a for r in rows for a in r]
+    return Operator(capi.fm_op_create_blocks(len(rows), len(rows[0]), [a.handle for a in flat]), keep=tuple(flat))
+
+
+def Partial(A: Operator, rows=None, cols=None) -> Operator:
+    """A restricted to the selected rows and / or columns: S_rows A S_cols^H
+    (x of length len(cols) is placed at the selected columns, zeros
+    elsewhere)."""
+    terms = []
+    if rows is not None:
+        terms.append(SelectRows(A.shape[0], rows, A.dtype))
+    terms.append(A)
+    if cols is not None:
+        terms.append(SelectRows(A.shape[1], cols, A.dtype).H)
+    return terms[0] if len(terms) == 1 else Product(*terms)
+
+
+def compressed_ultrasound(t: torch.Tensor, psi_rows):
+    """The compressed ultrasound model b = Psi H x (eq. (9) with the block
+    structure of eq. (6)/(7)). t: (n1, n1, 2 n2 - 1, 2 n3 - 1) generators of
+    the 2-level Toeplitz blocks H_ij (levels n2, n3); psi_rows: (n1 n2, nf)
+    Fourier rows kept per A-scan of n3 samples. Psi = BlkDiag of the row
+    selections S_a F_n3, applied as one batched DFT of all A-scans followed by
+    one gather. Returns (H, Psi, Psi H)."""
+    t = _dev(t)
+    n1, n2, n3 = t.shape[0], (t.shape[2] + 1) // 2, (t.shape[3] + 1) // 2
+    if t.shape[1] != n1:
+        raise ValueError("t must hold an n1 x n1 grid of generators")
+    H = Blocks([[MLToeplitz([n2, n3], t[i, j].contiguous()) for j in range(n1)] for i in range(n1)])
+    rows = torch.as_tensor(psi_rows, dtype=torch.int64)
+    glob = (rows + n3 * torch.arange(rows.shape[0], dtype=torch.int64)[:, None]).reshape(-1)
+    F = Fourier(n3, t.dtype)
+    Psi = Product(SelectRows(n1 * n2 * n3, glob.to(device=t.device, dtype=torch.int32), t.dtype),
+                  BlkDiag(*([F] * (n1 * n2))))
+    return H, Psi, Product(Psi, H)
+
+
 # ---------------------------------------------------------------- solver
 def fista_options(iters=200, momentum=True, lam=None, lam_rel=None, L=None, stop_tol=0.0,
                   x0_given=False, power_iters=500, power_tol=1e-13, seed=0):

@@ -60,6 +60,9 @@ def test_invalid_arguments_return_status(lib):
     assert st(lib, "fm_op_create_select_rows", C.byref(h), 4, 5, C.c_void_p(16), 1, None) == 2  # m > n
     assert st(lib, "fm_op_create_mltoeplitz", C.byref(h), 4, None, None, 1, None) == 5
     assert st(lib, "fm_op_compose", C.byref(h), 0, 0, None) == 1
+    assert st(lib, "fm_op_create_blocks", C.byref(h), 0, 2, None) == 1    # empty grid
+    assert st(lib, "fm_op_create_blocks", None, 1, 1, None) == 1          # NULL out
+    assert st(lib, "fm_op_create_blocks", C.byref(h), 2, 2, (C.c_void_p * 4)(0x1000, 0x1000, 0x1000, 0x1000)) == 9
     assert st(lib, "fm_op_release", None) == 1
     # a pointer that was never a handle
     bogus = C.c_void_p(0x1000)

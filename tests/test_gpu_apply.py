@@ -325,6 +325,27 @@ def test_kron_hfg_full_size_sampled_columns(gpu):
     assert ey <= TOL["c64"] and ez <= TOL["c64"]
 
 
+def test_circulant_wide_block_sampled_columns(gpu):
+    """The 1024-point circulant on 65,536 CN(0,1) columns (512 MiB per block),
+    forward and adjoint, in the launch configuration the benchmark times.
+    Oracle: the dense complex128 circulant on 64 seeded columns."""
+    import torch
+
+    from workloads import many_columns
+
+    c, X = many_columns(device=torch.device("cuda:0"))
+    op = gpu.Circulant(to_dev(c))
+    Y = op @ X
+    Z = op.H @ Y
+    cols = np.sort(np.random.default_rng(7).choice(X.shape[0], 64, replace=False))
+    a = dense.circulant(c)
+    xs = to_host(X[cols])
+    ey = rel_err(to_host(Y[cols]), dense.apply(a, xs))
+    ez = rel_err(to_host(Z[cols]), dense.apply(a, to_host(Y[cols]), True))
+    print(f"circulant 1024 x 65536: fwd {ey:.2e} adj {ez:.2e}")
+    assert ey <= TOL["c64"] and ez <= TOL["c64"]
+
+
 @pytest.mark.parametrize("prec", ["c64", "c128"])
 @pytest.mark.parametrize("shape", [(32, 32), (20, 12), (5, 40), (64, 64)])
 @pytest.mark.parametrize("real", [True, False])

@@ -296,3 +296,53 @@ def test_ml_toeplitz_fft64_matches_dense():
     for adj in (False, True):
         x = crand(2, 12)
         assert np.allclose(structured.ml_toeplitz_apply_fft64(nl, t, x, adj), dense.apply(a, x, adj))
+
+
+# ---------------------------------------------------------------- block matrices
+def test_blocks_single_block_and_diagonal_grid():
+    a, b = crand(3, 4), crand(2, 5)
+    assert np.array_equal(dense.blocks([[a]]), a)
+    z1, z2 = np.zeros((3, 5)), np.zeros((2, 4))
+    assert np.array_equal(dense.blocks([[a, z1], [z2, b]]), scipy.linalg.block_diag(a, b))
+
+
+def test_blocks_brute_force_products():
+    """y_i = sum_j A_ij x_j and x_j = sum_i A_ij^H y_i with explicit loops over
+    uneven block sizes."""
+    ms, ns = [3, 1, 4], [2, 5]
+    grid = [[crand(m, n) for n in ns] for m in ms]
+    H = dense.blocks(grid)
+    x = crand(sum(ns))
+    y = crand(sum(ms))
+    yref = np.zeros(sum(ms), dtype=complex)
+    xref = np.zeros(sum(ns), dtype=complex)
+    r0 = 0
+    for i, m in enumerate(ms):
+        c0 = 0
+        for j, n in enumerate(ns):
+            for r in range(m):
+                for c in range(n):
+                    yref[r0 + r] += grid[i][j][r, c] * x[c0 + c]
+                    xref[c0 + c] += np.conj(grid[i][j][r, c]) * y[r0 + r]
+            c0 += n
+        r0 += m
+    assert np.allclose(H @ x, yref, atol=1e-12)
+    assert np.allclose(H.conj().T @ y, xref, atol=1e-12)
+
+
+def test_blocks_of_shifted_toeplitz_is_two_level_toeplitz():
+    """Blocks whose generator depends on i - j only form a block-Toeplitz matrix
+    with Toeplitz blocks, i.e. the 2-level Toeplitz of the combined generator."""
+    n1, n2 = 3, 4
+    t = crand(2 * n1 - 1, 2 * n2 - 1)
+    grid = [[dense.ml_toeplitz([n2], t[i - j + n1 - 1]) for j in range(n1)] for i in range(n1)]
+    assert np.array_equal(dense.blocks(grid), dense.ml_toeplitz([n1, n2], t))
+
+
+def test_ml_toeplitz_rows_and_fourier_rows():
+    t = crand(5, 7)
+    full = dense.ml_toeplitz([3, 4], t)
+    rows = [0, 5, 11, 7]
+    assert np.array_equal(dense.ml_toeplitz_rows([3, 4], t, rows), full[rows])
+    f = dense.fourier(12)
+    assert np.allclose(dense.fourier_rows(12, [0, 3, 11]), f[[0, 3, 11]], atol=1e-14)

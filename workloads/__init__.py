@@ -18,4 +18,5 @@ from .gen import (  # noqa: F401
     learn_circulant,
     many_columns,
     power_start,
+    ultrasound,
 )

@@ -162,6 +162,32 @@ def many_columns(ncols: int = 65536, n: int = 1024, seed: int = 5, device=None):
     return c, torch.randn((ncols, n), dtype=torch.complex64, device=device, generator=gen)
 
 
+def ultrasound(n1: int = 32, n2: int = 32, n3: int = 512, nf: int = 1, k: int = 32,
+               sigma: float = 1e-3, ncols: int = 1, seed: int = 7, blocks=None):
+    """Synthetic inputs shaped like the compressed ultrasound model
+    b = Psi H x + n: H is an n1 x n1 grid of 2-level Toeplitz blocks (levels
+    n2, n3), Psi keeps nf Fourier coefficients of each of the n1 n2 A-scans
+    of n3 samples.
+
+    Returns a dict with the block generators ``t`` (n1, n1, 2 n2 - 1, 2 n3 - 1),
+    CN(0,1) / sqrt(n1 n2 n3) each from its own stream [seed, 1, i, j] (only the
+    blocks in ``blocks``, a list of (i, j), when given; the others stay zero),
+    the kept Fourier rows ``psi_rows`` (n1 n2, nf) per A-scan, the sparse
+    ground truth ``x_true`` (ncols, n1 n2 n3) with k real N(0,1) amplitudes
+    and the noise ``noise`` (ncols, n1 n2 nf) already scaled by sigma.
+    """
+    rng = np.random.default_rng([seed, 0])
+    psi_rows = np.stack([_sorted_subset(rng, n3, nf) for _ in range(n1 * n2)])
+    x_true = _sparse_block(rng, n1 * n2 * n3, k, ncols)
+    noise = (sigma * cn(rng, (ncols, n1 * n2 * nf)).astype(np.complex128)).astype(C64)
+    t = np.zeros((n1, n1, 2 * n2 - 1, 2 * n3 - 1), dtype=C64)
+    scale = 1.0 / math.sqrt(n1 * n2 * n3)
+    for i, j in (blocks if blocks is not None else [(i, j) for i in range(n1) for j in range(n1)]):
+        t[i, j] = (cn(np.random.default_rng([seed, 1, i, j]), (2 * n2 - 1, 2 * n3 - 1)) * scale).astype(C64)
+    return {"t": t, "psi_rows": psi_rows, "x_true": x_true, "noise": noise, "sigma": sigma,
+            "shape": (n1, n2, n3, nf)}
+
+
 def power_start(n: int, seed: int = 0) -> np.ndarray:
     """CN(0,1) start vector of length n for a power iteration, rounded to
     complex64 so that it is exactly representable in both precisions."""
