@@ -512,17 +512,27 @@ fm_status fm_op_create_blocks(fm_op* out, int32_t nbr, int32_t nbc, const fm_op*
   for (int64_t k = 0; k < nb && mix; ++k)
     mix = terms[k]->kind == Kind::MLToeplitz && terms[k]->lv == terms[0]->lv && terms[k]->lL == terms[0]->lL;
   if (mix) {
+    // pack the block spectra bin-tiled (tiles of up to 64 bins) for the mixing kernel
+    int64_t total = 1;
+    for (int64_t l : terms[0]->lL) total *= l;
+    op->mix_logtw = ilog2(total < 64 ? total : 64);
     std::vector<const void*> t32(nb), t64(nb);
     for (int64_t k = 0; k < nb; ++k) {
       t32[k] = terms[k]->p32.p;
       t64[k] = terms[k]->p64.p;
     }
-    FM_TRY(op->p64.alloc(size_t(nb) * sizeof(void*)));
-    FM_HIP(hipMemcpy(op->p64.p, t64.data(), size_t(nb) * sizeof(void*), hipMemcpyHostToDevice));
+    DevBuf tab;
+    FM_TRY(tab.alloc(size_t(nb) * sizeof(void*)));
+    FM_HIP(hipMemcpy(tab.p, t64.data(), size_t(nb) * sizeof(void*), hipMemcpyHostToDevice));
+    FM_TRY(op->p64.alloc(size_t(nb * total) * 16));
+    FM_TRY(launch_block_pack(Elem::C128, nb, total, op->mix_logtw, tab.p, op->p64.p, nullptr));
     if (op->dt == FM_C64) {
-      FM_TRY(op->p32.alloc(size_t(nb) * sizeof(void*)));
-      FM_HIP(hipMemcpy(op->p32.p, t32.data(), size_t(nb) * sizeof(void*), hipMemcpyHostToDevice));
+      FM_HIP(hipDeviceSynchronize());
+      FM_HIP(hipMemcpy(tab.p, t32.data(), size_t(nb) * sizeof(void*), hipMemcpyHostToDevice));
+      FM_TRY(op->p32.alloc(size_t(nb * total) * 8));
+      FM_TRY(launch_block_pack(Elem::C64, nb, total, op->mix_logtw, tab.p, op->p32.p, nullptr));
     }
+    FM_HIP(hipDeviceSynchronize());
     op->lv = terms[0]->lv;
     op->lL = terms[0]->lL;
   }

@@ -68,14 +68,18 @@ __global__ __launch_bounds__(256) void diag_kernel(int64_t n, Batch b, const V* 
   }
 }
 
-// Spectral mixing of a block matrix (one thread per bin and column, OB
-// outputs per work-group row): the inputs of PC blocks are held in registers
-// while the OB x PC spectrum values of the chunk stream in, all loads of a
-// chunk in flight together; the OB sums stay in registers over the chunks.
+// Spectral mixing of a block matrix. The spectra are packed bin-tiled:
+// S[((f / TW) nb + o ld + p) TW + f % TW] for block (o, p) (nb blocks, TW
+// bins per tile), so the 64 lanes of a wave (64 consecutive bins, TW = 64)
+// read 512 contiguous bytes per block and a work-group's reads stay inside one
+// compact region. One thread per bin and column, OB outputs per work-group
+// row; the inputs of PC blocks are held in registers while the OB x PC
+// spectrum values of a chunk stream in, all loads of a chunk in flight
+// together; the OB sums stay in registers over the chunks.
 struct MixArgs {
-  int nout, nin, ld, adjoint;
-  int64_t total, ncols;
-  const void* const* table;
+  int nout, nin, ld, adjoint, logtw;
+  int64_t total, ncols, nb;
+  const void* spec;
   const void* x;
   void* y;
 };
@@ -86,8 +90,10 @@ __global__ __launch_bounds__(256) void block_mix_kernel(MixArgs a) {
   if (f >= a.total) return;
   const Cx<R>* X = static_cast<const Cx<R>*>(a.x);
   Cx<R>* Y = static_cast<Cx<R>*>(a.y);
-  const Cx<R>* const* tab = reinterpret_cast<const Cx<R>* const*>(a.table);
+  const int tw = 1 << a.logtw;
+  const Cx<R>* S = static_cast<const Cx<R>*>(a.spec) + (f >> a.logtw) * a.nb * tw + (f & (tw - 1));
   const int o0 = int(blockIdx.z) * OB;
+  const int no = a.nout - o0 < OB ? a.nout - o0 : OB;
   for (int64_t c = blockIdx.y; c < a.ncols; c += gridDim.y) {
     Cx<R> acc[OB];
 #pragma unroll
@@ -99,22 +105,38 @@ __global__ __launch_bounds__(256) void block_mix_kernel(MixArgs a) {
         xr[q] = p0 + q < a.nin ? X[(int64_t(p0 + q) * a.ncols + c) * a.total + f] : Cx<R>{R(0), R(0)};
 #pragma unroll
       for (int k = 0; k < OB; ++k) {
-        const int o = o0 + k;
-        if (o >= a.nout) break;
-        Cx<R> sv[PC];
+        if (k < no) {
+          const int o = o0 + k;
+          Cx<R> sv[PC];
 #pragma unroll
-        for (int q = 0; q < PC; ++q) {
-          const int p = p0 + q;
-          sv[q] = p < a.nin ? (a.adjoint ? tab[int64_t(p) * a.ld + o][f] : tab[int64_t(o) * a.ld + p][f])
-                            : Cx<R>{R(0), R(0)};
+          for (int q = 0; q < PC; ++q) {
+            const int p = p0 + q;
+            const int64_t blk = a.adjoint ? int64_t(p) * a.ld + o : int64_t(o) * a.ld + p;
+            sv[q] = p < a.nin ? S[blk * tw] : Cx<R>{R(0), R(0)};
+          }
+#pragma unroll
+          for (int q = 0; q < PC; ++q)
+            acc[k] = cadd(acc[k], a.adjoint ? cmulc(xr[q], sv[q]) : cmul(xr[q], sv[q]));
         }
-#pragma unroll
-        for (int q = 0; q < PC; ++q) acc[k] = cadd(acc[k], a.adjoint ? cmulc(xr[q], sv[q]) : cmul(xr[q], sv[q]));
       }
     }
 #pragma unroll
     for (int k = 0; k < OB; ++k)
-      if (o0 + k < a.nout) Y[(int64_t(o0 + k) * a.ncols + c) * a.total + f] = acc[k];
+      if (k < no) Y[(int64_t(o0 + k) * a.ncols + c) * a.total + f] = acc[k];
+  }
+}
+
+// Packs nb spectra (table of device pointers, total bins each) bin-tiled as
+// read by block_mix_kernel.
+template <typename R>
+__global__ __launch_bounds__(256) void block_pack_kernel(int64_t nb, int64_t total, int logtw,
+                                                         const void* const* table, Cx<R>* out) {
+  const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (f >= total) return;
+  const int tw = 1 << logtw;
+  for (int64_t k = blockIdx.y; k < nb; k += gridDim.y) {
+    const Cx<R>* src = static_cast<const Cx<R>*>(table[k]);
+    out[((f >> logtw) * nb + k) * tw + (f & (tw - 1))] = src[f];
   }
 }
 
@@ -312,6 +334,7 @@ __global__ __launch_bounds__(kDV) void dense_vec_kernel(int64_t m, int64_t n, co
 struct Box {
   int ndim;
   int64_t box[3], src[3], dst[3];
+  int64_t outer, xos, yos;  // vector q = (c, o): x + c ldx + o xos, y + c ldy + o yos
 };
 
 template <typename V>
@@ -333,12 +356,14 @@ __global__ __launch_bounds__(256) void box_kernel(Box bx, int64_t ncols, const V
     src += idx[d] * stride;
     stride *= bx.src[d];
   }
-  for (int64_t c = blockIdx.y; c < ncols; c += gridDim.y) {
-    const V v = inside ? x[c * ldx + src] : Ops<V>::zero();
+  for (int64_t q = blockIdx.y; q < ncols * bx.outer; q += gridDim.y) {
+    const int64_t c = q / bx.outer, o = q - c * bx.outer;
+    const V v = inside ? x[c * ldx + o * bx.xos + src] : Ops<V>::zero();
+    V* dst = y + c * ldy + o * bx.yos + f;
     if (acc) {
-      if (inside) store(y + c * ldy + f, v, 1);
+      if (inside) store(dst, v, 1);
     } else {
-      y[c * ldy + f] = v;
+      *dst = v;
     }
   }
 }
@@ -546,11 +571,14 @@ fm_status launch_dense(Elem e, int64_t m, int64_t n, const void* a, int64_t lda,
 
 fm_status launch_box_copy(Elem e, int ndim, const int64_t* box, const int64_t* src_dims,
                           const int64_t* dst_dims, int64_t ncols, const void* x, int64_t ldx,
-                          void* y, int64_t ldy, int acc, hipStream_t s) {
-  if (ncols == 0) return FM_OK;
+                          void* y, int64_t ldy, int acc, hipStream_t s, int64_t outer, int64_t xos, int64_t yos) {
+  if (ncols == 0 || outer == 0) return FM_OK;
   FM_CHECK_ARG(ndim >= 1 && ndim <= 3, FM_E_UNSUPPORTED, "box copy: 1..3 dimensions");
   Box bx{};
   bx.ndim = ndim;
+  bx.outer = outer;
+  bx.xos = xos;
+  bx.yos = yos;
   int64_t total = 1;
   for (int d = 0; d < ndim; ++d) {
     bx.box[d] = box[d];
@@ -558,17 +586,18 @@ fm_status launch_box_copy(Elem e, int ndim, const int64_t* box, const int64_t* s
     bx.dst[d] = dst_dims[d];
     total *= dst_dims[d];
   }
-  dim3 g(unsigned(cdiv(total, 256)), unsigned(ncols < 65535 ? ncols : 65535));
+  const int64_t nv = ncols * outer;
+  dim3 g(unsigned(cdiv(total, 256)), unsigned(nv < 65535 ? nv : 65535));
   FM_ELEM_SWITCH(e, V, hipLaunchKernelGGL(box_kernel<V>, g, dim3(256), 0, s, bx, ncols, (const V*)x,
                                           ldx, (V*)y, ldy, acc));
   FM_LAUNCHED();
   return FM_OK;
 }
 
-fm_status launch_block_mix(Elem e, int nout, int nin, int ld, int64_t total, int64_t ncols, const void* table,
-                           int adjoint, const void* x, void* y, hipStream_t s) {
+fm_status launch_block_mix(Elem e, int nout, int nin, int ld, int64_t nb, int64_t total, int logtw, int64_t ncols,
+                           const void* spec, int adjoint, const void* x, void* y, hipStream_t s) {
   if (ncols == 0 || total == 0 || nout == 0) return FM_OK;
-  MixArgs a{nout, nin, ld, adjoint, total, ncols, static_cast<const void* const*>(table), x, y};
+  MixArgs a{nout, nin, ld, adjoint, logtw, total, ncols, nb, spec, x, y};
   const unsigned gy = unsigned(ncols < 65535 ? ncols : 65535);
   if (e == Elem::C64) {
     constexpr int OB = 8;
@@ -580,6 +609,23 @@ fm_status launch_block_mix(Elem e, int nout, int nin, int ld, int64_t total, int
     hipLaunchKernelGGL((block_mix_kernel<double, OB, 16>), g, dim3(256), 0, s, a);
   } else {
     set_error("block mix: integer element type");
+    return FM_E_DTYPE;
+  }
+  FM_LAUNCHED();
+  return FM_OK;
+}
+
+fm_status launch_block_pack(Elem e, int64_t nb, int64_t total, int logtw, const void* table, void* out,
+                            hipStream_t s) {
+  if (nb == 0 || total == 0) return FM_OK;
+  const dim3 g(unsigned(cdiv(total, 256)), unsigned(nb < 65535 ? nb : 65535));
+  const auto* tab = static_cast<const void* const*>(table);
+  if (e == Elem::C64)
+    hipLaunchKernelGGL(block_pack_kernel<float>, g, dim3(256), 0, s, nb, total, logtw, tab, (c64*)out);
+  else if (e == Elem::C128)
+    hipLaunchKernelGGL(block_pack_kernel<double>, g, dim3(256), 0, s, nb, total, logtw, tab, (c128*)out);
+  else {
+    set_error("block pack: integer element type");
     return FM_E_DTYPE;
   }
   FM_LAUNCHED();

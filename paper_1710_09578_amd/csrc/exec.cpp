@@ -420,19 +420,20 @@ fm_status exec_blocks_mix(const fm_op_s* op, bool adj, Elem e, const Batch& b, c
   char* w1 = static_cast<char*>(ws.take(size_t(nmax) * size_t(nc * total) * es));
   char* w2 = static_cast<char*>(ws.take(size_t(nmax) * size_t(nc * total) * es));
   const fm_op_s* kf = op->terms[0]->terms[0];  // Kron of Fourier(L_l) of the first block
-  for (int p = 0; p < nin; ++p)
-    LAUNCH(launch_box_copy(e, d, op->lv.data(), op->lv.data(), op->lL.data(), nc,
-                           static_cast<const char*>(x) + size_t(ioff[p]) * es, fb.ldx,
-                           w1 + size_t(p) * size_t(nc * total) * es, total, 0, s));
+  // all blocks have the same size: slice p starts at row p * nblk; w holds
+  // vector (p, c) at (p nc + c) total
+  const int64_t nblk = ioff[1] - ioff[0];
+  (void)ooff;
+  LAUNCH(launch_box_copy(e, d, op->lv.data(), op->lv.data(), op->lL.data(), nc, x, fb.ldx, w1, total, 0, s,
+                         nin, nblk, nc * total));
   Batch kin{nin * nc, 1, 1, total, total, total, total};
   FM_TRY(exec(kf, false, e, kin, w1, w2, false, ws, s));
-  LAUNCH(launch_block_mix(e, nout, nin, op->nbc, total, nc, param(op, e), adj, w2, w1, s));
+  LAUNCH(launch_block_mix(e, nout, nin, op->nbc, int64_t(op->nbr) * op->nbc, total, op->mix_logtw, nc,
+                          param(op, e), adj, w2, w1, s));
   Batch kout{nout * nc, 1, 1, total, total, total, total};
   FM_TRY(exec(kf, true, e, kout, w1, w2, false, ws, s));
-  for (int o = 0; o < nout; ++o)
-    LAUNCH(launch_box_copy(e, d, op->lv.data(), op->lL.data(), op->lv.data(), nc,
-                           w2 + size_t(o) * size_t(nc * total) * es, total,
-                           static_cast<char*>(y) + size_t(ooff[o]) * es, fb.ldy, acc, s));
+  LAUNCH(launch_box_copy(e, d, op->lv.data(), op->lL.data(), op->lv.data(), nc, w2, total, y, fb.ldy, acc, s,
+                         nout, nc * total, nblk));
   ws.release(mk);
   return FM_OK;
 }

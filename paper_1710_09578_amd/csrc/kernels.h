@@ -87,16 +87,24 @@ fm_status launch_dense(Elem e, int64_t m, int64_t n, const void* a, int64_t lda,
 // Zero-pad / crop copy between multi-dimensional grids (multilevel Toeplitz):
 // copies the box [0, nbox) of the source grid (dims src_dims) into the
 // destination grid (dims dst_dims), zero-filling the rest of the destination.
+// Vectors: (c, o) for c < ncols, o < outer, at x + c ldx + o xos and
+// y + c ldy + o yos.
 fm_status launch_box_copy(Elem e, int ndim, const int64_t* box, const int64_t* src_dims,
                           const int64_t* dst_dims, int64_t ncols, const void* x, int64_t ldx,
-                          void* y, int64_t ldy, int accumulate, hipStream_t s);
+                          void* y, int64_t ldy, int accumulate, hipStream_t s, int64_t outer = 1,
+                          int64_t xos = 0, int64_t yos = 0);
 // Spectral mixing of a block matrix of convolutions: for o < nout, column
 // c < ncols, bin f < total:
 //   y[(o ncols + c) total + f] = sum_{p < nin} S(o, p)[f] x[(p ncols + c) total + f]
-// with S(o, p) = table[o * ld + p] (forward) or conj(table[p * ld + o])
-// (adjoint); table: DEVICE array of spectrum pointers (complex types).
-fm_status launch_block_mix(Elem e, int nout, int nin, int ld, int64_t total, int64_t ncols, const void* table,
-                           int adjoint, const void* x, void* y, hipStream_t s);
+// with S(o, p) the spectrum of block o * ld + p (forward) or the conjugate of
+// block p * ld + o (adjoint). spec: the nb spectra packed bin-tiled by
+// launch_block_pack (tiles of 2^logtw bins).
+fm_status launch_block_mix(Elem e, int nout, int nin, int ld, int64_t nb, int64_t total, int logtw, int64_t ncols,
+                           const void* spec, int adjoint, const void* x, void* y, hipStream_t s);
+// Packs nb spectra of total bins (table: DEVICE array of nb pointers) into
+// out[((f >> logtw) nb + k) 2^logtw + (f mod 2^logtw)].
+fm_status launch_block_pack(Elem e, int64_t nb, int64_t total, int logtw, const void* table, void* out,
+                            hipStream_t s);
 // y = alpha * x (contiguous, count elements of type e); alpha real.
 fm_status launch_scale_copy(Elem e, int64_t count, double alpha, const void* x, void* y,
                             hipStream_t s);

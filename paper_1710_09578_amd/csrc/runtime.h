@@ -76,11 +76,12 @@ struct fm_op_s {
   std::vector<fm_op> terms;     // composites (retained) / adjoint child
   // Blocks: grid shape, row / column offsets of the block rows / columns
   // (nbr + 1 and nbc + 1 entries); mix: every block is a multilevel Toeplitz
-  // of one geometry (p32 / p64 then hold device tables of the blocks'
-  // spectrum pointers, row-major)
+  // of one geometry (p32 / p64 then hold the blocks' spectra packed
+  // bin-tiled, tiles of 2^mix_logtw bins)
   int32_t nbr = 0, nbc = 0;
   std::vector<int64_t> roff, coff;
   bool mix = false;
+  int mix_logtw = 0;
 };
 
 namespace fm {
