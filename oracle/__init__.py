@@ -21,10 +21,11 @@ Tiers (all independent of the GPU path):
                     generated on the fly, Kronecker products by mode products
                     with dense factors, and an FFT64 cross-check;
 * ``grad``       -- gradients by CPU float64 autograd through dense unrolled
-                    FISTA.
+                    FISTA;
+* ``omp``        -- orthogonal matching pursuit with FP64 least squares.
 
 Parity status of every function is stated in its docstring; functions without
 an independent pin say "parity unpinned".
 """
 
-from . import dense, fista, grad, structured  # noqa: F401
+from . import dense, fista, grad, omp, structured  # noqa: F401
