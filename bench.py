@@ -443,6 +443,36 @@ def ultrasound_model(steps=5, warmup=2):
             "alg_bytes_per_direction": int(alg_dir)}
 
 
+def omp_solves(ncols=64, k=64, reps=3):
+    """OMP with 64 atoms on the row-selected Rademacher circulant (N = 65536,
+    M = 4096, 64-sparse truths, noise 1e-3): one problem per call, and 64
+    problems (columns) per call."""
+    import torch
+
+    import paper_1710_09578_amd as fm
+    from workloads import compressed_sensing_65536
+
+    dev = torch.device("cuda:0")
+    w = compressed_sensing_65536(ncols=ncols)
+    n = w["c"].size
+    A = fm.Product(fm.SelectRows(n, torch.from_numpy(w["rows"]).to(dev)), fm.Circulant(torch.from_numpy(w["c"]).to(dev)))
+    b = A.apply(torch.from_numpy(w["x_true"]).to(dev)) + torch.from_numpy(w["noise"]).to(dev)
+    out = {}
+    for cols in (1, ncols):
+        bb = b[:cols].contiguous()
+        fm.omp(A, bb, k)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            x, sup, st = fm.omp(A, bb, k)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        out[f"ncols_{cols}"] = {"ms_per_call": round(dt * 1e3, 3), "solves_per_s": round(cols / dt, 1)}
+        log(f"OMP k={k} on N=65536 M=4096, {cols} problem(s) per call: {dt * 1e3:.2f} ms, {cols / dt:.1f} solves/s")
+    out["workload"] = "OMP, 64 atoms, row-selected Rademacher circulant N=65536 M=4096, complex64"
+    return out
+
+
 def copy_bandwidth(nbytes=1 << 30, reps=10):
     """Device-to-device copy rate (read + write bytes per second): the
     practical ceiling of a streaming kernel on this device."""
@@ -504,6 +534,7 @@ def main():
     ap.add_argument("--no-kron", action="store_true")
     ap.add_argument("--no-wide", action="store_true", help="skip the 1024-point circulant on 65536 columns")
     ap.add_argument("--no-ultrasound", action="store_true", help="skip the compressed ultrasound model")
+    ap.add_argument("--no-omp", action="store_true", help="skip the OMP solves")
     ap.add_argument("--no-tune", action="store_true", help="keep the default batch schedule")
     ap.add_argument("--schedule", default="", help="MAX_FUSE,REGION_MIB: fixed batch schedule (no tuning)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -579,6 +610,7 @@ def main():
     kron = None if args.no_kron else kron_hfg_bandwidth()
     wide = None if args.no_wide else circulant_wide_bandwidth()
     us = None if args.no_ultrasound else ultrasound_model()
+    ompr = None if args.no_omp else omp_solves()
     copy_gbs = copy_bandwidth()
     log(f"device copy: {copy_gbs:.1f} GB/s")
     roof["copy_gbs"] = round(copy_gbs, 1)
@@ -614,6 +646,7 @@ def main():
         "kron": kron,
         "wide_circulant": wide,
         "ultrasound": us,
+        "omp": ompr,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

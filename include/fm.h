@@ -216,6 +216,31 @@ fm_status fm_fista_workspace_size(fm_op a, int64_t ncols, const fm_fista_opts* o
 fm_status fm_power_iteration(fm_op a, const void* v0, uint64_t seed, int32_t max_iters, double tol,
                              double* L_out, int32_t* iters_out, void* stream);
 
+/* Orthogonal matching pursuit, the greedy sparse recovery the paper runs
+ * beside FISTA on the ultrasound model (section "Application to Ultrasonic
+ * Nondestructive Testing"), per column b_j of b (each column one problem):
+ * k times (or until ||r|| <= tol ||b_j||): c = A^H r, pick the unchosen index
+ * of largest |c_i| (first on ties; correlations are not normalised by column
+ * norms), solve the least-squares problem on the chosen columns, r = b - A x.
+ * The least squares are kept as A_S = Q R (Gram-Schmidt applied twice against
+ * the chosen columns) and solved by back substitution at the end.
+ * x (n x ncols, ldx): the solution, zero outside the support. support: DEVICE
+ * int32 array of ncols * k entries (column j at support + j*k, atoms in
+ * selection order, -1 after the last) or NULL. stats: HOST array of ncols
+ * entries or NULL; status 0 ok, 1 non-finite value, 2 stopped early because
+ * the chosen column depends on the earlier ones (that atom is not kept).
+ * 1 <= k <= min(m, n, 1024). Workspace as for fm_fista (size from
+ * fm_omp_workspace_size; NULL and 0: allocated on the stream). Synchronises
+ * `stream` when stats is given. Complex dtypes. */
+typedef struct {
+  int32_t atoms;    /* chosen atoms kept */
+  int32_t status;
+  double res_norm;  /* ||b - A x||_2 at the end */
+} fm_omp_stat;
+fm_status fm_omp(fm_op a, int64_t ncols, const void* b, int64_t ldb, int32_t k, double tol, void* x, int64_t ldx,
+                 int32_t* support, fm_omp_stat* stats, void* ws, size_t ws_bytes, void* stream);
+fm_status fm_omp_workspace_size(fm_op a, int64_t ncols, int32_t k, size_t* bytes);
+
 /* ------------------------------------------------------------------ batching
  * Many independent Circulant / Toeplitz operators of uneven sizes applied
  * together (the batch-of-operators extension of the per-column evaluation of

@@ -28,6 +28,7 @@ from .operators import (  # noqa: F401
     compressed_ultrasound,
     fista,
     fista_options,
+    omp,
     power_iteration,
 )
 

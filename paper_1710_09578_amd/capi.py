@@ -67,6 +67,10 @@ class fm_fista_stat(C.Structure):
     ]
 
 
+class fm_omp_stat(C.Structure):
+    _fields_ = [("atoms", C.c_int32), ("status", C.c_int32), ("res_norm", C.c_double)]
+
+
 class fm_batch_schedule(C.Structure):
     _fields_ = [
         ("max_fuse", C.c_int32),
@@ -94,6 +98,8 @@ SIGNATURES = {
     "fm_op_create_select_rows": (ST, [C.POINTER(P), I64, I64, P, C.c_int, P]),
     "fm_op_compose": (ST, [C.POINTER(P), C.c_int, I32, C.POINTER(P)]),
     "fm_op_create_blocks": (ST, [C.POINTER(P), I32, I32, C.POINTER(P)]),
+    "fm_omp": (ST, [P, I64, P, I64, I32, C.c_double, P, I64, P, C.POINTER(fm_omp_stat), P, C.c_size_t, P]),
+    "fm_omp_workspace_size": (ST, [P, I64, I32, C.POINTER(C.c_size_t)]),
     "fm_op_adjoint": (ST, [C.POINTER(P), P]),
     "fm_op_shape": (ST, [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(C.c_int)]),
     "fm_op_release": (ST, [P]),
@@ -233,6 +239,17 @@ def fm_op_create_blocks(nbr, nbc, terms):
     arr = (P * len(terms))(*[t.value if isinstance(t, P) else t for t in terms])
     _call("fm_op_create_blocks", C.byref(h), nbr, nbc, arr)
     return h
+
+
+def fm_omp(a, ncols, b, ldb, k, tol, x, ldx, support, stats, ws, ws_bytes, stream):
+    _call("fm_omp", a, ncols, _ptr(b), ldb, k, tol, _ptr(x), ldx, _ptr(support),
+          C.cast(stats, C.POINTER(fm_omp_stat)) if stats is not None else None, _ptr(ws), ws_bytes, _ptr(stream))
+
+
+def fm_omp_workspace_size(a, ncols, k):
+    v = C.c_size_t()
+    _call("fm_omp_workspace_size", a, ncols, k, C.byref(v))
+    return v.value
 
 
 def fm_op_adjoint(a):

@@ -1,0 +1,452 @@
+// Orthogonal matching pursuit: the greedy sparse-recovery method the paper
+// runs beside FISTA on the ultrasound model (section "Application to
+// Ultrasonic Nondestructive Testing"; OMP after Tropp and Gilbert), built
+// only on the operator's forward and backward transforms.
+//
+// Per column b (each column is one problem), k steps of
+//   c = A^H r                        (one backward transform of the block)
+//   j = argmax over unchosen i of |c_i|, first index on ties
+//   a = A e_j                        (one forward transform of a one-hot block)
+//   orthogonalise a against the basis Q of the chosen columns (classical
+//   Gram-Schmidt, applied twice), append q = a'/||a'|| to Q and the
+//   coefficients to the triangular factor R (A_S = Q R)
+//   z_k = q^H r, r <- r - z_k q      (r = b - Q Q^H b stays orthogonal to Q)
+// then x_S = R^{-1} z by back substitution, scattered into x. A column stops
+// early when ||r|| <= tol ||b||, or when the chosen column depends on the
+// earlier ones (status 2), or on a non-finite value (status 1).
+//
+// All columns advance together: the transforms run on the whole block, the
+// selection, orthogonalisation and final solve take one work-group per column.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "runtime.h"
+#include "solve.h"
+
+namespace fm {
+namespace {
+
+size_t up(size_t v) { return (v + 255) & ~size_t(255); }
+
+template <typename R>
+__device__ __forceinline__ R wave_sum(R v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Sums G complex values over the work-group (NT threads); every thread gets
+// the totals. red: LDS of 2 * G * (NT / 64) reals.
+template <typename R, int G, int NT>
+__device__ __forceinline__ void block_sum(Cx<R>* v, R* red) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int NW = NT / 64;
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const R sx = wave_sum(v[g].x), sy = wave_sum(v[g].y);
+    if (lane == 0) {
+      red[(2 * g) * NW + wave] = sx;
+      red[(2 * g + 1) * NW + wave] = sy;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    R sx = R(0), sy = R(0);
+    for (int w = 0; w < NW; ++w) {
+      sx += red[(2 * g) * NW + w];
+      sy += red[(2 * g + 1) * NW + w];
+    }
+    v[g] = {sx, sy};
+  }
+  __syncthreads();
+}
+
+struct OmpState {
+  int64_t m, n, k;       // rows, columns, atom budget
+  const void* b;         // caller's right-hand sides (ldb)
+  int64_t ldb;
+  void* r;               // residuals, ncols x m
+  void* c;               // correlations, ncols x n
+  void* e;               // one-hot block, ncols x n
+  void* acol;            // chosen columns A e_j, ncols x m
+  void* q;               // orthonormal bases, ncols x k x m
+  void* rf;              // triangular factors, ncols x k x k (column-major per column)
+  void* z;               // Q^H b, ncols x k
+  int* idx;              // chosen atoms, ncols x k (-1: unused)
+  unsigned char* sel;    // chosen flags, ncols x n
+  double* bnorm2;        // ||b||^2 per column
+  double* rnorm2;        // ||r||^2 per column
+  int* active;
+  int* nsel;
+  int* status;
+  double tol2;
+};
+
+template <typename R>
+__global__ __launch_bounds__(256) void omp_init_kernel(OmpState s) {
+  __shared__ R red[2 * 4];
+  const int64_t col = blockIdx.x;
+  const Cx<R>* B = static_cast<const Cx<R>*>(s.b) + col * s.ldb;
+  Cx<R>* r = static_cast<Cx<R>*>(s.r) + col * s.m;
+  Cx<R>* e = static_cast<Cx<R>*>(s.e) + col * s.n;
+  Cx<R> acc[1] = {{R(0), R(0)}};
+  for (int64_t t = threadIdx.x; t < s.m; t += 256) {
+    const Cx<R> v = B[t];
+    r[t] = v;
+    acc[0].x += v.x * v.x + v.y * v.y;
+  }
+  for (int64_t t = threadIdx.x; t < s.n; t += 256) {
+    e[t] = {R(0), R(0)};
+    s.sel[col * s.n + t] = 0;
+  }
+  for (int64_t t = threadIdx.x; t < s.k; t += 256) s.idx[col * s.k + t] = -1;
+  block_sum<R, 1, 256>(acc, red);
+  if (threadIdx.x == 0) {
+    s.bnorm2[col] = double(acc[0].x);
+    s.rnorm2[col] = double(acc[0].x);
+    s.nsel[col] = 0;
+    s.status[col] = 0;
+    s.active[col] = acc[0].x > R(0) && s.tol2 < 1.0 ? 1 : 0;
+  }
+}
+
+// Argmax of |c_i|^2 over unchosen i (first index on ties); moves the one-hot
+// entry of the column to it.
+template <typename R>
+__global__ __launch_bounds__(256) void omp_select_kernel(OmpState s, int step) {
+  __shared__ R bv[256];
+  __shared__ int64_t bi[256];
+  const int64_t col = blockIdx.x;
+  if (!s.active[col]) return;
+  const Cx<R>* c = static_cast<const Cx<R>*>(s.c) + col * s.n;
+  const unsigned char* sel = s.sel + col * s.n;
+  R best = R(-1);
+  int64_t bj = -1;
+  for (int64_t j = threadIdx.x; j < s.n; j += 256) {
+    if (sel[j]) continue;
+    const Cx<R> v = c[j];
+    const R mag = v.x * v.x + v.y * v.y;
+    if (mag > best) {  // strided order: the first maximum of this thread wins
+      best = mag;
+      bj = j;
+    }
+  }
+  bv[threadIdx.x] = best;
+  bi[threadIdx.x] = bj;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      const R ov = bv[threadIdx.x + w];
+      const int64_t oi = bi[threadIdx.x + w];
+      const R mv = bv[threadIdx.x];
+      const int64_t mi = bi[threadIdx.x];
+      if (oi >= 0 && (mi < 0 || ov > mv || (ov == mv && oi < mi))) {
+        bv[threadIdx.x] = ov;
+        bi[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int64_t j = bi[0];
+    Cx<R>* e = static_cast<Cx<R>*>(s.e) + col * s.n;
+    if (step > 0) {
+      const int prev = s.idx[col * s.k + step - 1];
+      if (prev >= 0) e[prev] = {R(0), R(0)};
+    }
+    if (j < 0) {  // every unchosen correlation is NaN (k <= n leaves one unchosen)
+      s.active[col] = 0;
+      s.status[col] = 1;
+      return;
+    }
+    s.idx[col * s.k + step] = int(j);
+    s.sel[col * s.n + j] = 1;
+    e[j] = {R(1), R(0)};
+  }
+}
+
+// Gram-Schmidt step of one column (NT threads, G dot products per sweep).
+template <typename R, int NT>
+__global__ __launch_bounds__(NT) void omp_orth_kernel(OmpState s, int step, R dep2) {
+  constexpr int G = 8;
+  __shared__ R red[2 * G * (NT / 64)];
+  extern __shared__ unsigned char smem[];
+  Cx<R>* h = reinterpret_cast<Cx<R>*>(smem);            // step entries: projections of this pass
+  Cx<R>* rcol = h + s.k;                                 // accumulated column of R
+  const int64_t col = blockIdx.x;
+  if (!s.active[col]) return;
+  const int64_t m = s.m;
+  Cx<R>* a = static_cast<Cx<R>*>(s.acol) + col * m;
+  Cx<R>* Q = static_cast<Cx<R>*>(s.q) + col * s.k * m;
+  Cx<R>* r = static_cast<Cx<R>*>(s.r) + col * m;
+  for (int i = threadIdx.x; i < step; i += NT) rcol[i] = {R(0), R(0)};
+  Cx<R> nrm[1] = {{R(0), R(0)}};
+  for (int64_t t = threadIdx.x; t < m; t += NT) nrm[0].x += a[t].x * a[t].x + a[t].y * a[t].y;
+  block_sum<R, 1, NT>(nrm, red);
+  const R anorm2 = nrm[0].x;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int i0 = 0; i0 < step; i0 += G) {
+      Cx<R> d[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) d[g] = {R(0), R(0)};
+      for (int64_t t = threadIdx.x; t < m; t += NT) {
+        const Cx<R> av = a[t];
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+          if (i0 + g < step) d[g] = cadd(d[g], cmulc(av, Q[int64_t(i0 + g) * m + t]));  // conj(q) a
+      }
+      block_sum<R, G, NT>(d, red);
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+        if (int(threadIdx.x) == g && i0 + g < step) {
+          h[i0 + g] = d[g];
+          rcol[i0 + g] = cadd(rcol[i0 + g], d[g]);
+        }
+    }
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < m; t += NT) {
+      Cx<R> av = a[t];
+      for (int i = 0; i < step; ++i) av = csub(av, cmul(Q[int64_t(i) * m + t], h[i]));
+      a[t] = av;
+    }
+    __syncthreads();
+  }
+  nrm[0] = {R(0), R(0)};
+  for (int64_t t = threadIdx.x; t < m; t += NT) nrm[0].x += a[t].x * a[t].x + a[t].y * a[t].y;
+  block_sum<R, 1, NT>(nrm, red);
+  const R rho2 = nrm[0].x;
+  if (!(rho2 == rho2) || !(anorm2 == anorm2) || rho2 > R(3.0e38)) {
+    if (threadIdx.x == 0) {
+      s.active[col] = 0;
+      s.status[col] = 1;
+      s.idx[col * s.k + step] = -1;
+    }
+    return;
+  }
+  if (rho2 <= dep2 * anorm2 || rho2 <= R(0)) {  // depends on the chosen columns
+    if (threadIdx.x == 0) {
+      s.active[col] = 0;
+      s.status[col] = 2;
+      s.idx[col * s.k + step] = -1;
+    }
+    return;
+  }
+  const R inv = R(1) / sqrt(rho2);
+  Cx<R>* qk = Q + int64_t(step) * m;
+  Cx<R> zk[1] = {{R(0), R(0)}};
+  for (int64_t t = threadIdx.x; t < m; t += NT) {
+    const Cx<R> qv = cscale(a[t], inv);
+    qk[t] = qv;
+    zk[0] = cadd(zk[0], cmulc(r[t], qv));  // conj(q) r
+  }
+  block_sum<R, 1, NT>(zk, red);
+  Cx<R> rn[1] = {{R(0), R(0)}};
+  for (int64_t t = threadIdx.x; t < m; t += NT) {
+    const Cx<R> rv = csub(r[t], cmul(qk[t], zk[0]));
+    r[t] = rv;
+    rn[0].x += rv.x * rv.x + rv.y * rv.y;
+  }
+  block_sum<R, 1, NT>(rn, red);
+  Cx<R>* Rf = static_cast<Cx<R>*>(s.rf) + col * s.k * s.k + int64_t(step) * s.k;  // column `step`
+  for (int i = threadIdx.x; i < step; i += NT) Rf[i] = rcol[i];
+  if (threadIdx.x == 0) {
+    Rf[step] = {sqrt(rho2), R(0)};
+    static_cast<Cx<R>*>(s.z)[col * s.k + step] = zk[0];
+    s.rnorm2[col] = double(rn[0].x);
+    s.nsel[col] = step + 1;
+    if (double(rn[0].x) <= s.tol2 * s.bnorm2[col]) s.active[col] = 0;
+  }
+}
+
+// x_S = R^{-1} z by back substitution, x = 0 elsewhere.
+template <typename R>
+__global__ __launch_bounds__(256) void omp_finish_kernel(OmpState s, void* xout, int64_t ldx, int* support) {
+  __shared__ R red[2 * 4];
+  extern __shared__ unsigned char smem[];
+  Cx<R>* xs = reinterpret_cast<Cx<R>*>(smem);
+  const int64_t col = blockIdx.x;
+  const int ns = s.nsel[col];
+  const Cx<R>* Rf = static_cast<const Cx<R>*>(s.rf) + col * s.k * s.k;
+  const Cx<R>* z = static_cast<const Cx<R>*>(s.z) + col * s.k;
+  for (int i = ns - 1; i >= 0; --i) {
+    Cx<R> acc[1] = {{R(0), R(0)}};
+    for (int j = i + 1 + threadIdx.x; j < ns; j += 256) acc[0] = cadd(acc[0], cmul(Rf[int64_t(j) * s.k + i], xs[j]));
+    block_sum<R, 1, 256>(acc, red);
+    if (threadIdx.x == 0) {
+      const Cx<R> d = Rf[int64_t(i) * s.k + i];  // real, positive
+      xs[i] = cscale(csub(z[i], acc[0]), R(1) / d.x);
+    }
+    __syncthreads();
+  }
+  Cx<R>* x = static_cast<Cx<R>*>(xout) + col * ldx;
+  for (int64_t t = threadIdx.x; t < s.n; t += 256) x[t] = {R(0), R(0)};
+  __syncthreads();
+  for (int i = threadIdx.x; i < ns; i += 256) x[s.idx[col * s.k + i]] = xs[i];
+  if (support)
+    for (int64_t i = threadIdx.x; i < s.k; i += 256) support[col * s.k + i] = i < ns ? s.idx[col * s.k + i] : -1;
+}
+
+struct OmpPlan {
+  size_t r, c, e, acol, q, rf, z, idx, sel, bn, rn, act, nsel, status, exec, total;
+};
+
+fm_status plan_omp(const fm_op_s* a, int64_t ncols, int64_t k, OmpPlan* p) {
+  const Elem e = elem_of(a->dt);
+  const size_t es = elem_bytes(e);
+  const int64_t m = a->m, n = a->n;
+  size_t off = 0;
+  auto take = [&](size_t* slot, size_t bytes) {
+    *slot = off;
+    off += up(bytes);
+  };
+  take(&p->r, size_t(ncols * m) * es);
+  take(&p->c, size_t(ncols * n) * es);
+  take(&p->e, size_t(ncols * n) * es);
+  take(&p->acol, size_t(ncols * m) * es);
+  take(&p->q, size_t(ncols) * size_t(k) * size_t(m) * es);
+  take(&p->rf, size_t(ncols) * size_t(k * k) * es);
+  take(&p->z, size_t(ncols * k) * es);
+  take(&p->idx, size_t(ncols * k) * 4);
+  take(&p->sel, size_t(ncols * n));
+  take(&p->bn, size_t(ncols) * 8);
+  take(&p->rn, size_t(ncols) * 8);
+  take(&p->act, size_t(ncols) * 4);
+  take(&p->nsel, size_t(ncols) * 4);
+  take(&p->status, size_t(ncols) * 4);
+  p->exec = off;
+  size_t ex = 0;
+  for (int adj = 0; adj < 2; ++adj) {
+    Batch b{ncols, 1, 1, in_rows(a, adj), in_rows(a, adj), out_rows(a, adj), out_rows(a, adj)};
+    Workspace ws;
+    ws.sizing = true;
+    FM_TRY(exec(a, adj != 0, e, b, nullptr, nullptr, false, ws, nullptr));
+    ex = std::max(ex, ws.peak);
+  }
+  p->total = off + up(ex);
+  return FM_OK;
+}
+
+template <typename R>
+fm_status run_omp(const fm_op_s* a, int64_t ncols, OmpState st, void* x, int64_t ldx, int* support, Workspace& w,
+                  hipStream_t s) {
+  const Elem e = elem_of(a->dt);
+  const int64_t m = a->m, n = a->n;
+  constexpr int NT = 256;
+  const R dep2 = sizeof(R) == 4 ? R(1e-10) : R(1e-24);  // (relative norm left after orthogonalisation)^2
+  const size_t orth_lds = size_t(2 * st.k) * sizeof(Cx<R>);
+  const size_t fin_lds = size_t(st.k) * sizeof(Cx<R>);
+  const dim3 grid{unsigned(ncols)};
+  hipLaunchKernelGGL(omp_init_kernel<R>, grid, dim3(256), 0, s, st);
+  FM_LAUNCHED();
+  const Batch bf{ncols, 1, 1, n, n, m, m}, ba{ncols, 1, 1, m, m, n, n};
+  for (int step = 0; step < int(st.k); ++step) {
+    FM_TRY(exec(a, true, e, ba, st.r, st.c, false, w, s));      // c = A^H r
+    hipLaunchKernelGGL(omp_select_kernel<R>, grid, dim3(256), 0, s, st, step);
+    FM_LAUNCHED();
+    FM_TRY(exec(a, false, e, bf, st.e, st.acol, false, w, s));  // a = A e_j
+    hipLaunchKernelGGL((omp_orth_kernel<R, NT>), grid, dim3(NT), orth_lds, s, st, step, dep2);
+    FM_LAUNCHED();
+  }
+  hipLaunchKernelGGL(omp_finish_kernel<R>, grid, dim3(256), fin_lds, s, st, x, ldx, support);
+  FM_LAUNCHED();
+  return FM_OK;
+}
+
+}  // namespace
+}  // namespace fm
+
+using namespace fm;
+
+extern "C" {
+
+fm_status fm_omp_workspace_size(fm_op a, int64_t ncols, int32_t k, size_t* bytes) {
+  set_error("");
+  FM_CHECK_ARG(a != nullptr, FM_E_INVALID, "operator handle is NULL");
+  FM_CHECK_ARG(op_alive(a), FM_E_RELEASED, "operator handle was released");
+  FM_CHECK_ARG(bytes != nullptr, FM_E_INVALID, "NULL argument");
+  FM_CHECK_ARG(ncols >= 0 && k >= 1, FM_E_INVALID, "need ncols >= 0 and k >= 1");
+  OmpPlan p;
+  FM_TRY(plan_omp(a, ncols, k, &p));
+  *bytes = p.total;
+  return FM_OK;
+}
+
+fm_status fm_omp(fm_op a, int64_t ncols, const void* b, int64_t ldb, int32_t k, double tol, void* x, int64_t ldx,
+                 int32_t* support, fm_omp_stat* stats, void* ws, size_t ws_bytes, void* stream) {
+  set_error("");
+  FM_CHECK_ARG(a != nullptr, FM_E_INVALID, "operator handle is NULL");
+  FM_CHECK_ARG(op_alive(a), FM_E_RELEASED, "operator handle was released");
+  FM_CHECK_ARG(is_complex(a->dt), FM_E_DTYPE, "OMP needs a complex operator");
+  FM_CHECK_ARG(ncols >= 0, FM_E_INVALID, "negative column count");
+  FM_CHECK_ARG(ncols < 65536, FM_E_UNSUPPORTED, "at most 65535 columns per call");
+  FM_CHECK_ARG(tol >= 0.0, FM_E_INVALID, "tol must be non-negative");
+  const int64_t m = a->m, n = a->n;
+  FM_CHECK_ARG(k >= 1 && k <= m && k <= n, FM_E_INVALID, "need 1 <= k <= min(m, n)");
+  FM_CHECK_ARG(k <= 1024, FM_E_UNSUPPORTED, "at most 1024 atoms");
+  if (ncols == 0) return FM_OK;
+  FM_CHECK_ARG(b != nullptr && x != nullptr, FM_E_INVALID, "NULL data pointer");
+  FM_CHECK_ARG(ldb >= m && ldx >= n, FM_E_SHAPE, "leading dimensions too small");
+  int dev = 0;
+  FM_HIP(hipGetDevice(&dev));
+  FM_CHECK_ARG(dev == a->device, FM_E_DEVICE, "operator lives on device %d, current is %d", a->device, dev);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  OmpPlan p;
+  FM_TRY(plan_omp(a, ncols, k, &p));
+  void* base = ws;
+  bool own = false;
+  if (ws == nullptr && ws_bytes == 0) {
+    FM_HIP(hipMallocAsync(&base, p.total, s));
+    own = true;
+  } else {
+    FM_CHECK_ARG(ws != nullptr && ws_bytes >= p.total, FM_E_WORKSPACE, "workspace of %zu bytes given, %zu needed",
+                 ws_bytes, p.total);
+  }
+  char* B = static_cast<char*>(base);
+  OmpState st{};
+  st.m = m;
+  st.n = n;
+  st.k = k;
+  st.b = b;
+  st.ldb = ldb;
+  st.r = B + p.r;
+  st.c = B + p.c;
+  st.e = B + p.e;
+  st.acol = B + p.acol;
+  st.q = B + p.q;
+  st.rf = B + p.rf;
+  st.z = B + p.z;
+  st.idx = reinterpret_cast<int*>(B + p.idx);
+  st.sel = reinterpret_cast<unsigned char*>(B + p.sel);
+  st.bnorm2 = reinterpret_cast<double*>(B + p.bn);
+  st.rnorm2 = reinterpret_cast<double*>(B + p.rn);
+  st.active = reinterpret_cast<int*>(B + p.act);
+  st.nsel = reinterpret_cast<int*>(B + p.nsel);
+  st.status = reinterpret_cast<int*>(B + p.status);
+  st.tol2 = tol * tol;
+  Workspace w;
+  w.base = B + p.exec;
+  w.cap = p.total - p.exec;
+  auto body = [&]() -> fm_status {
+    if (a->dt == FM_C64)
+      FM_TRY(run_omp<float>(a, ncols, st, x, ldx, support, w, s));
+    else
+      FM_TRY(run_omp<double>(a, ncols, st, x, ldx, support, w, s));
+    if (stats) {
+      std::vector<int> hn(ncols), hs(ncols);
+      std::vector<double> hr(ncols);
+      FM_HIP(hipMemcpyAsync(hn.data(), st.nsel, size_t(ncols) * 4, hipMemcpyDeviceToHost, s));
+      FM_HIP(hipMemcpyAsync(hs.data(), st.status, size_t(ncols) * 4, hipMemcpyDeviceToHost, s));
+      FM_HIP(hipMemcpyAsync(hr.data(), st.rnorm2, size_t(ncols) * 8, hipMemcpyDeviceToHost, s));
+      FM_HIP(hipStreamSynchronize(s));
+      for (int64_t j = 0; j < ncols; ++j) stats[j] = fm_omp_stat{hn[j], hs[j], std::sqrt(hr[j])};
+    }
+    return FM_OK;
+  };
+  fm_status res = body();
+  if (own) (void)hipFreeAsync(base, s);
+  return res;
+}
+
+}  // extern "C"

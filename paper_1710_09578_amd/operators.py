@@ -277,6 +277,29 @@ def fista(A: Operator, b: torch.Tensor, iters=200, momentum=True, lam=None, lam_
     return (x.squeeze(0) if b.dim() == 1 else x), st
 
 
+def omp(A: Operator, b: torch.Tensor, k: int, tol: float = 0.0):
+    """Orthogonal matching pursuit with at most k atoms per column of b (shape
+    (ncols, m)), stopping a column once ||b - A x|| <= tol ||b||. Returns
+    (x, support, stats): support (ncols, k) int32 on the device in selection
+    order (-1 after the last atom), stats a list of dicts per column."""
+    m, n = A.shape
+    bb = b.unsqueeze(0) if b.dim() == 1 else b
+    if bb.stride(1) != 1:
+        bb = bb.contiguous()
+    ncols = bb.shape[0]
+    x = torch.empty((ncols, n), dtype=A.dtype, device=bb.device)
+    sup = torch.empty((ncols, k), dtype=torch.int32, device=bb.device)
+    need = capi.fm_omp_workspace_size(A.handle, ncols, k)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=bb.device)
+    stats = (capi.fm_omp_stat * max(ncols, 1))()
+    capi.fm_omp(A.handle, ncols, bb, max(bb.stride(0), m), int(k), float(tol), x, n, sup, stats, ws, ws.numel(),
+                _stream())
+    st = [{"atoms": stats[j].atoms, "status": stats[j].status, "res_norm": stats[j].res_norm} for j in range(ncols)]
+    if b.dim() == 1:
+        return x.squeeze(0), sup.squeeze(0), st
+    return x, sup, st
+
+
 def power_iteration(A: Operator, v0: torch.Tensor | None = None, seed=0, max_iters=500, tol=1e-13):
     """L = ||A||_2^2 in FP64; v0: complex128 GPU start vector (default:
     SplitMix64 vector of ``seed``). Returns (L, iterations)."""

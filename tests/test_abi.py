@@ -85,6 +85,9 @@ def test_invalid_arguments_return_status(lib):
               C.c_double(1.0), C.c_double(0.0), 4, None) == 3  # integer dtype
     assert st(lib, "fm_axpby", 8, 1, C.c_double(1.0), None, 4, C.c_double(1.0), None, 8, None, 8, 1, None) == 2
     assert st(lib, "fm_op_norm_bound", None, None, None) == 1
+    assert st(lib, "fm_omp", None, 1, None, 8, 4, C.c_double(0.0), None, 8, None, None, None, 0, None) == 1
+    assert st(lib, "fm_omp", bogus, 1, None, 8, 4, C.c_double(0.0), None, 8, None, None, None, 0, None) == 9
+    assert st(lib, "fm_omp_workspace_size", None, 1, 4, C.byref(size)) == 1
     assert st(lib, "fm_op_norm_bound", bogus, None, None) == 9
     # batch schedule / tuner
     from paper_1710_09578_amd import capi

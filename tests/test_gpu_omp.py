@@ -1,0 +1,132 @@
+"""GPU parity of orthogonal matching pursuit (fm_omp) against the FP64 oracle.
+
+The greedy choice is an argmax taken in the kernel's precision, so the
+supports are compared exactly on problems whose correlations are well
+separated, and x is compared with the oracle's least-squares solution on the
+support the GPU chose (unique for a full-rank A_S), column by column
+(relative L2 <= 2e-5 complex64, <= 1e-12 complex128).
+"""
+
+import numpy as np
+import pytest
+
+from oracle import dense, omp
+from tests.gpu_util import TOL, crandn, rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+NP = {"c64": np.complex64, "c128": np.complex128}
+
+
+def tdt(prec):
+    import torch
+
+    return {"c64": torch.complex64, "c128": torch.complex128}[prec]
+
+
+def cs_problem(gpu, prec, n=1024, m=256, k=12, ncols=3, seed=0, sigma=1e-3):
+    rng = np.random.default_rng(seed)
+    c = crandn(rng, n, NP[prec])
+    rows = np.sort(rng.choice(n, m, replace=False)).astype(np.int32)
+    a = dense.product(dense.select_rows(n, rows), dense.circulant(c))
+    xt = np.zeros((ncols, n), np.complex128)
+    for j in range(ncols):
+        xt[j, rng.choice(n, k, replace=False)] = np.sign(rng.standard_normal(k)) * (1 + rng.random(k))
+    b = (dense.apply(a, xt) + sigma * crandn(rng, (ncols, m), np.complex128)).astype(NP[prec])
+    A = gpu.Product(gpu.SelectRows(n, to_dev(rows), tdt(prec)), gpu.Circulant(to_dev(c)))
+    return A, a, b, xt
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+@pytest.mark.parametrize("k", [1, 5, 12, 20])
+def test_omp_matches_oracle(gpu, prec, k):
+    A, a, b, _ = cs_problem(gpu, prec)
+    x_ref, sup_ref, atoms_ref = omp.omp(a, b, k)
+    x, sup, st = gpu.omp(A, to_dev(b), k)
+    sup = to_host(sup)
+    assert np.array_equal(sup, sup_ref), (sup, sup_ref)
+    assert [s["atoms"] for s in st] == list(atoms_ref) and all(s["status"] == 0 for s in st)
+    xh = to_host(x)
+    assert rel_err(xh, x_ref) <= TOL[prec]
+    for j in range(b.shape[0]):
+        assert rel_err(xh[j], omp.least_squares_on(a, b[j], sup[j])) <= TOL[prec]
+        res = np.linalg.norm(dense.apply(a, xh[j:j + 1])[0] - b[j])
+        assert abs(st[j]["res_norm"] - res) <= 1e-3 * max(res, 1e-3 * np.linalg.norm(b[j]))
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_omp_recovers_support_and_stops_on_tolerance(gpu, prec):
+    """Noiseless sparse vectors: the tolerance ends each column after exactly
+    its own sparsity (uneven across columns)."""
+    rng = np.random.default_rng(3)
+    n, m = 512, 192
+    c = crandn(rng, n, NP[prec])
+    rows = np.sort(rng.choice(n, m, replace=False)).astype(np.int32)
+    a = dense.product(dense.select_rows(n, rows), dense.circulant(c))
+    ks = [2, 7, 4]
+    xt = np.zeros((3, n), np.complex128)
+    for j, kk in enumerate(ks):
+        xt[j, rng.choice(n, kk, replace=False)] = 1 + rng.random(kk)
+    b = dense.apply(a, xt).astype(NP[prec])
+    A = gpu.Product(gpu.SelectRows(n, to_dev(rows), tdt(prec)), gpu.Circulant(to_dev(c)))
+    tol = 1e-4 if prec == "c64" else 1e-10
+    x, sup, st = gpu.omp(A, to_dev(b), 16, tol=tol)
+    x_ref, sup_ref, atoms_ref = omp.omp(a, b, 16, tol=tol)
+    assert [s["atoms"] for s in st] == ks == list(atoms_ref)
+    assert np.array_equal(to_host(sup), sup_ref)
+    assert rel_err(to_host(x), xt) <= (1e-5 if prec == "c64" else 1e-11)
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_omp_dependent_atom_stops(gpu, prec):
+    """Columns 0 and 1 of A are equal: once the other columns are used up the
+    only candidate left depends on the chosen ones; the column stops with
+    status 2 and keeps its independent atoms."""
+    rng = np.random.default_rng(5)
+    d = crandn(rng, (8, 4), NP[prec])
+    d[:, 1] = d[:, 0]
+    b = crandn(rng, (1, 8), NP[prec])
+    x, sup, st = gpu.omp(gpu.Dense(to_dev(d)), to_dev(b), 4)
+    assert st[0]["status"] == 2 and st[0]["atoms"] == 3
+    s = to_host(sup)[0]
+    assert s[3] == -1 and len(set(s[:3].tolist()) & {0, 1}) == 1
+    assert rel_err(to_host(x), omp.least_squares_on(d, b[0], s)[None, :]) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_omp_zero_and_trivial_inputs(gpu, prec):
+    A, a, b, _ = cs_problem(gpu, prec, ncols=2)
+    b = b.copy()
+    b[1] = 0
+    x, sup, st = gpu.omp(A, to_dev(b), 6)
+    assert st[1]["atoms"] == 0 and np.all(to_host(x)[1] == 0) and np.all(to_host(sup)[1] == -1)
+    x, sup, st = gpu.omp(A, to_dev(b), 6, tol=1.0)  # tol >= 1: nothing to do
+    assert all(s["atoms"] == 0 for s in st) and np.all(to_host(x) == 0)
+
+
+def test_omp_compressed_sensing_full_size(gpu):
+    """N = 65536, M = 4096 rows of a Rademacher circulant, 64-sparse truth,
+    noise 1e-3, 64 atoms (complex64). The support is recovered exactly; x is
+    compared with the least-squares solution on it, whose 4096 x 64 columns
+    are built from the circulant's definition."""
+    from workloads import compressed_sensing_65536
+
+    w = compressed_sensing_65536()
+    c, rows, xt = w["c"], w["rows"], w["x_true"]
+    n = c.size
+    A = gpu.Product(gpu.SelectRows(n, to_dev(rows)), gpu.Circulant(to_dev(c)))
+
+    def columns(js):  # (S C(c))[:, j] = c[(rows - j) mod n], from the definition
+        return np.stack([c.astype(np.complex128)[(rows - j) % n] for j in js], axis=1)
+
+    truth = np.nonzero(xt[0])[0]
+    bh = (columns(truth) @ xt[0, truth] + w["noise"][0]).astype(np.complex64)
+    x, sup, st = gpu.omp(A, to_dev(bh[None, :]), 64)
+    s = to_host(sup)[0]
+    assert sorted(s.tolist()) == sorted(truth.tolist())
+    xs = np.linalg.lstsq(columns(s), bh.astype(np.complex128), rcond=None)[0]
+    ref = np.zeros(n, np.complex128)
+    ref[s] = xs
+    err = rel_err(to_host(x), ref[None, :])
+    print(f"omp N=65536 M=4096 K=64: support recovered, x rel err {err:.2e}, status {st[0]}")
+    assert err <= TOL["c64"]
