@@ -68,7 +68,11 @@ typedef enum {
  */
 
 /* Unnormalised DFT matrix F_n, F[i,k] = exp(-2 pi j i k / n), eq. (1) read with
- * 0-based indices. n must be a power of two, 1 <= n <= 2^20. Complex dtypes. */
+ * 0-based indices. 1 <= n <= 2^20 for powers of two (Stockham transforms);
+ * other n up to 2^19 through Bluestein's identity F = D T D, with
+ * D = diag(exp(-pi j i^2 / n)) and the Toeplitz T[i,k] = exp(pi j (i-k)^2 / n)
+ * (chirps from FP64 with exact angle reduction). Complex dtypes; the
+ * non-power-of-two form allocates device memory and synchronises. */
 fm_status fm_op_create_fourier(fm_op* out, int64_t n, fm_dtype dt);
 
 /* Walsh-Hadamard matrix H_n in natural (Sylvester) order, entries +-1,
@@ -89,8 +93,24 @@ fm_status fm_op_create_dense(fm_op* out, int64_t m, int64_t n, const void* a, in
 /* Circulant C(c): y = c cyclically convolved with x (eq. (5)), c = first column,
  * C[i,j] = c[(i-j) mod n]. The spectrum DFT(c) is computed once here in FP64
  * (section "General Matrix-free Representations": FFT(c) is precomputed at
- * initialisation). n a power of two, 1 <= n <= 2^20. Complex dtypes. */
+ * initialisation). 1 <= n <= 2^20 for powers of two; other n up to 2^19 are
+ * created as the n x n Toeplitz with first column c and first row
+ * (c_0, c_{n-1}, ..., c_1), applied through its power-of-two embedding (the
+ * handle then behaves as a Toeplitz: no fused Gramian or inverse).
+ * Complex dtypes. */
 fm_status fm_op_create_circulant(fm_op* out, int64_t n, const void* c, fm_dtype dt, void* stream);
+
+/* Circulant whose generator is the +-1 output of a linear feedback shift
+ * register (the LFSR circulant of the operator zoo): `order` bits, taps and a
+ * nonzero start state in the low `order` bits. Step k outputs s_k = +1 when
+ * bit 0 of the register is 0 and -1 when it is 1, then shifts the register
+ * right by one and sets bit order-1 to the parity of (register & taps) taken
+ * before the shift, i.e. bit i of the register holds s_{k+i} and
+ * s_{k+order} = XOR of s_{k+i} over the set bits i of taps. c = (s_0, ...,
+ * s_{n-1}), n = 2^order - 1 (the period when x^order + sum_{i in taps} x^i is
+ * primitive). 2 <= order <= 19. Complex dtypes. */
+fm_status fm_op_create_lfsr_circulant(fm_op* out, int32_t order, uint64_t taps, uint64_t state, fm_dtype dt,
+                                      void* stream);
 
 /* Toeplitz m x n (a non-circular convolution): T[i,j] = col[i-j] for i >= j,
  * row[j-i] for i < j. col has m entries and defines the diagonal; row has n
@@ -145,6 +165,30 @@ fm_status fm_op_create_blocks(fm_op* out, int32_t nbr, int32_t nbc, const fm_op*
 fm_status fm_op_adjoint(fm_op* out, fm_op a);
 
 /* Shape (m rows, n columns) and dtype of an operator. Any pointer may be NULL. */
+/* Views and derived operators of the base-class feature table (section
+ * "General Matrix-free Representations": transpose, Hermitian transpose,
+ * complex conjugate, Gramian, inverse). Each returns a new immutable handle
+ * that retains what it is built from.
+ *   fm_op_conj:    conj(A), applied as conj(A conj(x)); the transpose is
+ *                  fm_op_adjoint of it (A^T = conj(A)^H). Integer operators
+ *                  are their own conjugates.
+ *   fm_op_gram:    A^H A. Built from the structure where one exists: a
+ *                  circulant gives the circulant of spectrum |c_hat|^2 (one
+ *                  convolution), Fourier and Hadamard give n I, a diagonal
+ *                  diag(|d|^2), a row selection the diagonal of its indices,
+ *                  Kron and BlkDiag the Kron / BlkDiag of the terms' Gramians,
+ *                  conj(A) conj(A^H A); anything else the product A^H A.
+ *                  Complex dtypes.
+ *   fm_op_inverse: A^-1 for square operators with a structured inverse:
+ *                  Circulant (spectrum 1/c_hat), Diag (1/d), Fourier (F^H / n),
+ *                  Hadamard (H / n), square row selections (permutations:
+ *                  S^H), and Kron, BlkDiag, Product, adjoint and conj views of
+ *                  those. FM_E_INVALID for a singular circulant or diagonal,
+ *                  FM_E_SHAPE for non-square, FM_E_UNSUPPORTED for other kinds.
+ *                  Complex dtypes; synchronises the device. */
+fm_status fm_op_conj(fm_op* out, fm_op a);
+fm_status fm_op_gram(fm_op* out, fm_op a);
+fm_status fm_op_inverse(fm_op* out, fm_op a);
 fm_status fm_op_shape(fm_op a, int64_t* m, int64_t* n, fm_dtype* dt);
 
 /* Drops one reference; storage is freed when the last reference goes. */

@@ -186,6 +186,24 @@ def fourier_rows(n: int, rows) -> np.ndarray:
     return np.exp(-2j * np.pi * ((k * j) % n) / n)
 
 
+def lfsr_sequence(order: int, taps: int, state: int, n: int | None = None) -> np.ndarray:
+    """+-1 output of a linear feedback shift register (the generator of the
+    LFSR circulant): bit i of the register holds s_{k+i}; each step outputs
+    bit 0 (0 -> +1, 1 -> -1) and appends s_{k+order} = XOR of the register
+    bits selected by taps. n defaults to 2^order - 1 values."""
+    n = (1 << order) - 1 if n is None else n
+    reg = [(state >> i) & 1 for i in range(order)]
+    tap = [(taps >> i) & 1 for i in range(order)]
+    out = np.empty(n, dtype=C128)
+    for k in range(n):
+        out[k] = -1.0 if reg[0] else 1.0
+        new = 0
+        for i in range(order):
+            new ^= reg[i] & tap[i]
+        reg = reg[1:] + [new]
+    return out
+
+
 def adjoint(a) -> np.ndarray:
     """Hermitian transpose, the matrix of the backward transform (eq. 4)."""
     return np.asarray(a).conj().T

@@ -18,6 +18,7 @@ from .operators import (  # noqa: F401
     Fourier,
     Hadamard,
     Kron,
+    LFSRCirculant,
     MLToeplitz,
     Operator,
     Partial,

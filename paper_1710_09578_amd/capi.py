@@ -93,6 +93,7 @@ SIGNATURES = {
     "fm_op_create_diag": (ST, [C.POINTER(P), I64, P, C.c_int, P]),
     "fm_op_create_dense": (ST, [C.POINTER(P), I64, I64, P, I64, C.c_int, P]),
     "fm_op_create_circulant": (ST, [C.POINTER(P), I64, P, C.c_int, P]),
+    "fm_op_create_lfsr_circulant": (ST, [C.POINTER(P), I32, C.c_uint64, C.c_uint64, C.c_int, P]),
     "fm_op_create_toeplitz": (ST, [C.POINTER(P), I64, I64, P, P, C.c_int, P]),
     "fm_op_create_mltoeplitz": (ST, [C.POINTER(P), I32, C.POINTER(I64), P, C.c_int, P]),
     "fm_op_create_select_rows": (ST, [C.POINTER(P), I64, I64, P, C.c_int, P]),
@@ -101,6 +102,9 @@ SIGNATURES = {
     "fm_omp": (ST, [P, I64, P, I64, I32, C.c_double, P, I64, P, C.POINTER(fm_omp_stat), P, C.c_size_t, P]),
     "fm_omp_workspace_size": (ST, [P, I64, I32, C.POINTER(C.c_size_t)]),
     "fm_op_adjoint": (ST, [C.POINTER(P), P]),
+    "fm_op_conj": (ST, [C.POINTER(P), P]),
+    "fm_op_gram": (ST, [C.POINTER(P), P]),
+    "fm_op_inverse": (ST, [C.POINTER(P), P]),
     "fm_op_shape": (ST, [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(C.c_int)]),
     "fm_op_release": (ST, [P]),
     "fm_workspace_size": (ST, [P, C.c_int, I64, C.POINTER(C.c_size_t)]),
@@ -207,6 +211,12 @@ def fm_op_create_circulant(n, c, dt, stream):
     return h
 
 
+def fm_op_create_lfsr_circulant(order, taps, state, dt, stream):
+    h = P()
+    _call("fm_op_create_lfsr_circulant", C.byref(h), order, taps, state, dt, _ptr(stream))
+    return h
+
+
 def fm_op_create_toeplitz(m, n, col, row, dt, stream):
     h = P()
     _call("fm_op_create_toeplitz", C.byref(h), m, n, _ptr(col), _ptr(row), dt, _ptr(stream))
@@ -255,6 +265,24 @@ def fm_omp_workspace_size(a, ncols, k):
 def fm_op_adjoint(a):
     h = P()
     _call("fm_op_adjoint", C.byref(h), a)
+    return h
+
+
+def fm_op_conj(a):
+    h = P()
+    _call("fm_op_conj", C.byref(h), a)
+    return h
+
+
+def fm_op_gram(a):
+    h = P()
+    _call("fm_op_gram", C.byref(h), a)
+    return h
+
+
+def fm_op_inverse(a):
+    h = P()
+    _call("fm_op_inverse", C.byref(h), a)
     return h
 
 

@@ -169,14 +169,56 @@ fm_status fm_op_create_fourier(fm_op* out, int64_t n, fm_dtype dt) {
   CHECK_OUT(out);
   FM_CHECK_ARG(valid_dtype(dt), FM_E_INVALID, "unknown dtype %d", int(dt));
   FM_CHECK_ARG(is_complex(dt), FM_E_DTYPE, "Fourier needs a complex dtype");
-  FM_CHECK_ARG(n >= 1 && is_pow2(n) && ilog2(n) <= kMaxLog, FM_E_UNSUPPORTED,
-               "Fourier size %lld: powers of two up to 2^20 are supported", (long long)n);
+  FM_CHECK_ARG(n >= 1 && n <= (int64_t(1) << kMaxLog), FM_E_UNSUPPORTED,
+               "Fourier size %lld: 1 .. 2^20 are supported", (long long)n);
+  FM_CHECK_ARG(is_pow2(n) || n <= (int64_t(1) << (kMaxLog - 1)), FM_E_UNSUPPORTED,
+               "Fourier size %lld: sizes that are not powers of two go up to 2^19", (long long)n);
   fm_op_s* op;
   FM_TRY(new_op(Kind::Fourier, dt, n, n, &op));
+  Building g{op};
   op->L = n;
-  op->s32 = split_for(Elem::C64, ilog2(n));
-  op->s64 = split_for(Elem::C128, ilog2(n));
-  return publish(op, out);
+  if (is_pow2(n)) {
+    op->s32 = split_for(Elem::C64, ilog2(n));
+    op->s64 = split_for(Elem::C128, ilog2(n));
+    return publish(g.release(), out);
+  }
+  // Bluestein: W^(jk) = W^(j^2/2) W^(k^2/2) W^(-(k-j)^2/2) with W = exp(-2 pi i / n),
+  // so F = D T D with D = diag(exp(-pi i j^2 / n)) and the Toeplitz
+  // T[j, k] = exp(pi i (j - k)^2 / n). Angles reduced exactly (j^2 mod 2n).
+  const size_t es = elem_size(dt);
+  std::vector<unsigned char> dh(size_t(n) * es), th(size_t(n) * es);
+  const double pi = 3.14159265358979323846;
+  for (int64_t j = 0; j < n; ++j) {
+    const int64_t q = (j * j) % (2 * n);
+    const double ang = pi * double(q) / double(n);
+    const double c = std::cos(ang), sn = std::sin(ang);
+    if (dt == FM_C64) {
+      float* d = reinterpret_cast<float*>(dh.data()) + 2 * j;
+      float* t = reinterpret_cast<float*>(th.data()) + 2 * j;
+      d[0] = float(c), d[1] = float(-sn), t[0] = float(c), t[1] = float(sn);
+    } else {
+      double* d = reinterpret_cast<double*>(dh.data()) + 2 * j;
+      double* t = reinterpret_cast<double*>(th.data()) + 2 * j;
+      d[0] = c, d[1] = -sn, t[0] = c, t[1] = sn;
+    }
+  }
+  DevBuf dd, td;
+  FM_TRY(dd.alloc(dh.size()));
+  FM_TRY(td.alloc(th.size()));
+  FM_HIP(hipMemcpy(dd.p, dh.data(), dh.size(), hipMemcpyHostToDevice));
+  FM_HIP(hipMemcpy(td.p, th.data(), th.size(), hipMemcpyHostToDevice));
+  fm_op D = nullptr, T = nullptr, P = nullptr;
+  fm_status st = fm_op_create_diag(&D, n, dd.p, dt, nullptr);
+  if (st == FM_OK) st = fm_op_create_toeplitz(&T, n, n, td.p, td.p, dt, nullptr);
+  if (st == FM_OK) {
+    fm_op t3[3] = {D, T, D};
+    st = fm_op_compose(&P, FM_PRODUCT, 3, t3);
+  }
+  if (D) fm_op_release(D);
+  if (T) fm_op_release(T);
+  FM_TRY(st);
+  op->terms.push_back(P);
+  return publish(g.release(), out);
 }
 
 fm_status fm_op_create_hadamard(fm_op* out, int64_t n, fm_dtype dt) {
@@ -243,10 +285,26 @@ fm_status fm_op_create_circulant(fm_op* out, int64_t n, const void* c, fm_dtype 
   CHECK_OUT(out);
   FM_CHECK_ARG(valid_dtype(dt), FM_E_INVALID, "unknown dtype %d", int(dt));
   FM_CHECK_ARG(is_complex(dt), FM_E_DTYPE, "Circulant needs a complex dtype");
-  FM_CHECK_ARG(n >= 1 && is_pow2(n) && ilog2(n) <= kMaxLog, FM_E_UNSUPPORTED,
-               "Circulant size %lld: powers of two up to 2^20 are supported", (long long)n);
+  FM_CHECK_ARG(n >= 1 && n <= (int64_t(1) << kMaxLog), FM_E_UNSUPPORTED,
+               "Circulant size %lld: 1 .. 2^20 are supported", (long long)n);
+  FM_CHECK_ARG(is_pow2(n) || n <= (int64_t(1) << (kMaxLog - 1)), FM_E_UNSUPPORTED,
+               "Circulant size %lld: sizes that are not powers of two go up to 2^19", (long long)n);
   FM_CHECK_ARG(c != nullptr, FM_E_INVALID, "Circulant: NULL generator");
   hipStream_t s = as_stream(stream);
+  if (!is_pow2(n)) {
+    // C(c) is the n x n Toeplitz with first column c and first row
+    // (c_0, c_{n-1}, ..., c_1): applied through the power-of-two embedding
+    const size_t es = elem_size(dt);
+    std::vector<unsigned char> ch(size_t(n) * es), rh(size_t(n) * es);
+    FM_HIP(hipMemcpyAsync(ch.data(), c, ch.size(), hipMemcpyDeviceToHost, s));
+    FM_HIP(hipStreamSynchronize(s));
+    std::memcpy(rh.data(), ch.data(), es);
+    for (int64_t k = 1; k < n; ++k) std::memcpy(rh.data() + size_t(k) * es, ch.data() + size_t(n - k) * es, es);
+    DevBuf rd;
+    FM_TRY(rd.alloc(rh.size()));
+    FM_HIP(hipMemcpy(rd.p, rh.data(), rh.size(), hipMemcpyHostToDevice));
+    return fm_op_create_toeplitz(out, n, n, c, rd.p, dt, stream);
+  }
   fm_op_s* op;
   FM_TRY(new_op(Kind::Circulant, dt, n, n, &op));
   Building g{op};
@@ -265,6 +323,38 @@ fm_status fm_op_create_circulant(fm_op* out, int64_t n, const void* c, fm_dtype 
   FM_TRY(store_spectrum(op, ghat.p, s));
   FM_HIP(hipStreamSynchronize(s));
   return publish(g.release(), out);
+}
+
+fm_status fm_op_create_lfsr_circulant(fm_op* out, int32_t order, uint64_t taps, uint64_t state, fm_dtype dt,
+                                       void* stream) {
+  set_error("");
+  CHECK_OUT(out);
+  FM_CHECK_ARG(valid_dtype(dt), FM_E_INVALID, "unknown dtype %d", int(dt));
+  FM_CHECK_ARG(is_complex(dt), FM_E_DTYPE, "LFSR circulant needs a complex dtype");
+  FM_CHECK_ARG(order >= 2 && order <= kMaxLog - 1, FM_E_UNSUPPORTED, "LFSR order %d: 2 .. 19 are supported",
+               int(order));
+  const uint64_t mask = (uint64_t(1) << order) - 1;
+  FM_CHECK_ARG((taps & mask) != 0 && (taps & ~mask) == 0, FM_E_INVALID, "LFSR taps must lie in the low %d bits",
+               int(order));
+  FM_CHECK_ARG((state & mask) != 0 && (state & ~mask) == 0, FM_E_INVALID,
+               "LFSR state must be nonzero and lie in the low %d bits", int(order));
+  const int64_t n = int64_t(mask);
+  const size_t es = elem_size(dt);
+  std::vector<unsigned char> ch(size_t(n) * es, 0);
+  uint64_t r = state;
+  for (int64_t k = 0; k < n; ++k) {
+    const double v = (r & 1) ? -1.0 : 1.0;  // output bit 0 -> +1, 1 -> -1
+    if (dt == FM_C64)
+      reinterpret_cast<float*>(ch.data())[2 * k] = float(v);
+    else
+      reinterpret_cast<double*>(ch.data())[2 * k] = v;
+    const uint64_t fb = uint64_t(__builtin_popcountll(r & taps) & 1);
+    r = (r >> 1) | (fb << (order - 1));
+  }
+  DevBuf cd;
+  FM_TRY(cd.alloc(ch.size()));
+  FM_HIP(hipMemcpy(cd.p, ch.data(), ch.size(), hipMemcpyHostToDevice));
+  return fm_op_create_circulant(out, n, cd.p, dt, stream);
 }
 
 fm_status fm_op_create_toeplitz(fm_op* out, int64_t m, int64_t n, const void* col, const void* row,
@@ -549,6 +639,201 @@ fm_status fm_op_adjoint(fm_op* out, fm_op a) {
   a->refs.fetch_add(1);
   op->terms.push_back(a);
   return publish(op, out);
+}
+
+fm_status fm_op_conj(fm_op* out, fm_op a) {
+  set_error("");
+  CHECK_OUT(out);
+  CHECK_LIVE(a);
+  fm_op_s* op;
+  FM_TRY(new_op(Kind::Conj, a->dt, a->m, a->n, &op));
+  a->refs.fetch_add(1);
+  op->terms.push_back(a);
+  return publish(op, out);
+}
+
+}  // extern "C"
+
+namespace {
+
+// Owns a handle until it is released or handed out.
+struct Held {
+  fm_op h = nullptr;
+  ~Held() {
+    if (h) fm_op_release(h);
+  }
+  fm_op give() {
+    fm_op r = h;
+    h = nullptr;
+    return r;
+  }
+};
+
+// Diagonal operator with every entry equal to `value`.
+fm_status diag_const(int64_t n, double value, fm_dtype dt, fm_op* out) {
+  const size_t es = elem_size(dt);
+  std::vector<unsigned char> host(size_t(n) * es, 0);
+  for (int64_t i = 0; i < n; ++i) {
+    if (dt == FM_C64)
+      reinterpret_cast<float*>(host.data())[2 * i] = float(value);
+    else
+      reinterpret_cast<double*>(host.data())[2 * i] = value;
+  }
+  DevBuf d;
+  FM_TRY(d.alloc(host.size()));
+  FM_HIP(hipMemcpy(d.p, host.data(), host.size(), hipMemcpyHostToDevice));
+  return fm_op_create_diag(out, n, d.p, dt, nullptr);
+}
+
+// New operator of src's kind and geometry whose parameters are an
+// elementwise map of src's FP64 parameters (mode / scale as launch_param_map),
+// rounded once for complex64.
+fm_status derive_params(const fm_op_s* src, int64_t count, int mode, double scale, fm_op* out) {
+  FM_CHECK_ARG(src->s32.log1 == src->s64.log1 && src->s32.log2 == src->s64.log2, FM_E_UNSUPPORTED,
+               "parameter orders differ between precisions");
+  fm_op_s* op;
+  FM_TRY(new_op(src->kind, src->dt, src->m, src->n, &op));
+  Building g{op};
+  op->L = src->L;
+  op->s32 = src->s32;
+  op->s64 = src->s64;
+  op->lv = src->lv;
+  op->lL = src->lL;
+  DevBuf flag;
+  FM_TRY(flag.alloc(sizeof(int)));
+  FM_HIP(hipMemset(flag.p, 0, sizeof(int)));
+  FM_TRY(op->p64.alloc(size_t(count) * 16));
+  FM_TRY(launch_param_map(count, mode, scale, src->p64.p, op->p64.p, static_cast<int*>(flag.p), nullptr));
+  if (op->dt == FM_C64) {
+    FM_TRY(op->p32.alloc(size_t(count) * 8));
+    FM_TRY(launch_c128_to_c64(count, op->p64.p, op->p32.p, nullptr));
+  }
+  int bad = 0;
+  FM_HIP(hipMemcpy(&bad, flag.p, sizeof(int), hipMemcpyDeviceToHost));
+  FM_CHECK_ARG(bad == 0, FM_E_INVALID, "the operator is singular (a zero eigenvalue or diagonal entry)");
+  return publish(g.release(), out);
+}
+
+fm_status compose_of(fm_compose_kind k, std::vector<Held>& parts, fm_op* out) {
+  std::vector<fm_op> hs;
+  for (Held& p : parts) hs.push_back(p.h);
+  return fm_op_compose(out, k, int32_t(hs.size()), hs.data());
+}
+
+fm_status gram_of(const fm_op_s* a, fm_op* out);
+fm_status inverse_of(const fm_op_s* a, fm_op* out);
+
+fm_status gram_of(const fm_op_s* a, fm_op* out) {
+  switch (a->kind) {
+    case Kind::Circulant:  // C^H C = F^-1 diag(|c_hat|^2) F; the stored spectrum carries 1/L
+      return derive_params(a, a->L, 0, double(a->L), out);
+    case Kind::Diag:
+      return derive_params(a, a->n, 0, 1.0, out);
+    case Kind::Fourier:
+    case Kind::Hadamard:  // F^H F = H^T H = n I
+      return diag_const(a->n, double(a->n), a->dt, out);
+    case Kind::Select: {  // S^H S = diag(1 at the selected indices)
+      std::vector<int32_t> idx(size_t(a->m));
+      if (a->m > 0) FM_HIP(hipMemcpy(idx.data(), a->idx.p, size_t(a->m) * 4, hipMemcpyDeviceToHost));
+      const size_t es = elem_size(a->dt);
+      std::vector<unsigned char> host(size_t(a->n) * es, 0);
+      for (int32_t i : idx) {
+        if (a->dt == FM_C64)
+          reinterpret_cast<float*>(host.data())[2 * size_t(i)] = 1.0f;
+        else
+          reinterpret_cast<double*>(host.data())[2 * size_t(i)] = 1.0;
+      }
+      DevBuf d;
+      FM_TRY(d.alloc(host.size()));
+      FM_HIP(hipMemcpy(d.p, host.data(), host.size(), hipMemcpyHostToDevice));
+      return fm_op_create_diag(out, a->n, d.p, a->dt, nullptr);
+    }
+    case Kind::Kron:
+    case Kind::BlkDiag: {  // (A (x) B)^H (A (x) B) = A^H A (x) B^H B; block diagonal likewise
+      std::vector<Held> parts(a->terms.size());
+      for (size_t i = 0; i < a->terms.size(); ++i) FM_TRY(gram_of(a->terms[i], &parts[i].h));
+      return compose_of(a->kind == Kind::Kron ? FM_KRON : FM_BLKDIAG, parts, out);
+    }
+    case Kind::Conj: {  // conj(A)^H conj(A) = conj(A^H A)
+      Held g;
+      FM_TRY(gram_of(a->terms[0], &g.h));
+      return fm_op_conj(out, g.h);
+    }
+    default: {
+      Held ah;
+      FM_TRY(fm_op_adjoint(&ah.h, const_cast<fm_op_s*>(a)));
+      std::vector<fm_op> t{ah.h, const_cast<fm_op_s*>(a)};
+      return fm_op_compose(out, FM_PRODUCT, 2, t.data());
+    }
+  }
+}
+
+fm_status inverse_of(const fm_op_s* a, fm_op* out) {
+  FM_CHECK_ARG(a->m == a->n, FM_E_SHAPE, "inverse of a non-square operator (%lld x %lld)", (long long)a->m,
+               (long long)a->n);
+  switch (a->kind) {
+    case Kind::Circulant:  // spectrum 1/c_hat; stored with 1/L: 1/(s L^2)
+      return derive_params(a, a->L, 1, 1.0 / (double(a->L) * double(a->L)), out);
+    case Kind::Diag:
+      return derive_params(a, a->n, 1, 1.0, out);
+    case Kind::Fourier:
+    case Kind::Hadamard: {  // F^-1 = F^H / n, H^-1 = H / n
+      Held d, t;
+      FM_TRY(diag_const(a->n, 1.0 / double(a->n), a->dt, &d.h));
+      if (a->kind == Kind::Fourier)
+        FM_TRY(fm_op_adjoint(&t.h, const_cast<fm_op_s*>(a)));
+      else {
+        fm_op_s* self = const_cast<fm_op_s*>(a);
+        self->refs.fetch_add(1);
+        t.h = self;
+      }
+      std::vector<fm_op> hs{d.h, t.h};
+      return fm_op_compose(out, FM_PRODUCT, 2, hs.data());
+    }
+    case Kind::Select:  // a square selection is a permutation: S^-1 = S^H
+      return fm_op_adjoint(out, const_cast<fm_op_s*>(a));
+    case Kind::Adjoint:
+    case Kind::Conj: {
+      Held i;
+      FM_TRY(inverse_of(a->terms[0], &i.h));
+      return a->kind == Kind::Adjoint ? fm_op_adjoint(out, i.h) : fm_op_conj(out, i.h);
+    }
+    case Kind::Kron:
+    case Kind::BlkDiag:
+    case Kind::Product: {  // (A B)^-1 = B^-1 A^-1 (square factors)
+      const size_t k = a->terms.size();
+      std::vector<Held> parts(k);
+      for (size_t i = 0; i < k; ++i) {
+        const fm_op_s* t = a->kind == Kind::Product ? a->terms[k - 1 - i] : a->terms[i];
+        FM_TRY(inverse_of(t, &parts[i].h));
+      }
+      return compose_of(a->kind == Kind::Kron ? FM_KRON : a->kind == Kind::BlkDiag ? FM_BLKDIAG : FM_PRODUCT, parts,
+                        out);
+    }
+    default:
+      set_error("no structured inverse for this operator kind");
+      return FM_E_UNSUPPORTED;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+fm_status fm_op_gram(fm_op* out, fm_op a) {
+  set_error("");
+  CHECK_OUT(out);
+  CHECK_LIVE(a);
+  FM_CHECK_ARG(is_complex(a->dt), FM_E_DTYPE, "Gram operator of an integer operator");
+  return gram_of(a, out);
+}
+
+fm_status fm_op_inverse(fm_op* out, fm_op a) {
+  set_error("");
+  CHECK_OUT(out);
+  CHECK_LIVE(a);
+  FM_CHECK_ARG(is_complex(a->dt), FM_E_DTYPE, "inverse of an integer operator");
+  return inverse_of(a, out);
 }
 
 fm_status fm_op_shape(fm_op a, int64_t* m, int64_t* n, fm_dtype* dt) {

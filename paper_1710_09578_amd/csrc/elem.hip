@@ -181,6 +181,39 @@ __global__ __launch_bounds__(256) void copy_kernel(int64_t flat_n, Batch b, cons
   }
 }
 
+template <typename R>
+__global__ __launch_bounds__(256) void conj_kernel(int64_t flat_n, Batch b, const Cx<R>* x, Cx<R>* y,
+                                                   int acc) {
+  const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (f >= flat_n) return;
+  for (int64_t p = blockIdx.y; p < b.ncols * b.outer; p += gridDim.y) {
+    const int64_t c = p / b.outer, o = p - c * b.outer;
+    const Cx<R> v = cconj(x[c * b.ldx + o * b.xvs + f]);
+    Cx<R>* d = y + c * b.ldy + o * b.yvs + f;
+    *d = acc ? cadd(*d, v) : v;
+  }
+}
+
+// Elementwise map of complex128 parameters: mode 0 out = scale |in|^2,
+// mode 1 out = scale / in (flag[0] set when an entry is zero or not finite).
+__global__ __launch_bounds__(256) void param_map_kernel(int64_t count, int mode, double scale,
+                                                        const c128* __restrict__ in, c128* out, int* flag) {
+  const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (f >= count) return;
+  const c128 v = in[f];
+  const double m2 = v.x * v.x + v.y * v.y;
+  if (mode == 0) {
+    out[f] = {scale * m2, 0.0};
+  } else {
+    if (!(m2 > 0.0) || !(m2 < 1e300)) {
+      flag[0] = 1;
+      out[f] = {0.0, 0.0};
+    } else {
+      out[f] = {scale * v.x / m2, -scale * v.y / m2};
+    }
+  }
+}
+
 template <typename V>
 __global__ __launch_bounds__(256) void zero_kernel(int64_t flat_n, Batch b, V* y) {
   const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -492,6 +525,28 @@ fm_status launch_copy(Elem e, int64_t n, const Batch& b, const void* x, void* y,
   dim3 g = vec_grid(b.ncols * b.outer, n * b.inner, 256);
   FM_ELEM_SWITCH(e, V, hipLaunchKernelGGL(copy_kernel<V>, g, dim3(256), 0, s, n * b.inner, b,
                                           (const V*)x, (V*)y, acc));
+  FM_LAUNCHED();
+  return FM_OK;
+}
+
+fm_status launch_conj(Elem e, int64_t n, const Batch& b, const void* x, void* y, int acc, hipStream_t s) {
+  if (b.ncols == 0 || n == 0) return FM_OK;
+  dim3 g = vec_grid(b.ncols * b.outer, n * b.inner, 256);
+  if (e == Elem::C64)
+    hipLaunchKernelGGL(conj_kernel<float>, g, dim3(256), 0, s, n * b.inner, b, (const c64*)x, (c64*)y, acc);
+  else if (e == Elem::C128)
+    hipLaunchKernelGGL(conj_kernel<double>, g, dim3(256), 0, s, n * b.inner, b, (const c128*)x, (c128*)y, acc);
+  else
+    return launch_copy(e, n, b, x, y, acc, s);  // integers are their own conjugates
+  FM_LAUNCHED();
+  return FM_OK;
+}
+
+fm_status launch_param_map(int64_t count, int mode, double scale, const void* in, void* out, int* flag,
+                           hipStream_t s) {
+  if (count == 0) return FM_OK;
+  hipLaunchKernelGGL(param_map_kernel, dim3(unsigned(cdiv(count, 256))), dim3(256), 0, s, count, mode, scale,
+                     (const c128*)in, (c128*)out, flag);
   FM_LAUNCHED();
   return FM_OK;
 }

@@ -51,6 +51,7 @@ const Split& split(const fm_op_s* op, Elem e) { return e == Elem::C64 ? op->s32 
 // Plain DFT (or its unnormalised inverse) of length L along the vector axis.
 fm_status exec_fourier(const fm_op_s* op, bool adj, Elem e, const Batch& b, const void* x, void* y,
                        bool acc, Workspace& ws, hipStream_t s) {
+  if (!op->terms.empty()) return exec(op->terms[0], adj, e, b, x, y, acc, ws, s);  // Bluestein (any n)
   const Split& sp = split(op, e);
   const int64_t L = op->L;
   if (!sp.four_step()) {
@@ -324,7 +325,8 @@ fm_status exec_kron(const fm_op_s* op, bool adj, Elem e, const Batch& b, const v
   int64_t src_ld = b.ldx, src_vs = b.xvs;
   int stage = 0;
   int kstart = d - 1;
-  if (d >= 2 && b.inner == 1 && op->terms[d - 1]->kind == Kind::Dense && op->terms[d - 2]->kind == Kind::Fourier) {
+  if (d >= 2 && b.inner == 1 && op->terms[d - 1]->kind == Kind::Dense && op->terms[d - 2]->kind == Kind::Fourier &&
+      op->terms[d - 2]->terms.empty()) {
     // the last two factors (Fourier, small dense) in one slab pass
     const fm_op_s* F = op->terms[d - 2];
     const fm_op_s* G = op->terms[d - 1];
@@ -476,6 +478,27 @@ fm_status exec(const fm_op_s* op, bool adj, Elem e, const Batch& b, const void* 
   switch (op->kind) {
     case Kind::Adjoint:
       return exec(op->terms[0], !adj, e, b, x, y, acc, ws, s);
+    case Kind::Conj: {  // conj(A) x = conj(A conj(x)); the same for the adjoint direction
+      if (e == Elem::I32 || e == Elem::I64) return exec(op->terms[0], adj, e, b, x, y, acc, ws, s);
+      const int64_t rin = in_rows(op, adj), rout = out_rows(op, adj);
+      const size_t es = elem_bytes(e);
+      const size_t mk = ws.mark();
+      void* xc = ws.take(size_t(b.ncols * b.outer * rin * b.inner) * es);
+      const Batch cb{b.ncols, b.outer, b.inner, b.ldx, b.xvs, b.outer * rin * b.inner, rin * b.inner};
+      LAUNCH(launch_conj(e, rin, cb, x, xc, 0, s));
+      Batch ib{b.ncols, b.outer, b.inner, b.outer * rin * b.inner, rin * b.inner, b.ldy, b.yvs};
+      void* dst = y;
+      if (acc) {
+        dst = ws.take(size_t(b.ncols * b.outer * rout * b.inner) * es);
+        ib.ldy = b.outer * rout * b.inner;
+        ib.yvs = rout * b.inner;
+      }
+      FM_TRY(exec(op->terms[0], adj, e, ib, xc, dst, false, ws, s));
+      const Batch ob{b.ncols, b.outer, b.inner, ib.ldy, ib.yvs, b.ldy, b.yvs};
+      LAUNCH(launch_conj(e, rout, ob, dst, y, acc ? 1 : 0, s));
+      ws.release(mk);
+      return FM_OK;
+    }
     case Kind::Fourier:
       return exec_fourier(op, adj, e, b, x, y, acc, ws, s);
     case Kind::Circulant:

@@ -226,6 +226,7 @@ fm_status norm_bound(const fm_op_s* op, hipStream_t s, double* out) {
       return FM_OK;
     }
     case Kind::Adjoint:
+    case Kind::Conj:
       return norm_bound(op->terms[0], s, out);
     case Kind::Product:
     case Kind::Kron: {

@@ -122,6 +122,13 @@ fm_status launch_toeplitz_embed(int64_t m, int64_t n, int64_t L, const void* col
 // Check indices. flags: n + 1 zeroed ints; flags[n] becomes nonzero if any
 // idx is outside [0, n) or repeated.
 fm_status launch_check_indices(int64_t n, int64_t m, const int32_t* idx, int* flags, hipStream_t s);
+// y (+)= conj(x) over the vectors of a batch (n rows each); plain copy for integers.
+fm_status launch_conj(Elem e, int64_t n, const Batch& b, const void* x, void* y, int accumulate, hipStream_t s);
+// Elementwise map of count complex128 values: mode 0 out = scale |in|^2, mode 1
+// out = scale / in; flag[0] (an int, zeroed by the caller) is set to 1 when an
+// inverted entry is zero or not finite.
+fm_status launch_param_map(int64_t count, int mode, double scale, const void* in, void* out, int* flag,
+                           hipStream_t s);
 // y (+)= x over the vectors of a batch (n rows each).
 fm_status launch_copy(Elem e, int64_t n, const Batch& b, const void* x, void* y, int accumulate,
                       hipStream_t s);

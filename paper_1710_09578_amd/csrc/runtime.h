@@ -43,7 +43,8 @@ enum class Kind {
   Kron,
   BlkDiag,
   Blocks,
-  Adjoint
+  Adjoint,
+  Conj
 };
 
 // Split of a cyclic length L for one element type: L <= LDS limit runs in one

@@ -71,6 +71,28 @@ class Operator:
         """Hermitian transpose (shares storage)."""
         return Operator(capi.fm_op_adjoint(self._h), keep=(self,))
 
+    @property
+    def conj(self) -> "Operator":
+        """Complex conjugate conj(A) (shares storage)."""
+        return Operator(capi.fm_op_conj(self._h), keep=(self,))
+
+    @property
+    def T(self) -> "Operator":
+        """Transpose A^T = conj(A)^H (shares storage)."""
+        c = self.conj
+        return Operator(capi.fm_op_adjoint(c.handle), keep=(c,))
+
+    @property
+    def gram(self) -> "Operator":
+        """Gramian A^H A, fused from the structure where one exists."""
+        return Operator(capi.fm_op_gram(self._h), keep=(self,))
+
+    @property
+    def inverse(self) -> "Operator":
+        """Structured inverse A^-1 (Circulant, Diag, Fourier, Hadamard,
+        permutations and their Kron / BlkDiag / Product / views)."""
+        return Operator(capi.fm_op_inverse(self._h), keep=(self,))
+
     # ------------------------------------------------------------ application
     def _block(self, x: torch.Tensor, rows: int):
         if x.dtype != self.dtype:
@@ -149,6 +171,12 @@ def Dense(a: torch.Tensor) -> Operator:
 def Circulant(c: torch.Tensor) -> Operator:
     c = _dev(c)
     return Operator(capi.fm_op_create_circulant(c.numel(), c, _dt(c.dtype), _stream()))
+
+
+def LFSRCirculant(order: int, taps: int, state: int = 1, dtype=torch.complex64) -> Operator:
+    """Circulant of size 2^order - 1 whose first column is the +-1 output of a
+    linear feedback shift register (taps / state bit masks)."""
+    return Operator(capi.fm_op_create_lfsr_circulant(int(order), int(taps), int(state), _dt(dtype), _stream()))
 
 
 def Toeplitz(col: torch.Tensor, row: torch.Tensor) -> Operator:

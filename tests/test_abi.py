@@ -52,7 +52,13 @@ def test_invalid_arguments_return_status(lib):
     assert st(lib, "fm_op_create_fourier", None, 8, 1) == 1          # NULL out
     assert st(lib, "fm_op_create_fourier", C.byref(h), 8, 99) == 1   # bad dtype
     assert st(lib, "fm_op_create_fourier", C.byref(h), 8, 3) == 3    # integer Fourier
-    assert st(lib, "fm_op_create_fourier", C.byref(h), 12, 1) == 5   # not a power of two
+    assert st(lib, "fm_op_create_fourier", C.byref(h), (1 << 19) + 1, 1) == 5   # too long for Bluestein
+    assert st(lib, "fm_op_create_lfsr_circulant", C.byref(h), 4, 0, 1, 1, None) == 1  # no taps
+    assert st(lib, "fm_op_create_lfsr_circulant", C.byref(h), 4, 3, 0, 1, None) == 1  # zero state
+    assert st(lib, "fm_op_create_lfsr_circulant", C.byref(h), 30, 3, 1, 1, None) == 5  # order too large
+    assert st(lib, "fm_op_conj", None, None) == 1
+    assert st(lib, "fm_op_gram", C.byref(h), C.c_void_p(0x1000)) == 9
+    assert st(lib, "fm_op_inverse", C.byref(h), None) == 1
     assert st(lib, "fm_op_create_fourier", C.byref(h), 0, 1) == 5
     assert st(lib, "fm_op_create_circulant", C.byref(h), 8, None, 1, None) == 1
     assert st(lib, "fm_op_create_toeplitz", C.byref(h), 0, 4, None, None, 1, None) == 1
@@ -104,5 +110,5 @@ def test_binding_raises(lib):
     from paper_1710_09578_amd import capi
 
     with pytest.raises(capi.FmError) as e:
-        capi.fm_op_create_fourier(12, capi.FM_C64)
+        capi.fm_op_create_fourier(3 << 19, capi.FM_C64)
     assert e.value.code == "FM_E_UNSUPPORTED"

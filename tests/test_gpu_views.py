@@ -1,0 +1,129 @@
+"""GPU parity of the views and derived operators (conj, transpose, Gramian,
+structured inverse) and of the sizes served through an embedding: Fourier of
+any n (Bluestein), circulants of any n, the LFSR circulant. Oracle: the dense
+FP64 matrices of their definitions (conj / transpose / A^H A / numpy's
+inverse of the dense matrix)."""
+
+import numpy as np
+import pytest
+
+from oracle import dense
+from tests.gpu_util import TOL, crandn, rel_err, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+NP = {"c64": np.complex64, "c128": np.complex128}
+
+
+def tdt(prec):
+    import torch
+
+    return {"c64": torch.complex64, "c128": torch.complex128}[prec]
+
+
+def check_both(op, a, rng, prec, ncols=3, tol=None):
+    tol = TOL[prec] if tol is None else tol
+    m, n = a.shape
+    x = crandn(rng, (ncols, n), NP[prec])
+    y = crandn(rng, (ncols, m), NP[prec])
+    ey = rel_err(to_host(op @ to_dev(x)), dense.apply(a, x))
+    ez = rel_err(to_host(op.H @ to_dev(y)), dense.apply(a, y, True))
+    assert ey <= tol and ez <= tol, (ey, ez)
+
+
+def zoo(gpu, prec, rng):
+    """(name, operator, dense matrix) for a few square structured operators."""
+    dt = tdt(prec)
+    c = (crandn(rng, 64, np.complex128) / 8).astype(NP[prec])
+    c[0] += 4  # spectrum 4 + O(1): well conditioned, so the inverse checks stay tight
+    d = ((1 + rng.random(64)) * np.exp(2j * np.pi * rng.random(64))).astype(NP[prec])
+    g = crandn(rng, (8, 8), NP[prec])
+    col, row = crandn(rng, 64, NP[prec]), crandn(rng, 64, NP[prec])
+    perm = rng.permutation(64).astype(np.int32)
+    C, D = gpu.Circulant(to_dev(c)), gpu.Diag(to_dev(d))
+    F, H = gpu.Fourier(64, dt), gpu.Hadamard(64, dt)
+    G, T = gpu.Dense(to_dev(g)), gpu.Toeplitz(to_dev(col), to_dev(row))
+    S = gpu.SelectRows(64, to_dev(perm), dt)
+    dC, dD, dF, dH = dense.circulant(c), dense.diag(d), dense.fourier(64), dense.hadamard(64)
+    dG, dT, dS = g.astype(np.complex128), dense.toeplitz(col, row), dense.select_rows(64, perm)
+    F8 = gpu.Fourier(8, dt)
+    return [
+        ("circulant", C, dC), ("diag", D, dD), ("fourier", F, dF), ("hadamard", H, dH), ("dense", G, dG),
+        ("toeplitz", T, dT), ("permutation", S, dS),
+        ("kron", gpu.Kron(F8, G), dense.kron(dense.fourier(8), dG)),
+        ("kron_fc", gpu.Kron(F8, gpu.Circulant(to_dev(c[:8]))), dense.kron(dense.fourier(8), dense.circulant(c[:8]))),
+        ("product", gpu.Product(C, D), dC @ dD),
+        ("blkdiag", gpu.BlkDiag(C, D), dense.blkdiag(dC, dD)),
+        ("adjoint", C.H, dC.conj().T),
+        ("conj_of_circulant", C.conj, dC.conj()),
+    ]
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_conj_and_transpose(gpu, prec):
+    rng = np.random.default_rng(31)
+    for name, op, a in zoo(gpu, prec, rng):
+        check_both(op.conj, a.conj(), rng, prec)
+        check_both(op.T, a.T, rng, prec)
+    # accumulate path: a Sum of conj views
+    name, op, a = zoo(gpu, prec, rng)[5]
+    check_both(gpu.Sum(op.conj, op.conj), 2 * a.conj(), rng, prec)
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_gram(gpu, prec):
+    rng = np.random.default_rng(37)
+    tol = {"c64": 5e-5, "c128": 1e-12}[prec]  # |c_hat|^2 squares the spectrum's rounding
+    for name, op, a in zoo(gpu, prec, rng):
+        check_both(op.gram, a.conj().T @ a, rng, prec, tol=tol)
+    n, rows = 32, np.array([1, 4, 9, 30], np.int32)
+    S = gpu.SelectRows(n, to_dev(rows), tdt(prec))
+    check_both(S.gram, dense.select_rows(n, rows).T @ dense.select_rows(n, rows), rng, prec)
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_structured_inverse(gpu, prec):
+    import paper_1710_09578_amd as fm
+
+    rng = np.random.default_rng(41)
+    tol = {"c64": 1e-4, "c128": 1e-11}[prec]  # conditioning of the random spectra
+    for name, op, a in zoo(gpu, prec, rng):
+        if name in ("dense", "toeplitz", "kron"):
+            with pytest.raises(fm.FmError) as e:
+                op.inverse
+            assert e.value.code == "FM_E_UNSUPPORTED"
+            continue
+        check_both(op.inverse, np.linalg.inv(a), rng, prec, tol=tol)
+    with pytest.raises(fm.FmError) as e:  # singular circulant: c = ones has c_hat = (n, 0, ..., 0)
+        gpu.Circulant(to_dev(np.ones(16, NP[prec]))).inverse
+    assert e.value.code == "FM_E_INVALID"
+    with pytest.raises(fm.FmError) as e:
+        gpu.Dense(to_dev(crandn(rng, (4, 6), NP[prec]))).inverse
+    assert e.value.code == "FM_E_SHAPE"
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+@pytest.mark.parametrize("n", [3, 5, 12, 100, 1000, 3001])
+def test_fourier_any_size(gpu, prec, n):
+    rng = np.random.default_rng(n)
+    F = gpu.Fourier(n, tdt(prec))
+    check_both(F, dense.fourier(n), rng, prec)
+    if n <= 100:
+        check_both(gpu.Kron(F, gpu.Fourier(8, tdt(prec))), dense.kron(dense.fourier(n), dense.fourier(8)), rng, prec)
+        check_both(F.inverse, np.linalg.inv(dense.fourier(n)), rng, prec)
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+@pytest.mark.parametrize("n", [3, 100, 1000, 5000])
+def test_circulant_any_size(gpu, prec, n):
+    rng = np.random.default_rng(n + 1)
+    c = crandn(rng, n, NP[prec])
+    check_both(gpu.Circulant(to_dev(c)), dense.circulant(c), rng, prec)
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+@pytest.mark.parametrize("order,taps", [(4, 0b0011), (10, 0b1001), (12, 0b1010011)])
+def test_lfsr_circulant(gpu, prec, order, taps):
+    rng = np.random.default_rng(order)
+    op = gpu.LFSRCirculant(order, taps, 1, tdt(prec))
+    check_both(op, dense.circulant(dense.lfsr_sequence(order, taps, 1)), rng, prec)

@@ -346,3 +346,25 @@ def test_ml_toeplitz_rows_and_fourier_rows():
     assert np.array_equal(dense.ml_toeplitz_rows([3, 4], t, rows), full[rows])
     f = dense.fourier(12)
     assert np.allclose(dense.fourier_rows(12, [0, 3, 11]), f[[0, 3, 11]], atol=1e-14)
+
+
+# ---------------------------------------------------------------- LFSR generator
+def test_lfsr_golden_order4():
+    ref = np.array([float(v) for v in golden_rows("lfsr4.txt")[0]])
+    assert np.array_equal(dense.lfsr_sequence(4, 0b0011, 1).real, ref)
+
+
+def test_lfsr_m_sequence_properties():
+    """Primitive feedback polynomials give period 2^k - 1, one more -1 than +1,
+    and a two-valued cyclic autocorrelation (N at lag 0, -1 elsewhere); a
+    reducible one (x^4 + x^2 + 1) repeats after 6 values."""
+    for order, taps in ((4, 0b0011), (5, 0b00101), (7, 0b0000011)):
+        n = (1 << order) - 1
+        s = dense.lfsr_sequence(order, taps, 1, 2 * n).real
+        assert np.array_equal(s[:n], s[n:])
+        assert not any(np.array_equal(s[:p], s[p:2 * p]) for p in range(1, n) if n % p == 0)
+        assert np.sum(s[:n] < 0) == np.sum(s[:n] > 0) + 1
+        ac = [np.dot(s[:n], np.roll(s[:n], -t)) for t in range(n)]
+        assert ac[0] == n and all(v == -1 for v in ac[1:])
+    s = dense.lfsr_sequence(4, 0b0101, 1, 12).real
+    assert np.array_equal(s[:6], s[6:])
