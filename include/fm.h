@@ -182,7 +182,10 @@ fm_status fm_op_adjoint(fm_op* out, fm_op a);
  *   fm_op_inverse: A^-1 for square operators with a structured inverse:
  *                  Circulant (spectrum 1/c_hat), Diag (1/d), Fourier (F^H / n),
  *                  Hadamard (H / n), square row selections (permutations:
- *                  S^H), and Kron, BlkDiag, Product, adjoint and conj views of
+ *                  S^H), square Toeplitz (applied by Levinson recursion,
+ *                  O(n^2) per vector, one work-group per vector; a vector
+ *                  whose system has a singular leading minor comes out NaN),
+ *                  and Kron, BlkDiag, Product, adjoint and conj views of
  *                  those. FM_E_INVALID for a singular circulant or diagonal,
  *                  FM_E_SHAPE for non-square, FM_E_UNSUPPORTED for other kinds.
  *                  Complex dtypes; synchronises the device. */

@@ -381,6 +381,10 @@ fm_status fm_op_create_toeplitz(fm_op* out, int64_t m, int64_t n, const void* co
   FM_TRY(launch_toeplitz_embed(m, n, L, col, row != nullptr ? row : col, dt == FM_C64, emb.p, s));
   FM_TRY(dft128(L, emb.p, ghat.p, 1.0 / double(L), s));
   FM_TRY(store_spectrum(op, ghat.p, s));
+  if (m == n) {  // keep the generator for the inverse (Levinson)
+    FM_TRY(op->gen.alloc(size_t(L) * 16));
+    FM_HIP(hipMemcpyAsync(op->gen.p, emb.p, size_t(L) * 16, hipMemcpyDeviceToDevice, s));
+  }
   FM_HIP(hipStreamSynchronize(s));
   return publish(g.release(), out);
 }
@@ -792,6 +796,21 @@ fm_status inverse_of(const fm_op_s* a, fm_op* out) {
     }
     case Kind::Select:  // a square selection is a permutation: S^-1 = S^H
       return fm_op_adjoint(out, const_cast<fm_op_s*>(a));
+    case Kind::Toeplitz: {  // applied by Levinson solves
+      FM_CHECK_ARG(a->gen.p != nullptr, FM_E_UNSUPPORTED, "Toeplitz without a stored generator");
+      fm_op_s* op;
+      FM_TRY(new_op(Kind::ToeplitzInv, a->dt, a->n, a->n, &op));
+      fm_op_s* self = const_cast<fm_op_s*>(a);
+      self->refs.fetch_add(1);
+      op->terms.push_back(self);
+      return publish(op, out);
+    }
+    case Kind::ToeplitzInv: {  // (T^-1)^-1 = T
+      fm_op_s* t = a->terms[0];
+      t->refs.fetch_add(1);
+      *out = t;
+      return FM_OK;
+    }
     case Kind::Adjoint:
     case Kind::Conj: {
       Held i;

@@ -478,6 +478,26 @@ fm_status exec(const fm_op_s* op, bool adj, Elem e, const Batch& b, const void* 
   switch (op->kind) {
     case Kind::Adjoint:
       return exec(op->terms[0], !adj, e, b, x, y, acc, ws, s);
+    case Kind::ToeplitzInv: {  // Levinson solves with T (adjoint: T^H)
+      const fm_op_s* T = op->terms[0];
+      Batch fb;
+      FM_CHECK_ARG(b.inner == 1 && fold_outer(b, op->n, op->n, &fb) && fb.outer == 1, FM_E_UNSUPPORTED,
+                   "Toeplitz inverse along a strided axis");
+      const int64_t n = op->n, nc = fb.ncols;
+      const size_t es = elem_bytes(e);
+      const size_t mk = ws.mark();
+      void* work = ws.take(size_t(3 * n * nc) * es);
+      void* dst = y;
+      int64_t ldd = fb.ldy;
+      if (acc) {
+        dst = ws.take(size_t(n * nc) * es);
+        ldd = n;
+      }
+      LAUNCH(launch_levinson(e, n, T->L, T->gen.p, adj ? 1 : 0, nc, x, fb.ldx, dst, ldd, work, s));
+      if (acc) LAUNCH(launch_copy(e, n, Batch{nc, 1, 1, n, n, fb.ldy, fb.ldy}, dst, y, 1, s));
+      ws.release(mk);
+      return FM_OK;
+    }
     case Kind::Conj: {  // conj(A) x = conj(A conj(x)); the same for the adjoint direction
       if (e == Elem::I32 || e == Elem::I64) return exec(op->terms[0], adj, e, b, x, y, acc, ws, s);
       const int64_t rin = in_rows(op, adj), rout = out_rows(op, adj);

@@ -256,6 +256,9 @@ fm_status norm_bound(const fm_op_s* op, hipStream_t s, double* out) {
       *out = m;
       return FM_OK;
     }
+    case Kind::ToeplitzInv:
+      set_error("norm bound: no structural bound for a Toeplitz inverse (use the power iteration)");
+      return FM_E_UNSUPPORTED;
     case Kind::Blocks: {  // Schur test on the block norms: ||H||^2 <= max row sum * max column sum
       std::vector<double> rs(op->nbr, 0.0), cs(op->nbc, 0.0);
       for (int i = 0; i < op->nbr; ++i)

@@ -122,6 +122,13 @@ fm_status launch_toeplitz_embed(int64_t m, int64_t n, int64_t L, const void* col
 // Check indices. flags: n + 1 zeroed ints; flags[n] becomes nonzero if any
 // idx is outside [0, n) or repeated.
 fm_status launch_check_indices(int64_t n, int64_t m, const int32_t* idx, int* flags, hipStream_t s);
+// Levinson solves T x = b (adjoint: T^H x = b) for ncols right-hand sides of
+// the n x n Toeplitz T whose generator is embedded in gen (complex128, t_k at
+// index k mod L). x may be written in place of a workspace; work holds
+// 3 n ncols values of type e. A column whose leading minors are singular gets
+// NaN values.
+fm_status launch_levinson(Elem e, int64_t n, int64_t L, const void* gen, int adjoint, int64_t ncols, const void* b,
+                          int64_t ldb, void* x, int64_t ldx, void* work, hipStream_t s);
 // y (+)= conj(x) over the vectors of a batch (n rows each); plain copy for integers.
 fm_status launch_conj(Elem e, int64_t n, const Batch& b, const void* x, void* y, int accumulate, hipStream_t s);
 // Elementwise map of count complex128 values: mode 0 out = scale |in|^2, mode 1

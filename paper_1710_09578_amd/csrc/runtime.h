@@ -44,7 +44,8 @@ enum class Kind {
   BlkDiag,
   Blocks,
   Adjoint,
-  Conj
+  Conj,
+  ToeplitzInv
 };
 
 // Split of a cyclic length L for one element type: L <= LDS limit runs in one
@@ -83,6 +84,9 @@ struct fm_op_s {
   std::vector<int64_t> roff, coff;
   bool mix = false;
   int mix_logtw = 0;
+  // square Toeplitz: the embedded generator in complex128 (t_k at k mod L),
+  // kept for the Levinson solves of its inverse
+  fm::DevBuf gen;
 };
 
 namespace fm {

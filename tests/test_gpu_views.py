@@ -88,7 +88,9 @@ def test_structured_inverse(gpu, prec):
     rng = np.random.default_rng(41)
     tol = {"c64": 1e-4, "c128": 1e-11}[prec]  # conditioning of the random spectra
     for name, op, a in zoo(gpu, prec, rng):
-        if name in ("dense", "toeplitz", "kron"):
+        if name == "toeplitz":
+            continue  # Levinson: test_toeplitz_inverse_levinson
+        if name in ("dense", "kron"):
             with pytest.raises(fm.FmError) as e:
                 op.inverse
             assert e.value.code == "FM_E_UNSUPPORTED"
@@ -127,3 +129,25 @@ def test_lfsr_circulant(gpu, prec, order, taps):
     rng = np.random.default_rng(order)
     op = gpu.LFSRCirculant(order, taps, 1, tdt(prec))
     check_both(op, dense.circulant(dense.lfsr_sequence(order, taps, 1)), rng, prec)
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+@pytest.mark.parametrize("n", [1, 7, 100, 1500])
+def test_toeplitz_inverse_levinson(gpu, prec, n):
+    """Square Toeplitz inverse applied by Levinson recursion (forward and
+    adjoint), with a well-conditioned generator; the accumulate path through a
+    Sum; a zero diagonal (singular first leading minor) gives NaN."""
+    rng = np.random.default_rng(n + 7)
+    col = (crandn(rng, n, np.complex128) / np.sqrt(n)).astype(NP[prec])
+    row = (crandn(rng, n, np.complex128) / np.sqrt(n)).astype(NP[prec])
+    col[0] += 3
+    T = gpu.Toeplitz(to_dev(col), to_dev(row))
+    inv = np.linalg.inv(dense.toeplitz(col, row))
+    tol = {"c64": 1e-4, "c128": 1e-11}[prec]
+    check_both(T.inverse, inv, rng, prec, tol=tol)
+    check_both(gpu.Sum(T.inverse, T.inverse), 2 * inv, rng, prec, tol=tol)
+    if n > 1:
+        col0 = col.copy()
+        col0[0] = 0
+        y = to_host(gpu.Toeplitz(to_dev(col0), to_dev(row)).inverse @ to_dev(crandn(rng, (1, n), NP[prec])))
+        assert np.all(np.isnan(y))
