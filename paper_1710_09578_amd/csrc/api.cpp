@@ -110,7 +110,7 @@ fm_status store_spectrum(fm_op_s* op, const void* ghat, hipStream_t s) {
                                      tmp.p, s));
       src = tmp.p;
     }
-    FM_TRY(launch_c128_to_c64(L, src, op->p32.p, s));
+    FM_TRY(launch_spectrum_c64(L, src, op->p32.p, s));
     FM_HIP(hipStreamSynchronize(s));  // tmp is freed on return
   }
   return FM_OK;
@@ -710,7 +710,10 @@ fm_status derive_params(const fm_op_s* src, int64_t count, int mode, double scal
   FM_TRY(launch_param_map(count, mode, scale, src->p64.p, op->p64.p, static_cast<int*>(flag.p), nullptr));
   if (op->dt == FM_C64) {
     FM_TRY(op->p32.alloc(size_t(count) * 8));
-    FM_TRY(launch_c128_to_c64(count, op->p64.p, op->p32.p, nullptr));
+    if (op->kind == Kind::Circulant || op->kind == Kind::Toeplitz)
+      FM_TRY(launch_spectrum_c64(count, op->p64.p, op->p32.p, nullptr));  // convolution spectra: pair order
+    else
+      FM_TRY(launch_c128_to_c64(count, op->p64.p, op->p32.p, nullptr));
   }
   int bad = 0;
   FM_HIP(hipMemcpy(&bad, flag.p, sizeof(int), hipMemcpyDeviceToHost));

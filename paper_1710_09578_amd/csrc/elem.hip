@@ -416,6 +416,20 @@ __global__ __launch_bounds__(256) void down_kernel(int64_t count, const c128* __
   if (f < count) y[f] = {float(x[f].x), float(x[f].y)};
 }
 
+// Rounds a convolution spectrum to complex64 in the pair order read by the
+// transform engine: within each row of lr = 16 T values, natural entry
+// t + T k goes to 2 (t + T (k / 2)) + k % 2, so that a thread's values k and
+// k + 1 are adjacent (one 16-byte load per pair).
+__global__ __launch_bounds__(256) void down_paired_kernel(int64_t count, int64_t lr, const c128* __restrict__ x,
+                                                          c64* y) {
+  const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (f >= count) return;
+  const int64_t T = lr >> 4;
+  const int64_t row = f / lr, r = f - row * lr;
+  const int64_t t = r % T, k = r / T;
+  y[row * lr + 2 * (t + T * (k >> 1)) + (k & 1)] = {float(x[f].x), float(x[f].y)};
+}
+
 __global__ __launch_bounds__(256) void permute_kernel(int64_t n1, int64_t n2, const c128* __restrict__ x,
                                                       c128* y) {
   const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;  // f = k1 + n1 * k2
@@ -709,6 +723,16 @@ fm_status launch_c64_to_c128(int64_t count, const void* x, void* y, hipStream_t 
   if (count == 0) return FM_OK;
   hipLaunchKernelGGL(up_kernel, dim3(unsigned(cdiv(count, 256))), dim3(256), 0, s, count,
                      (const c64*)x, (c128*)y);
+  FM_LAUNCHED();
+  return FM_OK;
+}
+
+fm_status launch_spectrum_c64(int64_t count, const void* x, void* y, hipStream_t s) {
+  if (count == 0) return FM_OK;
+  if (count < 16) return launch_c128_to_c64(count, x, y, s);
+  const int64_t lr = count < 4096 ? count : 4096;
+  hipLaunchKernelGGL(down_paired_kernel, dim3(unsigned(cdiv(count, 256))), dim3(256), 0, s, count, lr,
+                     (const c128*)x, (c64*)y);
   FM_LAUNCHED();
   return FM_OK;
 }

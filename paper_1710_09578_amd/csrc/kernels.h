@@ -112,6 +112,11 @@ fm_status launch_scale_copy(Elem e, int64_t count, double alpha, const void* x, 
 fm_status launch_c64_to_c128(int64_t count, const void* x, void* y, hipStream_t s);
 // Round complex128 -> complex64 (count entries, contiguous).
 fm_status launch_c128_to_c64(int64_t count, const void* x, void* y, hipStream_t s);
+// Convolution spectrum (count = L entries, rows of min(L, 4096) in the order
+// the convolution reads them) rounded to complex64 in pair order: within each
+// row of 16 T values, entry t + T k is stored at 2 (t + T (k / 2)) + k % 2
+// (L >= 16; shorter spectra stay in natural order).
+fm_status launch_spectrum_c64(int64_t count, const void* x, void* y, hipStream_t s);
 // Permute a length N1*N2 spectrum from natural order X[k2 + N2 k1] into the
 // four-step order P[k1 + N1 k2] (complex128).
 fm_status launch_fourstep_permute(int64_t n1, int64_t n2, const void* x, void* y, hipStream_t s);

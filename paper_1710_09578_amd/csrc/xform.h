@@ -307,11 +307,25 @@ __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int lo
     forward(v, logn, t, my, tw);
     if (md.mode == FFT_CONV) {
       const Cx<R>* S = jb.S + b * jb.sbstride;
+      Cx<R> sv[kE];
+      if constexpr (sizeof(R) == 4) {
+        // complex64 spectra are stored in pair order: values k and k + 1 of a
+        // thread are adjacent, one 16-byte load per pair
+        const float4* S4 = reinterpret_cast<const float4*>(S);
+#pragma unroll
+        for (int j = 0; j < kE / 2; ++j) {
+          const float4 q = S4[t + T * j];
+          sv[2 * j] = {q.x, q.y};
+          sv[2 * j + 1] = {q.z, q.w};
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < kE; ++k) sv[k] = S[t + T * k];
+      }
 #pragma unroll
       for (int k = 0; k < kE; ++k) {
-        const Cx<R> s = S[t + T * k];
         // inverse follows: keep conj(X s) (or conj(X conj s)) for the conj trick
-        const Cx<R> p = md.spec_conj ? cmulc(v[k], s) : cmul(v[k], s);
+        const Cx<R> p = md.spec_conj ? cmulc(v[k], sv[k]) : cmul(v[k], sv[k]);
         v[k] = {p.x, -p.y};
       }
       forward(v, logn, t, my, tw);
