@@ -473,6 +473,30 @@ def omp_solves(ncols=64, k=64, reps=3):
     return out
 
 
+def calibration_small(ncols=65536):
+    """Run-time path choice for small operators on many columns: the times of
+    the structured and the dense evaluation and the path kept."""
+    import torch
+
+    import paper_1710_09578_amd as fm
+
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(11)
+    out = {}
+    for name, mk in (("circulant16", lambda: fm.Circulant(torch.randn(16, dtype=torch.complex64, device=dev,
+                                                                          generator=gen))),
+                     ("fourier32", lambda: fm.Fourier(32)),
+                     ("toeplitz48", lambda: fm.Toeplitz(torch.randn(48, dtype=torch.complex64, device=dev, generator=gen),
+                                                        torch.randn(48, dtype=torch.complex64, device=dev,
+                                                                    generator=gen)))):
+        info = mk().calibrate(ncols)
+        out[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in info.items()}
+        log(f"calibration {name} x {ncols} columns: structured {info['ms_structured']:.4f} ms, "
+            f"dense {info['ms_dense']:.4f} ms -> {info['path']}")
+    return out
+
+
 def copy_bandwidth(nbytes=1 << 30, reps=10):
     """Device-to-device copy rate (read + write bytes per second): the
     practical ceiling of a streaming kernel on this device."""
@@ -535,6 +559,7 @@ def main():
     ap.add_argument("--no-wide", action="store_true", help="skip the 1024-point circulant on 65536 columns")
     ap.add_argument("--no-ultrasound", action="store_true", help="skip the compressed ultrasound model")
     ap.add_argument("--no-omp", action="store_true", help="skip the OMP solves")
+    ap.add_argument("--no-calib", action="store_true", help="skip the small-operator path calibration")
     ap.add_argument("--no-tune", action="store_true", help="keep the default batch schedule")
     ap.add_argument("--schedule", default="", help="MAX_FUSE,REGION_MIB: fixed batch schedule (no tuning)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -611,6 +636,7 @@ def main():
     wide = None if args.no_wide else circulant_wide_bandwidth()
     us = None if args.no_ultrasound else ultrasound_model()
     ompr = None if args.no_omp else omp_solves()
+    calib = None if args.no_calib else calibration_small()
     copy_gbs = copy_bandwidth()
     log(f"device copy: {copy_gbs:.1f} GB/s")
     roof["copy_gbs"] = round(copy_gbs, 1)
@@ -647,6 +673,7 @@ def main():
         "wide_circulant": wide,
         "ultrasound": us,
         "omp": ompr,
+        "calibration": calib,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

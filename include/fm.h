@@ -192,6 +192,25 @@ fm_status fm_op_adjoint(fm_op* out, fm_op a);
 fm_status fm_op_conj(fm_op* out, fm_op a);
 fm_status fm_op_gram(fm_op* out, fm_op a);
 fm_status fm_op_inverse(fm_op* out, fm_op a);
+/* Run-time calibration of the evaluation path, after the paper's runtime
+ * path optimisation (section "Software description": algorithms are timed at
+ * run time and the faster one is kept per size and number of vectors). For
+ * an operator of at most 64 x 64 (any kind, composites included) the library
+ * can apply its structured transforms or a dense product with the
+ * operator's matrix, materialised once through the operator's own complex128
+ * transforms applied to the identity and rounded once for complex64.
+ *   fm_op_calibrate times both paths on ncols columns on `stream` (2 warm-up
+ *   and 5 timed applications each, HIP events), keeps the faster for every
+ *   later application of this handle and reports both times (ms per
+ *   application; any output pointer may be NULL). choice: 0 structured,
+ *   1 dense.
+ *   fm_op_set_path forces a path (0 or 1).
+ * The operator's value does not change (within the precision of either
+ * path), only how it is evaluated; calls serialise on a library mutex and
+ * synchronise. Complex dtypes; FM_E_UNSUPPORTED above 64 x 64. */
+fm_status fm_op_calibrate(fm_op a, int64_t ncols, int32_t* choice, double* ms_fast, double* ms_dense, void* stream);
+fm_status fm_op_set_path(fm_op a, int32_t path);
+
 fm_status fm_op_shape(fm_op a, int64_t* m, int64_t* n, fm_dtype* dt);
 
 /* Drops one reference; storage is freed when the last reference goes. */

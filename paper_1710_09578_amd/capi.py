@@ -105,6 +105,8 @@ SIGNATURES = {
     "fm_op_conj": (ST, [C.POINTER(P), P]),
     "fm_op_gram": (ST, [C.POINTER(P), P]),
     "fm_op_inverse": (ST, [C.POINTER(P), P]),
+    "fm_op_calibrate": (ST, [P, I64, C.POINTER(I32), C.POINTER(C.c_double), C.POINTER(C.c_double), P]),
+    "fm_op_set_path": (ST, [P, I32]),
     "fm_op_shape": (ST, [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(C.c_int)]),
     "fm_op_release": (ST, [P]),
     "fm_workspace_size": (ST, [P, C.c_int, I64, C.POINTER(C.c_size_t)]),
@@ -284,6 +286,16 @@ def fm_op_inverse(a):
     h = P()
     _call("fm_op_inverse", C.byref(h), a)
     return h
+
+
+def fm_op_calibrate(a, ncols, stream):
+    choice, tf, td = I32(), C.c_double(), C.c_double()
+    _call("fm_op_calibrate", a, ncols, C.byref(choice), C.byref(tf), C.byref(td), _ptr(stream))
+    return choice.value, tf.value, td.value
+
+
+def fm_op_set_path(a, path):
+    _call("fm_op_set_path", a, path)
 
 
 def fm_op_shape(a):

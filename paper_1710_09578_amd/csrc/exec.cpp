@@ -475,6 +475,12 @@ fm_status exec_blkdiag(const fm_op_s* op, bool adj, Elem e, const Batch& b, cons
 fm_status exec(const fm_op_s* op, bool adj, Elem e, const Batch& b, const void* x, void* y,
                bool acc, Workspace& ws, hipStream_t s) {
   if (b.ncols == 0 || b.outer == 0) return FM_OK;
+  if (op->path.load(std::memory_order_acquire) == 1 && (e == Elem::C64 || e == Elem::C128)) {
+    // calibrated: the dense product is faster for this operator
+    LAUNCH(launch_dense(e, op->m, op->n, e == Elem::C64 ? op->dense32.p : op->dense64.p, op->m, adj, 0, b, x, y,
+                        acc, s));
+    return FM_OK;
+  }
   switch (op->kind) {
     case Kind::Adjoint:
       return exec(op->terms[0], !adj, e, b, x, y, acc, ws, s);

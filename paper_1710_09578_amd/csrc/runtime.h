@@ -87,6 +87,11 @@ struct fm_op_s {
   // square Toeplitz: the embedded generator in complex128 (t_k at k mod L),
   // kept for the Levinson solves of its inverse
   fm::DevBuf gen;
+  // evaluation path chosen by calibration (0: the structured transforms,
+  // 1: a dense product with the operator's materialised matrix, column-major,
+  // lda = m, in dense32 / dense64); the operator's value is the same either way
+  std::atomic<int> path{0};
+  fm::DevBuf dense32, dense64;
 };
 
 namespace fm {

@@ -87,6 +87,16 @@ class Operator:
         """Gramian A^H A, fused from the structure where one exists."""
         return Operator(capi.fm_op_gram(self._h), keep=(self,))
 
+    def calibrate(self, ncols: int) -> dict:
+        """Time the structured and the dense evaluation on ncols columns and
+        keep the faster (operators up to 64 x 64)."""
+        choice, tf, td = capi.fm_op_calibrate(self._h, int(ncols), _stream())
+        return {"path": "dense" if choice else "structured", "ms_structured": tf, "ms_dense": td}
+
+    def set_path(self, path: str):
+        """Force the evaluation path: "structured" or "dense"."""
+        capi.fm_op_set_path(self._h, 1 if path == "dense" else 0)
+
     @property
     def inverse(self) -> "Operator":
         """Structured inverse A^-1 (Circulant, Diag, Fourier, Hadamard,

@@ -57,6 +57,8 @@ def test_invalid_arguments_return_status(lib):
     assert st(lib, "fm_op_create_lfsr_circulant", C.byref(h), 4, 3, 0, 1, None) == 1  # zero state
     assert st(lib, "fm_op_create_lfsr_circulant", C.byref(h), 30, 3, 1, 1, None) == 5  # order too large
     assert st(lib, "fm_op_conj", None, None) == 1
+    assert st(lib, "fm_op_calibrate", None, 16, None, None, None, None) == 1
+    assert st(lib, "fm_op_set_path", C.c_void_p(0x1000), 0) == 9
     assert st(lib, "fm_op_gram", C.byref(h), C.c_void_p(0x1000)) == 9
     assert st(lib, "fm_op_inverse", C.byref(h), None) == 1
     assert st(lib, "fm_op_create_fourier", C.byref(h), 0, 1) == 5

@@ -151,3 +151,36 @@ def test_toeplitz_inverse_levinson(gpu, prec, n):
         col0[0] = 0
         y = to_host(gpu.Toeplitz(to_dev(col0), to_dev(row)).inverse @ to_dev(crandn(rng, (1, n), NP[prec])))
         assert np.all(np.isnan(y))
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_calibrated_path(gpu, prec):
+    """Run-time calibration between the structured transforms and the dense
+    product: whichever path it keeps, and each path when forced, matches the
+    oracle; operators above 64 x 64 are refused."""
+    import paper_1710_09578_amd as fm
+
+    rng = np.random.default_rng(43)
+    dt = tdt(prec)
+    c = crandn(rng, 16, NP[prec])
+    col, row = crandn(rng, 24, NP[prec]), crandn(rng, 20, NP[prec])
+    rows = np.array([0, 3, 5, 9, 12, 15], np.int32)
+    cases = [
+        (gpu.Circulant(to_dev(c)), dense.circulant(c)),
+        (gpu.Toeplitz(to_dev(col), to_dev(row)), dense.toeplitz(col, row)),
+        (gpu.Fourier(32, dt), dense.fourier(32)),
+        (gpu.Kron(gpu.Fourier(4, dt), gpu.Hadamard(8, dt)), dense.kron(dense.fourier(4), dense.hadamard(8))),
+        (gpu.Product(gpu.SelectRows(16, to_dev(rows), dt), gpu.Circulant(to_dev(c))),
+         dense.select_rows(16, rows) @ dense.circulant(c)),
+    ]
+    for op, a in cases:
+        info = op.calibrate(4096)
+        assert info["path"] in ("dense", "structured") and info["ms_dense"] > 0 and info["ms_structured"] > 0
+        check_both(op, a, rng, prec, ncols=300)
+        for path in ("dense", "structured"):
+            op.set_path(path)
+            check_both(op, a, rng, prec, ncols=300)
+            check_both(gpu.Sum(op, op), 2 * a, rng, prec)
+    with pytest.raises(fm.FmError) as e:
+        gpu.Fourier(128, dt).calibrate(16)
+    assert e.value.code == "FM_E_UNSUPPORTED"
