@@ -13,8 +13,8 @@ constexpr int kLog1 = 12;   // contiguous factor of the four-step split (complex
 
 // Work items (one work-group each):
 //   SINGLE  whole zero-padded convolutions of length 2^lg for `sub` columns
-//   ROWF    row k2 = sub of a four-step column (L = 2^(12 + lg), lg <= conv_max_fuse()), the
-//           strided 2^lg-point transform folded into its load (reads x)
+//   ROWF    row k2 = sub of a four-step column (L = 4096 * n2, n2 <= 2^conv_max_fuse(); the
+//           item's parameter is n2), the strided n2-point transform folded into its load (reads x)
 //   FS1     strided 2^lg-point transforms of one column into its slot (lg not folded)
 //   FS2     row k2 = sub of a column whose FS1 pass has run (in place in the slot)
 //   FS3     strided inverse 2^lg-point transforms of one column and the cropped
@@ -31,9 +31,11 @@ struct Item {
 struct OpDev {
   const c64* spec;  // spectrum in the order of the operator's split, 1/L folded in
   int32_t m, n;
-  int32_t logL;
+  int32_t logL;     // log2 L (rounded down when L is not a power of two)
   int32_t ncols;
   int64_t col_base;  // index of the operator's first column among all columns of the batch
+  const c64* twl;   // four-step: table of W_L^m, 0 <= m < L (NULL for a single pass)
+  int32_t n2;       // four-step: L / 4096 (1 for a single pass)
 };
 
 struct FsCol {

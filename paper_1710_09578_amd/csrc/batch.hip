@@ -236,6 +236,7 @@ __device__ __forceinline__ void run_strided(const BArgs& a, const Item& it, cons
   jb.sbstride = 0;
   jb.q0 = i0;
   const int L = 1 << op.logL;
+  jb.twl = op.twl;
   if (first) {
     jb.x = pt.x + int64_t(fc.col) * pt.ldx + i0;
     jb.y = w + i0;
@@ -270,11 +271,12 @@ __device__ __forceinline__ void run_row(const BArgs& a, const Item& it, const Fs
   const OpDev op = a.ops[fc.op];
   c64* row = a.wpool + fc.woff + (int64_t(it.sub) << kLog1);
   Job<float> jb;
+  jb.twl = op.twl;
   if (fuse) {
     const Ptrs pt = a.ptrs[fc.op];
     jb.x = pt.x + int64_t(fc.col) * pt.ldx;
     jb.in_limit = a.adj ? op.m : op.n;
-    jb.fuse_log2 = fuse;
+    jb.fuse_n2 = fuse;
   } else {
     jb.x = row;
     jb.in_limit = 1 << kLog1;
@@ -325,6 +327,12 @@ __global__ __launch_bounds__(Geo<LOGW>::kThreads) void stage_kernel(BArgs a) {
 using namespace fm;
 
 namespace {
+// W_L table of a four-step operator (complex64), NULL when unavailable.
+const c64* op_twiddles(const fm_op_s* o) {
+  const void* t = twiddle_table(Elem::C64, ilog2(o->L));
+  return t ? static_cast<const c64*>(t) + o->L : nullptr;
+}
+
 std::mutex g_batch_mu;
 std::unordered_set<const fm_batch_s*>& live_batches() {
   static std::unordered_set<const fm_batch_s*> s;
@@ -542,7 +550,7 @@ fm_status fm::build_schedule(fm_batch_s* b, const Schedule& sc) {
         std::vector<Item> g;
         for (int t = 0; t < n2; ++t) {
           if (fuse && pass == 0)
-            g.push_back(Item{IT_ROWF | (lg2 << 8), cols[j].op, j, t});
+            g.push_back(Item{IT_ROWF | (n2 << 8), cols[j].op, j, t});
           else if (!fuse && pass == 0)
             g.push_back(Item{IT_FS1 | (lg2 << 8), cols[j].op, j, t});
           else if (!fuse && pass == 1)
@@ -619,6 +627,9 @@ fm_status fm_batch_create(fm_batch* out, int32_t nops, const fm_op* ops, const i
     FM_CHECK_ARG(ncols[i] >= 0 && ncols[i] < (int64_t(1) << 24), FM_E_INVALID, "batch: bad column count");
     FM_CHECK_ARG(!o->s32.four_step() || o->s32.log1 == kLog1, FM_E_UNSUPPORTED, "batch: unexpected transform split");
   }
+  for (int i = 0; i < nops; ++i)
+    FM_CHECK_ARG(ops[i]->L <= (int64_t(1) << kLog1) || op_twiddles(ops[i]) != nullptr, FM_E_DEVICE,
+                 "batch: twiddle table unavailable: %s", last_error());
   fm_batch_s* b = new (std::nothrow) fm_batch_s();
   FM_CHECK_ARG(b != nullptr, FM_E_NOMEM, "out of host memory");
   b->device = dev;
@@ -628,8 +639,9 @@ fm_status fm_batch_create(fm_batch* out, int32_t nops, const fm_op* ops, const i
     o->refs.fetch_add(1);
     b->ops.push_back(o);
     b->ncols.push_back(ncols[i]);
+    const c64* twl = o->L > (int64_t(1) << kLog1) ? op_twiddles(o) : nullptr;
     hops[i] = OpDev{static_cast<const c64*>(o->p32.p), int32_t(o->m), int32_t(o->n), ilog2(o->L), int32_t(ncols[i]),
-                    b->total_cols};
+                    b->total_cols, twl, int32_t(o->L > (int64_t(1) << kLog1) ? o->L >> kLog1 : 1)};
     b->col_base.push_back(b->total_cols);
     b->total_cols += ncols[i];
   }

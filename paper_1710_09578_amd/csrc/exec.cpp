@@ -149,7 +149,7 @@ fm_status exec_conv(const fm_op_s* op, bool adj, Elem e, const Batch& b, const v
     fr.spec_conj = adj;
     fr.tw_log = sp.logL;
     fr.tw_inv = 1;
-    fr.fuse_log2 = sp.log2;
+    fr.fuse_n2 = int(n2);
     LAUNCH(launch_fft(fr, s));
   } else {
     // step 1: forward length-n2 transforms at stride n1 of the zero-padded

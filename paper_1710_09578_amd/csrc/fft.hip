@@ -19,7 +19,8 @@ struct KArgs {
   const void* spec;
   int64_t spec_ostride;
   const void* tw;
-  int mode, spec_conj, tw_log, tw_inv, accumulate, logn, fuse_log2;
+  const void* twl;
+  int mode, spec_conj, tw_log, tw_inv, accumulate, logn, fuse_n2;
   int layout;  // contiguous: 0 transforms = columns, 1 packed (ncols*outer), 2 per column
   int64_t tiles;  // work-groups per column (layout 2) / per vector (strided)
 };
@@ -86,7 +87,8 @@ __global__ __launch_bounds__(Geo<LOGW>::kThreads) void fft_kernel(KArgs a) {
       jb.q0 = int(o0);
     }
   }
-  jb.fuse_log2 = a.fuse_log2;
+  jb.fuse_n2 = a.fuse_n2;
+  jb.twl = reinterpret_cast<const Cx<R>*>(a.twl);
   const Mode md{a.mode, a.spec_conj, a.tw_log, a.tw_inv, a.accumulate};
   run_job<R, STRIDED, LOGW>(jb, md, a.logn, lds, reinterpret_cast<const Cx<R>*>(a.tw));
 }
@@ -102,7 +104,7 @@ fm_status launch_typed(const FftLaunch& L, KArgs ka, hipStream_t s) {
   } else if (L.b.outer == 1) {
     ka.layout = 0;
     blocks = cdiv(L.b.ncols, tpw);
-  } else if (L.spec_ostride == 0 && L.tw_log == 0 && L.fuse_log2 == 0 &&
+  } else if (L.spec_ostride == 0 && L.tw_log == 0 && L.fuse_n2 == 0 &&
              (L.b.ncols == 1 || (L.b.ldx == L.b.outer * L.b.xvs && L.b.ldy == L.b.outer * L.b.yvs))) {
     ka.layout = 1;
     blocks = cdiv(L.b.ncols * L.b.outer, tpw);
@@ -115,7 +117,7 @@ fm_status launch_typed(const FftLaunch& L, KArgs ka, hipStream_t s) {
                "fft: grid of %lld work-groups is out of range", (long long)blocks);
   FM_CHECK_ARG((int64_t(1) << L.logn) * L.b.inner < (int64_t(1) << 30), FM_E_UNSUPPORTED,
                "fft: vector span above 2^30 elements");
-  FM_CHECK_ARG(L.fuse_log2 == 0 || (!strided && ka.layout == 2 && L.logn == LOGW && L.fuse_log2 <= 5),
+  FM_CHECK_ARG(L.fuse_n2 == 0 || (!strided && ka.layout == 2 && L.logn == LOGW && L.fuse_n2 <= 32),
                FM_E_UNSUPPORTED, "fft: fused column transform needs a full-size row per work-group");
   static bool attr_set = false;
   if (!attr_set) {
@@ -161,11 +163,17 @@ fm_status launch_fft(const FftLaunch& L, hipStream_t s) {
   ka.tw_inv = L.tw_inv;
   ka.accumulate = L.accumulate;
   ka.logn = L.logn;
-  ka.fuse_log2 = L.fuse_log2;
-  int need_log = L.tw_log > L.logn ? L.tw_log : L.logn;
-  if (L.logn + L.fuse_log2 > need_log) need_log = L.logn + L.fuse_log2;
+  ka.fuse_n2 = L.fuse_n2;
+  const bool own_table = L.twl == nullptr && L.tw_log > 0;
+  int need_log = own_table && L.tw_log > L.logn ? L.tw_log : L.logn;
   ka.tw = twiddle_table(L.elem, need_log);
   FM_CHECK_ARG(ka.tw != nullptr, FM_E_DEVICE, "fft: twiddle table unavailable: %s", last_error());
+  FM_CHECK_ARG(L.fuse_n2 == 0 || L.tw_log > 0, FM_E_INVALID, "fft: a fused row needs its twiddle table");
+  // W_L of the twiddle epilogue / fused row: the caller's table, or the
+  // power-of-two table of length 2^tw_log
+  ka.twl = L.twl ? L.twl
+                 : own_table ? static_cast<const char*>(ka.tw) + (size_t(1) << L.tw_log) * elem_bytes(L.elem)
+                             : nullptr;
   if (L.elem == Elem::C128) return launch_typed<double, 12>(L, ka, s);
   return launch_typed<float, 12>(L, ka, s);
 }

@@ -45,11 +45,14 @@ struct FftLaunch {
   const void* spec = nullptr;  // FFT_CONV: spectrum, entry r (+ o*spec_ostride)
   int64_t spec_ostride = 0;
   int spec_conj = 0;
-  int tw_log = 0;          // > 0: multiply result r by W^(r*q), W = exp(-+2 pi j / 2^tw_log),
-  int tw_inv = 0;          //      q = i (strided) or o (contiguous); tw_inv picks the + sign
+  int tw_log = 0;          // > 0: multiply result r by W^(r*q), W = exp(-+2 pi j / L) with
+  int tw_inv = 0;          //      L = 2^tw_log (or the table twl), q = i (strided) or o
+                           //      (contiguous); tw_inv picks the + sign
   int accumulate = 0;      // y += result
-  int fuse_log2 = 0;       // > 0: row o = k2 of a four-step convolution formed from the column x
-                           //      (L = 2^(logn + fuse_log2), logn = 12; see xform.h)
+  int fuse_n2 = 0;         // > 0: row o = k2 of a four-step convolution formed from the column x
+                           //      (L = 2^logn * fuse_n2, logn = 12; see xform.h)
+  const void* twl = nullptr;  // table W_L^m (0 <= m < L) for a four-step length that is not a
+                              // power of two; NULL: taken from the power-of-two tables (L = 2^tw_log)
 };
 fm_status launch_fft(const FftLaunch& L, hipStream_t s);
 

@@ -211,10 +211,13 @@ __device__ __forceinline__ void forward_tiny(Cx<R>* v, int logn) {
 // twiddle-epilogue index is q0 + b. Transforms with b >= nvalid are computed
 // on zeros and not stored.
 //
-// Fused input (fuse_log2 > 0, contiguous, one transform per work-group): the
-// row k2 = q0 of a four-step convolution with L = N * N2 (N2 = 2^fuse_log2 <=
-// 32) is formed while loading: point p is sum_n2 x[p + N n2] W_N2^(n2 k2)
-// (zero beyond in_limit), times W_L^(p k2); x is the column base.
+// Fused input (fuse_n2 > 0, contiguous, one transform per work-group): the
+// row k2 = q0 of a four-step convolution with L = N * N2 (N2 = fuse_n2 <= 32,
+// any integer) is formed while loading: point p is
+// sum_n2 x[p + N n2] W_N2^(n2 k2) (zero beyond in_limit), times W_L^(p k2);
+// x is the column base. twl is the table of W_L^m, 0 <= m < L, of the
+// four-step length L (row twiddles, the fold's W_N2 = W_L^(N .), and the
+// twiddle epilogue); every index formed from it is below L.
 template <typename R>
 struct Job {
   const Cx<R>* x;
@@ -228,7 +231,8 @@ struct Job {
   const Cx<R>* S;
   int64_t sbstride;
   int q0;
-  int fuse_log2 = 0;
+  int fuse_n2 = 0;
+  const Cx<R>* twl = nullptr;
 };
 struct Mode {
   int mode, spec_conj, tw_log, tw_inv, accumulate;
@@ -263,13 +267,12 @@ __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int lo
     const int ii = STRIDED ? jb.i0 + b : 0;
     const Cx<R>* X = STRIDED ? jb.x + b : jb.x + b * jb.xbstride;
     Cx<R>* Y = STRIDED ? jb.y + b : jb.y + b * jb.ybstride;
-    if (!STRIDED && jb.fuse_log2 > 0) {
+    if (!STRIDED && jb.fuse_n2 > 0) {
       // n2-outer order: the 16 loads of one n2 are in flight together and
       // consumed only after all of them were issued
-      const int n2s = 1 << jb.fuse_log2;
+      const int n2s = jb.fuse_n2;
       const int k2 = jb.q0;
       const int N = 1 << logn;
-      const int lgL = logn + jb.fuse_log2;
 #pragma unroll
       for (int k = 0; k < kE; ++k) v[k] = Cx<R>{R(0), R(0)};
       const int n2e = (jb.in_limit + N - 1) / N < n2s ? (jb.in_limit + N - 1) / N : n2s;  // rows holding data
@@ -280,14 +283,13 @@ __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int lo
           const int q = t + T * k + N * n2;
           val[k] = q < jb.in_limit ? X[q] : Cx<R>{R(0), R(0)};
         }
-        const Cx<R> w = tw[n2s + ((n2 * k2) & (n2s - 1))];
+        const Cx<R> w = jb.twl[N * ((n2 * k2) % n2s)];  // W_N2^(n2 k2)
 #pragma unroll
         for (int k = 0; k < kE; ++k) v[k] = cadd(v[k], cmul(val[k], w));
       }
       {  // W_L^((t + T k) k2) = W_L^(t k2) (W_L^(T k2))^k: two loads, the rest by products
-        const Cx<R>* tab = tw + (1 << lgL);
-        Cx<R> w = tab[(t * k2) & ((1 << lgL) - 1)];
-        const Cx<R> ws = tab[(T * k2) & ((1 << lgL) - 1)];
+        Cx<R> w = jb.twl[t * k2];
+        const Cx<R> ws = jb.twl[T * k2];
 #pragma unroll
         for (int k = 0; k < kE; ++k) {
           v[k] = cmul(v[k], w);
@@ -334,12 +336,11 @@ __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int lo
       conj_all(v);
     }
     if (md.tw_log > 0) {
-      const int twn = 1 << md.tw_log;
-      const Cx<R>* tab = tw + twn;
+      const Cx<R>* tab = jb.twl;
       const int qq = jb.q0 + b;
       // W^((t + T k) q) = W^(t q) (W^(T q))^k: two loads, the rest by products
-      Cx<R> w = tab[(t * qq) & (twn - 1)];
-      const Cx<R> ws = tab[(T * qq) & (twn - 1)];
+      Cx<R> w = tab[t * qq];
+      const Cx<R> ws = tab[T * qq];
 #pragma unroll
       for (int k = 0; k < kE; ++k) {
         v[k] = md.tw_inv ? cmulc(v[k], w) : cmul(v[k], w);
@@ -410,13 +411,12 @@ __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int lo
     conj_all(v);
   }
   if (md.tw_log > 0) {
-    const int twn = 1 << md.tw_log;
-    const Cx<R>* tab = tw + twn;
+    const Cx<R>* tab = jb.twl;
 #pragma unroll
     for (int k = 0; k < kE; ++k) {
       const int g = k >> logn, r = k & (N - 1);
       const int b = STRIDED ? tid + kWG * g : tid * G + g;
-      const Cx<R> w = tab[(r * (jb.q0 + b)) & (twn - 1)];
+      const Cx<R> w = tab[r * (jb.q0 + b)];
       v[k] = md.tw_inv ? cmulc(v[k], w) : cmul(v[k], w);
     }
   }
