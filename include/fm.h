@@ -115,8 +115,12 @@ fm_status fm_op_create_lfsr_circulant(fm_op* out, int32_t order, uint64_t taps, 
 /* Toeplitz m x n (a non-circular convolution): T[i,j] = col[i-j] for i >= j,
  * row[j-i] for i < j. col has m entries and defines the diagonal; row has n
  * entries and row[0] is ignored. Applied through a cyclic convolution of length
- * L = the smallest power of two >= m + n - 1 with zero padding and cropping
- * (the embedding described for eq. (7)); L <= 2^20. Complex dtypes. */
+ * L with zero padding and cropping (the embedding described for eq. (7)); L is
+ * the smallest length >= m + n - 1 among the powers of two and, above 4096,
+ * 4096 * n2 for n2 in {3, 5, 6, 9, 10, 12, 20, 24, 30} (any L >= m + n - 1
+ * gives the same matrix; these lengths waste less than the next power of two
+ * and have fast transforms here); the environment variable FM_EMBED=pow2 keeps
+ * powers of two. m + n - 1 <= 2^20. Complex dtypes. */
 fm_status fm_op_create_toeplitz(fm_op* out, int64_t m, int64_t n, const void* col,
                                 const void* row, fm_dtype dt, void* stream);
 

@@ -1,5 +1,7 @@
 // C ABI: operator creation (with the one-time precomputation of spectra),
 // composition, validation at every entry point, and fm_apply.
+#include <complex>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -357,6 +359,84 @@ fm_status fm_op_create_lfsr_circulant(fm_op* out, int32_t order, uint64_t taps, 
   return fm_op_create_circulant(out, n, cd.p, dt, stream);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Embedding length of a Toeplitz operator: the smallest L >= need among the
+// powers of two and, above 4096, the mixed lengths 4096 * n2 whose strided
+// passes exist (FM_EMBED=pow2 keeps powers of two).
+int64_t embed_length(int64_t need) {
+  int64_t best = next_pow2(need);
+  static const bool pow2_only = [] {
+    const char* e = std::getenv("FM_EMBED");
+    return e != nullptr && std::strcmp(e, "pow2") == 0;
+  }();
+  if (need <= 4096 || pow2_only) return best;
+  for (int n2 : {3, 5, 6, 9, 10, 12, 20, 24, 30}) {
+    const int64_t L = int64_t(4096) * n2;
+    if (L >= need && L < best) best = L;
+  }
+  return best;
+}
+
+// In-place forward DFT of 4096 points in FP64 (iterative radix 2).
+void host_fft4096(std::vector<std::complex<double>>& a, const std::vector<std::complex<double>>& w) {
+  const int n = 4096;
+  for (int i = 1, j = 0; i < n; ++i) {
+    int bit = n >> 1;
+    for (; j & bit; bit >>= 1) j ^= bit;
+    j ^= bit;
+    if (i < j) std::swap(a[i], a[j]);
+  }
+  for (int len = 2; len <= n; len <<= 1) {
+    const int half = len >> 1, stride = n / len;
+    for (int i = 0; i < n; i += len)
+      for (int k = 0; k < half; ++k) {
+        const std::complex<double> u = a[i + k], v = a[i + k + half] * w[size_t(k) * stride];
+        a[i + k] = u + v;
+        a[i + k + half] = u - v;
+      }
+  }
+}
+
+// Spectrum of a mixed length L = 4096 n2 in the row order the four-step
+// convolution reads, in FP64: row k2 holds ghat[k2 + n2 k1] / L at k1, with
+// ghat = DFT_L(g); row k2 = DFT_4096 of W_L^(n1 k2) sum_j g[n1 + 4096 j] W_n2^(j k2).
+std::vector<std::complex<double>> mixed_spectrum(const std::vector<std::complex<double>>& g, int64_t L) {
+  const int n2 = int(L / 4096);
+  std::vector<std::complex<double>> w4096(2048);
+  std::vector<std::complex<double>> out(static_cast<size_t>(L));
+  for (int k = 0; k < 2048; ++k) {
+    double re, im;
+    root_of_unity(k, 4096, &re, &im);
+    w4096[size_t(k)] = {re, im};
+  }
+  std::vector<std::complex<double>> row(4096);
+  for (int k2 = 0; k2 < n2; ++k2) {
+    std::vector<std::complex<double>> wn(static_cast<size_t>(n2));
+    for (int j = 0; j < n2; ++j) {
+      double re, im;
+      root_of_unity(int64_t(4096) * ((int64_t(j) * k2) % n2), L, &re, &im);  // W_n2^(j k2)
+      wn[size_t(j)] = {re, im};
+    }
+    for (int n1 = 0; n1 < 4096; ++n1) {
+      std::complex<double> acc = 0.0;
+      for (int j = 0; j < n2; ++j) acc += g[size_t(n1 + 4096 * j)] * wn[size_t(j)];
+      double re, im;
+      root_of_unity(int64_t(n1) * k2, L, &re, &im);  // W_L^(n1 k2)
+      row[size_t(n1)] = acc * std::complex<double>(re, im);
+    }
+    host_fft4096(row, w4096);
+    for (int k1 = 0; k1 < 4096; ++k1) out[size_t(k1 + 4096 * k2)] = row[size_t(k1)] / double(L);
+  }
+  return out;
+}
+
+}  // namespace
+
+extern "C" {
+
 fm_status fm_op_create_toeplitz(fm_op* out, int64_t m, int64_t n, const void* col, const void* row,
                                 fm_dtype dt, void* stream) {
   set_error("");
@@ -365,22 +445,37 @@ fm_status fm_op_create_toeplitz(fm_op* out, int64_t m, int64_t n, const void* co
   FM_CHECK_ARG(is_complex(dt), FM_E_DTYPE, "Toeplitz needs a complex dtype");
   FM_CHECK_ARG(m >= 1 && n >= 1, FM_E_INVALID, "Toeplitz shape must be positive");
   FM_CHECK_ARG(col != nullptr && (row != nullptr || n == 1), FM_E_INVALID, "Toeplitz: NULL generator");
-  const int64_t L = next_pow2(m + n - 1);
-  FM_CHECK_ARG(ilog2(L) <= kMaxLog, FM_E_UNSUPPORTED,
+  FM_CHECK_ARG(m + n - 1 <= (int64_t(1) << kMaxLog), FM_E_UNSUPPORTED,
                "Toeplitz %lld x %lld: embedding length above 2^20", (long long)m, (long long)n);
+  const int64_t L = embed_length(m + n - 1);
+  const bool mixed = !is_pow2(L);
   hipStream_t s = as_stream(stream);
   fm_op_s* op;
   FM_TRY(new_op(Kind::Toeplitz, dt, m, n, &op));
   Building g{op};
   op->L = L;
-  op->s32 = split_for(Elem::C64, ilog2(L));
-  op->s64 = split_for(Elem::C128, ilog2(L));
+  op->s32 = mixed ? split_mixed(L) : split_for(Elem::C64, ilog2(L));
+  op->s64 = mixed ? split_mixed(L) : split_for(Elem::C128, ilog2(L));
   DevBuf emb, ghat;
   FM_TRY(emb.alloc(size_t(L) * 16));
-  FM_TRY(ghat.alloc(size_t(L) * 16));
   FM_TRY(launch_toeplitz_embed(m, n, L, col, row != nullptr ? row : col, dt == FM_C64, emb.p, s));
-  FM_TRY(dft128(L, emb.p, ghat.p, 1.0 / double(L), s));
-  FM_TRY(store_spectrum(op, ghat.p, s));
+  if (mixed) {  // FP64 on the host, already in the four-step row order
+    std::vector<std::complex<double>> gh(static_cast<size_t>(L));
+    FM_HIP(hipMemcpyAsync(gh.data(), emb.p, size_t(L) * 16, hipMemcpyDeviceToHost, s));
+    FM_HIP(hipStreamSynchronize(s));
+    const std::vector<std::complex<double>> P = mixed_spectrum(gh, L);
+    FM_TRY(op->p64.alloc(size_t(L) * 16));
+    FM_HIP(hipMemcpyAsync(op->p64.p, P.data(), size_t(L) * 16, hipMemcpyHostToDevice, s));
+    if (dt == FM_C64) {
+      FM_TRY(op->p32.alloc(size_t(L) * 8));
+      FM_TRY(launch_spectrum_c64(L, op->p64.p, op->p32.p, s));
+    }
+    FM_HIP(hipStreamSynchronize(s));
+  } else {
+    FM_TRY(ghat.alloc(size_t(L) * 16));
+    FM_TRY(dft128(L, emb.p, ghat.p, 1.0 / double(L), s));
+    FM_TRY(store_spectrum(op, ghat.p, s));
+  }
   if (m == n) {  // keep the generator for the inverse (Levinson)
     FM_TRY(op->gen.alloc(size_t(L) * 16));
     FM_HIP(hipMemcpyAsync(op->gen.p, emb.p, size_t(L) * 16, hipMemcpyDeviceToDevice, s));

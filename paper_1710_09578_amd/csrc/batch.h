@@ -19,7 +19,16 @@ constexpr int kLog1 = 12;   // contiguous factor of the four-step split (complex
 //   FS2     row k2 = sub of a column whose FS1 pass has run (in place in the slot)
 //   FS3     strided inverse 2^lg-point transforms of one column and the cropped
 //           store into y (inner tile `sub`)
-enum ItemKind : int { IT_SINGLE = 0, IT_FS1 = 1, IT_FS2 = 2, IT_FS3 = 3, IT_ROWF = 4 };
+//   MX1/MX3 the FS1 / FS3 passes of a mixed length (L = 4096 * n2, n2 not a power of
+//           two; the item's parameter is n2): tile `sub` of mixed_tiles(n2) per column
+enum ItemKind : int { IT_SINGLE = 0, IT_FS1 = 1, IT_FS2 = 2, IT_FS3 = 3, IT_ROWF = 4, IT_MX1 = 5, IT_MX3 = 6 };
+
+// Column-pass work-groups (partial-sum slots of a solve) of a four-step
+// column with strided factor n2: n2 for powers of two (tiles of 4096 / n2
+// positions), mixed_tiles(n2) for mixed lengths.
+inline int32_t fs3_tiles(int32_t n2) {
+  return (n2 & (n2 - 1)) == 0 ? n2 : (n2 > 12 ? 32 : 16);
+}
 
 struct Item {
   int32_t kind_log;  // kind | (lg << 8)

@@ -25,6 +25,7 @@
 #include <unordered_set>
 
 #include "batch.h"
+#include "mixed.h"
 #include "xform.h"
 
 namespace fm {
@@ -294,8 +295,44 @@ __device__ __forceinline__ void run_row(const BArgs& a, const Item& it, const Fs
   run_job<float, false, kLogW>(jb, md, kLog1, smem, a.tw);
 }
 
+// MX1 / MX3: tile `sub` of the strided pass of a mixed-length column (first:
+// the forward n2-point DFTs of the zero-padded x with W_L^(n1 k2) into the
+// slot; last: the inverse DFTs of the slot, cropped into y or handed to the
+// solver's epilogue).
+template <int EPI>
+__device__ __forceinline__ void run_mixed(const BArgs& a, const Item& it, const FsCol& fc, int n2, bool first,
+                                          c64* smem) {
+  const OpDev op = a.ops[fc.op];
+  const Ptrs pt = a.ptrs[fc.op];
+  c64* w = a.wpool + fc.woff;
+  const int64_t L = int64_t(op.n2) << kLog1;
+  if (first) {
+    mixed_tile<float, NoEp>(n2, it.sub, pt.x + int64_t(fc.col) * pt.ldx, a.adj ? op.m : op.n, w, L, false, op.twl, L,
+                            0, static_cast<NoEp*>(nullptr), smem);
+    return;
+  }
+  c64* yc = pt.y + int64_t(fc.col) * pt.ldy;
+  const int64_t out_limit = a.adj ? op.n : op.m;
+  if constexpr (EPI == 1) {
+    const User u = a.epi.user[fc.op];
+    ResidualEp ep{u.b + int64_t(fc.col) * u.ldb, 0};
+    mixed_tile<float, ResidualEp>(n2, it.sub, w, L, yc, out_limit, true, op.twl, L, 0, &ep, smem);
+  } else if constexpr (EPI == 2) {
+    FistaEp ep = make_fista_ep<EPI>(a, fc.op, fc.col, true, 12);
+    mixed_tile<float, FistaEp>(n2, it.sub, w, L, yc, out_limit, true, op.twl, L, 0, &ep, smem);
+    fista_partials(ep, true, 12, 0, it.sub, smem);
+  } else {
+    mixed_tile<float, NoEp>(n2, it.sub, w, L, yc, out_limit, true, op.twl, L, 0, static_cast<NoEp*>(nullptr), smem);
+  }
+}
+
+// Waves per SIMD the stage kernel is compiled for (its register budget).
+#ifndef FM_STAGE_WAVES
+#define FM_STAGE_WAVES 3
+#endif
+
 template <int LOGW, int EPI>
-__global__ __launch_bounds__(Geo<LOGW>::kThreads) void stage_kernel(BArgs a) {
+__global__ __launch_bounds__(Geo<LOGW>::kThreads, FM_STAGE_WAVES) void stage_kernel(BArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   c64* smem = reinterpret_cast<c64*>(smem_raw);
   const Item it = a.items[blockIdx.x];
@@ -313,7 +350,9 @@ __global__ __launch_bounds__(Geo<LOGW>::kThreads) void stage_kernel(BArgs a) {
   }
   const FsCol fc = a.cols[it.col];
   if (a.active && !a.active[a.ops[fc.op].col_base + fc.col]) return;
-  if (kind == IT_ROWF)
+  if (kind == IT_MX1 || kind == IT_MX3)
+    run_mixed<EPI>(a, it, fc, lg, kind == IT_MX1, smem);
+  else if (kind == IT_ROWF)
     run_row(a, it, fc, lg, smem);
   else if (kind == IT_FS2)
     run_row(a, it, fc, 0, smem);
@@ -329,6 +368,7 @@ using namespace fm;
 namespace {
 // W_L table of a four-step operator (complex64), NULL when unavailable.
 const c64* op_twiddles(const fm_op_s* o) {
+  if (o->s32.mixed()) return static_cast<const c64*>(twiddle_table_L(Elem::C64, o->L));
   const void* t = twiddle_table(Elem::C64, ilog2(o->L));
   return t ? static_cast<const c64*>(t) + o->L : nullptr;
 }
@@ -497,11 +537,12 @@ fm_status fm::build_schedule(fm_batch_s* b, const Schedule& sc) {
   const int nops = int(b->ops.size());
   std::vector<Item> mid;  // single-pass items
   std::vector<FsCol> cols;
-  std::vector<int> col_log2;
+  std::vector<int> col_n2;  // strided factor L / 4096 of each four-step column
   for (int i = 0; i < nops; ++i) {
-    const int logL = ilog2(b->ops[i]->L);
+    const int64_t Lop = b->ops[i]->L;
+    const int logL = ilog2(Lop);
     const int64_t nc = b->ncols[i];
-    if (logL <= kLogW) {
+    if (Lop <= (int64_t(1) << kLogW)) {
       const int B = 1 << (kLogW - logL);  // transforms per work-group
       for (int64_t c0 = 0; c0 < nc; c0 += B) {
         const int cnt = int(std::min<int64_t>(B, nc - c0));
@@ -510,7 +551,7 @@ fm_status fm::build_schedule(fm_batch_s* b, const Schedule& sc) {
     } else {
       for (int64_t c = 0; c < nc; ++c) {
         cols.push_back(FsCol{i, int32_t(c), 0});
-        col_log2.push_back(logL - kLog1);
+        col_n2.push_back(int(Lop >> kLog1));
       }
     }
   }
@@ -520,7 +561,7 @@ fm_status fm::build_schedule(fm_batch_s* b, const Schedule& sc) {
   {
     size_t used = region_elems;  // forces a first chunk
     for (int j = 0; j < int(cols.size()); ++j) {
-      const size_t L = size_t(1) << (col_log2[j] + kLog1);
+      const size_t L = size_t(col_n2[j]) << kLog1;
       FM_CHECK_ARG(L <= region_elems, FM_E_UNSUPPORTED, "batch: slot region smaller than one column");
       if (used + L > region_elems) {
         chunks.emplace_back();
@@ -535,28 +576,33 @@ fm_status fm::build_schedule(fm_batch_s* b, const Schedule& sc) {
   for (int c = 0; c < nchunks; ++c)
     for (int j : chunks[c]) cols[j].woff += int64_t(c % 3) * int64_t(region_elems);
   bool unfused = false;
-  for (int lg2 : col_log2) unfused |= lg2 > sc.max_fuse;
+  for (int n2 : col_n2) unfused |= n2 > (1 << sc.max_fuse);
   const int nstages = nchunks > 0 ? nchunks + (unfused ? 2 : 1) : (mid.empty() ? 0 : 1);
   // per stage: reuse groups (the rows of one column, which re-read its x and
   // should share an XCD's L2)
   std::vector<std::vector<std::vector<Item>>> groups(size_t(std::max(nstages, 0)));
   for (int c = 0; c < nchunks; ++c) {
     for (int j : chunks[c]) {
-      const int lg2 = col_log2[j];
-      const int n2 = 1 << lg2;
-      const bool fuse = lg2 <= sc.max_fuse;
+      const int n2 = col_n2[j];
+      const bool mixed = (n2 & (n2 - 1)) != 0;
+      const int lg2 = mixed ? 0 : ilog2(n2);
+      const bool fuse = n2 <= (1 << sc.max_fuse);
       const int npass = fuse ? 2 : 3;
       for (int pass = 0; pass < npass; ++pass) {
+        const bool strided = pass == npass - 1 || (!fuse && pass == 0);
+        const int count = strided && mixed ? mixed_tiles(n2) : n2;
         std::vector<Item> g;
-        for (int t = 0; t < n2; ++t) {
+        for (int t = 0; t < count; ++t) {
           if (fuse && pass == 0)
             g.push_back(Item{IT_ROWF | (n2 << 8), cols[j].op, j, t});
           else if (!fuse && pass == 0)
-            g.push_back(Item{IT_FS1 | (lg2 << 8), cols[j].op, j, t});
+            g.push_back(mixed ? Item{IT_MX1 | (n2 << 8), cols[j].op, j, t}
+                              : Item{IT_FS1 | (lg2 << 8), cols[j].op, j, t});
           else if (!fuse && pass == 1)
             g.push_back(Item{IT_FS2 | (kLog1 << 8), cols[j].op, j, t});
           else
-            g.push_back(Item{IT_FS3 | (lg2 << 8), cols[j].op, j, t});
+            g.push_back(mixed ? Item{IT_MX3 | (n2 << 8), cols[j].op, j, t}
+                              : Item{IT_FS3 | (lg2 << 8), cols[j].op, j, t});
         }
         groups[size_t(c + pass)].push_back(std::move(g));
       }

@@ -23,7 +23,7 @@ struct SCol {  // one batch column
   int32_t n, m;     // rows of x (and y, g) and of b (and r)
   int64_t yoff, roff;  // offsets into the packed y/g and r buffers
   int64_t pbase;    // first partial-sum slot of the column
-  int32_t nslot;    // slots: 1, or 2^k for a four-step column of length 4096 * 2^k
+  int32_t nslot;    // slots: 1, or the column-pass tiles of a four-step column (fs3_tiles)
 };
 struct STile {
   int32_t g;     // batch column
@@ -129,7 +129,7 @@ fm_status ensure_state(fm_batch_s* b) {
     const fm_op_s* o = b->ops[i];
     b->s_yoff[i] = yo;
     b->s_roff[i] = ro;
-    const int32_t nslot = o->L > (int64_t(1) << kLog1) ? int32_t(o->L >> kLog1) : 1;
+    const int32_t nslot = o->L > (int64_t(1) << kLog1) ? fs3_tiles(int32_t(o->L >> kLog1)) : 1;
     for (int64_t c = 0; c < b->ncols[i]; ++c) {
       SCol sc{i, int32_t(c), int32_t(o->n), int32_t(o->m), yo + c * o->n, ro + c * o->m, slots, nslot};
       const int32_t gidx = int32_t(cols.size());

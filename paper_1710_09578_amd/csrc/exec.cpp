@@ -101,6 +101,52 @@ fm_status exec_fourier(const fm_op_s* op, bool adj, Elem e, const Batch& b, cons
   return FM_OK;
 }
 
+// Four-step convolution of a mixed length L = 4096 * n2 (n2 5-smooth, not a
+// power of two): rows formed from x with the strided n2-point DFT folded in
+// (n2 <= 2^conv_max_fuse()) or a separate strided pass, the 4096-point row
+// convolutions, then the strided inverse pass with the cropped store.
+fm_status exec_conv_mixed(const fm_op_s* op, bool adj, Elem e, const Batch& b, const void* x, void* y, bool acc,
+                          Workspace& ws, hipStream_t s) {
+  const Split& sp = split(op, e);
+  const int64_t L = op->L, n1 = 4096;
+  const int n2 = sp.n2;
+  const int64_t nin = in_rows(op, adj), nout = out_rows(op, adj);
+  Batch fb;
+  FM_CHECK_ARG(fold_outer(b, nin, nout, &fb) && fb.outer == 1, FM_E_UNSUPPORTED,
+               "convolution of mixed length %lld on an unpacked batch", (long long)L);
+  const void* twl = twiddle_table_L(e, L);
+  FM_CHECK_ARG(twl != nullptr, FM_E_DEVICE, "twiddle table unavailable: %s", last_error());
+  const size_t mk = ws.mark();
+  void* w = ws.take(size_t(fb.ncols * L) * elem_bytes(e));
+  FftLaunch fr;
+  fr.elem = e;
+  fr.logn = sp.log1;
+  fr.mode = FFT_CONV;
+  fr.b = Batch{fb.ncols, n2, 1, fb.ldx, 0, L, n1};
+  fr.out_limit = n1;
+  fr.spec = param(op, e);
+  fr.spec_ostride = n1;
+  fr.spec_conj = adj;
+  fr.tw_log = 1;  // twiddle epilogue from twl
+  fr.tw_inv = 1;
+  fr.twl = twl;
+  if (n2 <= (1 << conv_max_fuse())) {
+    fr.x = x;
+    fr.in_limit = nin;
+    fr.fuse_n2 = n2;
+  } else {
+    LAUNCH(launch_mixed(e, n2, 0, fb.ncols, x, fb.ldx, nin, w, L, L, twl, L, 0, s));
+    fr.b = Batch{fb.ncols, n2, 1, L, n1, L, n1};
+    fr.x = w;
+    fr.in_limit = n1;
+  }
+  fr.y = w;
+  LAUNCH(launch_fft(fr, s));
+  LAUNCH(launch_mixed(e, n2, 1, fb.ncols, w, L, L, y, fb.ldy, nout, twl, L, acc ? 1 : 0, s));
+  ws.release(mk);
+  return FM_OK;
+}
+
 // Cyclic convolution of length L with pad / crop (Circulant, Toeplitz):
 // y = crop(IFFT(spec .* FFT(pad(x)))), spec conj'ed for the adjoint.
 fm_status exec_conv(const fm_op_s* op, bool adj, Elem e, const Batch& b, const void* x, void* y,
@@ -127,6 +173,7 @@ fm_status exec_conv(const fm_op_s* op, bool adj, Elem e, const Batch& b, const v
   }
   FM_CHECK_ARG(b.inner == 1, FM_E_UNSUPPORTED, "convolution of length %lld along a strided axis",
                (long long)L);
+  if (sp.mixed()) return exec_conv_mixed(op, adj, e, b, x, y, acc, ws, s);
   const int64_t n1 = int64_t(1) << sp.log1, n2 = int64_t(1) << sp.log2;
   const size_t mk = ws.mark();
   void* w = ws.take(size_t(b.ncols * b.outer * L) * elem_bytes(e));

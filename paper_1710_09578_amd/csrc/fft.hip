@@ -3,6 +3,7 @@
 // engine of xform.h (one work-group = 4096 complex values).
 #include "kernels.h"
 #include "runtime.h"
+#include "mixed.h"
 #include "xform.h"
 
 namespace fm {
@@ -176,6 +177,76 @@ fm_status launch_fft(const FftLaunch& L, hipStream_t s) {
                              : nullptr;
   if (L.elem == Elem::C128) return launch_typed<double, 12>(L, ka, s);
   return launch_typed<float, 12>(L, ka, s);
+}
+
+// ---------------------------------------------------------------- mixed strided passes
+namespace {
+struct MArgs {
+  const void* x;
+  int64_t ldx, in_limit;
+  void* y;
+  int64_t ldy, out_limit;
+  const void* twl;
+  int64_t L, ncols;
+  int n2, inverse, acc;
+};
+
+// Tile blockIdx.x of every column (one or two threads per column position),
+// one instantiation per strided factor.
+template <typename R, int N2>
+__global__ __launch_bounds__(256) void mixed_kernel(MArgs a) {
+  extern __shared__ __align__(16) unsigned char mixed_lds[];
+  for (int64_t c = blockIdx.y; c < a.ncols; c += gridDim.y) {
+    const Cx<R>* x = static_cast<const Cx<R>*>(a.x) + c * a.ldx;
+    Cx<R>* y = static_cast<Cx<R>*>(a.y) + c * a.ldy;
+    mixed_tile_n<N2, R, NoEp>(int(blockIdx.x), x, a.in_limit, y, a.out_limit, a.inverse != 0,
+                              static_cast<const Cx<R>*>(a.twl), a.L, a.acc, static_cast<NoEp*>(nullptr),
+                              reinterpret_cast<Cx<R>*>(mixed_lds));
+    if constexpr (N2 > 12) __syncthreads();  // the pair buffers are reused by the next column
+  }
+}
+
+template <typename R>
+void launch_mixed_n(int n2, dim3 g, size_t lds, hipStream_t s, const MArgs& a) {
+  switch (n2) {
+#define FM_MIXED_LAUNCH(N) \
+  case N:                  \
+    hipLaunchKernelGGL((mixed_kernel<R, N>), g, dim3(256), lds, s, a); \
+    break;
+    FM_MIXED_LAUNCH(3)
+    FM_MIXED_LAUNCH(5)
+    FM_MIXED_LAUNCH(6)
+    FM_MIXED_LAUNCH(9)
+    FM_MIXED_LAUNCH(10)
+    FM_MIXED_LAUNCH(12)
+    FM_MIXED_LAUNCH(20)
+    FM_MIXED_LAUNCH(24)
+    FM_MIXED_LAUNCH(30)
+#undef FM_MIXED_LAUNCH
+    default:
+      break;
+  }
+}
+}  // namespace
+
+fm_status launch_mixed(Elem e, int n2, int inverse, int64_t ncols, const void* x, int64_t ldx, int64_t in_limit,
+                       void* y, int64_t ldy, int64_t out_limit, const void* twl, int64_t L, int acc, hipStream_t s) {
+  if (ncols == 0) return FM_OK;
+  FM_CHECK_ARG(mixed_n2_ok(n2) && L == int64_t(4096) * n2, FM_E_UNSUPPORTED, "mixed pass: strided factor %d", n2);
+  FM_CHECK_ARG(twl != nullptr, FM_E_INVALID, "mixed pass: no twiddle table");
+  MArgs a{x, ldx, in_limit, y, ldy, out_limit, twl, L, ncols, n2, inverse, acc};
+  const dim3 g(unsigned(mixed_tiles(n2)), unsigned(ncols < 65535 ? ncols : 65535));
+  const size_t lds = mixed_threads(n2) > 1 ? size_t(256 / mixed_threads(n2)) * n2 * elem_bytes(e) : 0;
+  if (e == Elem::C64)
+    launch_mixed_n<float>(n2, g, lds, s, a);
+  else if (e == Elem::C128)
+    launch_mixed_n<double>(n2, g, lds, s, a);
+  else {
+    set_error("mixed pass: integer element type");
+    return FM_E_DTYPE;
+  }
+  FM_LAUNCHED();
+  return FM_OK;
 }
 
 // ---------------------------------------------------------------- transpose

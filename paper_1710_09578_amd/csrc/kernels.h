@@ -56,6 +56,15 @@ struct FftLaunch {
 };
 fm_status launch_fft(const FftLaunch& L, hipStream_t s);
 
+// Strided pass of a mixed four-step length L = 4096 * n2 (n2 5-smooth, not a
+// power of two) for ncols columns: forward (inverse = 0) takes the n2 points
+// x[n1 + 4096 j] of every column position n1 (zero at or beyond in_limit),
+// their DFT times W_L^(n1 k2) into y[n1 + 4096 k2]; inverse takes the slot's
+// points, their inverse DFT, stored (added with acc) where n1 + 4096 k <
+// out_limit. twl: the W_L table (twiddle_table_L).
+fm_status launch_mixed(Elem e, int n2, int inverse, int64_t ncols, const void* x, int64_t ldx, int64_t in_limit,
+                       void* y, int64_t ldy, int64_t out_limit, const void* twl, int64_t L, int acc, hipStream_t s);
+
 // Column-wise transpose of a row-major rows x cols matrix per column block:
 // y[c*ldy + j*rows + i] (+)= x[c*ldx + i*cols + j].
 fm_status launch_transpose(Elem e, int64_t ncols, int64_t rows, int64_t cols, const void* x,

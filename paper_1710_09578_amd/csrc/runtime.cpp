@@ -74,6 +74,25 @@ Split split_for(Elem e, int logL) {
     s.log1 = lim;
     s.log2 = logL - lim;
   }
+  s.n2 = 1 << s.log2;
+  return s;
+}
+
+bool mixed_n2_ok(int n2) {
+  switch (n2) {
+    case 3: case 5: case 6: case 9: case 10: case 12: case 20: case 24: case 30:
+      return true;
+    default:
+      return false;
+  }
+}
+
+Split split_mixed(int64_t L) {
+  Split s;
+  s.logL = -1;
+  s.log1 = 12;
+  s.log2 = -1;
+  s.n2 = int(L >> 12);
   return s;
 }
 
@@ -87,6 +106,8 @@ struct Tables {
 };
 std::mutex g_tw_mu;
 std::map<int, Tables> g_tw;
+
+}  // namespace
 
 // exp(-2 pi j k / size), reduced to an angle of at most pi/4 before calling
 // cos/sin, then rotated by whole quadrants (exact).
@@ -121,7 +142,6 @@ void root_of_unity(int64_t k, int64_t size, double* re, double* im) {
   *re = c;
   *im = (s == 0.0) ? 0.0 : -s;
 }
-}  // namespace
 
 const void* twiddle_table(Elem e, int logmax) {
   if (logmax > kTwiddleLogMax) {
@@ -164,6 +184,50 @@ const void* twiddle_table(Elem e, int logmax) {
     t.t32 = d32;
   }
   return e == Elem::C64 ? t.t32 : t.t64;
+}
+
+namespace {
+struct MixedTables {
+  std::map<int64_t, void*> t32, t64;
+};
+std::map<int, MixedTables> g_twm;
+}  // namespace
+
+const void* twiddle_table_L(Elem e, int64_t L) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    set_error("twiddle table: hipGetDevice failed");
+    return nullptr;
+  }
+  if (L % 4096 != 0 || !mixed_n2_ok(int(L / 4096))) {
+    set_error("twiddle table: unsupported mixed length %lld", (long long)L);
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_tw_mu);
+  MixedTables& mt = g_twm[dev];
+  auto& slot = e == Elem::C64 ? mt.t32 : mt.t64;
+  auto it = slot.find(L);
+  if (it != slot.end()) return it->second;
+  std::vector<double> h64(size_t(2 * L));
+  std::vector<float> h32(size_t(2 * L));
+  for (int64_t k = 0; k < L; ++k) {
+    double re, im;
+    root_of_unity(k, L, &re, &im);
+    h64[2 * k] = re;
+    h64[2 * k + 1] = im;
+    h32[2 * k] = float(re);
+    h32[2 * k + 1] = float(im);
+  }
+  void* d = nullptr;
+  const size_t bytes = e == Elem::C64 ? h32.size() * sizeof(float) : h64.size() * sizeof(double);
+  const void* src = e == Elem::C64 ? static_cast<const void*>(h32.data()) : static_cast<const void*>(h64.data());
+  if (hipMalloc(&d, bytes) != hipSuccess || hipMemcpy(d, src, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+    if (d) (void)hipFree(d);
+    set_error("twiddle table: allocation or upload failed");
+    return nullptr;
+  }
+  slot[L] = d;
+  return d;
 }
 
 // ---------------------------------------------------------------- live handles

@@ -16,6 +16,9 @@ namespace fm {
 // in FP64 on the host with exact octant reduction and rounded once for
 // complex64. Returns nullptr on failure (error text set).
 const void* twiddle_table(Elem e, int logmax);
+// exp(-2 pi j k / size) in FP64 (angle reduced to at most pi/4, then exact
+// quadrant rotations); size 1, 2 or a multiple of 4.
+void root_of_unity(int64_t k, int64_t size, double* re, double* im);
 
 // Owned device allocation.
 struct DevBuf {
@@ -49,13 +52,26 @@ enum class Kind {
 };
 
 // Split of a cyclic length L for one element type: L <= LDS limit runs in one
-// work-group (n2 == 0); otherwise L = n1 * n2 (four-step, n1 contiguous).
+// work-group (n2 == 1); otherwise L = n1 * n2 (four-step, n1 = 2^log1
+// contiguous). n2 is a power of two (log2 = log2 n2) or, for a mixed length,
+// one of 3, 5, 6, 9, 10, 12, 20, 24, 30 (log2 = -1, logL = -1).
 struct Split {
   int logL = 0;
   int log1 = 0, log2 = 0;
-  bool four_step() const { return log2 > 0; }
+  int n2 = 1;
+  bool four_step() const { return n2 > 1; }
+  bool mixed() const { return n2 > 1 && (n2 & (n2 - 1)) != 0; }
 };
 Split split_for(Elem e, int logL);
+// Split of a mixed four-step length L = 4096 * n2 (n2 not a power of two).
+Split split_mixed(int64_t L);
+// Four-step strided factors that are not powers of two and have strided
+// passes (3, 5, 6, 9, 10, 12, 20, 24, 30).
+bool mixed_n2_ok(int n2);
+// Table of W_L^m = exp(-2 pi j m / L), 0 <= m < L, for a mixed length
+// L = 4096 * n2, generated in FP64 with exact quadrant reduction and rounded
+// once for complex64; cached per device. NULL on failure (error text set).
+const void* twiddle_table_L(Elem e, int64_t L);
 
 }  // namespace fm
 

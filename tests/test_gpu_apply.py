@@ -114,6 +114,30 @@ def test_toeplitz_dense(gpu, prec, m, n):
 
 
 @pytest.mark.parametrize("prec", ["c64", "c128"])
+@pytest.mark.parametrize("m,n,n2", [(5000, 5000, 3), (3000, 7000, 3), (9000, 9000, 5), (11000, 11000, 6),
+                                    (17000, 17000, 9), (20000, 20000, 10), (23000, 23000, 12),
+                                    (27000, 27000, 16), (36000, 36000, 20), (50000, 20000, 20),
+                                    (45000, 45000, 24), (55000, 55000, 30)])
+def test_toeplitz_mixed_embedding(gpu, prec, m, n, n2):
+    """Toeplitz operators whose embedding length is 4096 * n2 with n2 not a
+    power of two (the smallest admissible length >= m + n - 1): folded rows
+    (n2 <= 8), separate strided passes, two threads per column (n2 >= 20);
+    forward, adjoint and the accumulate path, against the FP64 FFT oracle."""
+    assert 4096 * n2 >= m + n - 1 > 4096 * max(v for v in (1, 2, 3, 4, 5, 6, 8, 9, 10, 12, 16, 20, 24)
+                                                if 4096 * v < m + n - 1)
+    rng = np.random.default_rng(m + 7 * n)
+    col, row = crandn(rng, m, NP[prec]), crandn(rng, n, NP[prec])
+    op = gpu.Toeplitz(to_dev(col), to_dev(row))
+    for adj in (False, True):
+        x = crandn(rng, (3, m if adj else n), NP[prec])
+        y = to_host(op.apply(to_dev(x), adjoint=adj))
+        assert rel_err(y, structured.toeplitz_apply_fft64(col, row, x, adj)) <= TOL[prec], adj
+    x = crandn(rng, (2, n), NP[prec])
+    y = to_host(gpu.Sum(op, op) @ to_dev(x))
+    assert rel_err(y, 2 * structured.toeplitz_apply_fft64(col, row, x)) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
 @pytest.mark.parametrize("m,n", [(4097, 4097), (9000, 6000), (20000, 20000), (40000, 40000), (65536, 65536)])
 def test_toeplitz_large(gpu, prec, m, n):
     rng = np.random.default_rng(m + 3 * n)

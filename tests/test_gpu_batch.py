@@ -125,6 +125,16 @@ def fista_batch_problem(gpu, sizes, ncols, seed):
     return ops, data
 
 
+def embedding_length(need):
+    """The documented Toeplitz embedding: the smallest L >= need among the
+    powers of two and, above 4096, 4096 * n2 for n2 in 3, 5, 6, 9, 10, 12,
+    20, 24, 30."""
+    cands = [1 << int(np.ceil(np.log2(need)))]
+    if need > 4096:
+        cands += [4096 * n2 for n2 in (3, 5, 6, 9, 10, 12, 20, 24, 30) if 4096 * n2 >= need]
+    return min(cands)
+
+
 def test_batch_fista_equals_plain_and_oracle(gpu):
     sizes = [300, 1000, 3000, 5000, 20000]
     ncols = [3, 2, 0, 2, 2]
@@ -141,7 +151,7 @@ def test_batch_fista_equals_plain_and_oracle(gpu):
         # the bound max |DFT(g)|^2 is at least ||T||^2 (here compared to the
         # spectrum of the embedding computed by the oracle)
         m = col.size
-        Lemb = 1 << int(np.ceil(np.log2(m + row.size - 1)))
+        Lemb = embedding_length(m + row.size - 1)
         g = np.zeros(Lemb, np.complex128)
         g[:m] = col
         g[Lemb - row.size + 1:] = row[1:][::-1]
