@@ -60,13 +60,6 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def next_pow2(v):
-    p = 1
-    while p < v:
-        p <<= 1
-    return p
-
-
 def setup_toeplitz(nops, device):
     import torch
 
@@ -88,7 +81,7 @@ def setup_toeplitz(nops, device):
     torch.cuda.synchronize()
     sizes = data["sizes"]
     ncols = data["ncols"]
-    Ls = np.array([next_pow2(2 * int(n) - 1) for n in sizes])
+    Ls = np.array([op.transform_length for op in ops])
     alg_bytes = int(np.sum(2 * (2 * sizes * ncols * 8) + 2 * Ls * 8))
     return {"ops": ops, "xs": xs, "ys": ys, "zs": zs, "sizes": sizes, "ncols": ncols,
             "Ls": Ls, "alg_bytes": alg_bytes, "data": data}
@@ -586,7 +579,7 @@ def main():
         del src, dst
     w = setup_toeplitz(args.nops, dev)
     alg = w["alg_bytes"]
-    log(f"algorithmic bytes per fwd+adj step: {alg / 1e9:.3f} GB")
+    log(f"algorithmic bytes per fwd+adj step: {alg / 1e9:.3f} GB ({alg} B)")
 
     plain_step, _ws = plain_step_factory(w)
     plain_ms, _ = time_steps(plain_step, max(2, args.steps // 4), 1)

@@ -217,6 +217,15 @@ fm_status fm_op_set_path(fm_op a, int32_t path);
 
 fm_status fm_op_shape(fm_op a, int64_t* m, int64_t* n, fm_dtype* dt);
 
+/* Cyclic length L the operator's transforms run at (section "Circulant
+ * Matrices", eq. (5), and the Toeplitz embedding of eq. (7)): n for Fourier
+ * and power-of-two Circulant, the embedding length for Toeplitz (the rule
+ * stated at fm_op_create_toeplitz; a Circulant whose size is not a power of
+ * two is built as a Toeplitz and reports its embedding; a Fourier whose size
+ * is not a power of two runs as D T D with a Toeplitz T and reports T's), 0
+ * for every other kind. *L must not be NULL. */
+fm_status fm_op_transform_length(fm_op a, int64_t* L);
+
 /* Drops one reference; storage is freed when the last reference goes. */
 fm_status fm_op_release(fm_op a);
 

@@ -108,6 +108,7 @@ SIGNATURES = {
     "fm_op_calibrate": (ST, [P, I64, C.POINTER(I32), C.POINTER(C.c_double), C.POINTER(C.c_double), P]),
     "fm_op_set_path": (ST, [P, I32]),
     "fm_op_shape": (ST, [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(C.c_int)]),
+    "fm_op_transform_length": (ST, [P, C.POINTER(I64)]),
     "fm_op_release": (ST, [P]),
     "fm_workspace_size": (ST, [P, C.c_int, I64, C.POINTER(C.c_size_t)]),
     "fm_apply": (ST, [P, C.c_int, I64, P, I64, P, I64, P, C.c_size_t, P]),
@@ -302,6 +303,12 @@ def fm_op_shape(a):
     m, n, dt = I64(), I64(), C.c_int()
     _call("fm_op_shape", a, C.byref(m), C.byref(n), C.byref(dt))
     return m.value, n.value, dt.value
+
+
+def fm_op_transform_length(a):
+    L = I64()
+    _call("fm_op_transform_length", a, C.byref(L))
+    return L.value
 
 
 def fm_op_release(a):

@@ -962,6 +962,19 @@ fm_status fm_op_shape(fm_op a, int64_t* m, int64_t* n, fm_dtype* dt) {
   return FM_OK;
 }
 
+fm_status fm_op_transform_length(fm_op a, int64_t* L) {
+  set_error("");
+  CHECK_LIVE(a);
+  FM_CHECK_ARG(L != nullptr, FM_E_INVALID, "NULL output");
+  const fm_op_s* c = a;
+  if (c->kind == Kind::Fourier && !c->terms.empty())  // Bluestein: the product D T D
+    for (const fm_op_s* t : c->terms[0]->terms)
+      if (t->kind == Kind::Toeplitz) c = t;
+  const bool cyclic = c->kind == Kind::Fourier || c->kind == Kind::Circulant || c->kind == Kind::Toeplitz;
+  *L = cyclic ? c->L : 0;
+  return FM_OK;
+}
+
 fm_status fm_op_release(fm_op a) {
   set_error("");
   CHECK_LIVE(a);

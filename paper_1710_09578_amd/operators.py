@@ -56,6 +56,12 @@ class Operator:
     def handle(self):
         return self._h
 
+    @property
+    def transform_length(self):
+        """Cyclic length of the operator's transforms (the embedding length
+        for Toeplitz), 0 for kinds without one."""
+        return capi.fm_op_transform_length(self._h)
+
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None:

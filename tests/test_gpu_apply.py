@@ -128,6 +128,7 @@ def test_toeplitz_mixed_embedding(gpu, prec, m, n, n2):
     rng = np.random.default_rng(m + 7 * n)
     col, row = crandn(rng, m, NP[prec]), crandn(rng, n, NP[prec])
     op = gpu.Toeplitz(to_dev(col), to_dev(row))
+    assert op.transform_length == 4096 * n2
     for adj in (False, True):
         x = crandn(rng, (3, m if adj else n), NP[prec])
         y = to_host(op.apply(to_dev(x), adjoint=adj))
@@ -135,6 +136,32 @@ def test_toeplitz_mixed_embedding(gpu, prec, m, n, n2):
     x = crandn(rng, (2, n), NP[prec])
     y = to_host(gpu.Sum(op, op) @ to_dev(x))
     assert rel_err(y, 2 * structured.toeplitz_apply_fft64(col, row, x)) <= TOL[prec]
+
+
+def test_transform_length(gpu):
+    """The cyclic length each kind reports: n for power-of-two Fourier and
+    Circulant, the embedding length for Toeplitz (power of two up to 4096,
+    then the smaller of the power of two and 4096 * n2) and for the sizes
+    served through one, 0 otherwise."""
+    rng = np.random.default_rng(2)
+
+    def toep(m, n):
+        return gpu.Toeplitz(to_dev(crandn(rng, m, np.complex64)), to_dev(crandn(rng, n, np.complex64)))
+
+    assert gpu.Fourier(256).transform_length == 256
+    assert gpu.Circulant(to_dev(crandn(rng, 512, np.complex64))).transform_length == 512
+    assert toep(100, 100).transform_length == 256
+    assert toep(2049, 2048).transform_length == 4096
+    assert toep(2049, 2049).transform_length == 8192  # 8192 < 3 * 4096
+    assert toep(5000, 5000).transform_length == 3 * 4096
+    assert toep(6145, 6145).transform_length == 16384
+    assert toep(40000, 40000).transform_length == 20 * 4096
+    assert toep(65536, 65536).transform_length == 131072
+    assert gpu.Circulant(to_dev(crandn(rng, 1000, np.complex64))).transform_length == 2048
+    assert gpu.Diag(to_dev(crandn(rng, 8, np.complex64))).transform_length == 0
+    assert gpu.Fourier(12).transform_length == 32  # Bluestein: Toeplitz 12 x 12, 23 <= 32
+    assert gpu.Fourier(3001).transform_length == 8192
+    assert gpu.Hadamard(64).transform_length == 0
 
 
 @pytest.mark.parametrize("prec", ["c64", "c128"])
