@@ -208,13 +208,13 @@ __device__ __forceinline__ void run_single(const BArgs& a, const Item& it, int l
   if constexpr (EPI == 1) {
     const User u = a.epi.user[it.op];
     ResidualEp ep{u.b + int64_t(it.col) * u.ldb, u.ldb};
-    run_job<float, false, LOGW>(jb, md, lg, smem, a.tw, &ep);
+    run_job<float, false, LOGW, true>(jb, md, lg, smem, a.tw, &ep);
   } else if constexpr (EPI == 2) {
     FistaEp ep = make_fista_ep<EPI>(a, it.op, it.col, false, lg);
-    run_job<float, false, LOGW>(jb, md, lg, smem, a.tw, &ep);
+    run_job<float, false, LOGW, true>(jb, md, lg, smem, a.tw, &ep);
     fista_partials(ep, false, lg, it.sub, 0, smem);
   } else {
-    run_job<float, false, LOGW>(jb, md, lg, smem, a.tw);
+    run_job<float, false, LOGW, true>(jb, md, lg, smem, a.tw);
   }
 }
 
@@ -244,7 +244,7 @@ __device__ __forceinline__ void run_strided(const BArgs& a, const Item& it, cons
     jb.in_limit = a.adj ? op.m : op.n;
     jb.out_limit = L;
     const Mode md{FFT_FWD, 0, op.logL, 0, 0};
-    run_job<float, true, kLogW>(jb, md, lg, smem, a.tw);
+    run_job<float, true, kLogW, true>(jb, md, lg, smem, a.tw);
   } else {
     jb.x = w + i0;
     jb.y = pt.y + int64_t(fc.col) * pt.ldy + i0;
@@ -254,13 +254,13 @@ __device__ __forceinline__ void run_strided(const BArgs& a, const Item& it, cons
     if constexpr (EPI == 1) {
       const User u = a.epi.user[fc.op];
       ResidualEp ep{u.b + int64_t(fc.col) * u.ldb, 0};
-      run_job<float, true, kLogW>(jb, md, lg, smem, a.tw, &ep);
+      run_job<float, true, kLogW, true>(jb, md, lg, smem, a.tw, &ep);
     } else if constexpr (EPI == 2) {
       FistaEp ep = make_fista_ep<EPI>(a, fc.op, fc.col, true, lg);
-      run_job<float, true, kLogW>(jb, md, lg, smem, a.tw, &ep);
+      run_job<float, true, kLogW, true>(jb, md, lg, smem, a.tw, &ep);
       fista_partials(ep, true, lg, tpw, it.sub, smem);
     } else {
-      run_job<float, true, kLogW>(jb, md, lg, smem, a.tw);
+      run_job<float, true, kLogW, true>(jb, md, lg, smem, a.tw);
     }
   }
 }
@@ -292,7 +292,7 @@ __device__ __forceinline__ void run_row(const BArgs& a, const Item& it, const Fs
   jb.sbstride = 0;
   jb.q0 = it.sub;
   const Mode md{FFT_CONV, a.adj, op.logL, 1, 0};
-  run_job<float, false, kLogW>(jb, md, kLog1, smem, a.tw);
+  run_job<float, false, kLogW, true>(jb, md, kLog1, smem, a.tw);
 }
 
 // MX1 / MX3: tile `sub` of the strided pass of a mixed-length column (first:
@@ -326,9 +326,11 @@ __device__ __forceinline__ void run_mixed(const BArgs& a, const Item& it, const 
   }
 }
 
-// Waves per SIMD the stage kernel is compiled for (its register budget).
+// Waves per SIMD the stage kernel is compiled for (its register budget):
+// four fits the plain and residual forms in 128 VGPRs without spills; the
+// FISTA form spills a few registers and still measured faster than at three.
 #ifndef FM_STAGE_WAVES
-#define FM_STAGE_WAVES 3
+#define FM_STAGE_WAVES 4
 #endif
 
 template <int LOGW, int EPI>
