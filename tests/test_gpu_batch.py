@@ -232,6 +232,32 @@ def test_batch_tune(gpu):
         assert rel_err(to_host(zs[i]), structured.toeplitz_apply_fft64(col, row, x, True)) <= TOL["c64"]
 
 
+def test_batch_every_mixed_factor(gpu):
+    """One operator per strided factor n2 of the mixed embedding (N = 2048 n2,
+    so L = 4096 n2 exactly), under fold limits 2^0 (every factor through the
+    separate strided passes), 2^3 (the default: n2 <= 8 folded) and 2^5 (all
+    folded): forward and adjoint against the FP64 oracle, and at the default
+    limit bit-identical to the plain path."""
+    n2s = (3, 5, 6, 9, 10, 12, 20, 24, 30)
+    sizes = [2048 * n2 for n2 in n2s]
+    ncols = [1, 2, 1, 2, 1, 2, 1, 2, 1]
+    ops, data = build_batch(gpu, sizes, ncols, seed=21)
+    assert [op.transform_length for op in ops] == [4096 * n2 for n2 in n2s]
+    batch = gpu.Batch(ops, ncols)
+    xs = [to_dev(d[2]) for d in data]
+    for mf in (0, 3, 5):
+        batch.set_schedule(mf, 48)
+        ys = batch.apply(xs)
+        zs = batch.apply(xs, adjoint=True)
+        for i, (op, (col, row, x, u)) in enumerate(zip(ops, data)):
+            y_b, z_b = to_host(ys[i]), to_host(zs[i])
+            assert rel_err(y_b, structured.toeplitz_apply_fft64(col, row, x)) <= TOL["c64"], (mf, n2s[i])
+            assert rel_err(z_b, structured.toeplitz_apply_fft64(col, row, x, True)) <= TOL["c64"], (mf, n2s[i])
+            if mf == 3:
+                assert np.array_equal(y_b, to_host(op @ xs[i])), n2s[i]
+                assert np.array_equal(z_b, to_host(op.H @ xs[i])), n2s[i]
+
+
 def test_batch_set_schedule(gpu):
     from paper_1710_09578_amd import capi
 
