@@ -9,8 +9,8 @@ Throughput = algorithmic bytes / time, where the algorithmic bytes of one
 direction of operator i are: read x (N_i n_i 8 B) + write y (M_i n_i 8 B) +
 read the spectrum once (L_i 8 B).
 
-Prints one JSON line. ``--gpus N`` with N > 1 exits: this build measures one
-GPU.
+Prints one JSON line. ``--gpus N`` with N > 1 exits: the benchmark measures
+one GPU.
 """
 
 from __future__ import annotations
@@ -559,8 +559,8 @@ def main():
                     help="first copy 512 MiB device to device (reference for traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
-              "(the path shards over independent columns and operators, see DESIGN.md)",
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(the path would shard over independent columns and operators, one process per GPU)",
               file=sys.stderr)
         sys.exit(2)
 

@@ -56,7 +56,7 @@ typedef enum {
   FM_E_SHAPE = 2,       /* inconsistent shapes, ld < rows, index out of range */
   FM_E_DTYPE = 3,       /* dtype mismatch or not supported by this operator  */
   FM_E_ALIAS = 4,       /* x and y overlap                                    */
-  FM_E_UNSUPPORTED = 5, /* valid request this build does not implement        */
+  FM_E_UNSUPPORTED = 5, /* valid request the library does not implement       */
   FM_E_WORKSPACE = 6,   /* workspace given but smaller than fm_workspace_size */
   FM_E_NOMEM = 7,       /* device allocation failed                           */
   FM_E_DEVICE = 8,      /* HIP runtime error (launch failure, device fault)   */
