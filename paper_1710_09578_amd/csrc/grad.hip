@@ -30,18 +30,41 @@ __device__ __forceinline__ Cx<R> soft(Cx<R> z, R s) {
   return {z.x * f, z.y * f};
 }
 
-// P[f] (+)= scale * sum_j A_j[f] conj(B_j[f]) over the columns of one chunk,
-// in column order (deterministic).
+// Column-summed spectral products of one chunk in two deterministic passes:
+// group g = blockIdx.y of the columns [g cpg, (g + 1) cpg) gives
+// part[g][f] = sum_j A_j[f] conj(B_j[f]) in column order; then
+// P[f] (+)= scale * sum_g part[g][f] in group order. The groups spread the
+// chunk over the chip (one thread per frequency alone leaves most CUs idle).
 template <typename R>
-__global__ __launch_bounds__(kTPB) void corr_reduce_kernel(int64_t n, int64_t ncols, const Cx<R>* __restrict__ A,
-                                                           const Cx<R>* __restrict__ B, R scale, Cx<R>* P,
-                                                           int accumulate) {
+__global__ __launch_bounds__(kTPB) void corr_part_kernel(int64_t n, int64_t ncols, int64_t cpg,
+                                                         const Cx<R>* __restrict__ A, const Cx<R>* __restrict__ B,
+                                                         Cx<R>* __restrict__ part) {
+  const int64_t f = int64_t(blockIdx.x) * kTPB + threadIdx.x;
+  if (f >= n) return;
+  const int64_t j0 = int64_t(blockIdx.y) * cpg;
+  const int64_t j1 = j0 + cpg < ncols ? j0 + cpg : ncols;
+  Cx<R> acc = {R(0), R(0)};
+  for (int64_t j = j0; j < j1; ++j) acc = cadd(acc, cmulc(A[j * n + f], B[j * n + f]));
+  part[int64_t(blockIdx.y) * n + f] = acc;
+}
+
+template <typename R>
+__global__ __launch_bounds__(kTPB) void corr_sum_kernel(int64_t n, int64_t ngroups, const Cx<R>* __restrict__ part,
+                                                        R scale, Cx<R>* P, int accumulate) {
   const int64_t f = int64_t(blockIdx.x) * kTPB + threadIdx.x;
   if (f >= n) return;
   Cx<R> acc = {R(0), R(0)};
-  for (int64_t j = 0; j < ncols; ++j) acc = cadd(acc, cmulc(A[j * n + f], B[j * n + f]));
+  for (int64_t g = 0; g < ngroups; ++g) acc = cadd(acc, part[g * n + f]);
   acc = cscale(acc, scale);
   P[f] = accumulate ? cadd(P[f], acc) : acc;
+}
+
+// Column groups for n frequencies and nc columns: about 2048 work-groups
+// in the first pass, at least 4 columns per group.
+int64_t corr_groups(int64_t n, int64_t nc) {
+  const int64_t tiles = cdiv(n, kTPB);
+  const int64_t want = std::max<int64_t>(1, 2048 / tiles);
+  return std::max<int64_t>(1, std::min<int64_t>(want, cdiv(nc, 4)));
 }
 
 struct StepArgs {
@@ -326,6 +349,7 @@ fm_status fm_circulant_grad_generator(int64_t n, int64_t ncols, fm_dir use, cons
   } rel{F};
   // columns per chunk: two spectra blocks of at most 256 MiB together
   const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(ncols, (int64_t(256) << 20) / (2 * n * int64_t(es))));
+  const int64_t maxg = corr_groups(n, chunk);
   Workspace sz;
   sz.sizing = true;
   {
@@ -336,35 +360,51 @@ fm_status fm_circulant_grad_generator(int64_t n, int64_t ncols, fm_dir use, cons
     sz.sizing = true;
     sz.take(size_t(2 * chunk * n) * es);
     sz.take(size_t(n) * es);
+    sz.take(size_t(maxg * n) * es);
     sz.take(fft_ws);
   }
-  DevBuf wsb;
-  FM_TRY(wsb.alloc(sz.peak));
+  // stream-ordered workspace: released after the last kernel that reads it,
+  // without a host wait
+  void* base = nullptr;
+  FM_HIP(hipMallocAsync(&base, sz.peak, s));
+  struct FreeAsync {
+    void* p;
+    hipStream_t s;
+    ~FreeAsync() { (void)hipFreeAsync(p, s); }
+  } fr{base, s};
   Workspace w;
-  w.base = static_cast<char*>(wsb.p);
-  w.cap = wsb.bytes;
+  w.base = static_cast<char*>(base);
+  w.cap = sz.peak;
   void* A = w.take(size_t(chunk * n) * es);
   void* B = w.take(size_t(chunk * n) * es);
   void* P = w.take(size_t(n) * es);
+  void* part = w.take(size_t(maxg * n) * es);
   for (int64_t c0 = 0; c0 < ncols; c0 += chunk) {
     const int64_t nc = std::min(chunk, ncols - c0);
     Batch ba{nc, 1, 1, lda, n, n, n};
     Batch bb{nc, 1, 1, ldb, n, n, n};
     FM_TRY(exec(F, false, e, ba, static_cast<const char*>(pa) + size_t(c0 * lda) * es, A, false, w, s));
     FM_TRY(exec(F, false, e, bb, static_cast<const char*>(pb) + size_t(c0 * ldb) * es, B, false, w, s));
-    const dim3 grid(unsigned(cdiv(n, kTPB)));
-    if (dt == FM_C64)
-      hipLaunchKernelGGL(corr_reduce_kernel<float>, grid, dim3(kTPB), 0, s, n, nc, static_cast<const c64*>(A),
-                         static_cast<const c64*>(B), float(1.0 / double(n)), static_cast<c64*>(P), int(c0 > 0));
-    else
-      hipLaunchKernelGGL(corr_reduce_kernel<double>, grid, dim3(kTPB), 0, s, n, nc, static_cast<const c128*>(A),
-                         static_cast<const c128*>(B), 1.0 / double(n), static_cast<c128*>(P), int(c0 > 0));
+    const int64_t ng = corr_groups(n, nc);
+    const int64_t cpg = cdiv(nc, ng);
+    const int64_t ngu = cdiv(nc, cpg);  // groups that hold columns
+    const dim3 g1(unsigned(cdiv(n, kTPB)), unsigned(ngu)), g2(unsigned(cdiv(n, kTPB)));
+    if (dt == FM_C64) {
+      hipLaunchKernelGGL(corr_part_kernel<float>, g1, dim3(kTPB), 0, s, n, nc, cpg, static_cast<const c64*>(A),
+                         static_cast<const c64*>(B), static_cast<c64*>(part));
+      hipLaunchKernelGGL(corr_sum_kernel<float>, g2, dim3(kTPB), 0, s, n, ngu, static_cast<const c64*>(part),
+                         float(1.0 / double(n)), static_cast<c64*>(P), int(c0 > 0));
+    } else {
+      hipLaunchKernelGGL(corr_part_kernel<double>, g1, dim3(kTPB), 0, s, n, nc, cpg, static_cast<const c128*>(A),
+                         static_cast<const c128*>(B), static_cast<c128*>(part));
+      hipLaunchKernelGGL(corr_sum_kernel<double>, g2, dim3(kTPB), 0, s, n, ngu, static_cast<const c128*>(part),
+                         1.0 / double(n), static_cast<c128*>(P), int(c0 > 0));
+    }
     FM_LAUNCHED();
   }
   // grad_c (+)= unnormalised inverse DFT of P (the 1/n is already in P)
   Batch b1{1, 1, 1, n, n, n, n};
   FM_TRY(exec(F, true, e, b1, P, grad_c, accumulate != 0, w, s));
-  FM_HIP(hipStreamSynchronize(s));  // the workspace is freed on return
   return FM_OK;
 }
 
