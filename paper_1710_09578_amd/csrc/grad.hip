@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "kernels.h"
 #include "runtime.h"
 #include "solve.h"
 
@@ -65,6 +66,62 @@ int64_t corr_groups(int64_t n, int64_t nc) {
   const int64_t tiles = cdiv(n, kTPB);
   const int64_t want = std::max<int64_t>(1, 2048 / tiles);
   return std::max<int64_t>(1, std::min<int64_t>(want, cdiv(nc, 4)));
+}
+
+// Four-step lengths (L = n1 n2 above one work-group): the correlation only
+// needs the column-summed products of two spectra, so both spectra stay in
+// the split's own order, X[k2 + n2 k1] at k1 + n1 k2, and the sum returns to
+// natural order through the inverse passes, with no transposes.
+// Forward DFT of nc columns of x (leading dimension ldx) into w (ld L).
+fm_status dft_split_order(Elem e, const Split& sp, int64_t nc, const void* x, int64_t ldx, void* w,
+                          hipStream_t s) {
+  const int64_t L = int64_t(1) << sp.logL, n1 = int64_t(1) << sp.log1, n2 = int64_t(1) << sp.log2;
+  FftLaunch f1;  // length-n2 transforms at stride n1, then W_L^(k2 n1)
+  f1.elem = e;
+  f1.logn = sp.log2;
+  f1.mode = FFT_FWD;
+  f1.b = Batch{nc, 1, n1, ldx, 0, L, 0};
+  f1.x = x;
+  f1.y = w;
+  f1.in_limit = f1.out_limit = L;
+  f1.tw_log = sp.logL;
+  FM_TRY(launch_fft(f1, s));
+  FftLaunch f2;  // contiguous length-n1 transforms of the rows, in place
+  f2.elem = e;
+  f2.logn = sp.log1;
+  f2.mode = FFT_FWD;
+  f2.b = Batch{nc, n2, 1, L, n1, L, n1};
+  f2.x = w;
+  f2.y = w;
+  f2.in_limit = f2.out_limit = n1;
+  return launch_fft(f2, s);
+}
+
+// Unnormalised inverse DFT of one vector p held in the split's order (p is
+// overwritten) into y in natural order, y = result or y += result.
+fm_status idft_from_split_order(Elem e, const Split& sp, void* p, void* y, int acc, hipStream_t s) {
+  const int64_t L = int64_t(1) << sp.logL, n1 = int64_t(1) << sp.log1, n2 = int64_t(1) << sp.log2;
+  FftLaunch f2;  // inverse row transforms (k1 -> n1), then W_L^-(n1 k2)
+  f2.elem = e;
+  f2.logn = sp.log1;
+  f2.mode = FFT_INV;
+  f2.b = Batch{1, n2, 1, L, n1, L, n1};
+  f2.x = p;
+  f2.y = p;
+  f2.in_limit = f2.out_limit = n1;
+  f2.tw_log = sp.logL;
+  f2.tw_inv = 1;
+  FM_TRY(launch_fft(f2, s));
+  FftLaunch f3;  // inverse length-n2 transforms at stride n1 (k2 -> n2), natural order
+  f3.elem = e;
+  f3.logn = sp.log2;
+  f3.mode = FFT_INV;
+  f3.b = Batch{1, 1, n1, L, L, L, L};
+  f3.x = p;
+  f3.y = y;
+  f3.in_limit = f3.out_limit = L;
+  f3.accumulate = acc;
+  return launch_fft(f3, s);
 }
 
 struct StepArgs {
@@ -350,12 +407,17 @@ fm_status fm_circulant_grad_generator(int64_t n, int64_t ncols, fm_dir use, cons
   // columns per chunk: two spectra blocks of at most 256 MiB together
   const int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(ncols, (int64_t(256) << 20) / (2 * n * int64_t(es))));
   const int64_t maxg = corr_groups(n, chunk);
+  const Split sp = split_for(e, ilog2(n));
+  const bool split_order = sp.four_step();
   Workspace sz;
   sz.sizing = true;
   {
-    Batch b{chunk, 1, 1, n, n, n, n};
-    FM_TRY(exec(F, false, e, b, nullptr, nullptr, false, sz, s));
-    const size_t fft_ws = sz.peak;
+    size_t fft_ws = 0;
+    if (!split_order) {
+      Batch b{chunk, 1, 1, n, n, n, n};
+      FM_TRY(exec(F, false, e, b, nullptr, nullptr, false, sz, s));
+      fft_ws = sz.peak;
+    }
     sz = Workspace{};
     sz.sizing = true;
     sz.take(size_t(2 * chunk * n) * es);
@@ -383,8 +445,15 @@ fm_status fm_circulant_grad_generator(int64_t n, int64_t ncols, fm_dir use, cons
     const int64_t nc = std::min(chunk, ncols - c0);
     Batch ba{nc, 1, 1, lda, n, n, n};
     Batch bb{nc, 1, 1, ldb, n, n, n};
-    FM_TRY(exec(F, false, e, ba, static_cast<const char*>(pa) + size_t(c0 * lda) * es, A, false, w, s));
-    FM_TRY(exec(F, false, e, bb, static_cast<const char*>(pb) + size_t(c0 * ldb) * es, B, false, w, s));
+    const void* xa = static_cast<const char*>(pa) + size_t(c0 * lda) * es;
+    const void* xb = static_cast<const char*>(pb) + size_t(c0 * ldb) * es;
+    if (split_order) {
+      FM_TRY(dft_split_order(e, sp, nc, xa, lda, A, s));
+      FM_TRY(dft_split_order(e, sp, nc, xb, ldb, B, s));
+    } else {
+      FM_TRY(exec(F, false, e, ba, xa, A, false, w, s));
+      FM_TRY(exec(F, false, e, bb, xb, B, false, w, s));
+    }
     const int64_t ng = corr_groups(n, nc);
     const int64_t cpg = cdiv(nc, ng);
     const int64_t ngu = cdiv(nc, cpg);  // groups that hold columns
@@ -403,6 +472,7 @@ fm_status fm_circulant_grad_generator(int64_t n, int64_t ncols, fm_dir use, cons
     FM_LAUNCHED();
   }
   // grad_c (+)= unnormalised inverse DFT of P (the 1/n is already in P)
+  if (split_order) return idft_from_split_order(e, sp, P, grad_c, accumulate != 0, s);
   Batch b1{1, 1, 1, n, n, n, n};
   FM_TRY(exec(F, true, e, b1, P, grad_c, accumulate != 0, w, s));
   return FM_OK;

@@ -45,6 +45,22 @@ def test_generator_grad(gpu, prec, n, ncols, adjoint):
     assert rel_err(to_host(out), ref + base) <= TOL[prec]
 
 
+@pytest.mark.parametrize("prec,n,ncols", [("c64", 65536, 7), ("c128", 65536, 3), ("c64", 1 << 20, 20)])
+def test_generator_grad_four_step_sampled_lags(gpu, prec, n, ncols):
+    """Four-step lengths (spectra kept in the split's order) and, at 2^20
+    with 20 columns, more columns than one internal chunk: lags sampled from
+    the correlation's definition r[k] = sum_j sum_i a_j[i] conj(b_j[i - k])."""
+    rng = np.random.default_rng(n + ncols + 1)
+    inp, g = crandn(rng, (ncols, n), NP[prec]), crandn(rng, (ncols, n), NP[prec])
+    lags = np.concatenate([[0, 1, n - 1], rng.choice(np.arange(2, n - 1), 5, replace=False)])
+    for adjoint in (False, True):
+        a, b = (inp, g) if adjoint else (g, inp)
+        a64, b64 = a.astype(np.complex128), b.astype(np.complex128)
+        ref = np.array([np.sum(a64 * np.conj(np.roll(b64, k, axis=1))) for k in lags])
+        out = to_host(gpu.autograd.grad_generator(to_dev(inp), to_dev(g), adjoint))
+        assert rel_err(out[lags], ref) <= TOL[prec], adjoint
+
+
 def test_generator_grad_zero_columns_and_errors(gpu):
     import torch
 
