@@ -602,6 +602,10 @@ fm_status fm_op_create_select_rows(fm_op* out, int64_t n_in, int64_t m, const in
     FM_HIP(hipMemcpyAsync(&bad, static_cast<int*>(flags.p) + n_in, 4, hipMemcpyDeviceToHost, s));
     FM_HIP(hipStreamSynchronize(s));
     FM_CHECK_ARG(bad == 0, FM_E_SHAPE, "selection: indices must be distinct and in [0, n_in)");
+    FM_TRY(op->inv.alloc(size_t(n_in) * 4));
+    FM_TRY(launch_invert_indices(n_in, m, static_cast<const int32_t*>(op->idx.p), static_cast<int32_t*>(op->inv.p),
+                                 s));
+    FM_HIP(hipStreamSynchronize(s));
   }
   return publish(g.release(), out);
 }

@@ -170,6 +170,25 @@ __global__ __launch_bounds__(256) void scatter_kernel(int64_t m, Batch b, const 
   }
 }
 
+// Adjoint of a row selection in one pass over the output: y[r] = x[inv[r]]
+// where row r is selected (inv[r] >= 0), 0 elsewhere (nothing added with acc).
+template <typename V>
+__global__ __launch_bounds__(256) void expand_kernel(int64_t n_in, Batch b, const int32_t* __restrict__ inv,
+                                                     const V* __restrict__ x, V* y, int acc) {
+  const int64_t flat_n = n_in * b.inner;
+  const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (f >= flat_n) return;
+  const int64_t r = b.inner == 1 ? f : f / b.inner;
+  const int64_t i = f - r * b.inner;
+  const int32_t k = inv[r];
+  if (acc && k < 0) return;
+  for (int64_t p = blockIdx.y; p < b.ncols * b.outer; p += gridDim.y) {
+    const int64_t c = p / b.outer, o = p - c * b.outer;
+    const V v = k >= 0 ? x[c * b.ldx + o * b.xvs + int64_t(k) * b.inner + i] : V{};
+    store(y + c * b.ldy + o * b.yvs + f, v, acc);
+  }
+}
+
 template <typename V>
 __global__ __launch_bounds__(256) void copy_kernel(int64_t flat_n, Batch b, const V* __restrict__ x, V* y,
                                                    int acc) {
@@ -453,6 +472,18 @@ __global__ __launch_bounds__(256) void embed_kernel(int64_t m, int64_t n, int64_
   g[k] = v;
 }
 
+__global__ __launch_bounds__(256) void fill_i32_kernel(int64_t n, int32_t v, int32_t* __restrict__ a) {
+  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r < n) a[r] = v;
+}
+
+// inv[idx[r]] = r for distinct, in-range indices (checked before).
+__global__ __launch_bounds__(256) void invert_idx_kernel(int64_t m, const int32_t* __restrict__ idx,
+                                                         int32_t* __restrict__ inv) {
+  const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (r < m) inv[idx[r]] = int32_t(r);
+}
+
 __global__ __launch_bounds__(256) void check_idx_kernel(int64_t n, int64_t m, const int32_t* __restrict__ idx,
                                                         int* flags, int* bad) {
   const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -509,13 +540,17 @@ fm_status launch_diag(Elem e, int64_t n, const Batch& b, const void* d, int conj
   return FM_OK;
 }
 
-fm_status launch_select(Elem e, int64_t n_in, int64_t m, const int32_t* idx, int adjoint,
+fm_status launch_select(Elem e, int64_t n_in, int64_t m, const int32_t* idx, const int32_t* inv, int adjoint,
                         const Batch& b, const void* x, void* y, int acc, hipStream_t s) {
   if (b.ncols == 0) return FM_OK;
   if (!adjoint) {
     if (m == 0) return FM_OK;
     dim3 g = vec_grid(b.ncols * b.outer, m * b.inner, 256);
     FM_ELEM_SWITCH(e, V, hipLaunchKernelGGL(gather_kernel<V>, g, dim3(256), 0, s, m, b, idx,
+                                            (const V*)x, (V*)y, acc));
+  } else if (inv != nullptr && m > 0) {
+    dim3 g = vec_grid(b.ncols * b.outer, n_in * b.inner, 256);
+    FM_ELEM_SWITCH(e, V, hipLaunchKernelGGL(expand_kernel<V>, g, dim3(256), 0, s, n_in, b, inv,
                                             (const V*)x, (V*)y, acc));
   } else {
     if (!acc && n_in > 0) {
@@ -761,6 +796,16 @@ fm_status launch_toeplitz_embed(int64_t m, int64_t n, int64_t L, const void* col
   else
     hipLaunchKernelGGL(embed_kernel<c128>, gr, dim3(256), 0, s, m, n, L, (const c128*)col,
                        (const c128*)row, (c128*)g);
+  FM_LAUNCHED();
+  return FM_OK;
+}
+
+fm_status launch_invert_indices(int64_t n, int64_t m, const int32_t* idx, int32_t* inv, hipStream_t s) {
+  if (n == 0) return FM_OK;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(unsigned(cdiv(n, 256))), dim3(256), 0, s, n, int32_t(-1), inv);
+  FM_LAUNCHED();
+  if (m == 0) return FM_OK;
+  hipLaunchKernelGGL(invert_idx_kernel, dim3(unsigned(cdiv(m, 256))), dim3(256), 0, s, m, idx, inv);
   FM_LAUNCHED();
   return FM_OK;
 }

@@ -586,8 +586,8 @@ fm_status exec(const fm_op_s* op, bool adj, Elem e, const Batch& b, const void* 
       LAUNCH(launch_dense(e, op->m, op->n, param(op, e), op->lda, adj, op->real_entries, b, x, y, acc, s));
       return FM_OK;
     case Kind::Select:
-      LAUNCH(launch_select(e, op->n, op->m, static_cast<const int32_t*>(op->idx.p), adj, b, x, y,
-                           acc, s));
+      LAUNCH(launch_select(e, op->n, op->m, static_cast<const int32_t*>(op->idx.p),
+                           static_cast<const int32_t*>(op->inv.p), adj, b, x, y, acc, s));
       return FM_OK;
     case Kind::MLToeplitz:
       return exec_mltoeplitz(op, adj, e, b, x, y, acc, ws, s);

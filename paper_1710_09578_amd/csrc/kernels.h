@@ -89,9 +89,12 @@ fm_status launch_kron_fg(int lognf, int64_t m, int64_t n, const void* g, int64_t
 fm_status launch_diag(Elem e, int64_t n, const Batch& b, const void* d, int conj, const void* x,
                       void* y, int accumulate, hipStream_t s);
 // Row selection: forward y[r] (+)= x[idx[r]] (m outputs); adjoint y = 0 except
-// y[idx[r]] (+)= x[r] (n outputs).
-fm_status launch_select(Elem e, int64_t n_in, int64_t m, const int32_t* idx, int adjoint,
+// y[idx[r]] (+)= x[r] (n outputs), in one pass over y through inv (inv[idx[r]]
+// = r, -1 elsewhere) when inv is given.
+fm_status launch_select(Elem e, int64_t n_in, int64_t m, const int32_t* idx, const int32_t* inv, int adjoint,
                         const Batch& b, const void* x, void* y, int accumulate, hipStream_t s);
+// inv[0..n) = -1, then inv[idx[r]] = r for the m distinct, in-range indices.
+fm_status launch_invert_indices(int64_t n, int64_t m, const int32_t* idx, int32_t* inv, hipStream_t s);
 // Dense mode product y[:, o, :, i] (+)= op(A) x[:, o, :, i], A m x n col-major.
 // real_a: every entry of A has a zero imaginary part (only real parts used).
 fm_status launch_dense(Elem e, int64_t m, int64_t n, const void* a, int64_t lda, int adjoint, int real_a,

@@ -86,6 +86,7 @@ struct fm_op_s {
   // (always, for the FP64 power iteration)
   fm::DevBuf p32, p64;
   fm::DevBuf idx;          // selection indices
+  fm::DevBuf inv;          // Select: inv[idx[r]] = r, -1 for rows not selected
   int64_t lda = 0;         // dense: leading dimension of the stored copy (= m)
   bool real_entries = false;  // dense: every entry has a zero imaginary part
   int64_t L = 0;           // cyclic length (Fourier/Circulant/Toeplitz)
