@@ -26,7 +26,15 @@ struct KArgs {
   int64_t tiles;  // work-groups per column (layout 2) / per vector (strided)
 };
 
-template <typename R, bool STRIDED, int LOGW>
+constexpr int kXcdCount = 8;  // work-group g runs on XCD g mod 8
+// Fewest columns for which the rows of a column are grouped on one XCD: with
+// fewer, grouping leaves XCDs idle in a launch that is short anyway.
+#ifndef FM_XCD_GROUP_MIN_COLS
+#define FM_XCD_GROUP_MIN_COLS 64
+#endif
+
+// XG (layout 2 only): the work-groups of column c take the indices = c (mod 8).
+template <typename R, bool STRIDED, int LOGW, bool XG = false>
 __global__ __launch_bounds__(Geo<LOGW>::kThreads) void fft_kernel(KArgs a) {
   extern __shared__ unsigned char smem_raw[];
   Cx<R>* lds = reinterpret_cast<Cx<R>*>(smem_raw);
@@ -77,7 +85,13 @@ __global__ __launch_bounds__(Geo<LOGW>::kThreads) void fft_kernel(KArgs a) {
       jb.sbstride = 0;
       jb.q0 = 0;
     } else {  // work-groups inside one column
-      const int64_t c = blockIdx.x / a.tiles, o0 = (blockIdx.x % a.tiles) * tpw;
+      int64_t c = blockIdx.x / a.tiles, o0 = (blockIdx.x % a.tiles) * tpw;
+      if constexpr (XG) {  // rows of one column on one XCD, where they share it in L2
+        const int64_t g = blockIdx.x, r = g / kXcdCount;
+        c = (r / a.tiles) * kXcdCount + g % kXcdCount;
+        o0 = (r % a.tiles) * tpw;
+        if (c >= a.ncols) return;  // padding of the last group of 8 columns
+      }
       jb.x = X + c * a.ldx + o0 * a.xvs;
       jb.y = Y + c * a.ldy + o0 * a.yvs;
       jb.xbstride = a.xvs;
@@ -114,6 +128,9 @@ fm_status launch_typed(const FftLaunch& L, KArgs ka, hipStream_t s) {
     ka.tiles = cdiv(L.b.outer, tpw);
     blocks = L.b.ncols * ka.tiles;
   }
+  // the rows of a column re-read it: keep them on one XCD
+  const bool xg = !strided && ka.layout == 2 && L.fuse_n2 > 0 && L.b.ncols >= FM_XCD_GROUP_MIN_COLS;
+  if (xg) blocks = cdiv(L.b.ncols, kXcdCount) * kXcdCount * ka.tiles;
   FM_CHECK_ARG(blocks > 0 && blocks < (int64_t(1) << 31), FM_E_UNSUPPORTED,
                "fft: grid of %lld work-groups is out of range", (long long)blocks);
   FM_CHECK_ARG((int64_t(1) << L.logn) * L.b.inner < (int64_t(1) << 30), FM_E_UNSUPPORTED,
@@ -126,11 +143,16 @@ fm_status launch_typed(const FftLaunch& L, KArgs ka, hipStream_t s) {
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&fft_kernel<R, false, LOGW>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&fft_kernel<R, false, LOGW, true>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr_set = true;
   }
   const dim3 wg(Geo<LOGW>::kThreads);
   if (strided)
     hipLaunchKernelGGL((fft_kernel<R, true, LOGW>), dim3(unsigned(blocks)), wg, (job_lds_bytes<R, LOGW>()), s, ka);
+  else if (xg)
+    hipLaunchKernelGGL((fft_kernel<R, false, LOGW, true>), dim3(unsigned(blocks)), wg, (job_lds_bytes<R, LOGW>()), s,
+                       ka);
   else
     hipLaunchKernelGGL((fft_kernel<R, false, LOGW>), dim3(unsigned(blocks)), wg, (job_lds_bytes<R, LOGW>()), s, ka);
   FM_LAUNCHED();
