@@ -138,6 +138,27 @@ def test_toeplitz_mixed_embedding(gpu, prec, m, n, n2):
     assert rel_err(y, 2 * structured.toeplitz_apply_fft64(col, row, x)) <= TOL[prec]
 
 
+@pytest.mark.parametrize("kind,n,ncols", [("circulant", 16384, 64), ("circulant", 8192, 83),
+                                           ("toeplitz", 5000, 83), ("toeplitz", 12000, 70)])
+def test_folded_rows_wide_blocks(gpu, kind, n, ncols):
+    """Folded four-step rows on 64 or more columns, where the rows of each
+    column are placed on one XCD (83 columns: the last group of 8 is padded
+    with work-groups that exit): forward and adjoint against the FP64 FFT
+    oracle, complex64."""
+    rng = np.random.default_rng(n + ncols)
+    x = crandn(rng, (ncols, n))
+    if kind == "circulant":
+        c = crandn(rng, n)
+        op = gpu.Circulant(to_dev(c))
+        refs = [structured.circulant_apply_fft64(c, x, adj) for adj in (False, True)]
+    else:
+        col, row = crandn(rng, n), crandn(rng, n)
+        op = gpu.Toeplitz(to_dev(col), to_dev(row))
+        refs = [structured.toeplitz_apply_fft64(col, row, x, adj) for adj in (False, True)]
+    for adj, ref in zip((False, True), refs):
+        assert rel_err(to_host(op.apply(to_dev(x), adjoint=adj)), ref) <= TOL["c64"], adj
+
+
 def test_transform_length(gpu):
     """The cyclic length each kind reports: n for power-of-two Fourier and
     Circulant, the embedding length for Toeplitz (power of two up to 4096,
