@@ -34,8 +34,10 @@ constexpr int kXcdCount = 8;  // work-group g runs on XCD g mod 8
 #endif
 
 // XG (layout 2 only): the work-groups of column c take the indices = c (mod 8).
+// The complex64 strided form is held to 128 VGPRs (four work-groups per CU; it
+// spills 6 registers there and measured faster than at three).
 template <typename R, bool STRIDED, int LOGW, bool XG = false>
-__global__ __launch_bounds__(Geo<LOGW>::kThreads) void fft_kernel(KArgs a) {
+__global__ __launch_bounds__(Geo<LOGW>::kThreads, (STRIDED && sizeof(R) == 4) ? 4 : 1) void fft_kernel(KArgs a) {
   extern __shared__ unsigned char smem_raw[];
   Cx<R>* lds = reinterpret_cast<Cx<R>*>(smem_raw);
   const int tpw = 1 << (LOGW - a.logn);  // transforms per work-group
