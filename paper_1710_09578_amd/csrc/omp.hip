@@ -54,6 +54,7 @@ __device__ __forceinline__ void block_sum(Cx<R>* v, R* red) {
 #pragma unroll
   for (int g = 0; g < G; ++g) {
     R sx = R(0), sy = R(0);
+#pragma unroll 4
     for (int w = 0; w < NW; ++w) {
       sx += red[(2 * g) * NW + w];
       sy += red[(2 * g + 1) * NW + w];
@@ -114,21 +115,41 @@ __global__ __launch_bounds__(256) void omp_init_kernel(OmpState s) {
 
 // Argmax of |c_i|^2 over unchosen i (first index on ties); moves the one-hot
 // entry of the column to it.
-template <typename R>
-__global__ __launch_bounds__(256) void omp_select_kernel(OmpState s, int step) {
-  __shared__ R bv[256];
-  __shared__ int64_t bi[256];
+template <typename R, int NT>
+__global__ __launch_bounds__(NT) void omp_select_kernel(OmpState s, int step) {
+  __shared__ R bv[NT];
+  __shared__ int64_t bi[NT];
   const int64_t col = blockIdx.x;
   if (!s.active[col]) return;
   const Cx<R>* c = static_cast<const Cx<R>*>(s.c) + col * s.n;
   const unsigned char* sel = s.sel + col * s.n;
   R best = R(-1);
   int64_t bj = -1;
-  for (int64_t j = threadIdx.x; j < s.n; j += 256) {
+  // strided order, 4 loads in flight: the first maximum of this thread wins
+  constexpr int U = 4;
+  int64_t j0 = threadIdx.x;
+  for (; j0 + (U - 1) * NT < s.n; j0 += U * NT) {
+    Cx<R> v[U];
+    unsigned char sl[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      v[u] = c[j0 + u * NT];
+      sl[u] = sel[j0 + u * NT];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const R mag = v[u].x * v[u].x + v[u].y * v[u].y;
+      if (!sl[u] && mag > best) {
+        best = mag;
+        bj = j0 + u * NT;
+      }
+    }
+  }
+  for (int64_t j = j0; j < s.n; j += NT) {
     if (sel[j]) continue;
     const Cx<R> v = c[j];
     const R mag = v.x * v.x + v.y * v.y;
-    if (mag > best) {  // strided order: the first maximum of this thread wins
+    if (mag > best) {
       best = mag;
       bj = j;
     }
@@ -136,7 +157,7 @@ __global__ __launch_bounds__(256) void omp_select_kernel(OmpState s, int step) {
   bv[threadIdx.x] = best;
   bi[threadIdx.x] = bj;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (int w = NT / 2; w > 0; w >>= 1) {
     if (threadIdx.x < w) {
       const R ov = bv[threadIdx.x + w];
       const int64_t oi = bi[threadIdx.x + w];
@@ -208,7 +229,15 @@ __global__ __launch_bounds__(NT) void omp_orth_kernel(OmpState s, int step, R de
     __syncthreads();
     for (int64_t t = threadIdx.x; t < m; t += NT) {
       Cx<R> av = a[t];
-      for (int i = 0; i < step; ++i) av = csub(av, cmul(Q[int64_t(i) * m + t], h[i]));
+      int i = 0;
+      for (; i + G <= step; i += G) {  // G loads in flight, subtracted in order
+        Cx<R> qv[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) qv[g] = Q[int64_t(i + g) * m + t];
+#pragma unroll
+        for (int g = 0; g < G; ++g) av = csub(av, cmul(qv[g], h[i + g]));
+      }
+      for (; i < step; ++i) av = csub(av, cmul(Q[int64_t(i) * m + t], h[i]));
       a[t] = av;
     }
     __syncthreads();
@@ -333,7 +362,9 @@ fm_status run_omp(const fm_op_s* a, int64_t ncols, OmpState st, void* x, int64_t
                   hipStream_t s) {
   const Elem e = elem_of(a->dt);
   const int64_t m = a->m, n = a->n;
-  constexpr int NT = 256;
+  // one work-group per column: 1024 threads keep more loads in flight (the
+  // complex128 Gram-Schmidt step needs more registers than 1024 threads allow)
+  constexpr int NT = sizeof(R) == 4 ? 1024 : 256;
   const R dep2 = sizeof(R) == 4 ? R(1e-10) : R(1e-24);  // (relative norm left after orthogonalisation)^2
   const size_t orth_lds = size_t(2 * st.k) * sizeof(Cx<R>);
   const size_t fin_lds = size_t(st.k) * sizeof(Cx<R>);
@@ -343,7 +374,7 @@ fm_status run_omp(const fm_op_s* a, int64_t ncols, OmpState st, void* x, int64_t
   const Batch bf{ncols, 1, 1, n, n, m, m}, ba{ncols, 1, 1, m, m, n, n};
   for (int step = 0; step < int(st.k); ++step) {
     FM_TRY(exec(a, true, e, ba, st.r, st.c, false, w, s));      // c = A^H r
-    hipLaunchKernelGGL(omp_select_kernel<R>, grid, dim3(256), 0, s, st, step);
+    hipLaunchKernelGGL((omp_select_kernel<R, NT>), grid, dim3(NT), 0, s, st, step);
     FM_LAUNCHED();
     FM_TRY(exec(a, false, e, bf, st.e, st.acol, false, w, s));  // a = A e_j
     hipLaunchKernelGGL((omp_orth_kernel<R, NT>), grid, dim3(NT), orth_lds, s, st, step, dep2);
