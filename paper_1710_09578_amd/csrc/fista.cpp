@@ -59,6 +59,12 @@ fm_status plan_fista(const fm_op_s* a, int64_t ncols, FistaPlan* p) {
 }
 
 // Power iteration in complex128 on A^H A; sizes of its buffers.
+// Power iterations run in chunks of this many between host checks of the
+// convergence test: each keeps its two norms in a device history, and the
+// host applies the test to the history in order, so the estimate and the
+// iteration count are those of a check after every iteration.
+constexpr int kPowerChunk = 16;
+
 struct PowerPlan {
   size_t v, av, w, partial, scal, exec, total;
   int nparts;
@@ -77,7 +83,7 @@ fm_status plan_power(const fm_op_s* a, PowerPlan* p) {
   p->partial = off;
   off += up(size_t(p->nparts) * 8);
   p->scal = off;
-  off += up(4 * 8);
+  off += up(size_t(2 * kPowerChunk + 2) * 8);
   p->exec = off;
   size_t ex = 0;
   for (int adj = 0; adj < 2; ++adj) {
@@ -118,27 +124,36 @@ fm_status power_iteration(const fm_op_s* a, const void* v0, uint64_t seed, int m
     ws.cap = p.total - p.exec;
     const Batch bf{1, 1, 1, n, n, m, m}, ba{1, 1, 1, m, m, n, n};
     double prev = 0.0, lk = 0.0;
-    int it = 0;
-    for (it = 1; it <= max_iters; ++it) {
-      FM_TRY(exec(a, false, Elem::C128, bf, v, av, false, ws, s));
-      FM_TRY(launch_norm2(m, av, partial, p.nparts, scal, s));
-      FM_TRY(exec(a, true, Elem::C128, ba, av, w, false, ws, s));
-      FM_TRY(launch_norm2(n, w, partial, p.nparts, scal + 1, s));
-      double h[2];
-      FM_HIP(hipMemcpyAsync(h, scal, 16, hipMemcpyDeviceToHost, s));
-      FM_HIP(hipStreamSynchronize(s));
-      lk = h[0];
-      if (h[1] == 0.0) {
-        lk = 0.0;
-        break;
+    int it = 0;  // iterations whose test has been applied
+    bool done = false;
+    while (!done && it < max_iters) {
+      // iteration j of the chunk: ||A v||^2 -> scal[2j], ||A^H A v|| -> scal[2j+1]
+      const int chunk = std::min(kPowerChunk, max_iters - it);
+      for (int j = 0; j < chunk; ++j) {
+        FM_TRY(exec(a, false, Elem::C128, bf, v, av, false, ws, s));
+        FM_TRY(launch_norm2(m, av, partial, p.nparts, scal + 2 * j, s));
+        FM_TRY(exec(a, true, Elem::C128, ba, av, w, false, ws, s));
+        FM_TRY(launch_norm2(n, w, partial, p.nparts, scal + 2 * j + 1, s));
+        FM_TRY(launch_normalize(n, w, scal + 2 * j + 1, s));  // iterates past a stop are discarded
+        std::swap(v, w);
       }
-      FM_TRY(launch_normalize(n, w, scal + 1, s));
-      std::swap(v, w);
-      if (it > 1 && std::fabs(lk - prev) <= tol * lk) break;
-      prev = lk;
+      double h[2 * kPowerChunk];
+      FM_HIP(hipMemcpyAsync(h, scal, size_t(2 * chunk) * 8, hipMemcpyDeviceToHost, s));
+      FM_HIP(hipStreamSynchronize(s));
+      for (int j = 0; j < chunk && !done; ++j) {
+        ++it;
+        lk = h[2 * j];
+        if (h[2 * j + 1] == 0.0) {
+          lk = 0.0;
+          done = true;
+        } else if (it > 1 && std::fabs(lk - prev) <= tol * lk) {
+          done = true;
+        }
+        prev = lk;
+      }
     }
     *L_out = lk;
-    if (iters_out) *iters_out = it > max_iters ? max_iters : it;
+    if (iters_out) *iters_out = it;
     return FM_OK;
   };
   st = run();
