@@ -364,8 +364,11 @@ typedef struct {
 /* Autotuner, in the spirit of the paper's run-time calibration (Sec. 2.1):
  * times fm_batch_apply(dir) on the caller's blocks for every candidate
  * schedule (max_fuse 0..5 x slot regions of 24, 48 and 96 MiB), `reps`
- * timed runs each after one warm-up, and keeps the fastest (a candidate
- * replaces the best so far only when it is more than 1 % faster). y receives the
+ * timed runs each after one warm-up, then times the four fastest and the
+ * schedule in use on entry again in two interleaved rounds of 2 * reps runs,
+ * and keeps the fastest by each candidate's minimum (a candidate replaces the
+ * best so far only when it is more than 1 % faster). The default schedule
+ * is (3, 96 MiB). y receives the
  * correct result. Synchronises the device. A schedule whose max_fuse differs
  * from the per-operator path's default (3, FM_MAX_FUSE) computes the same
  * products with a different rounding order, so results then agree with

@@ -61,7 +61,7 @@ struct Ptrs {
 // Tunable parameters of a batch's work list.
 struct Schedule {
   int max_fuse = 3;                         // strided factors up to 2^max_fuse folded into the row pass
-  size_t region_bytes = size_t(48) << 20;   // slot region of one chunk (three rotate)
+  size_t region_bytes = size_t(96) << 20;   // slot region of one chunk (three rotate)
 };
 
 
