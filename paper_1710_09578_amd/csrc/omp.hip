@@ -83,6 +83,13 @@ struct OmpState {
   int* nsel;
   int* status;
   double tol2;
+  // split Gram-Schmidt step (P > 1 work-groups per column, `chunk` rows each):
+  // part: per column and work-group, k + 4 partial sums (projections, then
+  // ||a||^2, ||a'||^2, q^H r, ||r'||^2); hbuf: the projections of a pass
+  void* part;
+  void* hbuf;
+  int P;
+  int64_t chunk;
 };
 
 template <typename R>
@@ -289,6 +296,202 @@ __global__ __launch_bounds__(NT) void omp_orth_kernel(OmpState s, int step, R de
   }
 }
 
+// ---- Gram-Schmidt step split over P work-groups per column (few columns).
+// The same arithmetic as omp_orth_kernel, with every sum over the rows taken
+// as P chunk sums added in work-group order (deterministic; every work-group
+// of a column forms the same totals, so all take the same decisions).
+template <typename R>
+__device__ __forceinline__ Cx<R>* split_part(const OmpState& s, int64_t col, int w) {
+  return static_cast<Cx<R>*>(s.part) + (col * s.P + w) * (s.k + 4);
+}
+
+template <typename R>
+__device__ __forceinline__ Cx<R> split_total(const OmpState& s, int64_t col, int64_t slot) {
+  Cx<R> acc = {R(0), R(0)};
+  for (int w = 0; w < s.P; ++w) acc = cadd(acc, split_part<R>(s, col, w)[slot]);
+  return acc;
+}
+
+// Chunk sums of conj(q_i) a (i < step) for one pass; pass 0 also ||a||^2.
+template <typename R, int NT>
+__global__ __launch_bounds__(NT) void omp_sdot_kernel(OmpState s, int step, int pass) {
+  constexpr int G = 8;
+  __shared__ R red[2 * G * (NT / 64)];
+  const int64_t col = blockIdx.y;
+  const int w = int(blockIdx.x);
+  if (!s.active[col]) return;
+  const int64_t m = s.m, t0 = int64_t(w) * s.chunk, t1 = t0 + s.chunk < m ? t0 + s.chunk : m;
+  const Cx<R>* a = static_cast<const Cx<R>*>(s.acol) + col * m;
+  const Cx<R>* Q = static_cast<const Cx<R>*>(s.q) + col * s.k * m;
+  Cx<R>* part = split_part<R>(s, col, w);
+  if (pass == 0) {
+    Cx<R> nrm[1] = {{R(0), R(0)}};
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += NT) nrm[0].x += a[t].x * a[t].x + a[t].y * a[t].y;
+    block_sum<R, 1, NT>(nrm, red);
+    if (threadIdx.x == 0) part[s.k] = nrm[0];
+  }
+  for (int i0 = 0; i0 < step; i0 += G) {
+    Cx<R> d[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) d[g] = {R(0), R(0)};
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += NT) {
+      const Cx<R> av = a[t];
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+        if (i0 + g < step) d[g] = cadd(d[g], cmulc(av, Q[int64_t(i0 + g) * m + t]));
+    }
+    block_sum<R, G, NT>(d, red);
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      if (int(threadIdx.x) == g && i0 + g < step) part[i0 + g] = d[g];
+  }
+}
+
+// Projections of the pass (h) and the accumulated column of R (column `step`
+// of the factor, written in place; used only once the step succeeds).
+template <typename R>
+__global__ __launch_bounds__(256) void omp_sred_kernel(OmpState s, int step, int pass) {
+  const int64_t col = blockIdx.x;
+  if (!s.active[col]) return;
+  Cx<R>* h = static_cast<Cx<R>*>(s.hbuf) + col * s.k;
+  Cx<R>* Rf = static_cast<Cx<R>*>(s.rf) + col * s.k * s.k + int64_t(step) * s.k;
+  for (int i = threadIdx.x; i < step; i += 256) {
+    const Cx<R> v = split_total<R>(s, col, i);
+    h[i] = v;
+    Rf[i] = pass == 0 ? v : cadd(Rf[i], v);
+  }
+}
+
+// a -= Q h over the chunk, projections subtracted in order.
+template <typename R, int NT>
+__global__ __launch_bounds__(NT) void omp_supd_kernel(OmpState s, int step) {
+  extern __shared__ unsigned char smem[];
+  Cx<R>* hs = reinterpret_cast<Cx<R>*>(smem);
+  const int64_t col = blockIdx.y;
+  const int w = int(blockIdx.x);
+  if (!s.active[col]) return;
+  const int64_t m = s.m, t0 = int64_t(w) * s.chunk, t1 = t0 + s.chunk < m ? t0 + s.chunk : m;
+  const Cx<R>* h = static_cast<const Cx<R>*>(s.hbuf) + col * s.k;
+  for (int i = threadIdx.x; i < step; i += NT) hs[i] = h[i];
+  __syncthreads();
+  Cx<R>* a = static_cast<Cx<R>*>(s.acol) + col * m;
+  const Cx<R>* Q = static_cast<const Cx<R>*>(s.q) + col * s.k * m;
+  constexpr int G = 8;
+  for (int64_t t = t0 + threadIdx.x; t < t1; t += NT) {
+    Cx<R> av = a[t];
+    int i = 0;
+    for (; i + G <= step; i += G) {
+      Cx<R> qv[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) qv[g] = Q[int64_t(i + g) * m + t];
+#pragma unroll
+      for (int g = 0; g < G; ++g) av = csub(av, cmul(qv[g], hs[i + g]));
+    }
+    for (; i < step; ++i) av = csub(av, cmul(Q[int64_t(i) * m + t], hs[i]));
+    a[t] = av;
+  }
+}
+
+// Chunk sums of ||a'||^2 (slot k + 1).
+template <typename R, int NT>
+__global__ __launch_bounds__(NT) void omp_snorm_kernel(OmpState s) {
+  __shared__ R red[2 * (NT / 64)];
+  const int64_t col = blockIdx.y;
+  const int w = int(blockIdx.x);
+  if (!s.active[col]) return;
+  const int64_t m = s.m, t0 = int64_t(w) * s.chunk, t1 = t0 + s.chunk < m ? t0 + s.chunk : m;
+  const Cx<R>* a = static_cast<const Cx<R>*>(s.acol) + col * m;
+  Cx<R> nrm[1] = {{R(0), R(0)}};
+  for (int64_t t = t0 + threadIdx.x; t < t1; t += NT) nrm[0].x += a[t].x * a[t].x + a[t].y * a[t].y;
+  block_sum<R, 1, NT>(nrm, red);
+  if (threadIdx.x == 0) split_part<R>(s, col, w)[s.k + 1] = nrm[0];
+}
+
+// Outcome of the step from the summed norms: 0 ok, 1 non-finite, 2 the new
+// column depends on the chosen ones. Every kernel after the norms derives it
+// from the same sums; only omp_sfin_kernel records it, so no kernel changes
+// `active` while work-groups of its own launch may still read it.
+template <typename R>
+__device__ __forceinline__ int split_outcome(const OmpState& s, int64_t col, R dep2, R* rho2_out) {
+  const R anorm2 = split_total<R>(s, col, s.k).x;
+  const R rho2 = split_total<R>(s, col, s.k + 1).x;
+  *rho2_out = rho2;
+  if (!(rho2 == rho2) || !(anorm2 == anorm2) || rho2 > R(3.0e38)) return 1;
+  if (rho2 <= dep2 * anorm2 || rho2 <= R(0)) return 2;
+  return 0;
+}
+
+// q = a'/||a'|| over the chunk and the chunk sums of conj(q) r (slot k + 2).
+template <typename R, int NT>
+__global__ __launch_bounds__(NT) void omp_sq_kernel(OmpState s, int step, R dep2) {
+  __shared__ R red[2 * (NT / 64)];
+  const int64_t col = blockIdx.y;
+  const int w = int(blockIdx.x);
+  if (!s.active[col]) return;
+  R rho2;
+  if (split_outcome<R>(s, col, dep2, &rho2) != 0) return;
+  const int64_t m = s.m, t0 = int64_t(w) * s.chunk, t1 = t0 + s.chunk < m ? t0 + s.chunk : m;
+  const R inv = R(1) / sqrt(rho2);
+  const Cx<R>* a = static_cast<const Cx<R>*>(s.acol) + col * m;
+  Cx<R>* qk = static_cast<Cx<R>*>(s.q) + col * s.k * m + int64_t(step) * m;
+  const Cx<R>* r = static_cast<const Cx<R>*>(s.r) + col * m;
+  Cx<R> zk[1] = {{R(0), R(0)}};
+  for (int64_t t = t0 + threadIdx.x; t < t1; t += NT) {
+    const Cx<R> qv = cscale(a[t], inv);
+    qk[t] = qv;
+    zk[0] = cadd(zk[0], cmulc(r[t], qv));
+  }
+  block_sum<R, 1, NT>(zk, red);
+  if (threadIdx.x == 0) split_part<R>(s, col, w)[s.k + 2] = zk[0];
+}
+
+// r -= q (q^H r) over the chunk; chunk sums of ||r'||^2 (slot k + 3).
+template <typename R, int NT>
+__global__ __launch_bounds__(NT) void omp_sr_kernel(OmpState s, int step, R dep2) {
+  __shared__ R red[2 * (NT / 64)];
+  const int64_t col = blockIdx.y;
+  const int w = int(blockIdx.x);
+  if (!s.active[col]) return;
+  R rho2;
+  if (split_outcome<R>(s, col, dep2, &rho2) != 0) return;
+  const int64_t m = s.m, t0 = int64_t(w) * s.chunk, t1 = t0 + s.chunk < m ? t0 + s.chunk : m;
+  const Cx<R> zk = split_total<R>(s, col, s.k + 2);
+  const Cx<R>* qk = static_cast<const Cx<R>*>(s.q) + col * s.k * m + int64_t(step) * m;
+  Cx<R>* r = static_cast<Cx<R>*>(s.r) + col * m;
+  Cx<R> rn[1] = {{R(0), R(0)}};
+  for (int64_t t = t0 + threadIdx.x; t < t1; t += NT) {
+    const Cx<R> rv = csub(r[t], cmul(qk[t], zk));
+    r[t] = rv;
+    rn[0].x += rv.x * rv.x + rv.y * rv.y;
+  }
+  block_sum<R, 1, NT>(rn, red);
+  if (threadIdx.x == 0) split_part<R>(s, col, w)[s.k + 3] = rn[0];
+}
+
+// The step's outcome; on success the diagonal of R, z, residual norm, atom
+// count and the tolerance stop.
+template <typename R>
+__global__ __launch_bounds__(64) void omp_sfin_kernel(OmpState s, int step, R dep2) {
+  const int64_t col = blockIdx.x;
+  if (!s.active[col] || threadIdx.x != 0) return;
+  R rho2;
+  const int outcome = split_outcome<R>(s, col, dep2, &rho2);
+  if (outcome != 0) {
+    s.active[col] = 0;
+    s.status[col] = outcome;
+    s.idx[col * s.k + step] = -1;
+    return;
+  }
+  const Cx<R> zk = split_total<R>(s, col, s.k + 2);
+  const R rn = split_total<R>(s, col, s.k + 3).x;
+  Cx<R>* Rf = static_cast<Cx<R>*>(s.rf) + col * s.k * s.k + int64_t(step) * s.k;
+  Rf[step] = {sqrt(rho2), R(0)};
+  static_cast<Cx<R>*>(s.z)[col * s.k + step] = zk;
+  s.rnorm2[col] = double(rn);
+  s.nsel[col] = step + 1;
+  if (double(rn) <= s.tol2 * s.bnorm2[col]) s.active[col] = 0;
+}
+
 // x_S = R^{-1} z by back substitution, x = 0 elsewhere.
 template <typename R>
 __global__ __launch_bounds__(256) void omp_finish_kernel(OmpState s, void* xout, int64_t ldx, int* support) {
@@ -318,8 +521,18 @@ __global__ __launch_bounds__(256) void omp_finish_kernel(OmpState s, void* xout,
 }
 
 struct OmpPlan {
-  size_t r, c, e, acol, q, rf, z, idx, sel, bn, rn, act, nsel, status, exec, total;
+  size_t r, c, e, acol, q, rf, z, idx, sel, bn, rn, act, nsel, status, part, hbuf, exec, total;
+  int P;
 };
+
+// Work-groups per column of the Gram-Schmidt step: enough to spread few
+// columns over the chip (~256 work-groups), at least 256 rows each, at most 16.
+int omp_split(int64_t ncols, int64_t m, int64_t k, size_t es) {
+  if (ncols <= 0 || ncols >= 128 || size_t(k) * es > 65536) return 1;  // projections staged in LDS
+  int64_t p = std::min<int64_t>(256 / ncols, 16);
+  p = std::min<int64_t>(p, m / 256);
+  return int(std::max<int64_t>(p, 1));
+}
 
 fm_status plan_omp(const fm_op_s* a, int64_t ncols, int64_t k, OmpPlan* p) {
   const Elem e = elem_of(a->dt);
@@ -344,6 +557,9 @@ fm_status plan_omp(const fm_op_s* a, int64_t ncols, int64_t k, OmpPlan* p) {
   take(&p->act, size_t(ncols) * 4);
   take(&p->nsel, size_t(ncols) * 4);
   take(&p->status, size_t(ncols) * 4);
+  p->P = omp_split(ncols, m, k, es);
+  take(&p->part, p->P > 1 ? size_t(ncols) * size_t(p->P) * size_t(k + 4) * es : 0);
+  take(&p->hbuf, p->P > 1 ? size_t(ncols * k) * es : 0);
   p->exec = off;
   size_t ex = 0;
   for (int adj = 0; adj < 2; ++adj) {
@@ -377,7 +593,21 @@ fm_status run_omp(const fm_op_s* a, int64_t ncols, OmpState st, void* x, int64_t
     hipLaunchKernelGGL((omp_select_kernel<R, NT>), grid, dim3(NT), 0, s, st, step);
     FM_LAUNCHED();
     FM_TRY(exec(a, false, e, bf, st.e, st.acol, false, w, s));  // a = A e_j
-    hipLaunchKernelGGL((omp_orth_kernel<R, NT>), grid, dim3(NT), orth_lds, s, st, step, dep2);
+    if (st.P > 1) {
+      const dim3 g2{unsigned(st.P), unsigned(ncols)};
+      constexpr int NS = 256;
+      for (int pass = 0; pass < 2; ++pass) {
+        hipLaunchKernelGGL((omp_sdot_kernel<R, NS>), g2, dim3(NS), 0, s, st, step, pass);
+        hipLaunchKernelGGL(omp_sred_kernel<R>, grid, dim3(256), 0, s, st, step, pass);
+        hipLaunchKernelGGL((omp_supd_kernel<R, NS>), g2, dim3(NS), size_t(st.k) * sizeof(Cx<R>), s, st, step);
+      }
+      hipLaunchKernelGGL((omp_snorm_kernel<R, NS>), g2, dim3(NS), 0, s, st);
+      hipLaunchKernelGGL((omp_sq_kernel<R, NS>), g2, dim3(NS), 0, s, st, step, dep2);
+      hipLaunchKernelGGL((omp_sr_kernel<R, NS>), g2, dim3(NS), 0, s, st, step, dep2);
+      hipLaunchKernelGGL(omp_sfin_kernel<R>, grid, dim3(64), 0, s, st, step, dep2);
+    } else {
+      hipLaunchKernelGGL((omp_orth_kernel<R, NT>), grid, dim3(NT), orth_lds, s, st, step, dep2);
+    }
     FM_LAUNCHED();
   }
   hipLaunchKernelGGL(omp_finish_kernel<R>, grid, dim3(256), fin_lds, s, st, x, ldx, support);
@@ -456,6 +686,10 @@ fm_status fm_omp(fm_op a, int64_t ncols, const void* b, int64_t ldb, int32_t k, 
   st.nsel = reinterpret_cast<int*>(B + p.nsel);
   st.status = reinterpret_cast<int*>(B + p.status);
   st.tol2 = tol * tol;
+  st.P = p.P;
+  st.chunk = cdiv(m, p.P);
+  st.part = B + p.part;
+  st.hbuf = B + p.hbuf;
   Workspace w;
   w.base = B + p.exec;
   w.cap = p.total - p.exec;

@@ -78,19 +78,34 @@ def test_omp_recovers_support_and_stops_on_tolerance(gpu, prec):
 
 
 @pytest.mark.parametrize("prec", ["c64", "c128"])
-def test_omp_dependent_atom_stops(gpu, prec):
+@pytest.mark.parametrize("rows", [8, 600])
+def test_omp_dependent_atom_stops(gpu, prec, rows):
     """Columns 0 and 1 of A are equal: once the other columns are used up the
     only candidate left depends on the chosen ones; the column stops with
-    status 2 and keeps its independent atoms."""
+    status 2 and keeps its independent atoms (600 rows: the Gram-Schmidt step
+    split over work-groups)."""
     rng = np.random.default_rng(5)
-    d = crandn(rng, (8, 4), NP[prec])
+    d = crandn(rng, (rows, 4), NP[prec])
     d[:, 1] = d[:, 0]
-    b = crandn(rng, (1, 8), NP[prec])
+    b = crandn(rng, (1, rows), NP[prec])
     x, sup, st = gpu.omp(gpu.Dense(to_dev(d)), to_dev(b), 4)
     assert st[0]["status"] == 2 and st[0]["atoms"] == 3
     s = to_host(sup)[0]
     assert s[3] == -1 and len(set(s[:3].tolist()) & {0, 1}) == 1
     assert rel_err(to_host(x), omp.least_squares_on(d, b[0], s)[None, :]) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+@pytest.mark.parametrize("ncols", [5, 130])
+def test_omp_column_counts(gpu, prec, ncols):
+    """Few columns take the Gram-Schmidt step split over several work-groups
+    per column, many columns one work-group each: both against the oracle."""
+    A, a, b, _ = cs_problem(gpu, prec, n=512, m=256, k=6, ncols=ncols, seed=9)
+    x_ref, sup_ref, atoms_ref = omp.omp(a, b, 8)
+    x, sup, st = gpu.omp(A, to_dev(b), 8)
+    assert np.array_equal(to_host(sup), sup_ref)
+    assert [s["atoms"] for s in st] == list(atoms_ref)
+    assert rel_err(to_host(x), x_ref) <= TOL[prec]
 
 
 @pytest.mark.parametrize("prec", ["c64", "c128"])
