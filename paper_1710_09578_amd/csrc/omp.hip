@@ -312,10 +312,14 @@ __device__ __forceinline__ Cx<R> split_total(const OmpState& s, int64_t col, int
   return acc;
 }
 
-// Chunk sums of conj(q_i) a (i < step) for one pass; pass 0 also ||a||^2.
+// Chunk sums of conj(q_i) a for the projections i0 = blockIdx.z * kSdotG ..
+// i0 + kSdotG - 1 (i < step; one group per work-group, the groups side by
+// side in the grid); pass 0, group 0 also ||a||^2.
+constexpr int kSdotG = 8;
+
 template <typename R, int NT>
 __global__ __launch_bounds__(NT) void omp_sdot_kernel(OmpState s, int step, int pass) {
-  constexpr int G = 8;
+  constexpr int G = kSdotG;
   __shared__ R red[2 * G * (NT / 64)];
   const int64_t col = blockIdx.y;
   const int w = int(blockIdx.x);
@@ -324,27 +328,27 @@ __global__ __launch_bounds__(NT) void omp_sdot_kernel(OmpState s, int step, int 
   const Cx<R>* a = static_cast<const Cx<R>*>(s.acol) + col * m;
   const Cx<R>* Q = static_cast<const Cx<R>*>(s.q) + col * s.k * m;
   Cx<R>* part = split_part<R>(s, col, w);
-  if (pass == 0) {
+  if (pass == 0 && blockIdx.z == 0) {
     Cx<R> nrm[1] = {{R(0), R(0)}};
     for (int64_t t = t0 + threadIdx.x; t < t1; t += NT) nrm[0].x += a[t].x * a[t].x + a[t].y * a[t].y;
     block_sum<R, 1, NT>(nrm, red);
     if (threadIdx.x == 0) part[s.k] = nrm[0];
   }
-  for (int i0 = 0; i0 < step; i0 += G) {
-    Cx<R> d[G];
+  const int i0 = int(blockIdx.z) * G;
+  if (i0 >= step) return;  // uniform over the work-group
+  Cx<R> d[G];
 #pragma unroll
-    for (int g = 0; g < G; ++g) d[g] = {R(0), R(0)};
-    for (int64_t t = t0 + threadIdx.x; t < t1; t += NT) {
-      const Cx<R> av = a[t];
-#pragma unroll
-      for (int g = 0; g < G; ++g)
-        if (i0 + g < step) d[g] = cadd(d[g], cmulc(av, Q[int64_t(i0 + g) * m + t]));
-    }
-    block_sum<R, G, NT>(d, red);
+  for (int g = 0; g < G; ++g) d[g] = {R(0), R(0)};
+  for (int64_t t = t0 + threadIdx.x; t < t1; t += NT) {
+    const Cx<R> av = a[t];
 #pragma unroll
     for (int g = 0; g < G; ++g)
-      if (int(threadIdx.x) == g && i0 + g < step) part[i0 + g] = d[g];
+      if (i0 + g < step) d[g] = cadd(d[g], cmulc(av, Q[int64_t(i0 + g) * m + t]));
   }
+  block_sum<R, G, NT>(d, red);
+#pragma unroll
+  for (int g = 0; g < G; ++g)
+    if (int(threadIdx.x) == g && i0 + g < step) part[i0 + g] = d[g];
 }
 
 // Projections of the pass (h) and the accumulated column of R (column `step`
@@ -597,7 +601,8 @@ fm_status run_omp(const fm_op_s* a, int64_t ncols, OmpState st, void* x, int64_t
       const dim3 g2{unsigned(st.P), unsigned(ncols)};
       constexpr int NS = 256;
       for (int pass = 0; pass < 2; ++pass) {
-        hipLaunchKernelGGL((omp_sdot_kernel<R, NS>), g2, dim3(NS), 0, s, st, step, pass);
+        const dim3 g3{unsigned(st.P), unsigned(ncols), unsigned(std::max(1, (step + kSdotG - 1) / kSdotG))};
+        hipLaunchKernelGGL((omp_sdot_kernel<R, NS>), g3, dim3(NS), 0, s, st, step, pass);
         hipLaunchKernelGGL(omp_sred_kernel<R>, grid, dim3(256), 0, s, st, step, pass);
         hipLaunchKernelGGL((omp_supd_kernel<R, NS>), g2, dim3(NS), size_t(st.k) * sizeof(Cx<R>), s, st, step);
       }
