@@ -39,8 +39,11 @@ def cs_problem(gpu, prec, n=1024, m=256, k=12, ncols=3, seed=0, sigma=1e-3):
 
 @pytest.mark.parametrize("prec", ["c64", "c128"])
 @pytest.mark.parametrize("k", [1, 5, 12, 20])
-def test_omp_matches_oracle(gpu, prec, k):
-    A, a, b, _ = cs_problem(gpu, prec)
+@pytest.mark.parametrize("m", [256, 768])
+def test_omp_matches_oracle(gpu, prec, k, m):
+    """m = 256: one work-group per column for the Gram-Schmidt step; m = 768:
+    the step split over three work-groups per column."""
+    A, a, b, _ = cs_problem(gpu, prec, m=m)
     x_ref, sup_ref, atoms_ref = omp.omp(a, b, k)
     x, sup, st = gpu.omp(A, to_dev(b), k)
     sup = to_host(sup)
@@ -55,11 +58,13 @@ def test_omp_matches_oracle(gpu, prec, k):
 
 
 @pytest.mark.parametrize("prec", ["c64", "c128"])
-def test_omp_recovers_support_and_stops_on_tolerance(gpu, prec):
+@pytest.mark.parametrize("m", [192, 640])
+def test_omp_recovers_support_and_stops_on_tolerance(gpu, prec, m):
     """Noiseless sparse vectors: the tolerance ends each column after exactly
-    its own sparsity (uneven across columns)."""
+    its own sparsity (uneven across columns); m = 640 takes the split
+    Gram-Schmidt step."""
     rng = np.random.default_rng(3)
-    n, m = 512, 192
+    n = 1024 if m > 512 else 512
     c = crandn(rng, n, NP[prec])
     rows = np.sort(rng.choice(n, m, replace=False)).astype(np.int32)
     a = dense.product(dense.select_rows(n, rows), dense.circulant(c))
@@ -100,7 +105,7 @@ def test_omp_dependent_atom_stops(gpu, prec, rows):
 def test_omp_column_counts(gpu, prec, ncols):
     """Few columns take the Gram-Schmidt step split over several work-groups
     per column, many columns one work-group each: both against the oracle."""
-    A, a, b, _ = cs_problem(gpu, prec, n=512, m=256, k=6, ncols=ncols, seed=9)
+    A, a, b, _ = cs_problem(gpu, prec, n=1024, m=600, k=6, ncols=ncols, seed=9)
     x_ref, sup_ref, atoms_ref = omp.omp(a, b, 8)
     x, sup, st = gpu.omp(A, to_dev(b), 8)
     assert np.array_equal(to_host(sup), sup_ref)
@@ -109,8 +114,9 @@ def test_omp_column_counts(gpu, prec, ncols):
 
 
 @pytest.mark.parametrize("prec", ["c64", "c128"])
-def test_omp_zero_and_trivial_inputs(gpu, prec):
-    A, a, b, _ = cs_problem(gpu, prec, ncols=2)
+@pytest.mark.parametrize("m", [256, 768])
+def test_omp_zero_and_trivial_inputs(gpu, prec, m):
+    A, a, b, _ = cs_problem(gpu, prec, m=m, ncols=2)
     b = b.copy()
     b[1] = 0
     x, sup, st = gpu.omp(A, to_dev(b), 6)
