@@ -290,8 +290,10 @@ fm_status fm_fista_workspace_size(fm_op a, int64_t ncols, const fm_fista_opts* o
  * v <- w/||w|| until |L_k - L_{k-1}| <= tol * L_k or max_iters. v0: DEVICE
  * complex128 start vector of n entries, or NULL for the SplitMix64 vector of
  * `seed` (entry i = (u(2i) - 1/2) + j (u(2i+1) - 1/2), u(k) the k-th SplitMix64
- * output of `seed` scaled to [0,1) by its top 53 bits). Synchronises `stream`.
- * iters_out may be NULL. */
+ * output of `seed` scaled to [0,1) by its top 53 bits). Synchronises `stream`
+ * once every 16 iterations (the stopping test is applied to every iteration
+ * in order from a device history of the norms; iterations past the stop are
+ * discarded). iters_out may be NULL. */
 fm_status fm_power_iteration(fm_op a, const void* v0, uint64_t seed, int32_t max_iters, double tol,
                              double* L_out, int32_t* iters_out, void* stream);
 
@@ -399,8 +401,10 @@ fm_status fm_batch_set_schedule(fm_batch b, const fm_batch_schedule* sc);
  * of n entries (leading dimensions ld_in, ld_g >= n); grad_c: DEVICE vector of
  * n entries, overwritten (accumulate = 0) or added to; it must not overlap the
  * inputs. n: power of two <= 2^20; complex dtypes. ncols = 0 leaves grad_c
- * unchanged (accumulate) or zeroes it. Allocates its own device workspace and
- * synchronises the stream before returning. */
+ * unchanged (accumulate) or zeroes it. Takes its own workspace from the
+ * stream-ordered allocator (hipMallocAsync / hipFreeAsync on `stream`) and
+ * does not wait on the host; the column sum is deterministic (a fixed grouping
+ * of the columns, groups added in order). */
 fm_status fm_circulant_grad_generator(int64_t n, int64_t ncols, fm_dir use, const void* in,
                                       int64_t ld_in, const void* g, int64_t ld_g, void* grad_c,
                                       int32_t accumulate, fm_dtype dt, void* stream);
