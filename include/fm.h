@@ -136,7 +136,9 @@ fm_status fm_op_create_mltoeplitz(fm_op* out, int32_t levels, const int64_t* n_p
 /* Row selection S (m x n_in), S[r, idx[r]] = 1 (the Partial operator, and the
  * row selections of Psi in eq. (9)). idx: DEVICE int32 array of m distinct
  * indices in [0, n_in); validated here (FM_E_SHAPE on a duplicate or an index
- * out of range). Forward gathers, adjoint scatters into zeros. All dtypes. */
+ * out of range). Forward gathers; the adjoint writes every one of the n_in
+ * outputs once, through an inverse index map the handle keeps (n_in int32,
+ * -1 for rows not selected), with zeros where no row is selected. All dtypes. */
 fm_status fm_op_create_select_rows(fm_op* out, int64_t n_in, int64_t m, const int32_t* idx,
                                    fm_dtype dt, void* stream);
 
