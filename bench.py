@@ -330,7 +330,7 @@ def kron_hfg_bandwidth(steps=5, warmup=2):
             "alg_bytes_per_step": int(alg)}
 
 
-def circulant_wide_bandwidth(steps=10, warmup=3):
+def circulant_wide_bandwidth(steps=40, warmup=5):
     """Forward + adjoint of the 1024-point circulant on 65,536 columns
     (complex64, 512 MiB per block): one single-pass convolution launch per
     direction. Algorithmic bytes per direction: read the block + write the
