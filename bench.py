@@ -171,10 +171,14 @@ def time_steps(step, steps, warmup):
     return max(wall * 1e3 / steps, gpu_ms), gpu_ms
 
 
-def fista_solves(w, iters=100, stop_tol=1e-5, tune=True):
+def fista_solves(w, iters=100, stop_tol=1e-5, tune=True, reps=3):
     """FISTA for every column of every operator: batched (fm_batch_fista) and
     plain (one fm_fista per operator). Measurements b = T x_true + noise are
-    formed on the GPU by the library's batched forward apply."""
+    formed on the GPU by the library's batched forward apply. Each form is
+    timed ``reps`` times after a warm-up (the plain warm-up solves every
+    operator once, so its workspaces and tables exist); the median is
+    reported. A seeded sample of operators is checked: batched and plain x
+    must be equal bit for bit."""
     import torch
 
     import paper_1710_09578_amd as fm
@@ -193,28 +197,143 @@ def fista_solves(w, iters=100, stop_tol=1e-5, tune=True):
     total = sum(ncols)
     batch.fista(bs, iters=2, lam_rel=0.05)  # warm-up (state allocation, bounds)
     torch.cuda.synchronize()
-    t0 = time.time()
-    _, st = batch.fista(bs, iters=iters, lam_rel=0.05, stop_tol=stop_tol)
-    torch.cuda.synchronize()
-    tb = time.time() - t0
+    tbs = []
+    for _ in range(reps):
+        t0 = time.time()
+        xb, st = batch.fista(bs, iters=iters, lam_rel=0.05, stop_tol=stop_tol)
+        torch.cuda.synchronize()
+        tbs.append(time.time() - t0)
+    tb = float(np.median(tbs))
     counts = np.array([s["iters"] for s in st])
     Ls = []
     gi = 0
     for i in range(len(ncols)):
         Ls.append(st[gi]["L"] if ncols[i] else 1.0)
         gi += ncols[i]
-    t0 = time.time()
-    for i, op in enumerate(w["ops"]):
+
+    def plain():
+        out = []
+        for i, op in enumerate(w["ops"]):
+            out.append(fm.fista(op, bs[i], iters=iters, lam_rel=0.05, L=Ls[i], stop_tol=stop_tol)[0]
+                       if ncols[i] else None)
+        return out
+
+    for i, op in enumerate(w["ops"]):  # warm-up: every operator once
         if ncols[i]:
-            fm.fista(op, bs[i], iters=iters, lam_rel=0.05, L=Ls[i], stop_tol=stop_tol)
+            fm.fista(op, bs[i], iters=2, lam_rel=0.05, L=Ls[i])
     torch.cuda.synchronize()
-    tp = time.time() - t0
-    log(f"FISTA {iters} it, stop {stop_tol}: batched {tb:.3f} s, plain {tp:.3f} s for {total} problems; "
-        f"iterations used: mean {counts.mean():.1f}, min {counts.min()}, max {counts.max()}")
+    tps = []
+    for _ in range(reps):
+        t0 = time.time()
+        xp = plain()
+        torch.cuda.synchronize()
+        tps.append(time.time() - t0)
+    tp = float(np.median(tps))
+    rng = np.random.default_rng(0)
+    sample = sorted(rng.choice(len(ncols), 32, replace=False).tolist())
+    same = all(torch.equal(xb[i], xp[i]) for i in sample if ncols[i])
+    log(f"FISTA {iters} it, stop {stop_tol}: batched {tb:.3f} s, plain {tp:.3f} s for {total} problems "
+        f"(median of {reps}); iterations used: mean {counts.mean():.1f}, min {counts.min()}, max {counts.max()}; "
+        f"batched == plain bit for bit on {len(sample)} sampled operators: {same}")
+    if not same:
+        raise RuntimeError("batched and plain FISTA solutions differ")
     return {"problems": total, "iters": iters, "stop_tol": stop_tol, "batched_s": round(tb, 4),
             "plain_s": round(tp, 4), "batched_solves_per_s": round(total / tb, 1),
             "plain_solves_per_s": round(total / tp, 1), "batched_over_plain": round(tp / tb, 2),
-            "mean_iters": round(float(counts.mean()), 2)}
+            "mean_iters": round(float(counts.mean()), 2), "reps": reps, "statistic": "median",
+            "batched_equals_plain_sampled_ops": len(sample)}
+
+
+def circulant_1024_latency(ncols=16, steps=2000, warmup=50):
+    """Forward + adjoint of the 1024-point circulant on 16 columns (complex64,
+    128 KiB per block; cache-resident and launch-bound): microseconds per
+    fwd+adj, as two fm_apply calls per step and as the same two calls
+    captured once in a graph and replayed. The replay is checked against the
+    eager result bit for bit."""
+    import torch
+
+    from paper_1710_09578_amd import capi
+    import paper_1710_09578_amd as fm
+    from workloads import circulant_1024
+
+    dev = torch.device("cuda:0")
+    c, x = circulant_1024(ncols=ncols)
+    C = fm.Circulant(torch.from_numpy(c).to(dev))
+    X = torch.from_numpy(x).to(dev)
+    Y = torch.empty_like(X)
+    Z = torch.empty_like(X)
+    n = c.size
+    h = C.handle
+
+    def step():
+        st = torch.cuda.current_stream().cuda_stream
+        capi.fm_apply(h, capi.FM_FWD, ncols, X, n, Y, n, None, 0, st)
+        capi.fm_apply(h, capi.FM_ADJ, ncols, Y, n, Z, n, None, 0, st)
+
+    ms_plain, ev_plain = time_steps(step, steps, warmup)
+    z_eager = Z.clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    Z.zero_()
+    ms_graph, ev_graph = time_steps(g.replay, steps, warmup)
+    same = torch.equal(Z, z_eager)
+    alg = 2 * (2 * X.numel() * 8 + n * 8)
+    log(f"circulant 1024 x {ncols}: {ev_plain * 1e3:.2f} us per fwd+adj (two fm_apply calls, events), "
+        f"{ev_graph * 1e3:.2f} us replayed from a graph; replay == eager: {same}")
+    if not same:
+        raise RuntimeError("graph replay of the circulant differs from the eager result")
+    return {"workload": f"Circulant N=1024, {ncols} CN(0,1) columns, complex64, fwd+adj",
+            "us_per_fwd_adj_plain": round(ev_plain * 1e3, 3), "us_per_fwd_adj_graph": round(ev_graph * 1e3, 3),
+            "us_per_fwd_adj_plain_wall": round(ms_plain * 1e3, 3), "us_per_fwd_adj_graph_wall": round(ms_graph * 1e3, 3),
+            "alg_bytes_per_step": int(alg), "steps": steps}
+
+
+def compressed_sensing_fista(iters=200, reps=3):
+    """FISTA on the row-selected Rademacher circulant (N = 65536, M = 4096
+    rows, 64-sparse truth, noise 1e-3, lam = 0.05 ||A^H b||_inf, 200
+    iterations), in complex64 and complex128: solves per second (median of
+    ``reps``), with the FP64 power iteration for L timed on its own."""
+    import torch
+
+    import paper_1710_09578_amd as fm
+    from workloads import compressed_sensing_65536
+
+    dev = torch.device("cuda:0")
+    w = compressed_sensing_65536()
+    n = w["c"].size
+    out = {"workload": "FISTA 200 it on S C(c): N=65536 Rademacher circulant, M=4096 rows, K=64, noise 1e-3, "
+                       "lam = 0.05 ||A^H b||_inf, one problem"}
+    for name, dt in (("c64", torch.complex64), ("c128", torch.complex128)):
+        rows = torch.from_numpy(w["rows"]).to(dev)
+        A = fm.Product(fm.SelectRows(n, rows, dt), fm.Circulant(torch.from_numpy(w["c"]).to(dev).to(dt)))
+        b = A.apply(torch.from_numpy(w["x_true"]).to(dev).to(dt)) + torch.from_numpy(w["noise"]).to(dev).to(dt)
+        fm.power_iteration(A)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L, pit = fm.power_iteration(A)
+        torch.cuda.synchronize()
+        t_pow = time.perf_counter() - t0
+        fm.fista(A, b, iters=iters, lam_rel=0.05, L=L)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            x, st = fm.fista(A, b, iters=iters, lam_rel=0.05, L=L)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        t = float(np.median(ts))
+        log(f"compressed sensing FISTA {iters} it ({name}): {t * 1e3:.3f} ms per solve, {1 / t:.1f} solves/s "
+            f"(median of {reps}); power iteration {t_pow * 1e3:.2f} ms ({pit} it, L = {L:.6g})")
+        out[name] = {"ms_per_solve": round(t * 1e3, 4), "solves_per_s": round(1 / t, 2),
+                     "power_iteration_ms": round(t_pow * 1e3, 3), "power_iterations": int(pit),
+                     "us_per_iteration": round(t / iters * 1e6, 2)}
+    return out
 
 
 def learn_circulant_steps(steps=5, warmup=2, iters=20, checkpoint=5):
@@ -251,7 +370,7 @@ def learn_circulant_steps(steps=5, warmup=2, iters=20, checkpoint=5):
     def run(kind):
         c = torch.from_numpy(d["c_init"]).to(dev).requires_grad_(True)
         opt = torch.optim.Adam([c], lr=1e-3)
-        betas = ag.momentum_weights(iters)
+        betas = [fm.capi.fm_fista_momentum(k) for k in range(iters)]
 
         def one():
             opt.zero_grad(set_to_none=True)
@@ -539,6 +658,61 @@ def cpu_baseline_toeplitz(w, budget_s=15.0):
                       f"dense-definition row blocks x BLAS in {dt:.1f} s"}
 
 
+def host_info():
+    """CPU model, core count available to this process and the BLAS NumPy uses."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = "unknown"
+    try:
+        cfg = np.show_config(mode="dicts")
+        bl = cfg.get("Build Dependencies", {}).get("blas", {})
+        blas = f"{bl.get('name', '?')} {bl.get('version', '')}".strip()
+    except Exception:
+        pass
+    return {"cpu_model": model, "cores": len(os.sched_getaffinity(0)), "blas": blas}
+
+
+def cpu_structured_toeplitz(w, budget_s=15.0):
+    """The same fast algorithm on the host: every sampled operator's
+    fwd + adj as zero-padded FFT convolutions (scipy.fft, complex64, all
+    cores), over the operators in order until the time budget is spent; the
+    stand-in for the paper's matrix-free CPU evaluation."""
+    import scipy.fft as sf
+
+    cores = len(os.sched_getaffinity(0))
+    data = w["data"]
+    done_bytes, used = 0, 0
+    t0 = time.time()
+    for i in range(len(w["ops"])):
+        d = data["ops"][i]
+        n = int(w["sizes"][i])
+        L = sf.next_fast_len(2 * n - 1)
+        g = np.zeros(L, np.complex64)
+        g[:n] = d["col"]
+        g[L - n + 1:] = d["row"][1:][::-1]
+        gh = sf.fft(g, workers=cores)
+        xp = np.zeros((d["x"].shape[0], L), np.complex64)
+        xp[:, :n] = d["x"]
+        y = sf.ifft(sf.fft(xp, axis=1, workers=cores) * gh, axis=1, workers=cores)[:, :n]
+        xp[:, :n] = y
+        xp[:, n:] = 0
+        sf.ifft(sf.fft(xp, axis=1, workers=cores) * np.conj(gh), axis=1, workers=cores)
+        done_bytes += 2 * (2 * n * int(w["ncols"][i]) * 8) + 2 * int(w["Ls"][i]) * 8
+        used += 1
+        if time.time() - t0 > budget_s:
+            break
+    dt = time.time() - t0
+    return {"value": done_bytes / dt / 1e9, "unit": "GB/s", "cores": cores, "kind": "structured (scipy.fft c64)",
+            "sample": f"{used} of the 512 operators in order, fwd+adj by zero-padded FFT convolution in {dt:.1f} s"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -553,6 +727,8 @@ def main():
     ap.add_argument("--no-ultrasound", action="store_true", help="skip the compressed ultrasound model")
     ap.add_argument("--no-omp", action="store_true", help="skip the OMP solves")
     ap.add_argument("--no-calib", action="store_true", help="skip the small-operator path calibration")
+    ap.add_argument("--no-c1", action="store_true", help="skip the 1024-point circulant on 16 columns")
+    ap.add_argument("--no-cs", action="store_true", help="skip the compressed-sensing FISTA solves")
     ap.add_argument("--no-tune", action="store_true", help="keep the default batch schedule")
     ap.add_argument("--schedule", default="", help="MAX_FUSE,REGION_MIB: fixed batch schedule (no tuning)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -624,6 +800,8 @@ def main():
             "kernel": "stage_kernel: all stage launches of one direction (fm_batch_apply)",
             "alg_bytes_per_launch": int(per_launch), "launch_ms": round(launch_ms, 4)}
     fres = None if args.no_fista else fista_solves(w, tune=not args.no_tune)
+    c1 = None if args.no_c1 else circulant_1024_latency()
+    cs = None if args.no_cs else compressed_sensing_fista()
     learn = None if args.no_learn else learn_circulant_steps()
     kron = None if args.no_kron else kron_hfg_bandwidth()
     wide = None if args.no_wide else circulant_wide_bandwidth()
@@ -634,10 +812,17 @@ def main():
     log(f"device copy: {copy_gbs:.1f} GB/s")
     roof["copy_gbs"] = round(copy_gbs, 1)
     roof["copy_frac"] = round(achieved / copy_gbs, 4)
-    cpu = None
+    cpu = cpu_struct = None
+    host = host_info()
+    log(f"host: {host}")
     if not args.no_cpu_baseline:
         cpu = cpu_baseline_toeplitz(w)
+        cpu.update({"cpu_model": host["cpu_model"], "blas": host["blas"]})
         log(f"cpu oracle baseline: {cpu['value']:.3f} GB/s on {cpu['cores']} cores")
+        cpu_struct = cpu_structured_toeplitz(w)
+        cpu_struct.update({"cpu_model": host["cpu_model"]})
+        log(f"cpu structured baseline: {cpu_struct['value']:.3f} GB/s on {cpu_struct['cores']} cores "
+            f"({cpu_struct['sample']})")
     out = {
         "metric": "batched fwd+adj operator GB/s (% HBM peak); FISTA solves/s, batched vs plain",
         "value": round(gbs, 2),
@@ -661,6 +846,8 @@ def main():
                    "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)},
         "roofline": roof,
         "fista": fres,
+        "circulant_1024x16": c1,
+        "compressed_sensing": cs,
         "learn_circulant": learn,
         "kron": kron,
         "wide_circulant": wide,
@@ -668,6 +855,8 @@ def main():
         "omp": ompr,
         "calibration": calib,
         "cpu_baseline": cpu,
+        "cpu_structured": cpu_struct,
+        "host": host,
     }
     print(json.dumps(out), flush=True)
 

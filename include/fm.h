@@ -411,20 +411,31 @@ fm_status fm_circulant_grad_generator(int64_t n, int64_t ncols, fm_dir use, cons
                                       int64_t ld_in, const void* g, int64_t ld_g, void* grad_c,
                                       int32_t accumulate, fm_dtype dt, void* stream);
 
+/* Momentum weight of FISTA iteration `iter` (0-based: the weight applied
+ * after the (iter+1)-th gradient step), the accelerated form of the solver of
+ * eq. (8): t_1 = 1, t_{j+1} = (1 + sqrt(1 + 4 t_j^2))/2, beta = (t_{iter+1} - 1)
+ * / t_{iter+2} (0 for iter = 0), formed in FP64 by the recurrence; 0 when
+ * momentum = 0 (ISTA). The same value fm_fista, fm_batch_fista and
+ * fm_fista_step use. beta: HOST output. */
+fm_status fm_fista_momentum(int32_t iter, int32_t momentum, double* beta);
+
 /* One proximal-gradient step of the solver of eq. (8) on DEVICE blocks of
  * ncols columns of n entries (all with leading dimension ld), given the
- * gradient g = A^H (A y - b):
+ * gradient g = A^H (A y - b), as iteration `iter` (0-based) of the solve:
  *   z = y - g / L,  x_new = soft(z, lam[j] / L),  y_new = x_new + beta (x_new - x_old)
- * soft(z, s) = z (|z| - s)/|z| for |z| > s, else 0 (complex modulus). lam:
- * DEVICE array of ncols doubles. z_out (may be NULL) receives z. x_new may be
- * x_old and y_new may be y (elementwise in place); x_new, y_new and z_out must
- * not overlap each other. The arithmetic is that of fm_fista's update, so a
- * step recomputed from the same inputs gives the same bits. Stream-ordered. */
+ * with beta the momentum weight of that iteration (fm_fista_momentum; 0 when
+ * momentum = 0). soft(z, s) = z (|z| - s)/|z| for |z| > s, else 0 (complex
+ * modulus). lam: DEVICE array of ncols doubles. z_out (may be NULL) receives
+ * z. x_new may be x_old and y_new may be y (elementwise in place); x_new, y_new
+ * and z_out must not overlap each other. The arithmetic is that of fm_fista's
+ * update, so a step recomputed from the same inputs gives the same bits.
+ * iter < 0 or L <= 0 is rejected. Stream-ordered. */
 fm_status fm_fista_step(int64_t n, int64_t ncols, const void* y, const void* g, const void* x_old,
                         void* x_new, void* y_new, void* z_out, int64_t ld, const double* lam,
-                        double L, double beta, fm_dtype dt, void* stream);
+                        double L, int32_t iter, int32_t momentum, fm_dtype dt, void* stream);
 
-/* Vector-Jacobian product of fm_fista_step. Given z of the forward step and
+/* Vector-Jacobian product of fm_fista_step (iteration `iter`, momentum weight
+ * beta as there). Given z of the forward step and
  * the upstream gradients gx_new, gy_new of x_new, y_new, with
  * xt = gx_new + (1 + beta) gy_new and s = lam[j]/L:
  *   gz     = xt (1 - s/(2|z|)) + conj(xt) s z^2 / (2 |z|^3)   if |z| > s, else 0
@@ -435,7 +446,8 @@ fm_status fm_fista_step(int64_t n, int64_t ncols, const void* y, const void* g, 
  * are rejected. Same layout rules as fm_fista_step. Stream-ordered. */
 fm_status fm_fista_step_vjp(int64_t n, int64_t ncols, const void* z, const void* gx_new,
                             const void* gy_new, void* gz, void* gg, void* gx_old, int64_t ld,
-                            const double* lam, double L, double beta, fm_dtype dt, void* stream);
+                            const double* lam, double L, int32_t iter, int32_t momentum, fm_dtype dt,
+                            void* stream);
 
 /* out = alpha x + beta y on DEVICE blocks (real alpha, beta; complex dtypes).
  * out may be x or y with the same leading dimension. Stream-ordered. */

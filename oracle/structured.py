@@ -147,15 +147,18 @@ def toeplitz_apply_fft64(col, row, x, adjoint_dir: bool = False, L: int | None =
     return np.fft.ifft(np.fft.fft(xp, axis=1) * gh[None, :], axis=1)[:, :m]
 
 
-def toeplitz_fista_fft64(col, row, b, lam, L, iters, momentum=True, stop_tol=0.0):
+def toeplitz_fista_fft64(col, row, b, lam, L, iters, momentum=True, stop_tol=0.0, embed: int | None = None,
+                         history: bool = False):
     """FISTA of ``fista.fista_op`` with the Toeplitz products done by
-    ``toeplitz_apply_fft64``; for batches too large for dense products."""
+    ``toeplitz_apply_fft64``; for batches too large for dense products.
+    ``embed``: the cyclic length of the products (any L >= M + N - 1 gives the
+    same products; a power of two is faster for numpy.fft)."""
     from .fista import fista_op
 
     n = np.asarray(row).shape[0]
-    return fista_op(lambda v: toeplitz_apply_fft64(col, row, v),
-                    lambda v: toeplitz_apply_fft64(col, row, v, adjoint_dir=True),
-                    n, b, lam, L, iters, momentum=momentum, stop_tol=stop_tol)
+    return fista_op(lambda v: toeplitz_apply_fft64(col, row, v, L=embed),
+                    lambda v: toeplitz_apply_fft64(col, row, v, adjoint_dir=True, L=embed),
+                    n, b, lam, L, iters, momentum=momentum, stop_tol=stop_tol, history=history)
 
 
 def select_circulant_fft64(c, rows):

@@ -97,16 +97,6 @@ def circulant_apply(c: torch.Tensor, x: torch.Tensor, adjoint: bool = False) -> 
 
 
 # ---------------------------------------------------------------- unrolled FISTA
-def momentum_weights(iters: int, momentum: bool = True):
-    """beta_k = (t_k - 1)/t_{k+1}, t_1 = 1, t_{k+1} = (1 + sqrt(1 + 4 t_k^2))/2."""
-    betas, t = [], 1.0
-    for _ in range(iters):
-        tn = (1.0 + (1.0 + 4.0 * t * t) ** 0.5) / 2.0
-        betas.append((t - 1.0) / tn if momentum else 0.0)
-        t = tn
-    return betas
-
-
 class _Problem:
     """A = S C(c) (S omitted without rows) and the buffers of one solve."""
 
@@ -137,9 +127,9 @@ class _Problem:
             self.S.apply(r, adjoint=True, out=v)
         self.C.apply(v, adjoint=True, out=g)
 
-    def step(self, y, g, x_old, x_new, y_new, z, lam, L, beta):
-        capi.fm_fista_step(self.n, self.ncols, y, g, x_old, x_new, y_new, z, self.n, lam, L, beta, self.dt,
-                           _stream())
+    def step(self, y, g, x_old, x_new, y_new, z, lam, L, k, momentum):
+        capi.fm_fista_step(self.n, self.ncols, y, g, x_old, x_new, y_new, z, self.n, lam, L, k, int(momentum),
+                           self.dt, _stream())
 
 
 class _UnrolledFista(torch.autograd.Function):
@@ -155,7 +145,6 @@ class _UnrolledFista(torch.autograd.Function):
             lam = lam.expand(ncols).contiguous()
         if L is None:
             L = capi.fm_op_norm_bound(P.A.handle, _stream())
-        betas = momentum_weights(iters, momentum)
         x = torch.zeros((ncols, P.n), dtype=P.dtype, device=P.dev)
         y = x.clone()
         xn, yn, g, v = P.block(), P.block(), P.block(), P.block()
@@ -165,16 +154,16 @@ class _UnrolledFista(torch.autograd.Function):
             if k % checkpoint == 0:
                 ckpts.append((x.clone(), y.clone()))
             P.gradient(y, bb, r, v, g)
-            P.step(y, g, x, xn, yn, None, lam, L, betas[k])
+            P.step(y, g, x, xn, yn, None, lam, L, k, momentum)
             x, xn = xn, x
             y, yn = yn, y
-        ctx.P, ctx.lam, ctx.L, ctx.betas, ctx.ckpts = P, lam, float(L), betas, ckpts
+        ctx.P, ctx.lam, ctx.L, ctx.momentum, ctx.ckpts = P, lam, float(L), int(momentum), ckpts
         ctx.iters, ctx.checkpoint, ctx.bb = iters, checkpoint, bb
         return x
 
     @staticmethod
     def backward(ctx, gx_out):
-        P, lam, L, betas = ctx.P, ctx.lam, ctx.L, ctx.betas
+        P, lam, L, mom = ctx.P, ctx.lam, ctx.L, ctx.momentum
         K, seg = ctx.iters, ctx.checkpoint
         need_c, need_b = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
         nc, n, m = P.ncols, P.n, P.m
@@ -199,13 +188,13 @@ class _UnrolledFista(torch.autograd.Function):
                 j = k - s0
                 P.gradient(Y[j][:nc], ctx.bb, r, U[j][nc:], g)
                 yn = Y[j + 1][:nc] if k + 1 < s1 else P.block()
-                P.step(Y[j][:nc], g, x, xs, yn, Z[j], lam, L, betas[k])
+                P.step(Y[j][:nc], g, x, xs, yn, Z[j], lam, L, k, mom)
                 x, xs = xs, x
             for k in range(s1 - 1, s0 - 1, -1):
                 j = k - s0
                 gbar = Y[j][nc:]
                 # xbar <- gz (gradient of z_k), ybar <- -beta_k ybar (x_k part), gbar = -gz/L
-                capi.fm_fista_step_vjp(n, nc, Z[j], xbar, ybar, xbar, gbar, ybar, n, lam, L, betas[k],
+                capi.fm_fista_step_vjp(n, nc, Z[j], xbar, ybar, xbar, gbar, ybar, n, lam, L, k, mom,
                                        P.dt, _stream())
                 u = U[j][:nc]
                 if P.S is not None:

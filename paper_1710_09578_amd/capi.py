@@ -127,8 +127,9 @@ SIGNATURES = {
     "fm_batch_get_schedule": (ST, [P, C.POINTER(fm_batch_schedule)]),
     "fm_batch_set_schedule": (ST, [P, C.POINTER(fm_batch_schedule)]),
     "fm_circulant_grad_generator": (ST, [I64, I64, C.c_int, P, I64, P, I64, P, I32, C.c_int, P]),
-    "fm_fista_step": (ST, [I64, I64, P, P, P, P, P, P, I64, P, C.c_double, C.c_double, C.c_int, P]),
-    "fm_fista_step_vjp": (ST, [I64, I64, P, P, P, P, P, P, I64, P, C.c_double, C.c_double, C.c_int, P]),
+    "fm_fista_momentum": (ST, [I32, I32, C.POINTER(C.c_double)]),
+    "fm_fista_step": (ST, [I64, I64, P, P, P, P, P, P, I64, P, C.c_double, I32, I32, C.c_int, P]),
+    "fm_fista_step_vjp": (ST, [I64, I64, P, P, P, P, P, P, I64, P, C.c_double, I32, I32, C.c_int, P]),
     "fm_axpby": (ST, [I64, I64, C.c_double, P, I64, C.c_double, P, I64, P, I64, C.c_int, P]),
     "fm_op_norm_bound": (ST, [P, C.POINTER(C.c_double), P]),
     "fm_last_error": (C.c_char_p, []),
@@ -403,14 +404,20 @@ def fm_circulant_grad_generator(n, ncols, use, inp, ld_in, g, ld_g, grad_c, accu
           accumulate, dt, _ptr(stream))
 
 
-def fm_fista_step(n, ncols, y, g, x_old, x_new, y_new, z_out, ld, lam, L, beta, dt, stream):
+def fm_fista_momentum(it, momentum=1):
+    v = C.c_double()
+    _call("fm_fista_momentum", it, momentum, C.byref(v))
+    return v.value
+
+
+def fm_fista_step(n, ncols, y, g, x_old, x_new, y_new, z_out, ld, lam, L, it, momentum, dt, stream):
     _call("fm_fista_step", n, ncols, _ptr(y), _ptr(g), _ptr(x_old), _ptr(x_new), _ptr(y_new), _ptr(z_out),
-          ld, _ptr(lam), L, beta, dt, _ptr(stream))
+          ld, _ptr(lam), L, it, momentum, dt, _ptr(stream))
 
 
-def fm_fista_step_vjp(n, ncols, z, gx_new, gy_new, gz, gg, gx_old, ld, lam, L, beta, dt, stream):
+def fm_fista_step_vjp(n, ncols, z, gx_new, gy_new, gz, gg, gx_old, ld, lam, L, it, momentum, dt, stream):
     _call("fm_fista_step_vjp", n, ncols, _ptr(z), _ptr(gx_new), _ptr(gy_new), _ptr(gz), _ptr(gg), _ptr(gx_old),
-          ld, _ptr(lam), L, beta, dt, _ptr(stream))
+          ld, _ptr(lam), L, it, momentum, dt, _ptr(stream))
 
 
 def fm_axpby(n, ncols, alpha, x, ldx, beta, y, ldy, out, ldo, dt, stream):

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "batch.h"
+#include "solve.h"
 
 namespace fm {
 namespace {
@@ -274,12 +275,8 @@ extern "C" fm_status fm_batch_fista(fm_batch b, const void* const* bvec, const i
   // iteration are the same and replay from one captured graph per direction)
   {
     std::vector<float> betas(size_t(std::max(o->max_iters, 1)), 0.f);
-    double t = 1.0;
-    for (int k = 0; k < o->max_iters; ++k) {
-      const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
-      betas[size_t(k)] = float((t - 1.0) / tn);
-      t = tn;
-    }
+    const std::vector<double> w = fista_momentum_weights(o->max_iters);
+    for (int k = 0; k < o->max_iters; ++k) betas[size_t(k)] = float(w[size_t(k)]);
     if (b->s_beta.bytes < betas.size() * 4) {
       FM_HIP(hipStreamSynchronize(s));  // earlier work may still read the old array
       b->s_beta.reset();

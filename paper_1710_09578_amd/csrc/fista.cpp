@@ -265,11 +265,9 @@ fm_status fm_fista(fm_op a, int64_t ncols, const void* b, int64_t ldb, void* x, 
     FM_TRY(launch_fill_int(ncols, active, 1, s));
     FM_TRY(launch_fill_int(ncols, status, 0, s));
     FM_TRY(launch_fill_int(ncols, iters, o->max_iters, s));
-    double t = 1.0;
+    const std::vector<double> betas = fista_momentum_weights(o->max_iters);
     for (int k = 0; k < o->max_iters; ++k) {
-      const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
-      const double beta = (t - 1.0) / tn;
-      t = tn;
+      const double beta = betas[size_t(k)];
       FM_TRY(exec(a, false, e, bf, y, r, false, w, s));             // r = A y
       FM_TRY(launch_sub(e, m, ncols, b, ldb, r, m, active, s));     // r = A y - b
       FM_TRY(exec(a, true, e, ba, r, g, false, w, s));              // g = A^H r

@@ -479,12 +479,14 @@ fm_status fm_circulant_grad_generator(int64_t n, int64_t ncols, fm_dir use, cons
 }
 
 fm_status fm_fista_step(int64_t n, int64_t ncols, const void* y, const void* g, const void* x_old, void* x_new,
-                        void* y_new, void* z_out, int64_t ld, const double* lam, double L, double beta, fm_dtype dt,
-                        void* stream) {
+                        void* y_new, void* z_out, int64_t ld, const double* lam, double L, int32_t iter,
+                        int32_t momentum, fm_dtype dt, void* stream) {
   set_error("");
   FM_CHECK_ARG(dt == FM_C64 || dt == FM_C128, FM_E_DTYPE, "FISTA step needs a complex dtype");
   FM_CHECK_ARG(n >= 0 && ncols >= 0 && ld >= n, FM_E_SHAPE, "bad block shape");
   FM_CHECK_ARG(L > 0.0 && std::isfinite(L), FM_E_INVALID, "step constant L must be positive");
+  FM_CHECK_ARG(iter >= 0, FM_E_INVALID, "iteration index must be non-negative");
+  const double beta = fista_momentum(iter, momentum != 0);
   if (n == 0 || ncols == 0) return FM_OK;
   FM_CHECK_ARG(y && g && x_old && x_new && y_new && lam, FM_E_INVALID, "NULL pointer");
   const size_t bytes = block_bytes(n, ncols, ld, elem_size(dt));
@@ -502,12 +504,14 @@ fm_status fm_fista_step(int64_t n, int64_t ncols, const void* y, const void* g, 
 }
 
 fm_status fm_fista_step_vjp(int64_t n, int64_t ncols, const void* z, const void* gx_new, const void* gy_new,
-                            void* gz, void* gg, void* gx_old, int64_t ld, const double* lam, double L, double beta,
-                            fm_dtype dt, void* stream) {
+                            void* gz, void* gg, void* gx_old, int64_t ld, const double* lam, double L, int32_t iter,
+                            int32_t momentum, fm_dtype dt, void* stream) {
   set_error("");
   FM_CHECK_ARG(dt == FM_C64 || dt == FM_C128, FM_E_DTYPE, "FISTA step needs a complex dtype");
   FM_CHECK_ARG(n >= 0 && ncols >= 0 && ld >= n, FM_E_SHAPE, "bad block shape");
   FM_CHECK_ARG(L > 0.0 && std::isfinite(L), FM_E_INVALID, "step constant L must be positive");
+  FM_CHECK_ARG(iter >= 0, FM_E_INVALID, "iteration index must be non-negative");
+  const double beta = fista_momentum(iter, momentum != 0);
   if (n == 0 || ncols == 0) return FM_OK;
   FM_CHECK_ARG(z && gx_new && gy_new && gz && lam, FM_E_INVALID, "NULL pointer");
   const size_t bytes = block_bytes(n, ncols, ld, elem_size(dt));
@@ -529,6 +533,14 @@ fm_status fm_fista_step_vjp(int64_t n, int64_t ncols, const void* z, const void*
   else
     hipLaunchKernelGGL(step_vjp_kernel<double>, grid2(n, ncols), dim3(kTPB), 0, s, a);
   FM_LAUNCHED();
+  return FM_OK;
+}
+
+fm_status fm_fista_momentum(int32_t iter, int32_t momentum, double* beta) {
+  set_error("");
+  FM_CHECK_ARG(beta != nullptr, FM_E_INVALID, "NULL output");
+  FM_CHECK_ARG(iter >= 0, FM_E_INVALID, "iteration index must be non-negative");
+  *beta = fista_momentum(iter, momentum != 0);
   return FM_OK;
 }
 

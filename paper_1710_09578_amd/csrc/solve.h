@@ -1,9 +1,32 @@
 // Launch interfaces of the solver kernels (solve.hip).
 #pragma once
 
+#include <cmath>
+#include <vector>
+
 #include "kernels.h"
 
 namespace fm {
+
+// Momentum weights of the accelerated iteration (FISTA, Beck-Teboulle):
+// t_1 = 1, t_{j+1} = (1 + sqrt(1 + 4 t_j^2)) / 2, and iteration k (0-based,
+// the (k+1)-th gradient step) extrapolates with (t_{k+1} - 1) / t_{k+2}, so the
+// first weight is 0. FP64, by the recurrence in order: every caller (solver,
+// batched solver, single step) gets the same bits.
+inline std::vector<double> fista_momentum_weights(int iters) {
+  std::vector<double> out(size_t(iters > 0 ? iters : 0));
+  double t = 1.0;
+  for (int k = 0; k < iters; ++k) {
+    const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
+    out[size_t(k)] = (t - 1.0) / tn;
+    t = tn;
+  }
+  return out;
+}
+inline double fista_momentum(int k, bool momentum) {
+  if (!momentum || k < 0) return 0.0;
+  return fista_momentum_weights(k + 1)[size_t(k)];
+}
 
 struct UpdateArgs {
   void* x;        // iterate x_k (overwritten by x_{k+1})

@@ -86,11 +86,22 @@ def test_invalid_arguments_return_status(lib):
     assert st(lib, "fm_circulant_grad_generator", 12, 1, 0, None, 12, None, 12, C.c_void_p(16), 0, 1, None) == 5
     assert st(lib, "fm_circulant_grad_generator", 16, 1, 7, None, 16, None, 16, None, 0, 1, None) == 1  # direction
     assert st(lib, "fm_fista_step", 8, 1, None, None, None, None, None, None, 4, None,
-              C.c_double(1.0), C.c_double(0.0), 1, None) == 2  # ld < n
+              C.c_double(1.0), 0, 1, 1, None) == 2  # ld < n
     assert st(lib, "fm_fista_step", 8, 1, None, None, None, None, None, None, 8, None,
-              C.c_double(0.0), C.c_double(0.0), 1, None) == 1  # L <= 0
+              C.c_double(0.0), 0, 1, 1, None) == 1  # L <= 0
+    assert st(lib, "fm_fista_step", 8, 1, None, None, None, None, None, None, 8, None,
+              C.c_double(1.0), -1, 1, 1, None) == 1  # negative iteration index
     assert st(lib, "fm_fista_step_vjp", 8, 1, None, None, None, None, None, None, 8, None,
-              C.c_double(1.0), C.c_double(0.0), 4, None) == 3  # integer dtype
+              C.c_double(1.0), 0, 1, 4, None) == 3  # integer dtype
+    # momentum weights: the oracle's sequence (no GPU needed)
+    from oracle import fista as ofista
+
+    beta = C.c_double()
+    _, ref = ofista.momentum_sequence(40)
+    for k in (0, 1, 2, 7, 39):
+        assert st(lib, "fm_fista_momentum", k, 1, C.byref(beta)) == 0 and abs(beta.value - ref[k]) <= 1e-15
+    assert st(lib, "fm_fista_momentum", 5, 0, C.byref(beta)) == 0 and beta.value == 0.0
+    assert st(lib, "fm_fista_momentum", -1, 1, C.byref(beta)) == 1
     assert st(lib, "fm_axpby", 8, 1, C.c_double(1.0), None, 4, C.c_double(1.0), None, 8, None, 8, 1, None) == 2
     assert st(lib, "fm_op_norm_bound", None, None, None) == 1
     assert st(lib, "fm_omp", None, 1, None, 8, 4, C.c_double(0.0), None, 8, None, None, None, 0, None) == 1

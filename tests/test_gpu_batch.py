@@ -275,3 +275,97 @@ def test_batch_set_schedule(gpu):
             assert rel_err(to_host(ys[i]), structured.toeplitz_apply_fft64(col, row, x)) <= TOL["c64"]
     with pytest.raises(capi.FmError):
         batch.set_schedule(6, 48)
+
+
+def _pow2_at_least(v):
+    return 1 << int(np.ceil(np.log2(v)))
+
+
+def test_batch_fista_full_workload(gpu):
+    """The batched-FISTA workload itself: 512 Toeplitz operators (N
+    log-uniform in [256, 65536], 1-32 columns each), K = N/256-sparse truths,
+    noise 1e-3, 100 iterations, lam = 0.05 ||T^H b||_inf per column, stop
+    1e-5. Measurements b = T x_true + noise come from the oracle. Checked
+    against the FP64 oracle (its own L and lam, FFT64 products): a seeded
+    pair of columns of every operator with N <= 4096, and of one operator per
+    embedding length above 4096, so that every FISTA form of the stage kernel
+    (every strided factor of the four-step split) meets the oracle.
+
+    Each column must equal the oracle's iterate at the GPU's own iteration
+    count. The count itself is a decision taken on complex64 iterates: the
+    relative change ||x_k - x_{k-1}|| / ||x_k|| is compared with 1e-5, about
+    80 float32 ulps, so rounding moves the crossing by several iterations
+    where the change flattens out near the tolerance. The count is therefore
+    checked against the oracle's window: not before the first k whose FP64
+    relative change is <= 1e-5 (1 + s), not after the first k whose change is
+    <= 1e-5 (1 - s), s = 0.5 (the change carries the difference of two
+    iterate errors, up to ~2.5e-6 of ||x_k||). The per-length operators are
+    also solved by the plain fm_fista and must give the same bits and
+    counts."""
+    from workloads import toeplitz_batch
+
+    iters, tol, rel, band = 100, 1e-5, 0.05, 0.5
+    full = toeplitz_batch(with_fista=True)
+    sizes, ncols = full["sizes"], full["ncols"]
+    nops = len(sizes)
+    ops, bs = [], []
+    for i in range(nops):
+        d = full["ops"][i]
+        n = int(sizes[i])
+        b = structured.toeplitz_apply_fft64(d["col"], d["row"], d["x_true"], L=_pow2_at_least(2 * n - 1))
+        bs.append((b + d["noise"]).astype(np.complex64))
+        ops.append(gpu.Toeplitz(to_dev(d["col"]), to_dev(d["row"])))
+    bd = [to_dev(b) for b in bs]
+    batch = gpu.Batch(ops, list(ncols))
+    xs, st = batch.fista(bd, iters=iters, lam_rel=rel, stop_tol=tol)
+    first = np.concatenate([[0], np.cumsum(ncols)[:-1]])
+    # the checked columns
+    rng = np.random.default_rng(77)
+    lengths = {}
+    for i in range(nops):
+        lengths.setdefault(embedding_length(2 * int(sizes[i]) - 1), []).append(i)
+    chosen = [i for i in range(nops) if sizes[i] <= 4096]
+    per_length = [min(v, key=lambda i: (ncols[i], i)) for L, v in sorted(lengths.items()) if L > 4096]
+    worst = {"x": 0.0, "lam": 0.0, "L": 0.0}
+    stopped = same_count = 0
+    for i in chosen + per_length:
+        d = full["ops"][i]
+        n = int(sizes[i])
+        cols = np.sort(rng.choice(int(ncols[i]), min(2, int(ncols[i])), replace=False))
+        Lemb = embedding_length(2 * n - 1)
+        g = np.zeros(Lemb, np.complex128)
+        g[:n] = d["col"]
+        g[Lemb - n + 1:] = d["row"][1:][::-1]
+        L_o = float(np.max(np.abs(np.fft.fft(g))) ** 2)
+        emb = _pow2_at_least(2 * n - 1)
+        b = bs[i][cols]
+        lam_o = rel * np.max(np.abs(structured.toeplitz_apply_fft64(d["col"], d["row"], b, True, L=emb)), axis=1)
+        _, _, hist = structured.toeplitz_fista_fft64(d["col"], d["row"], b, lam_o, L_o, iters, embed=emb,
+                                                     history=True)
+        H = np.stack([np.zeros_like(hist[0])] + hist)           # x_0 .. x_iters
+        change = np.linalg.norm(H[1:] - H[:-1], axis=2) / np.maximum(np.linalg.norm(H[1:], axis=2), 1e-30)
+        got_x = to_host(xs[i])[cols]
+        for jj, j in enumerate(cols):
+            s = st[first[i] + j]
+            worst["L"] = max(worst["L"], abs(s["L"] - L_o) / L_o)
+            worst["lam"] = max(worst["lam"], abs(s["lam"] - lam_o[jj]) / lam_o[jj])
+            k = int(s["iters"])
+            r = change[:, jj]                                  # r[k-1]: change of iteration k
+            lo = np.flatnonzero(r <= tol * (1 + band))
+            hi = np.flatnonzero(r <= tol * (1 - band))
+            k_lo = int(lo[0]) + 1 if lo.size else iters
+            k_hi = int(hi[0]) + 1 if hi.size else iters
+            assert k_lo <= k <= k_hi, f"op {i} column {j}: stopped at {k}, oracle window [{k_lo}, {k_hi}]"
+            stopped += k < iters
+            same_count += k == (int(np.flatnonzero(r <= tol)[0]) + 1 if np.any(r <= tol) else iters)
+            e = rel_err(got_x[jj:jj + 1], H[k, jj:jj + 1])
+            worst["x"] = max(worst["x"], e)
+            assert e <= TOL["c64"], f"op {i} (N={n}, L={Lemb}) column {j} at iteration {k}: {e:.3e}"
+    assert worst["L"] <= 1e-12 and worst["lam"] <= TOL["c64"], worst
+    print(f"batched FISTA workload: {len(chosen) + len(per_length)} operators checked, worst {worst}, "
+          f"{stopped} columns stopped early, {same_count} at the oracle's own count")
+    # plain solver on the same operators: same bits, same counts
+    for i in per_length:
+        x_p, st_p = gpu.fista(ops[i], bd[i], iters=iters, lam_rel=rel, L=st[first[i]]["L"], stop_tol=tol)
+        assert np.array_equal(to_host(x_p), to_host(xs[i])), f"op {i}: batched solve differs from plain"
+        assert [s["iters"] for s in st_p] == [st[first[i] + j]["iters"] for j in range(int(ncols[i]))]

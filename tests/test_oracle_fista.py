@@ -66,6 +66,30 @@ def test_large_lambda_gives_zero():
     assert np.count_nonzero(x) == 0
 
 
+def test_lambda_just_below_max_gives_nonzero():
+    """The other side of the threshold: for lam slightly below
+    ||A^H b||_inf the first step already keeps the largest correlation (x_1 =
+    soft(A^H b / L, lam / L) from x_0 = 0), at the index of the largest
+    |A^H b|, and the solve stays nonzero. A rule that overstates the maximum
+    (e.g. A^T in place of A^H) fails either this test or the one above."""
+    a = crand(6, 9)
+    b = crand(3, 6)
+    lam_max = fista.lambda_rule(a, b, 1.0)
+    L = fista.spectral_norm_sq(a)
+    lam = (1.0 - 1e-6) * lam_max
+    x1, _ = fista.fista(a, b, lam, L, 1)
+    corr = np.abs((a.conj().T @ b.T).T)
+    for j in range(3):
+        nz = np.flatnonzero(x1[j])
+        assert nz.tolist() == [int(np.argmax(corr[j]))]
+    x, _ = fista.fista(a, b, lam, L, 50)
+    assert np.all(np.count_nonzero(x, axis=1) >= 1)
+    # the rule itself against a brute-force maximum over every entry of A^H b
+    for j in range(3):
+        best = max(abs(sum(np.conj(a[i, k]) * b[j, i] for i in range(6))) for k in range(9))
+        assert abs(lam_max[j] - best) <= 1e-12 * best
+
+
 @pytest.mark.parametrize("kind", ["fourier", "hadamard", "kron"])
 @pytest.mark.parametrize("momentum", [True, False])
 def test_orthogonal_operator_closed_form(kind, momentum):
@@ -222,3 +246,21 @@ def test_fista_op_matches_dense_form():
     L2, _ = fista.power_iteration_op(lambda v: ap(v[None])[0], lambda u: ad(u[None])[0],
                                      crand(64), 5000, 1e-15)
     assert abs(L2 - L) <= 1e-9 * L
+
+
+@pytest.mark.parametrize("embed", [None, 64])
+def test_toeplitz_fista_fft64_matches_dense_form(embed):
+    """The FFT64 Toeplitz solve (zero-padded cyclic products, any cyclic
+    length >= M + N - 1) equals FISTA with the dense Toeplitz matrix, with and
+    without per-column stopping."""
+    from oracle import structured
+
+    col, row = crand(20), crand(20)
+    a = dense.toeplitz(col, row)
+    b = crand(3, 20)
+    L = fista.spectral_norm_sq(a)
+    lam = fista.lambda_rule(a, b, 0.05)
+    for tol in (0.0, 1e-5):
+        x1, d1 = fista.fista(a, b, lam, L, 60, stop_tol=tol)
+        x2, d2 = structured.toeplitz_fista_fft64(col, row, b, lam, L, 60, stop_tol=tol, embed=embed)
+        assert np.allclose(x1, x2, atol=1e-12) and np.array_equal(d1, d2)
