@@ -245,6 +245,23 @@ fm_status fm_workspace_size(fm_op a, fm_dir dir, int64_t ncols, size_t* bytes);
 fm_status fm_apply(fm_op a, fm_dir dir, int64_t ncols, const void* x, int64_t ldx, void* y,
                    int64_t ldy, void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): fm_apply
+ * with its workspace taken from a fixed array of FM_NOALLOC_SCRATCH_BYTES
+ * (64 MiB) that the library holds on every device it runs on until the
+ * process ends. Same arguments, layout and results as fm_apply (the same
+ * kernels: identical bits). Makes no hipMalloc / hipFree call and no other
+ * allocation; the operator's twiddle tables are created with the operator.
+ * A call whose workspace (fm_workspace_size) exceeds the array returns
+ * FM_E_WORKSPACE before anything is enqueued. The array's device address is
+ * looked up on the first call on each device. All calls on one device share
+ * that device's array and its contents stay from the last call: calls that
+ * overlap in time on one device (different streams or threads without
+ * ordering) race on it and must be serialised by the caller. Stream-ordered. */
+#define FM_NOALLOC_SCRATCH_BYTES (64u << 20)
+fm_status fm_apply_noalloc(fm_op a, fm_dir dir, int64_t ncols, const void* x, int64_t ldx, void* y,
+                           int64_t ldy, void* stream);
+
 /* ------------------------------------------------------------------ FISTA / ISTA
  * Per column j of b (each column is its own problem), minimise
  *   1/2 ||A x_j - b_j||_2^2 + lambda_j ||x_j||_1

@@ -112,6 +112,7 @@ SIGNATURES = {
     "fm_op_release": (ST, [P]),
     "fm_workspace_size": (ST, [P, C.c_int, I64, C.POINTER(C.c_size_t)]),
     "fm_apply": (ST, [P, C.c_int, I64, P, I64, P, I64, P, C.c_size_t, P]),
+    "fm_apply_noalloc": (ST, [P, C.c_int, I64, P, I64, P, I64, P]),
     "fm_fista": (ST, [P, I64, P, I64, P, I64, C.POINTER(fm_fista_opts), C.POINTER(fm_fista_stat),
                       P, C.c_size_t, P]),
     "fm_fista_workspace_size": (ST, [P, I64, C.POINTER(fm_fista_opts), C.POINTER(C.c_size_t)]),
@@ -324,6 +325,13 @@ def fm_workspace_size(a, direction, ncols):
 
 def fm_apply(a, direction, ncols, x, ldx, y, ldy, ws, ws_bytes, stream):
     _call("fm_apply", a, direction, ncols, _ptr(x), ldx, _ptr(y), ldy, _ptr(ws), ws_bytes, _ptr(stream))
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def fm_apply_noalloc(a, direction, ncols, x, ldx, y, ldy, stream):
+    _call("fm_apply_noalloc", a, direction, ncols, _ptr(x), ldx, _ptr(y), ldy, _ptr(stream))
 
 
 def fm_fista_workspace_size(a, ncols, opts):

@@ -54,7 +54,25 @@ void destroy(fm_op_s* op) {
   delete op;
 }
 
+// The twiddle tables an operator's transforms read, created with the
+// operator so that applying it never allocates (both precisions: the power
+// iteration runs in complex128 whatever the operator's dtype).
+fm_status ensure_tables(const fm_op_s* op) {
+  if (op->dt != FM_C64 && op->dt != FM_C128) return FM_OK;
+  if (!twiddle_table(Elem::C64, kMaxLog) || !twiddle_table(Elem::C128, kMaxLog)) return FM_E_NOMEM;
+  for (Elem e : {Elem::C64, Elem::C128}) {
+    const Split& sp = e == Elem::C64 ? op->s32 : op->s64;
+    if (op->L > 0 && sp.mixed() && !twiddle_table_L(e, op->L)) return FM_E_NOMEM;
+  }
+  return FM_OK;
+}
+
 fm_status publish(fm_op_s* op, fm_op* out) {
+  fm_status st = ensure_tables(op);
+  if (st != FM_OK) {
+    destroy(op);
+    return st;
+  }
   register_op(op);
   *out = op;
   return FM_OK;
@@ -160,6 +178,52 @@ fm_status size_of(const fm_op_s* op, bool adj, int64_t ncols, size_t* bytes) {
   } while (0)
 
 }  // namespace
+
+// fm_apply with its checks; with may_allocate = false a missing or short
+// workspace is an error instead of a stream-ordered allocation.
+fm_status fm::apply_op(const fm_op_s* a, fm_dir dir, int64_t ncols, const void* x, int64_t ldx, void* y, int64_t ldy,
+                   void* ws, size_t ws_bytes, bool may_allocate, void* stream) {
+  set_error("");
+  CHECK_LIVE(a);
+  FM_CHECK_ARG(dir == FM_FWD || dir == FM_ADJ, FM_E_INVALID, "unknown direction");
+  FM_CHECK_ARG(ncols >= 0, FM_E_INVALID, "negative column count");
+  if (ncols == 0) return FM_OK;
+  const bool adj = dir == FM_ADJ;
+  const int64_t rin = in_rows(a, adj), rout = out_rows(a, adj);
+  FM_CHECK_ARG(x != nullptr && y != nullptr, FM_E_INVALID, "NULL data pointer");
+  FM_CHECK_ARG(ldx >= rin && ldy >= rout, FM_E_SHAPE,
+               "leading dimensions too small: ldx %lld (need %lld), ldy %lld (need %lld)",
+               (long long)ldx, (long long)rin, (long long)ldy, (long long)rout);
+  const size_t es = elem_size(a->dt);
+  const char* xb = static_cast<const char*>(x);
+  const char* yb = static_cast<const char*>(y);
+  const size_t xlen = size_t((ncols - 1) * ldx + rin) * es, ylen = size_t((ncols - 1) * ldy + rout) * es;
+  FM_CHECK_ARG(xb + xlen <= yb || yb + ylen <= xb, FM_E_ALIAS, "x and y overlap");
+  int dev = 0;
+  FM_TRY(current_device(&dev));
+  FM_CHECK_ARG(dev == a->device, FM_E_DEVICE, "operator lives on device %d, current is %d", a->device, dev);
+  size_t need = 0;
+  FM_TRY(size_of(a, adj, ncols, &need));
+  hipStream_t s = as_stream(stream);
+  void* wsp = ws;
+  bool own = false;
+  if (need > 0) {
+    if (may_allocate && ws == nullptr && ws_bytes == 0) {
+      FM_HIP(hipMallocAsync(&wsp, need, s));
+      own = true;
+    } else {
+      FM_CHECK_ARG(ws != nullptr && ws_bytes >= need, FM_E_WORKSPACE,
+                   "workspace of %zu bytes given, %zu needed", ws_bytes, need);
+    }
+  }
+  Batch b{ncols, 1, 1, ldx, rin, ldy, rout};
+  Workspace w;
+  w.base = static_cast<char*>(wsp);
+  w.cap = own ? need : ws_bytes;
+  fm_status st = exec(a, adj, elem_of(a->dt), b, x, y, false, w, s);
+  if (own) (void)hipFreeAsync(wsp, s);
+  return st;
+}
 
 extern "C" {
 
@@ -997,46 +1061,7 @@ fm_status fm_workspace_size(fm_op a, fm_dir dir, int64_t ncols, size_t* bytes) {
 
 fm_status fm_apply(fm_op a, fm_dir dir, int64_t ncols, const void* x, int64_t ldx, void* y,
                    int64_t ldy, void* ws, size_t ws_bytes, void* stream) {
-  set_error("");
-  CHECK_LIVE(a);
-  FM_CHECK_ARG(dir == FM_FWD || dir == FM_ADJ, FM_E_INVALID, "unknown direction");
-  FM_CHECK_ARG(ncols >= 0, FM_E_INVALID, "negative column count");
-  if (ncols == 0) return FM_OK;
-  const bool adj = dir == FM_ADJ;
-  const int64_t rin = in_rows(a, adj), rout = out_rows(a, adj);
-  FM_CHECK_ARG(x != nullptr && y != nullptr, FM_E_INVALID, "NULL data pointer");
-  FM_CHECK_ARG(ldx >= rin && ldy >= rout, FM_E_SHAPE,
-               "leading dimensions too small: ldx %lld (need %lld), ldy %lld (need %lld)",
-               (long long)ldx, (long long)rin, (long long)ldy, (long long)rout);
-  const size_t es = elem_size(a->dt);
-  const char* xb = static_cast<const char*>(x);
-  const char* yb = static_cast<const char*>(y);
-  const size_t xlen = size_t((ncols - 1) * ldx + rin) * es, ylen = size_t((ncols - 1) * ldy + rout) * es;
-  FM_CHECK_ARG(xb + xlen <= yb || yb + ylen <= xb, FM_E_ALIAS, "x and y overlap");
-  int dev = 0;
-  FM_TRY(current_device(&dev));
-  FM_CHECK_ARG(dev == a->device, FM_E_DEVICE, "operator lives on device %d, current is %d", a->device, dev);
-  size_t need = 0;
-  FM_TRY(size_of(a, adj, ncols, &need));
-  hipStream_t s = as_stream(stream);
-  void* wsp = ws;
-  bool own = false;
-  if (need > 0) {
-    if (ws == nullptr && ws_bytes == 0) {
-      FM_HIP(hipMallocAsync(&wsp, need, s));
-      own = true;
-    } else {
-      FM_CHECK_ARG(ws != nullptr && ws_bytes >= need, FM_E_WORKSPACE,
-                   "workspace of %zu bytes given, %zu needed", ws_bytes, need);
-    }
-  }
-  Batch b{ncols, 1, 1, ldx, rin, ldy, rout};
-  Workspace w;
-  w.base = static_cast<char*>(wsp);
-  w.cap = own ? need : ws_bytes;
-  fm_status st = exec(a, adj, elem_of(a->dt), b, x, y, false, w, s);
-  if (own) (void)hipFreeAsync(wsp, s);
-  return st;
+  return apply_op(a, dir, ncols, x, ldx, y, ldy, ws, ws_bytes, true, stream);
 }
 
 }  // extern "C"

@@ -143,4 +143,10 @@ inline int64_t in_rows(const fm_op_s* op, bool adj) { return adj ? op->m : op->n
 
 bool op_alive(const fm_op_s* op);
 
+// fm_apply with its argument checks. With may_allocate = false a workspace
+// that is missing or too small is an error (FM_E_WORKSPACE) instead of a
+// stream-ordered allocation.
+fm_status apply_op(const fm_op_s* a, fm_dir dir, int64_t ncols, const void* x, int64_t ldx, void* y, int64_t ldy,
+                   void* ws, size_t ws_bytes, bool may_allocate, void* stream);
+
 }  // namespace fm
