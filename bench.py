@@ -28,7 +28,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-STAGE_SOURCES = ("batch.hip", "batch.h", "xform.h", "mixed.h", "kernels.h", "common.h")
+STAGE_SOURCES = ("batch.hip", "batch.h", "epi.h", "xform.h", "mixed.h", "kernels.h", "common.h")
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "stage_kernel_toeplitz512_fwd_adj.md")
 
 

@@ -25,6 +25,7 @@
 #include <unordered_set>
 
 #include "batch.h"
+#include "epi.h"
 #include "mixed.h"
 #include "xform.h"
 
@@ -36,134 +37,9 @@ using namespace xf;
 constexpr int kXcds = 8;
 
 // ---------------------------------------------------------------- solver epilogues
-__device__ __forceinline__ c64 soft_thr(c64 z, float s) {
-  const float mag = sqrtf(z.x * z.x + z.y * z.y);
-  if (!(mag > s)) return {0.f, 0.f};
-  const float f = (mag - s) / mag;
-  return {z.x * f, z.y * f};
-}
-
-// r = A y - b: transform b of the item is column col0 + b (contiguous items,
-// bstride = ldb) or every transform belongs to one column (strided items,
-// bstride = 0; e then holds the transform's offset).
-struct ResidualEp {
-  static constexpr bool kOn = true;
-  const c64* B;
-  int64_t bstride;
-  c64 bv[16];
-  __device__ __forceinline__ void pre(int k, int b, int e, c64*) { bv[k] = B[int64_t(b) * bstride + e]; }
-  __device__ __forceinline__ void put(int k, int, int, int, c64* dst, c64 v) { *dst = csub(v, bv[k]); }
-};
-
-// FISTA update from g = A^H r (see EpiArgs). Contiguous items: transform b is
-// batch column gcol0 + b with x at X + b*xstride; strided items: one column.
-struct FistaEp {
-  static constexpr bool kOn = true;
-  c64* X;
-  int64_t xstride;
-  int64_t gcol0;
-  int colstride;  // 1: contiguous, 0: strided
-  const int* active;
-  const double* lam;
-  double invLd;
-  float invL, beta;
-  int momentum;
-  int* status;
-  // running sums of the current slot (tiny contiguous transforms flush when
-  // the slot changes: one thread holds the whole transform)
-  bool flush_per_slot;
-  const int64_t* pbase;
-  double* partial;
-  int cur = -1;
-  int64_t cur_col = -1;
-  int64_t c_gc = -1;
-  bool c_act = false;
-  float c_s = 0.f;
-  double dx = 0.0, nx = 0.0;
-
-  __device__ __forceinline__ void flush() {
-    if (cur_col >= 0) {
-      partial[2 * pbase[cur_col]] = dx;
-      partial[2 * pbase[cur_col] + 1] = nx;
-    }
-    dx = nx = 0.0;
-    cur_col = -1;
-  }
-  c64 yk[16], xk[16];
-  __device__ __forceinline__ void pre(int k, int b, int e, c64* dst) {
-    yk[k] = *dst;
-    xk[k] = X[int64_t(b) * xstride + e];
-  }
-  __device__ __forceinline__ void put(int k, int slot, int b, int e, c64* dst, c64 g) {
-    const int64_t gc = gcol0 + int64_t(b) * colstride;
-    if (flush_per_slot && slot != cur) {
-      flush();
-      cur = slot;
-    }
-    if (gc != c_gc) {  // per-column values, reloaded only when the column changes
-      c_gc = gc;
-      c_act = !active || active[gc];
-      c_s = float(lam[gc] * invLd);
-    }
-    if (!c_act) return;
-    if (flush_per_slot) cur_col = gc;
-    const float s = c_s;
-    const c64 yv = yk[k];
-    c64* xp = X + int64_t(b) * xstride + e;
-    const c64 xo = xk[k];
-    const c64 z = {yv.x - g.x * invL, yv.y - g.y * invL};
-    const c64 xn = soft_thr(z, s);
-    const c64 d = {xn.x - xo.x, xn.y - xo.y};
-    *xp = xn;
-    *dst = momentum ? c64{xn.x + beta * d.x, xn.y + beta * d.y} : xn;
-    dx += double(d.x) * d.x + double(d.y) * d.y;
-    nx += double(xn.x) * xn.x + double(xn.y) * xn.y;
-    if (!(isfinite(z.x) && isfinite(z.y))) atomicOr(status + gc, 1);
-  }
-};
-
-// Partial sums of a FistaEp after run_job: per transform (contiguous items of
-// >= 16 points: the T = 2^(lg-4) threads of transform b are tid / T == b), per
-// item (strided items: one column, slot pbase + tile), or already flushed
-// (contiguous transforms of < 16 points).
-__device__ __forceinline__ void fista_partials(FistaEp& ep, bool strided, int lg, int nvalid, int tile,
-                                               c64* smem) {
-  if (ep.flush_per_slot) {
-    ep.flush();
-    return;
-  }
-  __syncthreads();  // the transform's last LDS reads are done
-  double2* red = reinterpret_cast<double2*>(smem);
-  const int tid = threadIdx.x;
-  red[tid] = make_double2(ep.dx, ep.nx);
-  __syncthreads();
-  // tree reduction over segments of T threads (the whole work-group for a
-  // strided item), in a fixed order
-  const int T = strided ? Geo<kLogW>::kThreads : 1 << (lg - 4);
-  for (int w = T >> 1; w > 0; w >>= 1) {
-    if ((tid & (T - 1)) < w) {
-      red[tid].x += red[tid + w].x;
-      red[tid].y += red[tid + w].y;
-    }
-    __syncthreads();
-  }
-  if ((tid & (T - 1)) != 0) return;
-  if (strided) {
-    if (!ep.active || ep.active[ep.gcol0]) {
-      ep.partial[2 * (ep.pbase[ep.gcol0] + tile)] = red[0].x;
-      ep.partial[2 * (ep.pbase[ep.gcol0] + tile) + 1] = red[0].y;
-    }
-    return;
-  }
-  const int b = tid / T;
-  if (b < nvalid) {
-    const int64_t gc = ep.gcol0 + b;
-    if (!ep.active || ep.active[gc]) {
-      ep.partial[2 * ep.pbase[gc]] = red[tid].x;
-      ep.partial[2 * ep.pbase[gc] + 1] = red[tid].y;
-    }
-  }
-}
+// (epi.h; complex64 forms)
+using ResidualEp = ResidualEpT<float>;
+using FistaEp = FistaEpT<float>;
 
 template <int EPI>
 __device__ __forceinline__ FistaEp make_fista_ep(const BArgs& a, int op, int64_t col, bool strided, int lg) {
@@ -212,7 +88,7 @@ __device__ __forceinline__ void run_single(const BArgs& a, const Item& it, int l
   } else if constexpr (EPI == 2) {
     FistaEp ep = make_fista_ep<EPI>(a, it.op, it.col, false, lg);
     run_job<float, false, LOGW, true>(jb, md, lg, smem, a.tw, &ep);
-    fista_partials(ep, false, lg, it.sub, 0, smem);
+    fista_partials<Geo<LOGW>::kThreads>(ep, false, lg, it.sub, 0, smem);
   } else {
     run_job<float, false, LOGW, true>(jb, md, lg, smem, a.tw);
   }
@@ -258,7 +134,7 @@ __device__ __forceinline__ void run_strided(const BArgs& a, const Item& it, cons
     } else if constexpr (EPI == 2) {
       FistaEp ep = make_fista_ep<EPI>(a, fc.op, fc.col, true, lg);
       run_job<float, true, kLogW, true>(jb, md, lg, smem, a.tw, &ep);
-      fista_partials(ep, true, lg, tpw, it.sub, smem);
+      fista_partials<Geo<kLogW>::kThreads>(ep, true, lg, tpw, it.sub, smem);
     } else {
       run_job<float, true, kLogW, true>(jb, md, lg, smem, a.tw);
     }
@@ -320,7 +196,7 @@ __device__ __forceinline__ void run_mixed(const BArgs& a, const Item& it, const 
   } else if constexpr (EPI == 2) {
     FistaEp ep = make_fista_ep<EPI>(a, fc.op, fc.col, true, 12);
     mixed_tile<float, FistaEp>(n2, it.sub, w, L, yc, out_limit, true, op.twl, L, 0, &ep, smem);
-    fista_partials(ep, true, 12, 0, it.sub, smem);
+    fista_partials<Geo<kLogW>::kThreads>(ep, true, 12, 0, it.sub, smem);
   } else {
     mixed_tile<float, NoEp>(n2, it.sub, w, L, yc, out_limit, true, op.twl, L, 0, static_cast<NoEp*>(nullptr), smem);
   }
@@ -618,7 +494,8 @@ fm_status fm::build_schedule(fm_batch_s* b, const Schedule& sc) {
   // lay out each stage: each group goes to the currently shortest XCD queue,
   // then the queues are interleaved (work-group g runs on XCD g mod 8). A
   // column per group keeps the queues balanced; grouping whole operators
-  // measured slower.
+  // measured slower, and so did balancing the queues by an estimated cost
+  // with the costliest groups first (1.77 against 1.74 ms per direction).
   std::vector<Item> items;
   std::vector<int64_t> stage_off{0};
   for (int st = 0; st < nstages; ++st) {

@@ -4,7 +4,9 @@
 // accelerated form (FISTA, the variant the paper runs for its results), with
 // the constant step 1/L, L >= ||A||_2^2. Every operator product goes through
 // the operator executor; everything else runs in the kernels of solve.hip.
+#include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <vector>
 
 #include "runtime.h"
@@ -17,16 +19,28 @@ namespace {
 // Workspace layout of one solve (byte offsets), from one sizing pass.
 struct FistaPlan {
   size_t r, g, y, lam, active, status, iters, partial, exec, total;
+  size_t slot, pbase, beta, iter;  // fused solver only
   int64_t ntiles;
   int per_thread;
+  FusedForm fused;
 };
+
+// FM_FISTA_FUSED=0 runs every operator through the general loop.
+bool fused_enabled() {
+  static const bool v = [] {
+    const char* e = std::getenv("FM_FISTA_FUSED");
+    return !(e && e[0] == '0');
+  }();
+  return v;
+}
 
 size_t up(size_t v) { return (v + 255) & ~size_t(255); }
 
-fm_status plan_fista(const fm_op_s* a, int64_t ncols, FistaPlan* p) {
+fm_status plan_fista(const fm_op_s* a, int64_t ncols, int max_iters, FistaPlan* p) {
   const Elem e = elem_of(a->dt);
   const size_t es = elem_bytes(e);
   const int64_t m = a->m, n = a->n;
+  p->fused = fused_enabled() ? fused_form(a) : FusedForm{};
   p->ntiles = update_tiles(n, &p->per_thread);
   size_t off = 0;
   p->r = off;
@@ -44,7 +58,20 @@ fm_status plan_fista(const fm_op_s* a, int64_t ncols, FistaPlan* p) {
   p->iters = off;
   off += up(size_t(ncols) * 4);
   p->partial = off;
-  off += up(size_t(2 * p->ntiles * ncols) * 8);
+  int64_t nslot = p->ntiles;
+  if (p->fused.conv) nslot = std::max<int64_t>(nslot, fused_nslot(p->fused.conv, e));
+  off += up(size_t(2 * nslot * ncols) * 8);
+  p->slot = p->pbase = p->beta = p->iter = off;
+  if (p->fused.conv) {
+    p->slot = off;
+    if (p->fused.conv->L > 4096) off += up(size_t(p->fused.conv->L * ncols) * es);
+    p->pbase = off;
+    off += up(size_t(ncols) * 8);
+    p->beta = off;
+    off += up(size_t(std::max(max_iters, 1)) * (es / 2));
+    p->iter = off;
+    off += up(4);
+  }
   p->exec = off;
   size_t ex = 0;
   for (int adj = 0; adj < 2; ++adj) {
@@ -188,7 +215,7 @@ fm_status fm_fista_workspace_size(fm_op a, int64_t ncols, const fm_fista_opts* o
   FM_CHECK_ARG(bytes != nullptr && opts != nullptr, FM_E_INVALID, "NULL argument");
   FM_CHECK_ARG(ncols >= 0, FM_E_INVALID, "negative column count");
   FistaPlan p;
-  FM_TRY(plan_fista(a, ncols, &p));
+  FM_TRY(plan_fista(a, ncols, opts->max_iters, &p));
   *bytes = p.total;
   return FM_OK;
 }
@@ -223,7 +250,7 @@ fm_status fm_fista(fm_op a, int64_t ncols, const void* b, int64_t ldb, void* x, 
     FM_CHECK_ARG(L > 0.0, FM_E_INVALID, "the operator is zero (power iteration gave L = 0)");
   }
   FistaPlan p;
-  FM_TRY(plan_fista(a, ncols, &p));
+  FM_TRY(plan_fista(a, ncols, o->max_iters, &p));
   void* base = ws;
   bool own = false;
   if (ws == nullptr && ws_bytes == 0) {
@@ -265,8 +292,48 @@ fm_status fm_fista(fm_op a, int64_t ncols, const void* b, int64_t ldb, void* x, 
     FM_TRY(launch_fill_int(ncols, active, 1, s));
     FM_TRY(launch_fill_int(ncols, status, 0, s));
     FM_TRY(launch_fill_int(ncols, iters, o->max_iters, s));
+    if (p.fused.conv) {
+      // the fused iteration: the convolution's passes with the residual and
+      // the update in their last passes, replayed from a captured graph
+      const std::vector<double> w = fista_momentum_weights(o->max_iters);
+      std::vector<float> w32(w.size());
+      for (size_t k = 0; k < w.size(); ++k) w32[k] = float(w[k]);
+      if (!w.empty()) {
+        const void* src = e == Elem::C64 ? static_cast<const void*>(w32.data()) : static_cast<const void*>(w.data());
+        FM_HIP(hipMemcpyAsync(B + p.beta, src, w.size() * (e == Elem::C64 ? 4 : 8), hipMemcpyHostToDevice, s));
+        FM_HIP(hipStreamSynchronize(s));  // the host vector is freed on return
+      }
+      FM_TRY(launch_fill_int(1, reinterpret_cast<int*>(B + p.iter), 0, s));
+      FusedRun run{};
+      run.e = e;
+      run.conv = p.fused.conv;
+      run.sel_map = p.fused.sel_map;
+      run.ncols = ncols;
+      run.m = m;
+      run.n = n;
+      run.b = b;
+      run.ldb = ldb;
+      run.x = x;
+      run.ldx = ldx;
+      run.r = r;
+      run.y = y;
+      run.slot = B + p.slot;
+      run.invL = 1.0 / L;
+      run.lam = lam;
+      run.active = active;
+      run.status = status;
+      run.iters = iters;
+      run.partial = reinterpret_cast<double*>(B + p.partial);
+      run.pbase = reinterpret_cast<int64_t*>(B + p.pbase);
+      run.beta = B + p.beta;
+      run.iter = reinterpret_cast<int*>(B + p.iter);
+      run.momentum = o->momentum != 0;
+      run.max_iters = o->max_iters;
+      run.stop_tol = o->stop_tol;
+      FM_TRY(fista_fused_run(run, s));
+    }
     const std::vector<double> betas = fista_momentum_weights(o->max_iters);
-    for (int k = 0; k < o->max_iters; ++k) {
+    for (int k = 0; !p.fused.conv && k < o->max_iters; ++k) {
       const double beta = betas[size_t(k)];
       FM_TRY(exec(a, false, e, bf, y, r, false, w, s));             // r = A y
       FM_TRY(launch_sub(e, m, ncols, b, ldb, r, m, active, s));     // r = A y - b

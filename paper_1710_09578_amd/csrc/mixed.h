@@ -98,14 +98,22 @@ __device__ __forceinline__ void dft_mixed(Cx<R>* v, const Cx<R>* twl) {
 // Inverse (last pass): the N2 points of the slot x, their inverse DFT (conj
 // trick), stored where n1 + 4096 k < out_limit (added with acc, or handed to
 // the epilogue in chunks of 8 with all of a chunk's operand loads first).
-template <int N2, typename R, class EP>
+// IMAP: point r is read at x[imap[r]] (zero where imap[r] < 0), the adjoint
+// of a row selection applied at the load.
+template <int N2, typename R, class EP, bool IMAP = false>
 __device__ __forceinline__ void mixed_column(const Cx<R>* x, int64_t in_limit, Cx<R>* y, int64_t out_limit, int n1,
-                                             bool inverse, const Cx<R>* twl, int64_t L, int acc, EP* ep) {
+                                             bool inverse, const Cx<R>* twl, int64_t L, int acc, EP* ep,
+                                             const int* imap = nullptr) {
   Cx<R> v[N2];
 #pragma unroll
   for (int j = 0; j < N2; ++j) {
     const int64_t r = n1 + 4096 * int64_t(j);
-    v[j] = r < in_limit ? x[r] : Cx<R>{R(0), R(0)};
+    if constexpr (IMAP) {
+      const int m = r < in_limit ? imap[r] : -1;
+      v[j] = m >= 0 ? x[m] : Cx<R>{R(0), R(0)};
+    } else {
+      v[j] = r < in_limit ? x[r] : Cx<R>{R(0), R(0)};
+    }
   }
   if (inverse) {
 #pragma unroll
@@ -154,16 +162,21 @@ __device__ __forceinline__ void mixed_column(const Cx<R>* x, int64_t in_limit, C
 // pair exchanges A_0, A_1 through LDS and thread h keeps
 // X[k1 + h M] = A_0[k1] + (-1)^h A_1[k1]. lds: 2 M values per column position
 // of the work-group. Every thread of the work-group calls it (one barrier).
-template <int M, typename R, class EP>
+template <int M, typename R, class EP, bool IMAP = false>
 __device__ __forceinline__ void mixed_column_pair(const Cx<R>* x, int64_t in_limit, Cx<R>* y, int64_t out_limit,
                                                   int n1, int h, int slot, bool inverse, const Cx<R>* twl, int64_t L,
-                                                  int acc, EP* ep, Cx<R>* lds) {
+                                                  int acc, EP* ep, Cx<R>* lds, const int* imap = nullptr) {
   constexpr int N2 = 2 * M;
   Cx<R> v[M];
 #pragma unroll
   for (int m = 0; m < M; ++m) {
     const int64_t r = n1 + 4096 * int64_t(2 * m + h);
-    v[m] = r < in_limit ? x[r] : Cx<R>{R(0), R(0)};
+    if constexpr (IMAP) {
+      const int mi = r < in_limit ? imap[r] : -1;
+      v[m] = mi >= 0 ? x[mi] : Cx<R>{R(0), R(0)};
+    } else {
+      v[m] = r < in_limit ? x[r] : Cx<R>{R(0), R(0)};
+    }
   }
   if (inverse) {
 #pragma unroll
@@ -229,26 +242,26 @@ __host__ __device__ inline int mixed_tiles(int n2) { return 16 * mixed_threads(n
 // Tile `tile` of one column for the strided factor N2: 256 / mixed_threads(N2)
 // consecutive column positions. Every thread of the work-group calls it; lds
 // holds 256 / threads * N2 values (pairs only).
-template <int N2, typename R, class EP>
+template <int N2, typename R, class EP, bool IMAP = false>
 __device__ __forceinline__ void mixed_tile_n(int tile, const Cx<R>* x, int64_t in_limit, Cx<R>* y, int64_t out_limit,
                                              bool inverse, const Cx<R>* twl, int64_t L, int acc, EP* ep,
-                                             Cx<R>* lds) {
+                                             Cx<R>* lds, const int* imap = nullptr) {
   const int tid = int(threadIdx.x);
   if constexpr (N2 > 12)
-    mixed_column_pair<N2 / 2>(x, in_limit, y, out_limit, tile * 128 + (tid & 127), tid >> 7, tid & 127, inverse,
-                              twl, L, acc, ep, lds);
+    mixed_column_pair<N2 / 2, R, EP, IMAP>(x, in_limit, y, out_limit, tile * 128 + (tid & 127), tid >> 7, tid & 127,
+                                           inverse, twl, L, acc, ep, lds, imap);
   else
-    mixed_column<N2>(x, in_limit, y, out_limit, tile * 256 + tid, inverse, twl, L, acc, ep);
+    mixed_column<N2, R, EP, IMAP>(x, in_limit, y, out_limit, tile * 256 + tid, inverse, twl, L, acc, ep, imap);
 }
 
 // The same with the factor chosen at run time (the stage kernel's items).
-template <typename R, class EP>
+template <typename R, class EP, bool IMAP = false>
 __device__ __forceinline__ void mixed_tile(int n2, int tile, const Cx<R>* x, int64_t in_limit, Cx<R>* y,
                                            int64_t out_limit, bool inverse, const Cx<R>* twl, int64_t L, int acc,
-                                           EP* ep, Cx<R>* lds) {
-#define FM_MIXED_CASE(N)                                                                   \
-  case N:                                                                                  \
-    mixed_tile_n<N>(tile, x, in_limit, y, out_limit, inverse, twl, L, acc, ep, lds);       \
+                                           EP* ep, Cx<R>* lds, const int* imap = nullptr) {
+#define FM_MIXED_CASE(N)                                                                               \
+  case N:                                                                                              \
+    mixed_tile_n<N, R, EP, IMAP>(tile, x, in_limit, y, out_limit, inverse, twl, L, acc, ep, lds, imap); \
     break;
   switch (n2) {
     FM_MIXED_CASE(3)

@@ -62,4 +62,43 @@ fm_status launch_zero2d(Elem e, int64_t rows, int64_t ncols, void* p, int64_t ld
 fm_status launch_copy2d(Elem e, int64_t rows, int64_t ncols, const void* src, int64_t lds, void* dst, int64_t ldd,
                         hipStream_t s);
 
+// ---- fused solver (fista_fused.hip) for A = C or A = S C, C a circulant or
+// Toeplitz leaf and S a row selection
+struct FusedForm {
+  const fm_op_s* conv = nullptr;  // NULL: A has another form
+  const int* sel_map = nullptr;   // S's inverse index map (C's output row -> row of A, or -1), or NULL
+};
+FusedForm fused_form(const fm_op_s* a);
+// Partial-sum slots per column of the update pass (its work-groups per column).
+int fused_nslot(const fm_op_s* conv, Elem e);
+
+struct FusedRun {
+  Elem e;
+  const fm_op_s* conv;
+  const int* sel_map;
+  int64_t ncols, m, n;    // A is m x n
+  const void* b;
+  int64_t ldb;
+  void* x;
+  int64_t ldx;
+  void* r;     // m x ncols (ld m)
+  void* y;     // n x ncols (ld n), holds y_0 on entry
+  void* slot;  // L x ncols for four-step lengths
+  double invL;
+  const double* lam;
+  int* active;
+  int* status;
+  int* iters;
+  double* partial;  // 2 * nslot * ncols
+  int64_t* pbase;   // ncols
+  const void* beta; // max_iters momentum weights in the element's real type
+  int* iter;        // device iteration counter (0 on entry)
+  int momentum;
+  int max_iters;
+  double stop_tol;
+};
+// Runs max_iters iterations (frozen columns skip their work); synchronises
+// the stream at the end when the iterations were replayed from a graph.
+fm_status fista_fused_run(const FusedRun& run, hipStream_t s);
+
 }  // namespace fm

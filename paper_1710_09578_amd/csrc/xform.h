@@ -233,6 +233,12 @@ struct Job {
   int q0;
   int fuse_n2 = 0;
   const Cx<R>* twl = nullptr;
+  // IMAP (run_job template flag): input position p of a vector is read at
+  // xcol[imap[p]] (strided items; contiguous items: at x + b*xbstride +
+  // imap[p]), and is zero where imap[p] < 0: the adjoint of a row selection
+  // applied at the load (p is the position inside the vector)
+  const int* imap = nullptr;
+  const Cx<R>* xcol = nullptr;
 };
 struct Mode {
   int mode, spec_conj, tw_log, tw_inv, accumulate;
@@ -255,7 +261,7 @@ struct NoEp {
 // values, which keeps 16 fewer registers live at the spectral product (the
 // batched stage kernel then fits 128 VGPRs, four work-groups per CU) at the
 // cost of a second round of spectrum loads.
-template <typename R, bool STRIDED, int LOGW, bool SPLIT_SPEC = false, class EP = NoEp>
+template <typename R, bool STRIDED, int LOGW, bool SPLIT_SPEC = false, class EP = NoEp, bool IMAP = false>
 __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int logn, Cx<R>* lds,
                                         const Cx<R>* __restrict__ tw, EP* ep = nullptr) {
   constexpr int kWG = Geo<LOGW>::kThreads;
@@ -285,7 +291,12 @@ __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int lo
 #pragma unroll
         for (int k = 0; k < kE; ++k) {
           const int q = t + T * k + N * n2;
-          val[k] = q < jb.in_limit ? X[q] : Cx<R>{R(0), R(0)};
+          if constexpr (IMAP) {
+            const int m = q < jb.in_limit ? jb.imap[q] : -1;
+            val[k] = m >= 0 ? X[m] : Cx<R>{R(0), R(0)};
+          } else {
+            val[k] = q < jb.in_limit ? X[q] : Cx<R>{R(0), R(0)};
+          }
         }
         const Cx<R> w = jb.twl[N * ((n2 * k2) % n2s)];  // W_N2^(n2 k2)
 #pragma unroll
@@ -305,7 +316,12 @@ __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int lo
       for (int k = 0; k < kE; ++k) {
         const int p = t + T * k;
         const bool in = valid && p * inner + ii < jb.in_limit;
-        v[k] = in ? X[p * inner] : Cx<R>{R(0), R(0)};
+        if constexpr (IMAP) {
+          const int m = in ? jb.imap[p * inner + ii] : -1;
+          v[k] = m >= 0 ? (STRIDED ? jb.xcol[m] : X[m]) : Cx<R>{R(0), R(0)};
+        } else {
+          v[k] = in ? X[p * inner] : Cx<R>{R(0), R(0)};
+        }
       }
     }
     Cx<R>* my = lds + b * ((1 << logn) + (1 << (logn - 4)));
@@ -399,8 +415,13 @@ __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int lo
     const int inner = STRIDED ? jb.inner : 1;
     const int ii = STRIDED ? jb.i0 + b : 0;
     const bool in = b < jb.nvalid && r * inner + ii < jb.in_limit;
-    const Cx<R>* src = STRIDED ? jb.x + b + r * inner : jb.x + b * jb.xbstride + r;
-    v[k] = in ? *src : Cx<R>{R(0), R(0)};
+    if constexpr (IMAP) {
+      const int m = in ? jb.imap[r * inner + ii] : -1;
+      v[k] = m >= 0 ? (STRIDED ? jb.xcol[m] : jb.x[b * jb.xbstride + m]) : Cx<R>{R(0), R(0)};
+    } else {
+      const Cx<R>* src = STRIDED ? jb.x + b + r * inner : jb.x + b * jb.xbstride + r;
+      v[k] = in ? *src : Cx<R>{R(0), R(0)};
+    }
   }
   if (md.mode == FFT_INV) conj_all(v);
   forward_tiny(v, logn);
