@@ -586,26 +586,45 @@ def omp_solves(ncols=64, k=64, reps=3):
 
 
 def calibration_small(ncols=65536):
-    """Run-time path choice for small operators on many columns: the times of
-    the structured and the dense evaluation and the path kept."""
+    """Run-time path choice for small operators: the device's calibration
+    model (structured vs dense, the dense product of complex64 on the matrix
+    cores) measured once over its grid, where the dense path wins, and the
+    per-handle timing of three examples on many columns."""
     import torch
 
     import paper_1710_09578_amd as fm
 
     dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    table = fm.calibration_build()
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    names = {0: "circulant", 1: "toeplitz", 2: "fourier"}
+    dense_wins = {}
+    for e in table:
+        if e["ms_dense"] < e["ms_fast"]:
+            key = f"{names[e['cls']]}_{'c64' if e['dt'] == 1 else 'c128'}"
+            dense_wins.setdefault(key, []).append([e["n"], e["ncols"], round(e["ms_fast"] / e["ms_dense"], 2)])
+    log(f"calibration model: {len(table)} grid points in {build_s:.2f} s; dense wins (n, ncols, speedup): {dense_wins}")
+    at_max = {f"{names[e['cls']]}_{'c64' if e['dt'] == 1 else 'c128'}_n{e['n']}":
+              {"structured_ms": round(e["ms_fast"], 4), "dense_ms": round(e["ms_dense"], 4)}
+              for e in table if e["ncols"] == 65536}
     gen = torch.Generator(device=dev)
     gen.manual_seed(11)
-    out = {}
+    out = {"model_points": len(table), "model_build_s": round(build_s, 3), "dense_wins": dense_wins,
+           "grid_at_65536_columns": at_max}
     for name, mk in (("circulant16", lambda: fm.Circulant(torch.randn(16, dtype=torch.complex64, device=dev,
                                                                           generator=gen))),
                      ("fourier32", lambda: fm.Fourier(32)),
                      ("toeplitz48", lambda: fm.Toeplitz(torch.randn(48, dtype=torch.complex64, device=dev, generator=gen),
                                                         torch.randn(48, dtype=torch.complex64, device=dev,
                                                                     generator=gen)))):
-        info = mk().calibrate(ncols)
+        op = mk()
+        info = op.calibrate(ncols)
         out[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in info.items()}
+        out[name]["model_choice"] = op.choose_path(ncols)
         log(f"calibration {name} x {ncols} columns: structured {info['ms_structured']:.4f} ms, "
-            f"dense {info['ms_dense']:.4f} ms -> {info['path']}")
+            f"dense {info['ms_dense']:.4f} ms -> {info['path']} (model: {out[name]['model_choice']})")
     return out
 
 
@@ -733,6 +752,9 @@ def main():
     ap.add_argument("--schedule", default="", help="MAX_FUSE,REGION_MIB: fixed batch schedule (no tuning)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 512 MiB device to device (reference for traffic counters)")
+    ap.add_argument("--only", default="", choices=["", "wide", "kron", "c1", "cs", "fista", "learn", "ultrasound",
+                                                    "omp", "calib"],
+                    help="run one leg alone (for profiling) and print its result")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -753,6 +775,16 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.only:
+        legs = {"wide": circulant_wide_bandwidth, "kron": kron_hfg_bandwidth, "c1": circulant_1024_latency,
+                "cs": compressed_sensing_fista, "learn": learn_circulant_steps, "ultrasound": ultrasound_model,
+                "omp": omp_solves, "calib": calibration_small}
+        if args.only == "fista":
+            res = fista_solves(setup_toeplitz(args.nops, dev), tune=not args.no_tune)
+        else:
+            res = legs[args.only]()
+        print(json.dumps({"only": args.only, "result": res}), flush=True)
+        return
     w = setup_toeplitz(args.nops, dev)
     alg = w["alg_bytes"]
     log(f"algorithmic bytes per fwd+adj step: {alg / 1e9:.3f} GB ({alg} B)")

@@ -217,6 +217,37 @@ fm_status fm_op_inverse(fm_op* out, fm_op a);
 fm_status fm_op_calibrate(fm_op a, int64_t ncols, int32_t* choice, double* ms_fast, double* ms_dense, void* stream);
 fm_status fm_op_set_path(fm_op a, int32_t path);
 
+/* Calibration model (the same run-time path optimisation, measured once per
+ * device instead of per handle): for three operator classes -- circulant,
+ * Toeplitz (square) and Fourier -- in complex64 and complex128, the times of
+ * the structured and of the dense evaluation on a grid of sizes n = 8, 16,
+ * 32, 48, 64 and column counts 1, 16, 256, 4096, 65536 (the dense product of
+ * complex64 runs on the matrix cores when there are 64 vectors or more).
+ *   fm_calibration_build measures the grid on the current device with
+ *   operators of deterministic test values (synchronises; about a second);
+ *   fm_calibration_entries copies the table out (out may be NULL to get the
+ *   count; cap: room in out); fm_calibration_load installs a saved table on
+ *   the current device (reuse across processes); fm_op_choose_path sets a
+ *   handle's path from the model without timing it: the log ratio of the two
+ *   times is interpolated bilinearly in (size, log2 ncols) between the grid
+ *   points around (max(m, n), ncols), clamped to the grid, and the dense path
+ *   is taken where it is negative. FM_E_INVALID without a model,
+ *   FM_E_UNSUPPORTED for other kinds (fm_op_calibrate times any kind). */
+enum { FM_CAL_CIRCULANT = 0, FM_CAL_TOEPLITZ = 1, FM_CAL_FOURIER = 2 };
+typedef struct {
+  int32_t cls;      /* FM_CAL_* */
+  int32_t dt;       /* FM_C64 or FM_C128 */
+  int32_t n;        /* operator size */
+  int32_t reserved; /* 0 */
+  int64_t ncols;
+  double ms_fast;   /* structured transforms, ms per application */
+  double ms_dense;  /* dense product, ms per application */
+} fm_calib_entry;
+fm_status fm_calibration_build(void* stream);
+fm_status fm_calibration_entries(fm_calib_entry* out, int32_t cap, int32_t* count);
+fm_status fm_calibration_load(const fm_calib_entry* in, int32_t count);
+fm_status fm_op_choose_path(fm_op a, int64_t ncols, int32_t* choice);
+
 fm_status fm_op_shape(fm_op a, int64_t* m, int64_t* n, fm_dtype* dt);
 
 /* Cyclic length L the operator's transforms run at (section "Circulant

@@ -26,6 +26,9 @@ from .operators import (  # noqa: F401
     SelectRows,
     Sum,
     Toeplitz,
+    calibration_build,
+    calibration_load,
+    calibration_table,
     compressed_ultrasound,
     fista,
     fista_options,

@@ -71,6 +71,18 @@ class fm_omp_stat(C.Structure):
     _fields_ = [("atoms", C.c_int32), ("status", C.c_int32), ("res_norm", C.c_double)]
 
 
+class fm_calib_entry(C.Structure):
+    _fields_ = [
+        ("cls", C.c_int32),
+        ("dt", C.c_int32),
+        ("n", C.c_int32),
+        ("reserved", C.c_int32),
+        ("ncols", C.c_int64),
+        ("ms_fast", C.c_double),
+        ("ms_dense", C.c_double),
+    ]
+
+
 class fm_batch_schedule(C.Structure):
     _fields_ = [
         ("max_fuse", C.c_int32),
@@ -107,6 +119,10 @@ SIGNATURES = {
     "fm_op_inverse": (ST, [C.POINTER(P), P]),
     "fm_op_calibrate": (ST, [P, I64, C.POINTER(I32), C.POINTER(C.c_double), C.POINTER(C.c_double), P]),
     "fm_op_set_path": (ST, [P, I32]),
+    "fm_calibration_build": (ST, [P]),
+    "fm_calibration_entries": (ST, [C.POINTER(fm_calib_entry), I32, C.POINTER(I32)]),
+    "fm_calibration_load": (ST, [C.POINTER(fm_calib_entry), I32]),
+    "fm_op_choose_path": (ST, [P, I64, C.POINTER(I32)]),
     "fm_op_shape": (ST, [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(C.c_int)]),
     "fm_op_transform_length": (ST, [P, C.POINTER(I64)]),
     "fm_op_release": (ST, [P]),
@@ -299,6 +315,36 @@ def fm_op_calibrate(a, ncols, stream):
 
 def fm_op_set_path(a, path):
     _call("fm_op_set_path", a, path)
+
+
+CAL_CLASSES = {0: "circulant", 1: "toeplitz", 2: "fourier"}
+
+
+def fm_calibration_build(stream):
+    _call("fm_calibration_build", _ptr(stream))
+
+
+def fm_calibration_entries():
+    n = I32()
+    _call("fm_calibration_entries", None, 0, C.byref(n))
+    arr = (fm_calib_entry * max(n.value, 1))()
+    _call("fm_calibration_entries", arr, n.value, C.byref(n))
+    return [{"cls": arr[i].cls, "dt": arr[i].dt, "n": arr[i].n, "ncols": arr[i].ncols,
+             "ms_fast": arr[i].ms_fast, "ms_dense": arr[i].ms_dense} for i in range(n.value)]
+
+
+def fm_calibration_load(entries):
+    arr = (fm_calib_entry * max(len(entries), 1))()
+    for i, e in enumerate(entries):
+        arr[i] = fm_calib_entry(int(e["cls"]), int(e["dt"]), int(e["n"]), 0, int(e["ncols"]), float(e["ms_fast"]),
+                                float(e["ms_dense"]))
+    _call("fm_calibration_load", arr, len(entries))
+
+
+def fm_op_choose_path(a, ncols):
+    choice = I32()
+    _call("fm_op_choose_path", a, ncols, C.byref(choice))
+    return choice.value
 
 
 def fm_op_shape(a):

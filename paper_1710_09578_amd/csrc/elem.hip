@@ -1,6 +1,8 @@
 // Elementwise and data-movement kernels: Diag, row selection (gather /
 // scatter), the generic dense mode product, zero-pad / crop boxes, precision
 // conversions, spectrum permutation, Toeplitz embedding and index checks.
+#include <cstdlib>
+
 #include "kernels.h"
 
 namespace fm {
@@ -613,9 +615,21 @@ size_t max_lds_per_block() {
   return size_t(cached[dev]);
 }
 
+// FM_DENSE_MFMA=0 keeps complex64 dense products on the vector units.
+static bool dense_mfma_enabled() {
+  static const bool v = [] {
+    const char* e = std::getenv("FM_DENSE_MFMA");
+    return !(e && e[0] == '0');
+  }();
+  return v;
+}
+
 fm_status launch_dense(Elem e, int64_t m, int64_t n, const void* a, int64_t lda, int adjoint, int real_a,
                        const Batch& b, const void* x, void* y, int acc, hipStream_t s) {
   if (b.ncols == 0) return FM_OK;
+  // complex64 on the matrix cores when a work-group's 64 vectors are there
+  if (dense_mfma_enabled() && dense_mfma_supported(e, m, n, b) && b.ncols * b.outer >= 64)
+    return launch_dense_mfma(m, n, a, lda, adjoint, b, x, y, acc, s);
   const int64_t rows_out = adjoint ? n : m;
   if (rows_out == 0) return FM_OK;
   const int64_t rows_in = adjoint ? m : n;

@@ -95,6 +95,12 @@ fm_status launch_select(Elem e, int64_t n_in, int64_t m, const int32_t* idx, con
                         const Batch& b, const void* x, void* y, int accumulate, hipStream_t s);
 // inv[0..n) = -1, then inv[idx[r]] = r for the m distinct, in-range indices.
 fm_status launch_invert_indices(int64_t n, int64_t m, const int32_t* idx, int32_t* inv, hipStream_t s);
+// Dense complex64 product on the matrix cores (dense_mfma.hip) for m, n <= 64
+// along the contiguous axis (inner == 1) of a batch; same arguments as
+// launch_dense without real_a.
+bool dense_mfma_supported(Elem e, int64_t m, int64_t n, const Batch& b);
+fm_status launch_dense_mfma(int64_t m, int64_t n, const void* a, int64_t lda, int adjoint, const Batch& b,
+                            const void* x, void* y, int acc, hipStream_t s);
 // Dense mode product y[:, o, :, i] (+)= op(A) x[:, o, :, i], A m x n col-major.
 // real_a: every entry of A has a zero imaginary part (only real parts used).
 fm_status launch_dense(Elem e, int64_t m, int64_t n, const void* a, int64_t lda, int adjoint, int real_a,

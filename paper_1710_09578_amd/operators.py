@@ -103,6 +103,11 @@ class Operator:
         """Force the evaluation path: "structured" or "dense"."""
         capi.fm_op_set_path(self._h, 1 if path == "dense" else 0)
 
+    def choose_path(self, ncols: int) -> str:
+        """Set the evaluation path from the device's calibration model
+        (calibration_build / calibration_load) without timing this handle."""
+        return "dense" if capi.fm_op_choose_path(self._h, int(ncols)) else "structured"
+
     @property
     def inverse(self) -> "Operator":
         """Structured inverse A^-1 (Circulant, Diag, Fourier, Hadamard,
@@ -279,6 +284,25 @@ def compressed_ultrasound(t: torch.Tensor, psi_rows):
 
 
 # ---------------------------------------------------------------- solver
+def calibration_build():
+    """Measure the device's calibration model (structured vs dense times of
+    circulant, Toeplitz and Fourier operators over sizes 8..64 and 1..65536
+    columns); returns its table."""
+    capi.fm_calibration_build(_stream())
+    return capi.fm_calibration_entries()
+
+
+def calibration_table():
+    """The current device's calibration model as a list of dicts (empty when
+    none was built or loaded)."""
+    return capi.fm_calibration_entries()
+
+
+def calibration_load(table):
+    """Install a saved calibration model on the current device."""
+    capi.fm_calibration_load(list(table))
+
+
 def fista_options(iters=200, momentum=True, lam=None, lam_rel=None, L=None, stop_tol=0.0,
                   x0_given=False, power_iters=500, power_tol=1e-13, seed=0):
     o = capi.fm_fista_opts()

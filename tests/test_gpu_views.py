@@ -184,3 +184,68 @@ def test_calibrated_path(gpu, prec):
     with pytest.raises(fm.FmError) as e:
         gpu.Fourier(128, dt).calibrate(16)
     assert e.value.code == "FM_E_UNSUPPORTED"
+
+
+def test_dense_matrix_cores_every_shape(gpu):
+    """The complex64 dense product on the matrix cores (64 vectors or more)
+    for every padded shape 16/32/64 in and out, forward and adjoint, with
+    strided columns, a ragged last work-group, and accumulation; against the
+    FP64 product."""
+    rng = np.random.default_rng(77)
+    for m, n in ((5, 7), (16, 16), (20, 33), (33, 20), (64, 64), (48, 12), (1, 64), (64, 1)):
+        a = crandn(rng, (n, m)).T.copy()  # m x n
+        A = gpu.Dense(to_dev(a))
+        for adj in (False, True):
+            rin, rout = (m, n) if adj else (n, m)
+            x = crandn(rng, (200, rin))
+            y = to_host(A.apply(to_dev(x), adjoint=adj))
+            assert rel_err(y, dense.apply(a, x, adj)) <= TOL["c64"], (m, n, adj)
+        # accumulation through a Sum of the same operator
+        x = crandn(rng, (130, n))
+        y = to_host(gpu.Sum(A, A).apply(to_dev(x)))
+        assert rel_err(y, 2 * dense.apply(a, x)) <= TOL["c64"], (m, n)
+
+
+def test_calibration_model(gpu):
+    """The device's calibration model: measured once over its grid (three
+    classes, two dtypes, 5 sizes, 5 column counts), exported and loaded back,
+    consulted by handles without timing them; a synthetic model checks the
+    interpolation between grid points and the clamping outside the grid."""
+    import paper_1710_09578_amd as fm
+
+    table = fm.calibration_build()
+    assert len(table) == 150 and all(e["ms_fast"] > 0 and e["ms_dense"] > 0 for e in table)
+    fm.calibration_load(table)
+    assert fm.calibration_table() == table
+    rng = np.random.default_rng(5)
+    # at a grid point the decision is the measured one
+    for e in table[:10]:
+        if e["dt"] != 1 or e["cls"] != 0:
+            continue
+        c = crandn(rng, e["n"])
+        C = gpu.Circulant(to_dev(c))
+        want = "dense" if e["ms_dense"] < e["ms_fast"] else "structured"
+        assert C.choose_path(e["ncols"]) == want
+        check_both(C, dense.circulant(c), rng, "c64", ncols=70)
+    # synthetic model: dense faster by 2x at n <= 16 and ncols <= 16, slower elsewhere
+    syn = []
+    for cls in (0, 1, 2):
+        for dt in (1, 2):
+            for n in (8, 16, 32, 48, 64):
+                for nc in (1, 16, 256, 4096, 65536):
+                    fast = 1.0
+                    dense_t = 0.5 if (n <= 16 and nc <= 16) else 2.0
+                    syn.append({"cls": cls, "dt": dt, "n": n, "ncols": nc, "ms_fast": fast, "ms_dense": dense_t})
+    fm.calibration_load(syn)
+    col, row = crandn(rng, 12), crandn(rng, 12)
+    T = gpu.Toeplitz(to_dev(col), to_dev(row))
+    assert T.choose_path(4) == "dense"            # inside the dense corner
+    check_both(T, dense.toeplitz(col, row), rng, "c64", ncols=80)
+    assert T.choose_path(100000) == "structured"  # clamped to 65536
+    assert T.choose_path(64) == "structured"      # log2 64 halfway between 16 and 256: ratio 0, ties keep structured
+    assert T.choose_path(31) == "dense"           # log2 31 nearer 16: negative ratio
+    F = gpu.Fourier(64)
+    assert F.choose_path(1) == "structured"
+    with pytest.raises(fm.FmError):
+        gpu.Product(gpu.Circulant(to_dev(crandn(rng, 8))), gpu.Circulant(to_dev(crandn(rng, 8)))).choose_path(16)
+    fm.calibration_load(table)
