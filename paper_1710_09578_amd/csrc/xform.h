@@ -288,14 +288,19 @@ __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int lo
       const int n2e = (jb.in_limit + N - 1) / N < n2s ? (jb.in_limit + N - 1) / N : n2s;  // rows holding data
       for (int n2 = 0; n2 < n2e; ++n2) {
         Cx<R> val[kE];
+        if (!IMAP && N * (n2 + 1) <= jb.in_limit) {  // a full row of the input: unpredicated loads
 #pragma unroll
-        for (int k = 0; k < kE; ++k) {
-          const int q = t + T * k + N * n2;
-          if constexpr (IMAP) {
-            const int m = q < jb.in_limit ? jb.imap[q] : -1;
-            val[k] = m >= 0 ? X[m] : Cx<R>{R(0), R(0)};
-          } else {
-            val[k] = q < jb.in_limit ? X[q] : Cx<R>{R(0), R(0)};
+          for (int k = 0; k < kE; ++k) val[k] = X[t + T * k + N * n2];
+        } else {
+#pragma unroll
+          for (int k = 0; k < kE; ++k) {
+            const int q = t + T * k + N * n2;
+            if constexpr (IMAP) {
+              const int m = q < jb.in_limit ? jb.imap[q] : -1;
+              val[k] = m >= 0 ? X[m] : Cx<R>{R(0), R(0)};
+            } else {
+              val[k] = q < jb.in_limit ? X[q] : Cx<R>{R(0), R(0)};
+            }
           }
         }
         const Cx<R> w = jb.twl[N * ((n2 * k2) % n2s)];  // W_N2^(n2 k2)
@@ -311,6 +316,10 @@ __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int lo
           w = cmul(w, ws);
         }
       }
+    } else if (!IMAP && valid && ((1 << logn) - 1) * inner + ii < jb.in_limit) {
+      // the whole transform lies inside the input: unpredicated loads
+#pragma unroll
+      for (int k = 0; k < kE; ++k) v[k] = X[(t + T * k) * inner];
     } else {
 #pragma unroll
       for (int k = 0; k < kE; ++k) {
@@ -386,6 +395,12 @@ __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int lo
             if (p * inner + ii < jb.out_limit) ep->put(k, 0, b, p * inner + ii, Y + p * inner, v[k]);
           }
         }
+        return;
+      }
+      if (!md.accumulate && ((1 << logn) - 1) * inner + ii < jb.out_limit) {
+        // the whole transform lies inside the output: unpredicated stores
+#pragma unroll
+        for (int k = 0; k < kE; ++k) Y[(t + T * k) * inner] = v[k];
         return;
       }
 #pragma unroll
