@@ -6,6 +6,8 @@
 #include "mixed.h"
 #include "xform.h"
 
+#include <mutex>
+
 namespace fm {
 namespace {
 
@@ -27,6 +29,14 @@ struct KArgs {
 };
 
 constexpr int kXcdCount = 8;  // work-group g runs on XCD g mod 8
+// Contiguous transforms of up to 2^FM_SMALL_LOGW points run in work-groups of
+// 2^FM_SMALL_LOGW values (one wave at 10): with four work-groups' barriers
+// per CU replaced by sixteen, the loads of one overlap the arithmetic of the
+// others (1024-point convolution of 65536 columns: 0.535 -> 0.505 ms per
+// forward + adjoint; 2^11: 0.514).
+#ifndef FM_SMALL_LOGW
+#define FM_SMALL_LOGW 10
+#endif
 // Fewest columns for which the rows of a column are grouped on one XCD: with
 // fewer, grouping leaves XCDs idle in a launch that is short anyway.
 #ifndef FM_XCD_GROUP_MIN_COLS
@@ -36,11 +46,16 @@ constexpr int kXcdCount = 8;  // work-group g runs on XCD g mod 8
 // XG (layout 2 only): the work-groups of column c take the indices = c (mod 8).
 // The complex64 strided form is held to 128 VGPRs (four work-groups per CU; it
 // spills 6 registers there and measured faster than at three).
-template <typename R, bool STRIDED, int LOGW, bool XG = false>
-__global__ __launch_bounds__(Geo<LOGW>::kThreads, (STRIDED && sizeof(R) == 4) ? 4 : 1) void fft_kernel(KArgs a) {
+// FIX > 0: the transform length 2^FIX is a compile-time constant (a.logn ==
+// FIX), so the steps unroll and every LDS and twiddle index folds into
+// immediate offsets; the arithmetic is the same as the run-time form's, so
+// both give the same bits.
+template <typename R, bool STRIDED, int LOGW, bool XG = false, int FIX = 0>
+__global__ __launch_bounds__(Geo<LOGW>::kThreads, ((STRIDED || FIX > 0) && sizeof(R) == 4) ? 4 : 1) void fft_kernel(KArgs a) {
   extern __shared__ unsigned char smem_raw[];
   Cx<R>* lds = reinterpret_cast<Cx<R>*>(smem_raw);
-  const int tpw = 1 << (LOGW - a.logn);  // transforms per work-group
+  const int logn = FIX > 0 ? FIX : a.logn;
+  const int tpw = 1 << (LOGW - logn);  // transforms per work-group
   Job<R> jb;
   jb.in_limit = a.in_limit;
   jb.out_limit = a.out_limit;
@@ -49,6 +64,18 @@ __global__ __launch_bounds__(Geo<LOGW>::kThreads, (STRIDED && sizeof(R) == 4) ? 
   const Cx<R>* S = reinterpret_cast<const Cx<R>*>(a.spec);
   if constexpr (STRIDED) {
     int64_t bid = blockIdx.x;
+    // tiles whose row segments (tpw values) are shorter than a 128-byte line
+    // share lines: the P tiles of a line go to work-groups on one XCD
+    // (work-group g runs on XCD g mod 8), which then fetches it once
+    const int seg = tpw * int(sizeof(Cx<R>));
+    if (seg < 128) {
+      const int P = 128 / seg;
+      const int64_t grp = 8 * P;
+      if (bid < int64_t(gridDim.x) / grp * grp) {
+        const int64_t q = bid / grp, r = bid % grp;
+        bid = q * grp + (r % 8) * P + r / 8;
+      }
+    }
     const int64_t it = bid % a.tiles;
     bid /= a.tiles;
     const int64_t o = bid % a.outer, c = bid / a.outer;
@@ -107,7 +134,20 @@ __global__ __launch_bounds__(Geo<LOGW>::kThreads, (STRIDED && sizeof(R) == 4) ? 
   jb.fuse_n2 = a.fuse_n2;
   jb.twl = reinterpret_cast<const Cx<R>*>(a.twl);
   const Mode md{a.mode, a.spec_conj, a.tw_log, a.tw_inv, a.accumulate};
-  run_job<R, STRIDED, LOGW>(jb, md, a.logn, lds, reinterpret_cast<const Cx<R>*>(a.tw));
+  run_job<R, STRIDED, LOGW, (FIX > 0)>(jb, md, logn, lds, reinterpret_cast<const Cx<R>*>(a.tw));
+}
+
+// Contiguous transforms of 2^kFixMin .. 2^LOGW points run the compile-time
+// length forms.
+constexpr int kFixMin = 4;
+template <typename R, int LOGW, int LG = LOGW>
+const void* fixed_kernel(int lg) {
+  if constexpr (LG < kFixMin) {
+    return nullptr;
+  } else {
+    if (lg == LG) return reinterpret_cast<const void*>(&fft_kernel<R, false, LOGW, false, LG>);
+    return fixed_kernel<R, LOGW, LG - 1>(lg);
+  }
 }
 
 template <typename R, int LOGW>
@@ -139,23 +179,30 @@ fm_status launch_typed(const FftLaunch& L, KArgs ka, hipStream_t s) {
                "fft: vector span above 2^30 elements");
   FM_CHECK_ARG(L.fuse_n2 == 0 || (!strided && ka.layout == 2 && L.logn == LOGW && L.fuse_n2 <= 32),
                FM_E_UNSUPPORTED, "fft: fused column transform needs a full-size row per work-group");
-  static bool attr_set = false;
-  if (!attr_set) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&fft_kernel<R, true, LOGW>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&fft_kernel<R, false, LOGW>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&fft_kernel<R, false, LOGW, true>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    attr_set = true;
-  }
+  static std::once_flag attr_once;
+  std::call_once(attr_once, [] {
+    for (const void* f : {reinterpret_cast<const void*>(&fft_kernel<R, true, LOGW>),
+                          reinterpret_cast<const void*>(&fft_kernel<R, false, LOGW>),
+                          reinterpret_cast<const void*>(&fft_kernel<R, false, LOGW, true>),
+                          reinterpret_cast<const void*>(&fft_kernel<R, false, LOGW, true, LOGW>)})
+      (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    for (int lg = kFixMin; lg <= LOGW; ++lg)
+      (void)hipFuncSetAttribute(fixed_kernel<R, LOGW>(lg), hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  });
   const dim3 wg(Geo<LOGW>::kThreads);
   if (strided)
     hipLaunchKernelGGL((fft_kernel<R, true, LOGW>), dim3(unsigned(blocks)), wg, (job_lds_bytes<R, LOGW>()), s, ka);
+  else if (xg && L.logn == LOGW)
+    hipLaunchKernelGGL((fft_kernel<R, false, LOGW, true, LOGW>), dim3(unsigned(blocks)), wg,
+                       (job_lds_bytes<R, LOGW>()), s, ka);
   else if (xg)
     hipLaunchKernelGGL((fft_kernel<R, false, LOGW, true>), dim3(unsigned(blocks)), wg, (job_lds_bytes<R, LOGW>()), s,
                        ka);
-  else
+  else if (L.logn >= kFixMin) {
+    void* args[] = {&ka};
+    FM_HIP(hipLaunchKernel(fixed_kernel<R, LOGW>(L.logn), dim3(unsigned(blocks)), wg, args,
+                           job_lds_bytes<R, LOGW>(), s));
+  } else
     hipLaunchKernelGGL((fft_kernel<R, false, LOGW>), dim3(unsigned(blocks)), wg, (job_lds_bytes<R, LOGW>()), s, ka);
   FM_LAUNCHED();
   return FM_OK;
@@ -199,8 +246,10 @@ fm_status launch_fft(const FftLaunch& L, hipStream_t s) {
   ka.twl = L.twl ? L.twl
                  : own_table ? static_cast<const char*>(ka.tw) + (size_t(1) << L.tw_log) * elem_bytes(L.elem)
                              : nullptr;
-  if (L.elem == Elem::C128) return launch_typed<double, 12>(L, ka, s);
-  return launch_typed<float, 12>(L, ka, s);
+  // small work-groups: same arithmetic, so the same bits
+  const bool small = L.b.inner == 1 && L.logn <= FM_SMALL_LOGW && L.fuse_n2 == 0;
+  if (L.elem == Elem::C128) return small ? launch_typed<double, FM_SMALL_LOGW>(L, ka, s) : launch_typed<double, 12>(L, ka, s);
+  return small ? launch_typed<float, FM_SMALL_LOGW>(L, ka, s) : launch_typed<float, 12>(L, ka, s);
 }
 
 // ---------------------------------------------------------------- mixed strided passes
@@ -260,7 +309,7 @@ fm_status launch_mixed(Elem e, int n2, int inverse, int64_t ncols, const void* x
   FM_CHECK_ARG(twl != nullptr, FM_E_INVALID, "mixed pass: no twiddle table");
   MArgs a{x, ldx, in_limit, y, ldy, out_limit, twl, L, ncols, n2, inverse, acc};
   const dim3 g(unsigned(mixed_tiles(n2)), unsigned(ncols < 65535 ? ncols : 65535));
-  const size_t lds = mixed_threads(n2) > 1 ? size_t(256 / mixed_threads(n2)) * n2 * elem_bytes(e) : 0;
+  const size_t lds = mixed_threads(n2) > 1 ? size_t(256 / mixed_threads(n2)) * (n2 + 1) * elem_bytes(e) : 0;
   if (e == Elem::C64)
     launch_mixed_n<float>(n2, g, lds, s, a);
   else if (e == Elem::C128)

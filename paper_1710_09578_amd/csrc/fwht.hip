@@ -77,6 +77,23 @@ struct WPlan {
   static constexpr int lds_elems() { return LOW > 0 ? N + (N >> 4) : 1; }
 };
 
+// Offset (in values) between the LDS regions of the B = THREADS / T
+// transforms of a work-group. Strided layout: the lanes of a wave are
+// B' = min(B, 64) transforms times g = 64 / B' consecutive t, all at the same
+// offsets inside their regions, so the stride is g times an odd number (the
+// plain 17 N / 16 is a multiple of 32 values for N >= 512: every transform in
+// the same banks). Contiguous layout: the plain stride.
+template <int LOGN, int LE, bool STRIDED, int THREADS>
+constexpr int w_stride() {
+  using PL = WPlan<LOGN, LE>;
+  const int base = PL::lds_elems();
+  if (!STRIDED || PL::LOW == 0) return base;
+  const int B = THREADS / PL::T;
+  const int g = B >= 64 ? 1 : 64 / B;
+  const int s = (base + g - 1) / g * g;
+  return (s / g) % 2 ? s : s + g;
+}
+
 // One lower digit: bits [S, S+W) of the index.
 template <typename V, int LOGN, int LE, int S, int W>
 __device__ __forceinline__ void digit_pass(V* lds, int t) {
@@ -146,6 +163,19 @@ __global__ __launch_bounds__(THREADS) void fwht_kernel(WArgs a) {
     t = tid / a.B;
     const int64_t tiles = (a.inner + a.B - 1) / a.B;
     int64_t bid = blockIdx.x;
+    // A tile's row segments are B values, shorter than a 128-byte line when
+    // B sizeof(V) < 128: then the P tiles that share each line are given to
+    // work-groups on one XCD (work-group g runs on XCD g mod 8; groups of 8 P
+    // consecutive indices are permuted), so the line is fetched into that
+    // XCD's L2 once instead of once per XCD.
+    constexpr int P = (THREADS / PL::T) * int(sizeof(V)) < 128 ? 128 / ((THREADS / PL::T) * int(sizeof(V))) : 1;
+    if constexpr (P > 1) {
+      constexpr int64_t grp = 8 * P;
+      if (bid < int64_t(gridDim.x) / grp * grp) {
+        const int64_t q = bid / grp, r = bid % grp;
+        bid = q * grp + (r % 8) * P + r / 8;
+      }
+    }
     const int64_t it = bid % tiles;
     bid /= tiles;
     o = bid % a.outer;
@@ -160,7 +190,7 @@ __global__ __launch_bounds__(THREADS) void fwht_kernel(WArgs a) {
   for (int k = 0; k < PL::E; ++k) v[k] = valid ? X[int64_t(t + PL::T * k) * inner] : Arith<V>::zero();
   hadamard_regs<PL::LE>(v);
   if constexpr (PL::LOW > 0) {
-    V* lds = smem + b * PL::lds_elems();
+    V* lds = smem + b * w_stride<LOGN, LE, STRIDED, THREADS>();
 #pragma unroll
     for (int k = 0; k < PL::E; ++k) lds[pad16(t + PL::T * k)] = v[k];
     __syncthreads();
@@ -181,7 +211,7 @@ __global__ __launch_bounds__(THREADS) void fwht_kernel(WArgs a) {
 template <typename V, int LOGN, int LE, bool STRIDED, int THREADS>
 fm_status wlaunch_one(const Batch& bt, WArgs wa, hipStream_t s) {
   using PL = WPlan<LOGN, LE>;
-  const size_t per = size_t(PL::lds_elems()) * sizeof(V);
+  const size_t per = size_t(w_stride<LOGN, LE, STRIDED, THREADS>()) * sizeof(V);
   const int B = THREADS / PL::T;
   int64_t blocks;
   if (!STRIDED)

@@ -46,10 +46,7 @@ __global__ __launch_bounds__(kKT, 4) void kron_fg_kernel(KronArgs a) {
   const int nin = a.adj ? a.m : a.n, nout = a.adj ? a.n : a.m;
   const int S = (nin > nout ? nin : nout) + 1;  // padded row stride of the slab
   c64* slab = reinterpret_cast<c64*>(smem_raw);
-  const size_t slab_vals = size_t(nF) * S > size_t(Geo<kKW>::kVals + Geo<kKW>::kVals / 16)
-                               ? size_t(nF) * S
-                               : size_t(Geo<kKW>::kVals + Geo<kKW>::kVals / 16);
-  c64* gm = slab + slab_vals;  // op(G) rows: gm[r * NIN + k]
+  c64* gm = slab + size_t(nF) * S;  // op(G) rows: gm[r * NIN + k]
   const int tid = threadIdx.x;
   const int64_t col = blockIdx.x / a.outer, o = blockIdx.x % a.outer;
   const c64* X = a.x + col * a.ldx + o * int64_t(nF) * nin;
@@ -77,7 +74,8 @@ __global__ __launch_bounds__(kKT, 4) void kron_fg_kernel(KronArgs a) {
     for (int i = 0; i < 16; ++i) {
       const int e = tid + kKT * i;
       if (e < nF * nin) {
-        const int p = e / nin, k = e - p * nin;
+        const int p = nin == NIN ? e / NIN : e / nin;  // a shift when op(G) needs no padding
+        const int k = e - p * nin;
         slab[p * S + k] = ld[i];
       }
     }
@@ -194,8 +192,8 @@ __global__ __launch_bounds__(kKT, 4) void kron_fg_kernel(KronArgs a) {
   c64 v[kE];
 #pragma unroll
   for (int k = 0; k < kE; ++k) v[k] = b < nout ? slab[(t + T * k) * S + b] : c64{0.f, 0.f};
-  __syncthreads();  // the slab is free: its LDS becomes the transforms' exchange space
-  c64* my = slab + b * (nF + T);
+  __syncthreads();  // slab and op(G) are free: their LDS becomes the transforms' exchange space
+  c64* my = slab + b * region_stride(a.lognf, B, true);
   if (a.adj) conj_all(v);
   forward(v, a.lognf, t, my, a.tw);
   if (a.adj) conj_all(v);
@@ -245,8 +243,10 @@ fm_status launch_kron_fg(int lognf, int64_t m, int64_t n, const void* g, int64_t
   const int nin = int(adjoint ? m : n), nout = int(adjoint ? n : m);
   const int S = (nin > nout ? nin : nout) + 1;
   const int NIN = nin <= 8 ? 8 : nin <= 16 ? 16 : 32;
-  const size_t slab_vals = std::max<size_t>(size_t(nF) * S, size_t(Geo<kKW>::kVals + Geo<kKW>::kVals / 16));
-  const size_t lds = (slab_vals + size_t(nout) * NIN) * sizeof(c64);
+  // the slab and op(G), later the exchange regions of the 8192 / nF transforms
+  const int B = int((int64_t(1) << kKW) / nF);
+  const size_t lds = std::max<size_t>(size_t(nF) * S + size_t(nout) * NIN, size_t(B) * region_stride(lognf, B, true)) *
+                     sizeof(c64);
   const dim3 grid{unsigned(blocks)};
 #define FM_KRON_LAUNCH(N, RL)                                                                           \
   do {                                                                                                 \

@@ -160,8 +160,9 @@ __device__ __forceinline__ void mixed_column(const Cx<R>* x, int64_t in_limit, C
 // kernel's 128 at four work-groups per CU): thread h loads the
 // points 2m + h, forms their M-point DFT A_h (times W_N2^k1 for h = 1), the
 // pair exchanges A_0, A_1 through LDS and thread h keeps
-// X[k1 + h M] = A_0[k1] + (-1)^h A_1[k1]. lds: 2 M values per column position
-// of the work-group. Every thread of the work-group calls it (one barrier).
+// X[k1 + h M] = A_0[k1] + (-1)^h A_1[k1]. lds: 2 M + 1 values per column
+// position of the work-group (an odd stride: the 64 positions of a wave fall
+// in distinct banks). Every thread of the work-group calls it (one barrier).
 template <int M, typename R, class EP, bool IMAP = false>
 __device__ __forceinline__ void mixed_column_pair(const Cx<R>* x, int64_t in_limit, Cx<R>* y, int64_t out_limit,
                                                   int n1, int h, int slot, bool inverse, const Cx<R>* twl, int64_t L,
@@ -188,7 +189,7 @@ __device__ __forceinline__ void mixed_column_pair(const Cx<R>* x, int64_t in_lim
 #pragma unroll
     for (int k1 = 1; k1 < M; ++k1) v[k1] = cmul(v[k1], twl[step * k1]);
   }
-  Cx<R>* mine = lds + int64_t(slot) * N2;
+  Cx<R>* mine = lds + int64_t(slot) * (N2 + 1);
 #pragma unroll
   for (int k1 = 0; k1 < M; ++k1) mine[h * M + k1] = v[k1];
   __syncthreads();
@@ -241,7 +242,7 @@ __host__ __device__ inline int mixed_tiles(int n2) { return 16 * mixed_threads(n
 
 // Tile `tile` of one column for the strided factor N2: 256 / mixed_threads(N2)
 // consecutive column positions. Every thread of the work-group calls it; lds
-// holds 256 / threads * N2 values (pairs only).
+// holds 256 / threads * (N2 + 1) values (pairs only).
 template <int N2, typename R, class EP, bool IMAP = false>
 __device__ __forceinline__ void mixed_tile_n(int tile, const Cx<R>* x, int64_t in_limit, Cx<R>* y, int64_t out_limit,
                                              bool inverse, const Cx<R>* twl, int64_t L, int acc, EP* ep,

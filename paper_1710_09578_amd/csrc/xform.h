@@ -14,7 +14,7 @@
 // in the thread's own registers -- multiplies by W_{Ns R}^{(j mod Ns) r}, runs
 // a radix-R DFT in registers and writes result q to position
 // (j div Ns)*Ns*R + (j mod Ns) + q*Ns. Between steps the values go through LDS
-// (one padding slot every 16 spreads the banks); after the last step they are
+// (one padding slot every 32 spreads the banks); after the last step they are
 // back in the natural layout, so global loads and stores are coalesced and the
 // spectral product between a forward and an inverse transform needs no
 // exchange. The number of steps is a run-time value, so one code path serves
@@ -103,7 +103,7 @@ __device__ __forceinline__ void dft(Cx<R>* a) {
   }
 }
 
-__device__ __forceinline__ int pad16(int pos) { return pos + (pos >> 4); }
+__device__ __forceinline__ int pad32(int pos) { return pos + (pos >> 5); }
 
 // Twiddles W^(jj r), r = 1..15, from the single table entry W^(jj): W^(2jj),
 // W^(4jj), W^(8jj) by squaring, the others as products of at most three of
@@ -135,7 +135,7 @@ __device__ __forceinline__ void first_step(Cx<R>* v, Cx<R>* lds, int t, int T) {
     for (int r = 0; r < RR; ++r) a[r] = v[m + r * M];
     dft<RR>(a);
 #pragma unroll
-    for (int q = 0; q < RR; ++q) lds[pad16(j * RR + q)] = a[q];
+    for (int q = 0; q < RR; ++q) lds[pad32(j * RR + q)] = a[q];
   }
 }
 
@@ -156,7 +156,7 @@ __device__ __forceinline__ void forward(Cx<R>* v, int logn, int t, Cx<R>* lds, c
       first_step<8>(v, lds, t, T);
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < kE; ++k) v[k] = lds[pad16(t + T * k)];
+    for (int k = 0; k < kE; ++k) v[k] = lds[pad32(t + T * k)];
     __syncthreads();
     lns = first;
     step = 1;
@@ -173,10 +173,10 @@ __device__ __forceinline__ void forward(Cx<R>* v, int logn, int t, Cx<R>* lds, c
     if (step == nsteps - 1) break;
     const int idxd = ((t >> lns) << (lns + 4)) | (t & (ns - 1));
 #pragma unroll
-    for (int q = 0; q < 16; ++q) lds[pad16(idxd + q * ns)] = v[q];
+    for (int q = 0; q < 16; ++q) lds[pad32(idxd + q * ns)] = v[q];
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < kE; ++k) v[k] = lds[pad16(t + T * k)];
+    for (int k = 0; k < kE; ++k) v[k] = lds[pad32(t + T * k)];
     __syncthreads();
     lns += 4;
   }
@@ -256,6 +256,22 @@ struct NoEp {
   static constexpr bool kOn = false;
 };
 
+// Offset (in values) between the LDS regions of the transforms of one
+// work-group of B transforms of 2^logn points. A region holds 33/32 of its
+// points (pad32). Contiguous layout: the lanes of a wave are consecutive t of
+// 64/T transforms, and the plain 33 T / 2 keeps their accesses apart. Strided
+// layout: the lanes are B' = min(B, 64) transforms times g = 64/B' consecutive
+// t, all at the same in-region offset; a stride of g times an odd number puts
+// them in distinct banks (the plain 33 N/32 is an even multiple of g, which
+// folds the transforms onto half of the banks or fewer).
+__host__ __device__ constexpr int region_stride(int logn, int B, bool strided) {
+  const int base = (1 << logn) + ((1 << logn) >> 5);
+  if (!strided) return base;
+  const int g = B >= 64 ? 1 : 64 / B;
+  const int s = (base + g - 1) / g * g;
+  return (s / g) % 2 ? s : s + g;
+}
+
 // Loads, transforms and stores one job. Every thread of the work-group calls it.
 // SPLIT_SPEC: complex64 spectra are loaded and applied in two halves of 8
 // values, which keeps 16 fewer registers live at the spectral product (the
@@ -333,7 +349,7 @@ __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int lo
         }
       }
     }
-    Cx<R>* my = lds + b * ((1 << logn) + (1 << (logn - 4)));
+    Cx<R>* my = lds + b * region_stride(logn, kWG >> (logn - 4), STRIDED);
     if (md.mode == FFT_INV) conj_all(v);
     forward(v, logn, t, my, tw);
     if (md.mode == FFT_CONV) {
@@ -507,10 +523,21 @@ __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int lo
   }
 }
 
-// LDS bytes of one work-group.
+// LDS bytes of one work-group: the largest region set over the lengths that
+// use LDS (2^5 .. 2^LOGW points), strided or contiguous.
+template <int LOGW>
+constexpr int job_lds_values() {
+  int v = Geo<LOGW>::kVals + Geo<LOGW>::kVals / 16;
+  for (int lg = 5; lg <= LOGW; ++lg) {
+    const int B = 1 << (LOGW - lg);
+    const int need = B * region_stride(lg, B, true);
+    v = need > v ? need : v;
+  }
+  return v;
+}
 template <typename R, int LOGW>
 constexpr size_t job_lds_bytes() {
-  return size_t(Geo<LOGW>::kVals + Geo<LOGW>::kVals / 16) * sizeof(Cx<R>);
+  return size_t(job_lds_values<LOGW>()) * sizeof(Cx<R>);
 }
 
 }  // namespace xf
