@@ -79,19 +79,22 @@ struct WPlan {
 
 // Offset (in values) between the LDS regions of the B = THREADS / T
 // transforms of a work-group. Strided layout: the lanes of a wave are
-// B' = min(B, 64) transforms times g = 64 / B' consecutive t, all at the same
-// offsets inside their regions, so the stride is g times an odd number (the
-// plain 17 N / 16 is a multiple of 32 values for N >= 512: every transform in
-// the same banks). Contiguous layout: the plain stride.
-template <int LOGN, int LE, bool STRIDED, int THREADS>
+// min(B, 64) transforms, all at the same offsets inside their regions, and
+// the plain 17 N / 16 (a multiple of 64 values from N = 1024) puts them in the
+// same banks. The padding was chosen by timing the exchanges alone with
+// strides base + 0..32 for the work-group shapes below (2048 to 8192 points
+// with 8-byte values, 1024 to 4096 with 16-byte ones; 2-8x faster than +0
+// where B >= 4), the smallest odd stride of at least base + 2 elsewhere.
+// Contiguous layout: the plain stride.
+template <typename V, int LOGN, int LE, bool STRIDED, int THREADS>
 constexpr int w_stride() {
   using PL = WPlan<LOGN, LE>;
   const int base = PL::lds_elems();
-  if (!STRIDED || PL::LOW == 0) return base;
-  const int B = THREADS / PL::T;
-  const int g = B >= 64 ? 1 : 64 / B;
-  const int s = (base + g - 1) / g * g;
-  return (s / g) % 2 ? s : s + g;
+  if (!STRIDED || PL::LOW == 0 || THREADS / PL::T <= 1) return base;
+  if (sizeof(V) == 8 && LE == 4 && LOGN >= 10 && LOGN <= 13)
+    return base + (LOGN == 10 ? 3 : LOGN == 11 ? 6 : LOGN == 12 ? 4 : 8);
+  if (sizeof(V) == 16 && LE == 4 && LOGN >= 10 && LOGN <= 12) return base + (LOGN == 12 ? 4 : 2);
+  return (base + 2) | 1;
 }
 
 // One lower digit: bits [S, S+W) of the index.
@@ -124,13 +127,24 @@ __device__ __forceinline__ void lower_digits(V* lds, int t) {
   }
 }
 
-// Elements per thread and work-group size, as for the FFT.
+// Elements per thread and work-group size, as for the FFT. Strided: 16
+// fibres per work-group where the threads and the LDS allow (128-byte row
+// segments for 8-byte values, so a tile fetches whole lines), up to 1024
+// threads (512 for 16-byte values): 16 fibres of 1024 points in 1024 threads
+// ran the Kronecker workload's Hadamard pass in 1.95 ms against 2.36 ms for
+// 8 fibres in 512.
 constexpr int w_le(int logn) { return logn < 4 ? logn : (logn - 9 > 4 ? logn - 9 : 4); }
-constexpr int w_threads(int logn, bool strided) {
+constexpr int w_threads(int logn, bool strided, int esize) {
   const int t = 1 << (logn - w_le(logn));
   if (!strided) return t > 256 ? t : 256;
-  const int want = 16 * t > 256 ? 16 * t : 256;
-  return want > 512 ? (t > 512 ? t : 512) : want;
+  const int n = 1 << logn;
+  const int fit = (160 * 1024) / ((n + n / 16 + 64) * esize);  // regions the LDS holds (padding <= 64)
+  const int cap = (esize >= 16 ? 512 : 1024) / t;
+  int b = 16 * t > 256 ? 16 : 256 / t;
+  if (b > cap) b = cap;
+  if (b > fit) b = fit;
+  if (b < 1) b = 1;
+  return t * b;
 }
 
 struct WArgs {
@@ -190,7 +204,7 @@ __global__ __launch_bounds__(THREADS) void fwht_kernel(WArgs a) {
   for (int k = 0; k < PL::E; ++k) v[k] = valid ? X[int64_t(t + PL::T * k) * inner] : Arith<V>::zero();
   hadamard_regs<PL::LE>(v);
   if constexpr (PL::LOW > 0) {
-    V* lds = smem + b * w_stride<LOGN, LE, STRIDED, THREADS>();
+    V* lds = smem + b * w_stride<V, LOGN, LE, STRIDED, THREADS>();
 #pragma unroll
     for (int k = 0; k < PL::E; ++k) lds[pad16(t + PL::T * k)] = v[k];
     __syncthreads();
@@ -211,7 +225,7 @@ __global__ __launch_bounds__(THREADS) void fwht_kernel(WArgs a) {
 template <typename V, int LOGN, int LE, bool STRIDED, int THREADS>
 fm_status wlaunch_one(const Batch& bt, WArgs wa, hipStream_t s) {
   using PL = WPlan<LOGN, LE>;
-  const size_t per = size_t(w_stride<LOGN, LE, STRIDED, THREADS>()) * sizeof(V);
+  const size_t per = size_t(w_stride<V, LOGN, LE, STRIDED, THREADS>()) * sizeof(V);
   const int B = THREADS / PL::T;
   int64_t blocks;
   if (!STRIDED)
@@ -239,8 +253,8 @@ template <typename V, int LOGN>
 fm_status wdispatch(const Batch& bt, const WArgs& wa, int logn, hipStream_t s) {
   if constexpr (LOGN >= 0) {
     if (logn == LOGN) {
-      if (bt.inner > 1) return wlaunch_one<V, LOGN, w_le(LOGN), true, w_threads(LOGN, true)>(bt, wa, s);
-      return wlaunch_one<V, LOGN, w_le(LOGN), false, w_threads(LOGN, false)>(bt, wa, s);
+      if (bt.inner > 1) return wlaunch_one<V, LOGN, w_le(LOGN), true, w_threads(LOGN, true, sizeof(V))>(bt, wa, s);
+      return wlaunch_one<V, LOGN, w_le(LOGN), false, w_threads(LOGN, false, sizeof(V))>(bt, wa, s);
     }
     if constexpr (LOGN > 0) return wdispatch<V, LOGN - 1>(bt, wa, logn, s);
   }

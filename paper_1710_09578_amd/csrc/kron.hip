@@ -46,7 +46,11 @@ __global__ __launch_bounds__(kKT, 4) void kron_fg_kernel(KronArgs a) {
   const int nin = a.adj ? a.m : a.n, nout = a.adj ? a.n : a.m;
   const int S = (nin > nout ? nin : nout) + 1;  // padded row stride of the slab
   c64* slab = reinterpret_cast<c64*>(smem_raw);
-  c64* gm = slab + size_t(nF) * S;  // op(G) rows: gm[r * NIN + k]
+  // op(G) rows: gm[r * GS + k]; the odd row stride spreads the 32 rows a wave
+  // reads together over the banks (NIN values, a multiple of 64 bytes, folded
+  // them onto one to four banks)
+  constexpr int GS = NIN + 1;
+  c64* gm = slab + size_t(nF) * S;
   const int tid = threadIdx.x;
   const int64_t col = blockIdx.x / a.outer, o = blockIdx.x % a.outer;
   const c64* X = a.x + col * a.ldx + o * int64_t(nF) * nin;
@@ -59,7 +63,7 @@ __global__ __launch_bounds__(kKT, 4) void kron_fg_kernel(KronArgs a) {
       v = a.adj ? a.g[k + int64_t(r) * a.lda] : a.g[r + int64_t(k) * a.lda];
       if (a.adj) v.y = -v.y;
     }
-    gm[i] = v;
+    gm[r * GS + k] = v;
   }
   // slab rows (coalesced): element e = p*nin + k, at most 16 per thread; all
   // loads are issued before the first LDS store
@@ -109,7 +113,7 @@ __global__ __launch_bounds__(kKT, 4) void kron_fg_kernel(KronArgs a) {
 #pragma unroll
       for (int kk = 0; kk < KS; ++kk) {
         const int k = 2 * kk + lk;
-        bf[kk] = li < nout ? gf[2 * (li * NIN + k)] : 0.f;  // k >= nin: zero padding of op(G)
+        bf[kk] = li < nout ? gf[2 * (li * GS + k)] : 0.f;  // k >= nin: zero padding of op(G)
       }
 #pragma unroll
       for (int j0 = 0; j0 < 4; j0 += 2) {
@@ -150,7 +154,7 @@ __global__ __launch_bounds__(kKT, 4) void kron_fg_kernel(KronArgs a) {
             const int nr = n & 31, npart = n >> 5;
             float bv = 0.f;
             if (nr < nout) {
-              const float gr = gf[2 * (nr * NIN + kr)], gi = gf[2 * (nr * NIN + kr) + 1];
+              const float gr = gf[2 * (nr * GS + kr)], gi = gf[2 * (nr * GS + kr) + 1];
               bv = kpart == 0 ? (npart == 0 ? gr : gi) : (npart == 0 ? -gi : gr);
             }
             bf[kk] = bv;
@@ -245,7 +249,7 @@ fm_status launch_kron_fg(int lognf, int64_t m, int64_t n, const void* g, int64_t
   const int NIN = nin <= 8 ? 8 : nin <= 16 ? 16 : 32;
   // the slab and op(G), later the exchange regions of the 8192 / nF transforms
   const int B = int((int64_t(1) << kKW) / nF);
-  const size_t lds = std::max<size_t>(size_t(nF) * S + size_t(nout) * NIN, size_t(B) * region_stride(lognf, B, true)) *
+  const size_t lds = std::max<size_t>(size_t(nF) * S + size_t(nout) * (NIN + 1), size_t(B) * region_stride(lognf, B, true)) *
                      sizeof(c64);
   const dim3 grid{unsigned(blocks)};
 #define FM_KRON_LAUNCH(N, RL)                                                                           \

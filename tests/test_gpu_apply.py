@@ -337,6 +337,27 @@ def test_composites(gpu, prec):
 
 
 @pytest.mark.parametrize("prec", ["c64", "c128"])
+@pytest.mark.parametrize("n1,n2", [(1024, 64), (2048, 37), (4096, 5), (512, 3)])
+def test_long_transforms_along_a_strided_axis(gpu, prec, n1, n2):
+    """Fourier(n1) along the slow axis of Kron(F_n1, F_n2): strided transforms
+    of 512..4096 points whose work-group tiles hold 8 or fewer vectors, i.e.
+    row segments shorter than a 128-byte line (the tiles of a line are
+    regrouped onto one XCD); ragged tile counts (37, 5, 3 vectors). Oracle:
+    mode products with the dense factors."""
+    import torch
+
+    rng = np.random.default_rng([n1, n2])
+    dt = torch_dt(prec)
+    K = gpu.Kron(gpu.Fourier(n1, dt), gpu.Fourier(n2, dt))
+    fs = [dense.fourier(n1), dense.fourier(n2)]
+    for adj in (False, True):
+        x = crandn(rng, (5, n1 * n2), NP[prec])
+        y = to_host(K.apply(to_dev(x), adjoint=adj))
+        err = rel_err(y, structured.kron_apply(fs, x, adjoint_dir=adj))
+        assert err <= TOL[prec], f"adj={adj}: rel err {err:.3e}"
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
 def test_adjoint_identity(gpu, prec):
     """<A x, y> = <x, A^H y> for a composed operator, on the GPU."""
     import torch
