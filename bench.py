@@ -189,7 +189,13 @@ def fista_solves(w, iters=100, stop_tol=1e-5, tune=True, reps=3):
     batch = fm.Batch(w["ops"], ncols)
     xt = [torch.from_numpy(data["ops"][i]["x_true"]).cuda() for i in range(len(ncols))]
     if tune:
-        batch.tune(xt, reps=2)
+        # the fold limit stays the per-operator path's (the batch's initial
+        # schedule), so batched and plain x can be compared bit for bit; the
+        # slot region is tuned
+        fold = batch.schedule()["max_fuse"]
+        sc = batch.tune(xt, reps=2)
+        if sc["max_fuse"] != fold:
+            batch.set_schedule(fold, sc["region_mib"])
     bs = batch.apply(xt)
     for i in range(len(ncols)):
         bs[i].add_(torch.from_numpy(data["ops"][i]["noise"]).cuda())
