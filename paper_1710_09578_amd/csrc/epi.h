@@ -37,7 +37,11 @@ __device__ __forceinline__ Cx<R> soft_thr(Cx<R> z, R s) {
 // the store destination. With a map (MAP): position e of the column goes to
 // Rr[omap[e]], with b read at the same index; unselected positions are not
 // stored.
-template <typename R, bool MAP = false>
+// CAP: the epilogue also keeps, per register index k, the value the adjoint
+// reads at the same position through the selection (r where selected, 0
+// elsewhere and at positions that are not stored), for a pass that continues
+// from registers.
+template <typename R, bool MAP = false, bool CAP = false>
 struct ResidualEpT {
   static constexpr bool kOn = true;
   const Cx<R>* B;
@@ -47,6 +51,7 @@ struct ResidualEpT {
   int64_t rstride = 0;         // MAP: element offset between the residual columns of a contiguous item
   Cx<R> bv[16];
   int mk[MAP ? 16 : 1];
+  Cx<R> cap[CAP ? 16 : 1] = {};
   __device__ __forceinline__ void pre(int k, int b, int e, Cx<R>*) {
     if constexpr (MAP) {
       const int m = omap[e];
@@ -57,17 +62,23 @@ struct ResidualEpT {
     }
   }
   __device__ __forceinline__ void put(int k, int, int b, int, Cx<R>* dst, Cx<R> v) {
+    const Cx<R> r = csub(v, bv[k]);
     if constexpr (MAP) {
-      if (mk[k] >= 0) Rr[int64_t(b) * rstride + mk[k]] = csub(v, bv[k]);
+      if (mk[k] >= 0) Rr[int64_t(b) * rstride + mk[k]] = r;
+      if constexpr (CAP) cap[k] = mk[k] >= 0 ? r : Cx<R>{R(0), R(0)};
     } else {
-      *dst = csub(v, bv[k]);
+      *dst = r;
+      if constexpr (CAP) cap[k] = r;
     }
   }
 };
 
 // FISTA update from g = A^H r. Contiguous items: transform b is column
-// gcol0 + b with x at X + b*xstride; strided items: one column.
-template <typename R>
+// gcol0 + b with x at X + b*xstride; strided items: one column. CAP: the
+// epilogue also keeps, per register index k, the new y (the old one for a
+// frozen column; 0 at positions that are not stored), the next forward
+// pass's input at the same positions.
+template <typename R, bool CAP = false>
 struct FistaEpT {
   static constexpr bool kOn = true;
   Cx<R>* X;
@@ -101,6 +112,7 @@ struct FistaEpT {
     cur_col = -1;
   }
   Cx<R> yk[16], xk[16];
+  Cx<R> cap[CAP ? 16 : 1] = {};
   __device__ __forceinline__ void pre(int k, int b, int e, Cx<R>* dst) {
     yk[k] = *dst;
     xk[k] = X[int64_t(b) * xstride + e];
@@ -116,7 +128,10 @@ struct FistaEpT {
       c_act = !active || active[gc];
       c_s = R(lam[gc] * invLd);
     }
-    if (!c_act) return;
+    if (!c_act) {
+      if constexpr (CAP) cap[k] = yk[k];
+      return;
+    }
     if (flush_per_slot) cur_col = gc;
     const R s = c_s;
     const Cx<R> yv = yk[k];
@@ -126,7 +141,9 @@ struct FistaEpT {
     const Cx<R> xn = soft_thr(z, s);
     const Cx<R> d = {xn.x - xo.x, xn.y - xo.y};
     *xp = xn;
-    *dst = momentum ? Cx<R>{xn.x + beta * d.x, xn.y + beta * d.y} : xn;
+    const Cx<R> yn = momentum ? Cx<R>{xn.x + beta * d.x, xn.y + beta * d.y} : xn;
+    *dst = yn;
+    if constexpr (CAP) cap[k] = yn;
     dx += double(d.x) * d.x + double(d.y) * d.y;
     nx += double(xn.x) * xn.x + double(xn.y) * xn.y;
     if (!(isfinite(z.x) && isfinite(z.y))) atomicOr(status + gc, 1);
@@ -137,8 +154,8 @@ struct FistaEpT {
 // of >= 16 points: the T = 2^(lg-4) threads of transform b are tid / T == b),
 // per item (strided items: one column, slot pbase + tile), or already flushed
 // (contiguous transforms of < 16 points). kThreads: the work-group size.
-template <int kThreads, typename R>
-__device__ __forceinline__ void fista_partials(FistaEpT<R>& ep, bool strided, int lg, int nvalid, int tile,
+template <int kThreads, typename R, bool CAP>
+__device__ __forceinline__ void fista_partials(FistaEpT<R, CAP>& ep, bool strided, int lg, int nvalid, int tile,
                                                void* smem) {
   if (ep.flush_per_slot) {
     ep.flush();

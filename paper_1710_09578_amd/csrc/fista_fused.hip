@@ -32,7 +32,17 @@ namespace {
 
 using namespace xf;
 
-enum FKind : int { FK_SINGLE = 0, FK_ROWF = 1, FK_FS1 = 2, FK_FS2 = 3, FK_FS3 = 4, FK_MX1 = 5, FK_MX3 = 6 };
+// FS31 / FS3U1: the last strided pass of one direction and the first strided
+// pass of the next in one work-group. Both cover the same column positions
+// (tile i0 .. i0 + 4096 / n2 of every strided transform), and a thread holds
+// the same points of its transform in both, so the first pass's epilogue
+// keeps the values the second loads (S^H r after the residual, y after the
+// update) in registers: one launch and one read of them fewer, same bits.
+enum FKind : int {
+  FK_SINGLE = 0, FK_ROWF = 1, FK_FS1 = 2, FK_FS2 = 3, FK_FS3 = 4, FK_MX1 = 5, FK_MX3 = 6,
+  FK_FS31 = 7,   // forward FS3 with the residual, then the adjoint's FS1
+  FK_FS3U1 = 8   // adjoint FS3 with the update, then the next forward FS1
+};
 
 template <typename R>
 struct FArgs {
@@ -67,9 +77,9 @@ struct FArgs {
   int64_t ncols;
 };
 
-template <typename R>
-__device__ __forceinline__ FistaEpT<R> update_ep(const FArgs<R>& a, int64_t col, bool strided, int lg) {
-  FistaEpT<R> ep;
+template <typename R, bool CAP = false>
+__device__ __forceinline__ FistaEpT<R, CAP> update_ep(const FArgs<R>& a, int64_t col, bool strided, int lg) {
+  FistaEpT<R, CAP> ep;
   ep.X = a.x + col * a.ldx;
   ep.xstride = strided ? 0 : a.ldx;
   ep.gcol0 = col;
@@ -165,6 +175,46 @@ __global__ __launch_bounds__(256) void ff_kernel(FArgs<R> a) {
     jb.q0 = k2;
     const Mode md{FFT_CONV, a.adj, a.logL, 1, 0};
     run_job<R, false, 12, true, NoEp, KIND == FK_ROWF && IMAP>(jb, md, 12, smem, a.tw);
+    return;
+  } else if constexpr (KIND == FK_FS31 || KIND == FK_FS3U1) {
+    // the direction's inverse strided pass with its epilogue (capturing), then
+    // the next direction's forward strided pass on the captured values
+    const int lg = 31 - __builtin_clz(a.n2);
+    const int tpw = 1 << (12 - lg);
+    const int i0 = int(blockIdx.x) * tpw;
+    Job<R> jb;
+    jb.xbstride = jb.ybstride = 1;
+    jb.inner = 4096;
+    jb.nvalid = tpw;
+    jb.i0 = i0;
+    jb.S = nullptr;
+    jb.sbstride = 0;
+    jb.q0 = i0;
+    jb.twl = a.twl;
+    jb.x = w + i0;
+    jb.y = (KIND == FK_FS3U1 ? a.yv + c * a.ldy : a.r + c * a.ldr) + i0;
+    jb.in_limit = int(a.L);
+    jb.out_limit = a.out_rows;
+    const Mode mi{FFT_INV, 0, 0, 0, 0};
+    const Mode mf{FFT_FWD, 0, a.logL, 0, 0};
+    Job<R> jf = jb;  // the second pass: from registers into the slot
+    jf.x = nullptr;
+    jf.y = w + i0;
+    jf.out_limit = int(a.L);
+    if constexpr (KIND == FK_FS31) {
+      ResidualEpT<R, MAP, true> ep{a.b + c * a.ldb, 0, a.r + c * a.ldr, a.omap, 0};
+      run_job<R, true, 12, true, ResidualEpT<R, MAP, true>>(jb, mi, lg, smem, a.tw, &ep);
+      __syncthreads();  // every thread is past the first pass's LDS use
+      jf.rin = ep.cap;
+      run_job<R, true, 12, true, NoEp, false, true>(jf, mf, lg, smem, a.tw);
+    } else {
+      FistaEpT<R, true> ep = update_ep<R, true>(a, c, true, lg);
+      run_job<R, true, 12, true, FistaEpT<R, true>>(jb, mi, lg, smem, a.tw, &ep);
+      fista_partials<256>(ep, true, lg, tpw, int(blockIdx.x), smem);
+      __syncthreads();  // the partial sums have left the LDS
+      jf.rin = ep.cap;
+      run_job<R, true, 12, true, NoEp, false, true>(jf, mf, lg, smem, a.tw);
+    }
     return;
   } else if constexpr (KIND == FK_FS1 || KIND == FK_FS3) {
     // strided 2^lg-point transforms at stride 4096 over 4096 / 2^lg positions
@@ -315,10 +365,28 @@ fm_status launch_direction(const FArgs<R>& a, bool adj, int fuse_max, hipStream_
   return launch_ff<R, FK_FS3, 2, false, false>(dim3(tiles, nc), a, s);
 }
 
+// Separate power-of-two strided passes of at least 16 points: the chained
+// form (one pass before the first iteration, then FS2, FS31, FS2, FS3U1 and
+// the stop check per iteration: five launches instead of seven).
+template <typename R>
+bool chained(const FArgs<R>& a, int fuse_max) {
+  const int n2 = a.n2;
+  return a.L > 4096 && n2 > fuse_max && (n2 & (n2 - 1)) == 0 && n2 >= 16;
+}
+
 template <typename R>
 fm_status launch_iteration(const FArgs<R>& fa, const FArgs<R>& aa, const FusedRun& run, int fuse_max, int nslot,
                            hipStream_t s) {
-  if (run.sel_map) {
+  if (chained(fa, fuse_max)) {
+    const dim3 grid(unsigned(fa.n2), unsigned(fa.ncols));  // n2 rows / n2 tiles per column
+    FM_TRY((launch_ff<R, FK_FS2, 0, false, false>(grid, fa, s)));
+    if (run.sel_map)
+      FM_TRY((launch_ff<R, FK_FS31, 1, false, true>(grid, fa, s)));
+    else
+      FM_TRY((launch_ff<R, FK_FS31, 1, false, false>(grid, fa, s)));
+    FM_TRY((launch_ff<R, FK_FS2, 0, false, false>(grid, aa, s)));
+    FM_TRY((launch_ff<R, FK_FS3U1, 2, false, false>(grid, aa, s)));
+  } else if (run.sel_map) {
     FM_TRY((launch_direction<R, true>(fa, false, fuse_max, s)));
     FM_TRY((launch_direction<R, true>(aa, true, fuse_max, s)));
   } else {
@@ -411,6 +479,8 @@ fm_status run_typed(const FusedRun& run, hipStream_t s) {
                      run.pbase);
   FM_LAUNCHED();
   if (run.max_iters <= 0) return FM_OK;
+  if (chained(fa, fuse_max))  // the first forward strided pass (the iterations chain the others)
+    FM_TRY((launch_ff<R, FK_FS1, 0, false, false>(dim3(unsigned(fa.n2), unsigned(fa.ncols)), fa, s)));
   // `chunk` iterations captured once and replayed (0: direct launches)
   const int chunk = std::min(graph_chunk(), run.max_iters);
   hipGraphExec_t exec = nullptr;

@@ -239,6 +239,10 @@ struct Job {
   // applied at the load (p is the position inside the vector)
   const int* imap = nullptr;
   const Cx<R>* xcol = nullptr;
+  // RIN (run_job template flag): the input values are already in the
+  // caller's registers, rin[k] for value k of the thread (the layout of the
+  // job's transform), instead of being loaded
+  const Cx<R>* rin = nullptr;
 };
 struct Mode {
   int mode, spec_conj, tw_log, tw_inv, accumulate;
@@ -276,7 +280,8 @@ __host__ __device__ constexpr int region_stride(int logn, int B, bool strided) {
 // values, which keeps 16 fewer registers live at the spectral product (the
 // batched stage kernel then fits 128 VGPRs, four work-groups per CU) at the
 // cost of a second round of spectrum loads.
-template <typename R, bool STRIDED, int LOGW, bool SPLIT_SPEC = false, class EP = NoEp, bool IMAP = false>
+template <typename R, bool STRIDED, int LOGW, bool SPLIT_SPEC = false, class EP = NoEp, bool IMAP = false,
+          bool RIN = false>
 __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int logn, Cx<R>* lds,
                                         const Cx<R>* __restrict__ tw, EP* ep = nullptr) {
   constexpr int kWG = Geo<LOGW>::kThreads;
@@ -292,7 +297,10 @@ __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int lo
     const int ii = STRIDED ? jb.i0 + b : 0;
     const Cx<R>* X = STRIDED ? jb.x + b : jb.x + b * jb.xbstride;
     Cx<R>* Y = STRIDED ? jb.y + b : jb.y + b * jb.ybstride;
-    if (!STRIDED && jb.fuse_n2 > 0) {
+    if constexpr (RIN) {
+#pragma unroll
+      for (int k = 0; k < kE; ++k) v[k] = valid ? jb.rin[k] : Cx<R>{R(0), R(0)};
+    } else if (!STRIDED && jb.fuse_n2 > 0) {
       // n2-outer order: the 16 loads of one n2 are in flight together and
       // consumed only after all of them were issued
       const int n2s = jb.fuse_n2;
