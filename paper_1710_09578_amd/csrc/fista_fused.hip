@@ -174,7 +174,9 @@ __global__ __launch_bounds__(256) void ff_kernel(FArgs<R> a) {
     jb.sbstride = 0;
     jb.q0 = k2;
     const Mode md{FFT_CONV, a.adj, a.logL, 1, 0};
-    run_job<R, false, 12, true, NoEp, KIND == FK_ROWF && IMAP>(jb, md, 12, smem, a.tw);
+    // rows are latency-bound launches of n2 work-groups per column: the
+    // twiddle seeds go out with the input loads (PRETW)
+    run_job<R, false, 12, true, NoEp, KIND == FK_ROWF && IMAP, false, true>(jb, md, 12, smem, a.tw);
     return;
   } else if constexpr (KIND == FK_FS31 || KIND == FK_FS3U1) {
     // the direction's inverse strided pass with its epilogue (capturing), then

@@ -110,8 +110,8 @@ __device__ __forceinline__ int pad32(int pos) { return pos + (pos >> 5); }
 // them. The transform is bound by its loads, so one load and 14 complex
 // products beat four loads and 11 products.
 template <typename R>
-__device__ __forceinline__ void twiddles16(const Cx<R>* __restrict__ tab, int jj, Cx<R>* w) {
-  w[1] = tab[jj];
+__device__ __forceinline__ void twiddles16_from(Cx<R> w1, Cx<R>* w) {
+  w[1] = w1;
   w[2] = cmul(w[1], w[1]);
   w[3] = cmul(w[1], w[2]);
   w[4] = cmul(w[2], w[2]);
@@ -121,6 +121,32 @@ __device__ __forceinline__ void twiddles16(const Cx<R>* __restrict__ tab, int jj
   w[8] = cmul(w[4], w[4]);
 #pragma unroll
   for (int r = 9; r < 16; ++r) w[r] = cmul(w[r - 8], w[8]);
+}
+template <typename R>
+__device__ __forceinline__ void twiddles16(const Cx<R>* __restrict__ tab, int jj, Cx<R>* w) {
+  twiddles16_from(tab[jj], w);
+}
+
+// The table entries W_{16 Ns}^(t mod Ns) of the (at most two) twiddled steps
+// of a 2^logn-point transform (4 <= logn <= 12), in step order: loaded once,
+// ahead of the transform, instead of on the critical path of every step.
+template <typename R>
+__device__ __forceinline__ void twiddle_seeds(int logn, int t, const Cx<R>* __restrict__ tw, Cx<R>* seeds) {
+  const int first = logn & 3;
+  const int nsteps = (logn >> 2) + (first ? 1 : 0);
+  int lns = first;
+  int ti = 0;
+  for (int step = first ? 1 : 0; step < nsteps; ++step) {
+    if (lns > 0) {  // constant indices only (the step count may be a run-time value)
+      const Cx<R> w1 = tw[((1 << lns) << 4) + (t & ((1 << lns) - 1))];
+      if (ti == 0)
+        seeds[0] = w1;
+      else
+        seeds[1] = w1;
+      ++ti;
+    }
+    lns += 4;
+  }
 }
 
 // Short first step (radix RR = 2, 4, 8, span 1, no twiddles) into LDS.
@@ -139,9 +165,11 @@ __device__ __forceinline__ void first_step(Cx<R>* v, Cx<R>* lds, int t, int T) {
   }
 }
 
-// Forward transform of 2^logn points (4 <= logn <= 12) held as described above.
+// Forward transform of 2^logn points (4 <= logn <= 12) held as described
+// above. seeds: the twiddle_seeds of this length (NULL: loaded per step).
 template <typename R>
-__device__ __forceinline__ void forward(Cx<R>* v, int logn, int t, Cx<R>* lds, const Cx<R>* __restrict__ tw) {
+__device__ __forceinline__ void forward(Cx<R>* v, int logn, int t, Cx<R>* lds, const Cx<R>* __restrict__ tw,
+                                        const Cx<R>* seeds = nullptr) {
   const int T = 1 << (logn - 4);
   const int first = logn & 3;
   const int nsteps = (logn >> 2) + (first ? 1 : 0);
@@ -161,11 +189,15 @@ __device__ __forceinline__ void forward(Cx<R>* v, int logn, int t, Cx<R>* lds, c
     lns = first;
     step = 1;
   }
+  int ti = 0;
   for (; step < nsteps; ++step) {
     const int ns = 1 << lns;
     if (lns > 0) {
       Cx<R> w[16];
-      twiddles16(tw + (ns << 4), t & (ns - 1), w);  // table of W_{16 Ns}
+      if (seeds)
+        twiddles16_from(ti++ == 0 ? seeds[0] : seeds[1], w);
+      else
+        twiddles16(tw + (ns << 4), t & (ns - 1), w);  // table of W_{16 Ns}
 #pragma unroll
       for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], w[r]);
     }
@@ -280,8 +312,11 @@ __host__ __device__ constexpr int region_stride(int logn, int B, bool strided) {
 // values, which keeps 16 fewer registers live at the spectral product (the
 // batched stage kernel then fits 128 VGPRs, four work-groups per CU) at the
 // cost of a second round of spectrum loads.
+// PRETW: the twiddle seeds of the transforms and of the twiddle epilogue are
+// loaded with the input, ahead of the arithmetic (for latency-bound launches
+// of few work-groups; a few more registers live through the transforms).
 template <typename R, bool STRIDED, int LOGW, bool SPLIT_SPEC = false, class EP = NoEp, bool IMAP = false,
-          bool RIN = false>
+          bool RIN = false, bool PRETW = false>
 __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int logn, Cx<R>* lds,
                                         const Cx<R>* __restrict__ tw, EP* ep = nullptr) {
   constexpr int kWG = Geo<LOGW>::kThreads;
@@ -297,6 +332,15 @@ __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int lo
     const int ii = STRIDED ? jb.i0 + b : 0;
     const Cx<R>* X = STRIDED ? jb.x + b : jb.x + b * jb.xbstride;
     Cx<R>* Y = STRIDED ? jb.y + b : jb.y + b * jb.ybstride;
+    Cx<R> seeds[2], ew0, ews;
+    if constexpr (PRETW) {
+      twiddle_seeds(logn, t, tw, seeds);
+      if (md.tw_log > 0) {
+        ew0 = jb.twl[t * (jb.q0 + b)];
+        ews = jb.twl[T * (jb.q0 + b)];
+      }
+    }
+    const Cx<R>* sd = PRETW ? seeds : nullptr;
     if constexpr (RIN) {
 #pragma unroll
       for (int k = 0; k < kE; ++k) v[k] = valid ? jb.rin[k] : Cx<R>{R(0), R(0)};
@@ -358,7 +402,7 @@ __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int lo
     }
     Cx<R>* my = lds + b * region_stride(logn, kWG >> (logn - 4), STRIDED);
     if (md.mode == FFT_INV) conj_all(v);
-    forward(v, logn, t, my, tw);
+    forward(v, logn, t, my, tw, sd);
     if (md.mode == FFT_CONV) {
       const Cx<R>* S = jb.S + b * jb.sbstride;
       constexpr int kPart = (SPLIT_SPEC && sizeof(R) == 4) ? kE / 2 : kE;
@@ -386,7 +430,7 @@ __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int lo
           v[h + k] = {p.x, -p.y};
         }
       }
-      forward(v, logn, t, my, tw);
+      forward(v, logn, t, my, tw, sd);
       conj_all(v);
     } else if (md.mode == FFT_INV) {
       conj_all(v);
@@ -395,8 +439,8 @@ __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int lo
       const Cx<R>* tab = jb.twl;
       const int qq = jb.q0 + b;
       // W^((t + T k) q) = W^(t q) (W^(T q))^k: two loads, the rest by products
-      Cx<R> w = tab[t * qq];
-      const Cx<R> ws = tab[T * qq];
+      Cx<R> w = PRETW ? ew0 : tab[t * qq];
+      const Cx<R> ws = PRETW ? ews : tab[T * qq];
 #pragma unroll
       for (int k = 0; k < kE; ++k) {
         v[k] = md.tw_inv ? cmulc(v[k], w) : cmul(v[k], w);
