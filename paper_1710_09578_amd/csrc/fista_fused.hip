@@ -179,8 +179,9 @@ __global__ __launch_bounds__(256) void ff_kernel(FArgs<R> a) {
     run_job<R, false, 12, true, NoEp, KIND == FK_ROWF && IMAP, false, true>(jb, md, 12, smem, a.tw);
     return;
   } else if constexpr (KIND == FK_FS31 || KIND == FK_FS3U1) {
-    // the direction's inverse strided pass with its epilogue (capturing), then
-    // the next direction's forward strided pass on the captured values
+    // the direction's inverse strided pass with its epilogue (capturing; its
+    // operand loads issued first), then the next direction's forward strided
+    // pass on the captured values
     const int lg = 31 - __builtin_clz(a.n2);
     const int tpw = 1 << (12 - lg);
     const int i0 = int(blockIdx.x) * tpw;
@@ -205,13 +206,13 @@ __global__ __launch_bounds__(256) void ff_kernel(FArgs<R> a) {
     jf.out_limit = int(a.L);
     if constexpr (KIND == FK_FS31) {
       ResidualEpT<R, MAP, true> ep{a.b + c * a.ldb, 0, a.r + c * a.ldr, a.omap, 0};
-      run_job<R, true, 12, true, ResidualEpT<R, MAP, true>>(jb, mi, lg, smem, a.tw, &ep);
+      run_job<R, true, 12, true, ResidualEpT<R, MAP, true>, false, false, false, true>(jb, mi, lg, smem, a.tw, &ep);
       __syncthreads();  // every thread is past the first pass's LDS use
       jf.rin = ep.cap;
       run_job<R, true, 12, true, NoEp, false, true>(jf, mf, lg, smem, a.tw);
     } else {
       FistaEpT<R, true> ep = update_ep<R, true>(a, c, true, lg);
-      run_job<R, true, 12, true, FistaEpT<R, true>>(jb, mi, lg, smem, a.tw, &ep);
+      run_job<R, true, 12, true, FistaEpT<R, true>, false, false, false, true>(jb, mi, lg, smem, a.tw, &ep);
       fista_partials<256>(ep, true, lg, tpw, int(blockIdx.x), smem);
       __syncthreads();  // the partial sums have left the LDS
       jf.rin = ep.cap;
@@ -249,10 +250,10 @@ __global__ __launch_bounds__(256) void ff_kernel(FArgs<R> a) {
       const Mode md{FFT_INV, 0, 0, 0, 0};
       if constexpr (EPI == 1) {
         ResidualEpT<R, MAP> ep{a.b + c * a.ldb, 0, a.r + c * a.ldr, a.omap, 0};
-        run_job<R, true, 12, true, ResidualEpT<R, MAP>>(jb, md, lg, smem, a.tw, &ep);
+        run_job<R, true, 12, true, ResidualEpT<R, MAP>, false, false, false, true>(jb, md, lg, smem, a.tw, &ep);
       } else {
         FistaEpT<R> ep = update_ep(a, c, true, lg);
-        run_job<R, true, 12, true, FistaEpT<R>>(jb, md, lg, smem, a.tw, &ep);
+        run_job<R, true, 12, true, FistaEpT<R>, false, false, false, true>(jb, md, lg, smem, a.tw, &ep);
         fista_partials<256>(ep, true, lg, tpw, int(blockIdx.x), smem);
       }
     }

@@ -315,8 +315,11 @@ __host__ __device__ constexpr int region_stride(int logn, int B, bool strided) {
 // PRETW: the twiddle seeds of the transforms and of the twiddle epilogue are
 // loaded with the input, ahead of the arithmetic (for latency-bound launches
 // of few work-groups; a few more registers live through the transforms).
+// EARLY_EP: the store epilogue's operand loads (EP::pre) are issued before
+// the input loads, so their latency overlaps the transform (registers held
+// through it).
 template <typename R, bool STRIDED, int LOGW, bool SPLIT_SPEC = false, class EP = NoEp, bool IMAP = false,
-          bool RIN = false, bool PRETW = false>
+          bool RIN = false, bool PRETW = false, bool EARLY_EP = false>
 __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int logn, Cx<R>* lds,
                                         const Cx<R>* __restrict__ tw, EP* ep = nullptr) {
   constexpr int kWG = Geo<LOGW>::kThreads;
@@ -341,6 +344,15 @@ __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int lo
       }
     }
     const Cx<R>* sd = PRETW ? seeds : nullptr;
+    if constexpr (EARLY_EP && EP::kOn) {
+      if (valid) {
+#pragma unroll
+        for (int k = 0; k < kE; ++k) {
+          const int p = t + T * k;
+          if (p * inner + ii < jb.out_limit) ep->pre(k, b, p * inner + ii, Y + p * inner);
+        }
+      }
+    }
     if constexpr (RIN) {
 #pragma unroll
       for (int k = 0; k < kE; ++k) v[k] = valid ? jb.rin[k] : Cx<R>{R(0), R(0)};
@@ -454,7 +466,7 @@ __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int lo
 #pragma unroll
           for (int k = h; k < h + 8; ++k) {
             const int p = t + T * k;
-            if (p * inner + ii < jb.out_limit) ep->pre(k, b, p * inner + ii, Y + p * inner);
+            if (!EARLY_EP && p * inner + ii < jb.out_limit) ep->pre(k, b, p * inner + ii, Y + p * inner);
           }
 #pragma unroll
           for (int k = h; k < h + 8; ++k) {
