@@ -75,7 +75,31 @@ struct FArgs {
   const int* iter;
   int momentum;
   int64_t ncols;
+  // chained iterations: the forward's first launch (FS2) also runs the
+  // previous iteration's stop check (check), the next launch (FS31) advances
+  // the iteration counter (bump); see launch_chained
+  int check, bump, nslot;
+  double stop_tol;
+  int* active_w;
+  int* iters;
+  int* iter_w;
 };
+
+// Stop rule of one column after an iteration: freeze when it met a
+// non-finite value or when ||x+ - x|| <= tol * max(||x+||, 1e-30), with the
+// partial sums taken in slot order.
+__device__ __forceinline__ bool freeze_now(const double* partial, const int64_t* pbase, int nslot, int64_t c,
+                                           double tol, const int* status) {
+  if (status[c]) return true;
+  if (tol <= 0.0) return false;
+  double dx = 0.0, nx = 0.0;
+  for (int t = 0; t < nslot; ++t) {
+    dx += partial[2 * (pbase[c] + t)];
+    nx += partial[2 * (pbase[c] + t) + 1];
+  }
+  const double nrm = sqrt(nx);
+  return sqrt(dx) <= tol * (nrm > 1e-30 ? nrm : 1e-30);
+}
 
 template <typename R, bool CAP = false>
 __device__ __forceinline__ FistaEpT<R, CAP> update_ep(const FArgs<R>& a, int64_t col, bool strided, int lg) {
@@ -145,7 +169,20 @@ __global__ __launch_bounds__(256) void ff_kernel(FArgs<R> a) {
     return;
   }
   const int64_t c = blockIdx.y;
+  if constexpr (KIND == FK_FS31) {  // advance the counter once per launch (frozen columns included)
+    if (a.bump && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *a.iter_w = *a.iter + 1;
+  }
   if (a.active && !a.active[c]) return;
+  if constexpr (KIND == FK_FS2) {
+    // the previous iteration's stop check, taken by every work-group of the
+    // column alike (the same sums in the same order); the first one records
+    // it. The row pass of a column frozen here is computed and not used.
+    if (a.check && blockIdx.x == 0 && threadIdx.x == 0 &&
+        freeze_now(a.partial, a.pbase, a.nslot, c, a.stop_tol, a.status)) {
+      a.active_w[c] = 0;
+      a.iters[c] = *a.iter + 1;
+    }
+  }
   Cx<R>* w = a.slot + c * a.L;
   const Cx<R>* xin = a.in + c * a.ldin;
   if constexpr (KIND == FK_ROWF || KIND == FK_FS2) {
@@ -288,19 +325,7 @@ __global__ __launch_bounds__(256) void ff_stop_kernel(const double* partial, con
   const int k = *iter;
   for (int64_t c = threadIdx.x; c < ncols; c += blockDim.x) {
     if (!active[c]) continue;
-    if (status[c]) {
-      active[c] = 0;
-      iters[c] = k + 1;
-      continue;
-    }
-    if (tol <= 0.0) continue;
-    double dx = 0.0, nx = 0.0;
-    for (int t = 0; t < nslot; ++t) {
-      dx += partial[2 * (pbase[c] + t)];
-      nx += partial[2 * (pbase[c] + t) + 1];
-    }
-    const double nrm = sqrt(nx);
-    if (sqrt(dx) <= tol * (nrm > 1e-30 ? nrm : 1e-30)) {
+    if (freeze_now(partial, pbase, nslot, c, tol, status)) {
       active[c] = 0;
       iters[c] = k + 1;
     }
@@ -368,6 +393,13 @@ fm_status launch_direction(const FArgs<R>& a, bool adj, int fuse_max, hipStream_
   return launch_ff<R, FK_FS3, 2, false, false>(dim3(tiles, nc), a, s);
 }
 
+fm_status launch_final_check(const FusedRun& run, int nslot, hipStream_t s) {
+  hipLaunchKernelGGL(ff_stop_kernel, dim3(1), dim3(256), 0, s, run.partial, run.pbase, nslot, run.ncols,
+                     run.stop_tol, run.active, run.iters, run.status, run.iter);
+  FM_LAUNCHED();
+  return FM_OK;
+}
+
 // Separate power-of-two strided passes of at least 16 points: the chained
 // form (one pass before the first iteration, then FS2, FS31, FS2, FS3U1 and
 // the stop check per iteration: five launches instead of seven).
@@ -377,18 +409,25 @@ bool chained(const FArgs<R>& a, int fuse_max) {
   return a.L > 4096 && n2 > fuse_max && (n2 & (n2 - 1)) == 0 && n2 >= 16;
 }
 
+// One iteration. Chained form: FS2 (forward rows; from the second iteration
+// on also the previous iteration's stop check), FS31 (advances the counter
+// from the second iteration on), FS2 (adjoint rows), FS3U1; the check of the
+// last iteration is a stop kernel after the loop (launch_final_check). Other
+// forms: the direction's passes and a stop kernel.
 template <typename R>
 fm_status launch_iteration(const FArgs<R>& fa, const FArgs<R>& aa, const FusedRun& run, int fuse_max, int nslot,
-                           hipStream_t s) {
+                           bool first, hipStream_t s) {
   if (chained(fa, fuse_max)) {
     const dim3 grid(unsigned(fa.n2), unsigned(fa.ncols));  // n2 rows / n2 tiles per column
-    FM_TRY((launch_ff<R, FK_FS2, 0, false, false>(grid, fa, s)));
+    FArgs<R> f = fa;
+    f.check = f.bump = first ? 0 : 1;
+    FM_TRY((launch_ff<R, FK_FS2, 0, false, false>(grid, f, s)));
     if (run.sel_map)
-      FM_TRY((launch_ff<R, FK_FS31, 1, false, true>(grid, fa, s)));
+      FM_TRY((launch_ff<R, FK_FS31, 1, false, true>(grid, f, s)));
     else
-      FM_TRY((launch_ff<R, FK_FS31, 1, false, false>(grid, fa, s)));
+      FM_TRY((launch_ff<R, FK_FS31, 1, false, false>(grid, f, s)));
     FM_TRY((launch_ff<R, FK_FS2, 0, false, false>(grid, aa, s)));
-    FM_TRY((launch_ff<R, FK_FS3U1, 2, false, false>(grid, aa, s)));
+    return launch_ff<R, FK_FS3U1, 2, false, false>(grid, aa, s);
   } else if (run.sel_map) {
     FM_TRY((launch_direction<R, true>(fa, false, fuse_max, s)));
     FM_TRY((launch_direction<R, true>(aa, true, fuse_max, s)));
@@ -396,10 +435,7 @@ fm_status launch_iteration(const FArgs<R>& fa, const FArgs<R>& aa, const FusedRu
     FM_TRY((launch_direction<R, false>(fa, false, fuse_max, s)));
     FM_TRY((launch_direction<R, false>(aa, true, fuse_max, s)));
   }
-  hipLaunchKernelGGL(ff_stop_kernel, dim3(1), dim3(256), 0, s, run.partial, run.pbase, nslot, run.ncols,
-                     run.stop_tol, run.active, run.iters, run.status, run.iter);
-  FM_LAUNCHED();
-  return FM_OK;
+  return launch_final_check(run, nslot, s);
 }
 
 // Iterations per captured graph (FM_FISTA_GRAPH; 0: direct launches).
@@ -459,6 +495,12 @@ fm_status run_typed(const FusedRun& run, hipStream_t s) {
   fa.iter = run.iter;
   fa.momentum = run.momentum;
   fa.ncols = run.ncols;
+  fa.check = fa.bump = 0;
+  fa.nslot = fused_nslot(C, sizeof(R) == 4 ? Elem::C64 : Elem::C128);
+  fa.stop_tol = run.stop_tol;
+  fa.active_w = run.active;
+  fa.iters = run.iters;
+  fa.iter_w = run.iter;
   FArgs<R> aa = fa;
   // forward: C y (C's input rows n_C), r = S (C y) - b
   fa.in = fa.yv;
@@ -482,15 +524,20 @@ fm_status run_typed(const FusedRun& run, hipStream_t s) {
                      run.pbase);
   FM_LAUNCHED();
   if (run.max_iters <= 0) return FM_OK;
-  if (chained(fa, fuse_max))  // the first forward strided pass (the iterations chain the others)
+  const bool ch = chained(fa, fuse_max);
+  int k = 0;
+  if (ch) {  // the first forward strided pass and the first iteration (no check before it)
     FM_TRY((launch_ff<R, FK_FS1, 0, false, false>(dim3(unsigned(fa.n2), unsigned(fa.ncols)), fa, s)));
+    FM_TRY(launch_iteration<R>(fa, aa, run, fuse_max, nslot, true, s));
+    k = 1;
+  }
   // `chunk` iterations captured once and replayed (0: direct launches)
-  const int chunk = std::min(graph_chunk(), run.max_iters);
+  const int chunk = std::min(graph_chunk(), run.max_iters - k);
   hipGraphExec_t exec = nullptr;
   hipStream_t cs = chunk > 0 ? capture_stream() : nullptr;
   if (cs && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
     fm_status st = FM_OK;
-    for (int k = 0; k < chunk && st == FM_OK; ++k) st = launch_iteration<R>(fa, aa, run, fuse_max, nslot, cs);
+    for (int j = 0; j < chunk && st == FM_OK; ++j) st = launch_iteration<R>(fa, aa, run, fuse_max, nslot, false, cs);
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(cs, &g);
     if (st == FM_OK && ec == hipSuccess && g) {
@@ -500,14 +547,14 @@ fm_status run_typed(const FusedRun& run, hipStream_t s) {
     (void)hipGetLastError();
   }
   fm_status st = FM_OK;
-  int k = 0;
   for (; exec && k + chunk <= run.max_iters && st == FM_OK; k += chunk) {
     if (hipGraphLaunch(exec, s) != hipSuccess) {
       set_error("hipGraphLaunch failed");
       st = FM_E_DEVICE;
     }
   }
-  for (; k < run.max_iters && st == FM_OK; ++k) st = launch_iteration<R>(fa, aa, run, fuse_max, nslot, s);
+  for (; k < run.max_iters && st == FM_OK; ++k) st = launch_iteration<R>(fa, aa, run, fuse_max, nslot, false, s);
+  if (ch && st == FM_OK) st = launch_final_check(run, nslot, s);  // the last iteration's check
   if (exec) {
     (void)hipStreamSynchronize(s);  // the replays have finished before the graph goes
     (void)hipGraphExecDestroy(exec);
