@@ -312,9 +312,10 @@ __host__ __device__ constexpr int region_stride(int logn, int B, bool strided) {
 // values, which keeps 16 fewer registers live at the spectral product (the
 // batched stage kernel then fits 128 VGPRs, four work-groups per CU) at the
 // cost of a second round of spectrum loads.
-// PRETW: the twiddle seeds of the transforms and of the twiddle epilogue are
-// loaded with the input, ahead of the arithmetic (for latency-bound launches
-// of few work-groups; a few more registers live through the transforms).
+// PRETW: the twiddle seeds of the transforms and of the twiddle epilogue, and
+// a convolution's spectrum, are loaded with the input, ahead of the
+// arithmetic (for latency-bound launches of few work-groups; more registers
+// live through the transforms).
 // EARLY_EP: the store epilogue's operand loads (EP::pre) are issued before
 // the input loads, so their latency overlaps the transform (registers held
 // through it).
@@ -335,12 +336,27 @@ __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int lo
     const int ii = STRIDED ? jb.i0 + b : 0;
     const Cx<R>* X = STRIDED ? jb.x + b : jb.x + b * jb.xbstride;
     Cx<R>* Y = STRIDED ? jb.y + b : jb.y + b * jb.ybstride;
-    Cx<R> seeds[2], ew0, ews;
+    Cx<R> seeds[2], ew0, ews, spre[PRETW ? kE : 1];
     if constexpr (PRETW) {
       twiddle_seeds(logn, t, tw, seeds);
       if (md.tw_log > 0) {
         ew0 = jb.twl[t * (jb.q0 + b)];
         ews = jb.twl[T * (jb.q0 + b)];
+      }
+      if (md.mode == FFT_CONV) {  // the whole spectrum, in one round
+        const Cx<R>* S = jb.S + b * jb.sbstride;
+        if constexpr (sizeof(R) == 4) {
+          const float4* S4 = reinterpret_cast<const float4*>(S);
+#pragma unroll
+          for (int j = 0; j < kE / 2; ++j) {
+            const float4 q = S4[t + T * j];
+            spre[2 * j] = {q.x, q.y};
+            spre[2 * j + 1] = {q.z, q.w};
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < kE; ++k) spre[k] = S[t + T * k];
+        }
       }
     }
     const Cx<R>* sd = PRETW ? seeds : nullptr;
@@ -417,11 +433,14 @@ __device__ __forceinline__ void run_job(const Job<R>& jb, const Mode& md, int lo
     forward(v, logn, t, my, tw, sd);
     if (md.mode == FFT_CONV) {
       const Cx<R>* S = jb.S + b * jb.sbstride;
-      constexpr int kPart = (SPLIT_SPEC && sizeof(R) == 4) ? kE / 2 : kE;
+      constexpr int kPart = (SPLIT_SPEC && sizeof(R) == 4 && !PRETW) ? kE / 2 : kE;
 #pragma unroll
       for (int h = 0; h < kE; h += kPart) {
         Cx<R> sv[kPart];
-        if constexpr (sizeof(R) == 4) {
+        if constexpr (PRETW) {
+#pragma unroll
+          for (int k = 0; k < kPart; ++k) sv[k] = spre[h + k];
+        } else if constexpr (sizeof(R) == 4) {
           // complex64 spectra are stored in pair order: values k and k + 1 of
           // a thread are adjacent, one 16-byte load per pair
           const float4* S4 = reinterpret_cast<const float4*>(S);
