@@ -135,6 +135,37 @@ def test_stop_counts_and_warm_start_fused(gpu):
     assert rel_err(to_host(x), x_ref) <= TOL["c128"]
 
 
+def test_stop_counts_short_runs_and_warm_start_chained(gpu):
+    """The chained form (a separate power-of-two strided pass, n2 = 16: each
+    iteration's stop check runs inside the next iteration's first launch and
+    a stop kernel follows the last one): per-column stopping against the
+    oracle's counts, runs of 1 and 2 iterations, and a warm start
+    (complex128: the stop decision is taken on values within 1e-12 of the
+    oracle's)."""
+    n = 30000
+    col, row, rows, b, ap, ad, L = toeplitz_case("c128", n, 2, seed=78, select=12000)
+    T = gpu.Toeplitz(to_dev(col), to_dev(row))
+    assert T.transform_length == 65536
+    A = gpu.Product(gpu.SelectRows(n, to_dev(rows.astype(np.int32)), tdt("c128")), T)
+    lam = 0.05 * float(np.max(np.abs(ad(b))))
+    x, st = gpu.fista(A, to_dev(b), iters=400, lam=lam, L=L, stop_tol=1e-4)
+    _, done = fista.fista_op(ap, ad, n, b, lam, L, 400, stop_tol=1e-4)
+    counts = np.array([s["iters"] for s in st])
+    assert np.all(np.abs(counts - done) <= 1) and np.all(done < 400), (counts, done)
+    for j in range(2):
+        xj, _ = fista.fista_op(ap, ad, n, b[j:j + 1], lam, L, int(counts[j]))
+        assert rel_err(to_host(x)[j:j + 1], xj) <= TOL["c128"]
+    for iters in (1, 2):
+        x, st = gpu.fista(A, to_dev(b), iters=iters, lam=lam, L=L)
+        assert all(s["iters"] == iters for s in st)
+        x_ref, _ = fista.fista_op(ap, ad, n, b, lam, L, iters)
+        assert rel_err(to_host(x), x_ref) <= TOL["c128"], iters
+    x0 = crandn(np.random.default_rng(4), (1, n), np.complex128)
+    x, _ = gpu.fista(A, to_dev(b[:1]), iters=12, lam=lam, L=L, x0=to_dev(x0))
+    x_ref, _ = fista.fista_op(ap, ad, n, b[:1], lam, L, 12, x0=x0)
+    assert rel_err(to_host(x), x_ref) <= TOL["c128"]
+
+
 def test_general_loop_form(gpu):
     """Diag times Circulant has no fused form: the general loop solves it."""
     rng = np.random.default_rng(5)
