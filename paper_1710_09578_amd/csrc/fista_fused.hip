@@ -393,7 +393,8 @@ fm_status launch_direction(const FArgs<R>& a, bool adj, int fuse_max, hipStream_
   return launch_ff<R, FK_FS3, 2, false, false>(dim3(tiles, nc), a, s);
 }
 
-fm_status launch_final_check(const FusedRun& run, int nslot, hipStream_t s) {
+// The stop kernel of one iteration.
+fm_status launch_stop_check(const FusedRun& run, int nslot, hipStream_t s) {
   hipLaunchKernelGGL(ff_stop_kernel, dim3(1), dim3(256), 0, s, run.partial, run.pbase, nslot, run.ncols,
                      run.stop_tol, run.active, run.iters, run.status, run.iter);
   FM_LAUNCHED();
@@ -401,8 +402,9 @@ fm_status launch_final_check(const FusedRun& run, int nslot, hipStream_t s) {
 }
 
 // Separate power-of-two strided passes of at least 16 points: the chained
-// form (one pass before the first iteration, then FS2, FS31, FS2, FS3U1 and
-// the stop check per iteration: five launches instead of seven).
+// form (one pass before the first iteration, then FS2, FS31, FS2 and FS3U1
+// per iteration with the stop check inside them: four launches instead of
+// seven).
 template <typename R>
 bool chained(const FArgs<R>& a, int fuse_max) {
   const int n2 = a.n2;
@@ -412,7 +414,7 @@ bool chained(const FArgs<R>& a, int fuse_max) {
 // One iteration. Chained form: FS2 (forward rows; from the second iteration
 // on also the previous iteration's stop check), FS31 (advances the counter
 // from the second iteration on), FS2 (adjoint rows), FS3U1; the check of the
-// last iteration is a stop kernel after the loop (launch_final_check). Other
+// last iteration is a stop kernel after the loop (launch_stop_check). Other
 // forms: the direction's passes and a stop kernel.
 template <typename R>
 fm_status launch_iteration(const FArgs<R>& fa, const FArgs<R>& aa, const FusedRun& run, int fuse_max, int nslot,
@@ -435,7 +437,7 @@ fm_status launch_iteration(const FArgs<R>& fa, const FArgs<R>& aa, const FusedRu
     FM_TRY((launch_direction<R, false>(fa, false, fuse_max, s)));
     FM_TRY((launch_direction<R, false>(aa, true, fuse_max, s)));
   }
-  return launch_final_check(run, nslot, s);
+  return launch_stop_check(run, nslot, s);
 }
 
 // Iterations per captured graph (FM_FISTA_GRAPH; 0: direct launches).
@@ -554,7 +556,7 @@ fm_status run_typed(const FusedRun& run, hipStream_t s) {
     }
   }
   for (; k < run.max_iters && st == FM_OK; ++k) st = launch_iteration<R>(fa, aa, run, fuse_max, nslot, false, s);
-  if (ch && st == FM_OK) st = launch_final_check(run, nslot, s);  // the last iteration's check
+  if (ch && st == FM_OK) st = launch_stop_check(run, nslot, s);  // the last iteration's check
   if (exec) {
     (void)hipStreamSynchronize(s);  // the replays have finished before the graph goes
     (void)hipGraphExecDestroy(exec);
