@@ -50,8 +50,12 @@ constexpr int kXcdCount = 8;  // work-group g runs on XCD g mod 8
 // FIX), so the steps unroll and every LDS and twiddle index folds into
 // immediate offsets; the arithmetic is the same as the run-time form's, so
 // both give the same bits.
-template <typename R, bool STRIDED, int LOGW, bool XG = false, int FIX = 0>
-__global__ __launch_bounds__(Geo<LOGW>::kThreads, ((STRIDED || FIX > 0) && sizeof(R) == 4) ? 4 : 1) void fft_kernel(KArgs a) {
+// PRE (compile-time lengths only): the spectrum and the twiddle seeds are
+// loaded together with the input (the engine's PRETW), one dependent memory
+// round trip less per work-group, for launches too small to hide it (fewer
+// work-groups than CUs); more registers live, same arithmetic and bits.
+template <typename R, bool STRIDED, int LOGW, bool XG = false, int FIX = 0, bool PRE = false>
+__global__ __launch_bounds__(Geo<LOGW>::kThreads, (!PRE && (STRIDED || FIX > 0) && sizeof(R) == 4) ? 4 : 1) void fft_kernel(KArgs a) {
   extern __shared__ unsigned char smem_raw[];
   Cx<R>* lds = reinterpret_cast<Cx<R>*>(smem_raw);
   const int logn = FIX > 0 ? FIX : a.logn;
@@ -134,21 +138,26 @@ __global__ __launch_bounds__(Geo<LOGW>::kThreads, ((STRIDED || FIX > 0) && sizeo
   jb.fuse_n2 = a.fuse_n2;
   jb.twl = reinterpret_cast<const Cx<R>*>(a.twl);
   const Mode md{a.mode, a.spec_conj, a.tw_log, a.tw_inv, a.accumulate};
-  run_job<R, STRIDED, LOGW, (FIX > 0)>(jb, md, logn, lds, reinterpret_cast<const Cx<R>*>(a.tw));
+  run_job<R, STRIDED, LOGW, (FIX > 0), NoEp, false, false, PRE>(jb, md, logn, lds, reinterpret_cast<const Cx<R>*>(a.tw));
 }
 
 // Contiguous transforms of 2^kFixMin .. 2^LOGW points run the compile-time
 // length forms.
 constexpr int kFixMin = 4;
-template <typename R, int LOGW, int LG = LOGW>
+template <typename R, int LOGW, bool PRE = false, int LG = LOGW>
 const void* fixed_kernel(int lg) {
   if constexpr (LG < kFixMin) {
     return nullptr;
   } else {
-    if (lg == LG) return reinterpret_cast<const void*>(&fft_kernel<R, false, LOGW, false, LG>);
-    return fixed_kernel<R, LOGW, LG - 1>(lg);
+    if (lg == LG) return reinterpret_cast<const void*>(&fft_kernel<R, false, LOGW, false, LG, PRE>);
+    return fixed_kernel<R, LOGW, PRE, LG - 1>(lg);
   }
 }
+// Launches of at most this many work-groups take the PRE forms (one-wave
+// work-groups only).
+#ifndef FM_PRE_MAX_WG
+#define FM_PRE_MAX_WG 256
+#endif
 
 template <typename R, int LOGW>
 fm_status launch_typed(const FftLaunch& L, KArgs ka, hipStream_t s) {
@@ -200,8 +209,9 @@ fm_status launch_typed(const FftLaunch& L, KArgs ka, hipStream_t s) {
                        ka);
   else if (L.logn >= kFixMin) {
     void* args[] = {&ka};
-    FM_HIP(hipLaunchKernel(fixed_kernel<R, LOGW>(L.logn), dim3(unsigned(blocks)), wg, args,
-                           job_lds_bytes<R, LOGW>(), s));
+    const bool pre = LOGW == FM_SMALL_LOGW && blocks <= FM_PRE_MAX_WG;
+    FM_HIP(hipLaunchKernel(pre ? fixed_kernel<R, FM_SMALL_LOGW, true>(L.logn) : fixed_kernel<R, LOGW>(L.logn),
+                           dim3(unsigned(blocks)), wg, args, job_lds_bytes<R, LOGW>(), s));
   } else
     hipLaunchKernelGGL((fft_kernel<R, false, LOGW>), dim3(unsigned(blocks)), wg, (job_lds_bytes<R, LOGW>()), s, ka);
   FM_LAUNCHED();

@@ -90,6 +90,26 @@ def test_circulant_1024_x16_config(gpu):
 
 
 @pytest.mark.parametrize("prec", ["c64", "c128"])
+@pytest.mark.parametrize("n", [16, 32, 64, 128, 256, 512, 1024])
+def test_few_columns_same_bits_as_many(gpu, prec, n):
+    """A launch of few work-groups loads the spectrum and twiddle seeds with
+    the input (latency form); a launch of many does not. Both take the same
+    arithmetic: the first columns of a wide block equal the same columns
+    applied alone, bit for bit, and both match the oracle."""
+    rng = np.random.default_rng(900 + n)
+    c = crandn(rng, n, NP[prec])
+    op = gpu.Circulant(to_dev(c))
+    wide = crandn(rng, (512 * (1024 // n), n), NP[prec])  # 512 one-wave work-groups of 1024 // n transforms
+    few = wide[:16].copy()                                # at most 16
+    a = dense.circulant(c)
+    for adj in (False, True):
+        yw = to_host(op.apply(to_dev(wide), adjoint=adj))
+        yf = to_host(op.apply(to_dev(few), adjoint=adj))
+        assert np.array_equal(yw[:16], yf), f"adj={adj}: latency form differs from the throughput form"
+        assert rel_err(yf, dense.apply(a, few, adj)) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
 @pytest.mark.parametrize("n", [4096, 8192, 16384, 65536, 131072])
 def test_circulant_large(gpu, prec, n):
     rng = np.random.default_rng(200 + n)
