@@ -86,7 +86,9 @@ fm_status fm_op_create_hadamard(fm_op* out, int64_t n, fm_dtype dt);
 fm_status fm_op_create_diag(fm_op* out, int64_t n, const void* d, fm_dtype dt, void* stream);
 
 /* Dense m x n matrix, column-major with leading dimension lda >= m (the plain
- * product of eq. (2)); used mainly as a Kronecker factor. Complex dtypes. */
+ * product of eq. (2)); used mainly as a Kronecker factor. Complex dtypes.
+ * complex64 products of at most 64 x 64 with 64 or more vectors run on the
+ * matrix cores (FM_DENSE_MFMA=0 keeps them on the vector units). */
 fm_status fm_op_create_dense(fm_op* out, int64_t m, int64_t n, const void* a, int64_t lda,
                              fm_dtype dt, void* stream);
 
@@ -329,7 +331,14 @@ typedef struct {
 /* Runs the iteration on `stream`; b is m x ncols, x is n x ncols (output; also
  * the start when x0_given). stats: HOST array of ncols entries, filled after the
  * single synchronisation at the end (may be NULL). Workspace as in fm_apply
- * (size from fm_fista_workspace_size). Complex dtypes. */
+ * (size from fm_fista_workspace_size). Complex dtypes.
+ * For A = C or A = S C (C a circulant or Toeplitz leaf, S a row selection) the
+ * iteration runs in the convolution's own passes, with the residual and the
+ * update in their loads and stores, replayed from HIP graphs of 10 iterations;
+ * other operators run the general loop (products through fm_apply's executor,
+ * then the update). Environment: FM_FISTA_FUSED=0 sends every operator through
+ * the general loop; FM_FISTA_GRAPH=k captures k iterations per graph (0: direct
+ * launches). Both forms give the same iterates up to rounding. */
 fm_status fm_fista(fm_op a, int64_t ncols, const void* b, int64_t ldb, void* x, int64_t ldx,
                    const fm_fista_opts* opts, fm_fista_stat* stats, void* ws, size_t ws_bytes,
                    void* stream);
