@@ -13,8 +13,10 @@
 //             device iteration counter that selects the next momentum weight.
 // The passes and their work items are those of the batched stage kernel (the
 // same engine calls and epilogues), so a complex64 solve gives the same bits
-// as the same problem solved in a batch. One iteration's launches are captured
-// once per solve into a HIP graph and replayed for every iteration.
+// as the same problem solved in a batch. The launches of a chunk of steady
+// iterations (10 by default) are captured once per solve into a HIP graph and
+// replayed; the first iteration and a remainder shorter than a chunk are
+// launched directly.
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
