@@ -73,9 +73,8 @@ def test_conj_and_transpose(gpu, prec):
 @pytest.mark.parametrize("prec", ["c64", "c128"])
 def test_gram(gpu, prec):
     rng = np.random.default_rng(37)
-    tol = {"c64": 5e-5, "c128": 1e-12}[prec]  # |c_hat|^2 squares the spectrum's rounding
-    for name, op, a in zoo(gpu, prec, rng):
-        check_both(op.gram, a.conj().T @ a, rng, prec, tol=tol)
+    for name, op, a in zoo(gpu, prec, rng):  # measured <= 4.7e-7 (c64), 1.1e-15 (c128)
+        check_both(op.gram, a.conj().T @ a, rng, prec)
     n, rows = 32, np.array([1, 4, 9, 30], np.int32)
     S = gpu.SelectRows(n, to_dev(rows), tdt(prec))
     check_both(S.gram, dense.select_rows(n, rows).T @ dense.select_rows(n, rows), rng, prec)
@@ -86,8 +85,7 @@ def test_structured_inverse(gpu, prec):
     import paper_1710_09578_amd as fm
 
     rng = np.random.default_rng(41)
-    tol = {"c64": 1e-4, "c128": 1e-11}[prec]  # conditioning of the random spectra
-    for name, op, a in zoo(gpu, prec, rng):
+    for name, op, a in zoo(gpu, prec, rng):  # condition numbers <= 5.2; measured <= 3.0e-7 (c64), 2.3e-15 (c128)
         if name == "toeplitz":
             continue  # Levinson: test_toeplitz_inverse_levinson
         if name in ("dense", "kron"):
@@ -95,7 +93,7 @@ def test_structured_inverse(gpu, prec):
                 op.inverse
             assert e.value.code == "FM_E_UNSUPPORTED"
             continue
-        check_both(op.inverse, np.linalg.inv(a), rng, prec, tol=tol)
+        check_both(op.inverse, np.linalg.inv(a), rng, prec)
     with pytest.raises(fm.FmError) as e:  # singular circulant: c = ones has c_hat = (n, 0, ..., 0)
         gpu.Circulant(to_dev(np.ones(16, NP[prec]))).inverse
     assert e.value.code == "FM_E_INVALID"
@@ -143,7 +141,10 @@ def test_toeplitz_inverse_levinson(gpu, prec, n):
     col[0] += 3
     T = gpu.Toeplitz(to_dev(col), to_dev(row))
     inv = np.linalg.inv(dense.toeplitz(col, row))
-    tol = {"c64": 1e-4, "c128": 1e-11}[prec]
+    # the recursion runs n dependent steps in the working precision, so its
+    # rounding grows with n: measured 1.7e-5 at n = 1500 in complex64
+    # (condition number 9) and 4.3e-15 in complex128
+    tol = {"c64": 1e-4, "c128": 1e-12}[prec]
     check_both(T.inverse, inv, rng, prec, tol=tol)
     check_both(gpu.Sum(T.inverse, T.inverse), 2 * inv, rng, prec, tol=tol)
     if n > 1:
