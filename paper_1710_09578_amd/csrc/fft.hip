@@ -26,6 +26,27 @@ struct KArgs {
   int mode, spec_conj, tw_log, tw_inv, accumulate, logn, fuse_n2;
   int layout;  // contiguous: 0 transforms = columns, 1 packed (ncols*outer), 2 per column
   int64_t tiles;  // work-groups per column (layout 2) / per vector (strided)
+  const int* map;  // row selection at the load (MAP 1) or the store (MAP 2)
+};
+
+// Store epilogue of a row selection applied to the result: position e of a
+// transform's output vector goes to row omap[e] of its column (added with
+// acc), and nowhere where omap[e] < 0. Y: the column of transform 0 (strided
+// items: the one column of the work-group, stride 0).
+template <typename R>
+struct MapStoreEp {
+  static constexpr bool kOn = true;
+  Cx<R>* Y;
+  int64_t ystride;
+  const int* omap;
+  int acc;
+  int mk[kE];
+  __device__ __forceinline__ void pre(int k, int, int e, Cx<R>*) { mk[k] = omap[e]; }
+  __device__ __forceinline__ void put(int k, int, int b, int, Cx<R>*, Cx<R> v) {
+    if (mk[k] < 0) return;
+    Cx<R>* dst = Y + int64_t(b) * ystride + mk[k];
+    *dst = acc ? cadd(*dst, v) : v;
+  }
 };
 
 constexpr int kXcdCount = 8;  // work-group g runs on XCD g mod 8
@@ -54,7 +75,10 @@ constexpr int kXcdCount = 8;  // work-group g runs on XCD g mod 8
 // loaded together with the input (the engine's PRETW), one dependent memory
 // round trip less per work-group, for launches too small to hide it (fewer
 // work-groups than CUs); more registers live, same arithmetic and bits.
-template <typename R, bool STRIDED, int LOGW, bool XG = false, int FIX = 0, bool PRE = false>
+// MAP (run-time lengths only): 1 reads the input through a row selection's
+// inverse map, 2 stores the result through it (MapStoreEp): the selection of
+// a product S C or C^H S^H applied inside the transform's first / last pass.
+template <typename R, bool STRIDED, int LOGW, bool XG = false, int FIX = 0, bool PRE = false, int MAP = 0>
 __global__ __launch_bounds__(Geo<LOGW>::kThreads, (!PRE && (STRIDED || FIX > 0) && sizeof(R) == 4) ? 4 : 1) void fft_kernel(KArgs a) {
   extern __shared__ unsigned char smem_raw[];
   Cx<R>* lds = reinterpret_cast<Cx<R>*>(smem_raw);
@@ -66,6 +90,8 @@ __global__ __launch_bounds__(Geo<LOGW>::kThreads, (!PRE && (STRIDED || FIX > 0) 
   const Cx<R>* X = reinterpret_cast<const Cx<R>*>(a.x);
   Cx<R>* Y = reinterpret_cast<Cx<R>*>(a.y);
   const Cx<R>* S = reinterpret_cast<const Cx<R>*>(a.spec);
+  Cx<R>* ycol = Y;
+  int64_t ystr = 0;
   if constexpr (STRIDED) {
     int64_t bid = blockIdx.x;
     // tiles whose row segments (tpw values) are shorter than a 128-byte line
@@ -86,6 +112,9 @@ __global__ __launch_bounds__(Geo<LOGW>::kThreads, (!PRE && (STRIDED || FIX > 0) 
     const int64_t i0 = it * tpw;
     jb.x = X + c * a.ldx + o * a.xvs + i0;
     jb.y = Y + c * a.ldy + o * a.yvs + i0;
+    jb.xcol = X + c * a.ldx + o * a.xvs;
+    ycol = Y + c * a.ldy + o * a.yvs;
+    ystr = 0;
     jb.xbstride = jb.ybstride = 1;
     jb.inner = int(a.inner);
     jb.nvalid = int(a.inner - i0 < tpw ? a.inner - i0 : tpw);
@@ -100,6 +129,8 @@ __global__ __launch_bounds__(Geo<LOGW>::kThreads, (!PRE && (STRIDED || FIX > 0) 
       const int64_t c0 = int64_t(blockIdx.x) * tpw;
       jb.x = X + c0 * a.ldx;
       jb.y = Y + c0 * a.ldy;
+      ycol = jb.y;
+      ystr = a.ldy;
       jb.xbstride = a.ldx;
       jb.ybstride = a.ldy;
       jb.nvalid = int(a.ncols - c0 < tpw ? a.ncols - c0 : tpw);
@@ -110,6 +141,8 @@ __global__ __launch_bounds__(Geo<LOGW>::kThreads, (!PRE && (STRIDED || FIX > 0) 
       const int64_t q0 = int64_t(blockIdx.x) * tpw;
       jb.x = X + q0 * a.xvs;
       jb.y = Y + q0 * a.yvs;
+      ycol = jb.y;
+      ystr = a.yvs;
       jb.xbstride = a.xvs;
       jb.ybstride = a.yvs;
       const int64_t total = a.ncols * a.outer;
@@ -127,6 +160,8 @@ __global__ __launch_bounds__(Geo<LOGW>::kThreads, (!PRE && (STRIDED || FIX > 0) 
       }
       jb.x = X + c * a.ldx + o0 * a.xvs;
       jb.y = Y + c * a.ldy + o0 * a.yvs;
+      ycol = jb.y;
+      ystr = a.yvs;
       jb.xbstride = a.xvs;
       jb.ybstride = a.yvs;
       jb.nvalid = int(a.outer - o0 < tpw ? a.outer - o0 : tpw);
@@ -138,7 +173,18 @@ __global__ __launch_bounds__(Geo<LOGW>::kThreads, (!PRE && (STRIDED || FIX > 0) 
   jb.fuse_n2 = a.fuse_n2;
   jb.twl = reinterpret_cast<const Cx<R>*>(a.twl);
   const Mode md{a.mode, a.spec_conj, a.tw_log, a.tw_inv, a.accumulate};
-  run_job<R, STRIDED, LOGW, (FIX > 0), NoEp, false, false, PRE>(jb, md, logn, lds, reinterpret_cast<const Cx<R>*>(a.tw));
+  const Cx<R>* tw = reinterpret_cast<const Cx<R>*>(a.tw);
+  if constexpr (MAP == 2) {
+    MapStoreEp<R> ep;
+    ep.Y = ycol;
+    ep.ystride = ystr;
+    ep.omap = a.map;
+    ep.acc = a.accumulate;
+    run_job<R, STRIDED, LOGW, (FIX > 0), MapStoreEp<R>, false, false, PRE>(jb, md, logn, lds, tw, &ep);
+  } else {
+    if constexpr (MAP == 1) jb.imap = a.map;
+    run_job<R, STRIDED, LOGW, (FIX > 0), NoEp, MAP == 1, false, PRE>(jb, md, logn, lds, tw);
+  }
 }
 
 // Contiguous transforms of 2^kFixMin .. 2^LOGW points run the compile-time
@@ -153,6 +199,24 @@ const void* fixed_kernel(int lg) {
     return fixed_kernel<R, LOGW, PRE, LG - 1>(lg);
   }
 }
+// Run-time-length kernels with a row selection at the load (mode 1) or the
+// store (mode 2); strided and row-grouped (XG) forms exist at 4096-value
+// work-groups, where the four-step passes run. NULL where there is none.
+template <typename R, int LOGW>
+const void* map_kernel(bool strided, bool xg, int mode) {
+  if (mode != 1 && mode != 2) return nullptr;
+  if (!strided && !xg)
+    return mode == 1 ? reinterpret_cast<const void*>(&fft_kernel<R, false, LOGW, false, 0, false, 1>)
+                     : reinterpret_cast<const void*>(&fft_kernel<R, false, LOGW, false, 0, false, 2>);
+  if constexpr (LOGW == 12) {
+    if (strided)
+      return mode == 1 ? reinterpret_cast<const void*>(&fft_kernel<R, true, LOGW, false, 0, false, 1>)
+                       : reinterpret_cast<const void*>(&fft_kernel<R, true, LOGW, false, 0, false, 2>);
+    if (mode == 1) return reinterpret_cast<const void*>(&fft_kernel<R, false, LOGW, true, 0, false, 1>);
+  }
+  return nullptr;
+}
+
 // Launches of at most this many work-groups take the PRE forms (one-wave
 // work-groups only).
 #ifndef FM_PRE_MAX_WG
@@ -197,8 +261,22 @@ fm_status launch_typed(const FftLaunch& L, KArgs ka, hipStream_t s) {
       (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     for (int lg = kFixMin; lg <= LOGW; ++lg)
       (void)hipFuncSetAttribute(fixed_kernel<R, LOGW>(lg), hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    for (const void* f : {map_kernel<R, LOGW>(false, false, 1), map_kernel<R, LOGW>(false, false, 2),
+                          map_kernel<R, LOGW>(true, false, 1), map_kernel<R, LOGW>(true, false, 2),
+                          map_kernel<R, LOGW>(false, true, 1)})
+      if (f) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   });
   const dim3 wg(Geo<LOGW>::kThreads);
+  if (L.map_mode != 0) {
+    const void* fn = map_kernel<R, LOGW>(strided, xg, L.map_mode);
+    FM_CHECK_ARG(fn != nullptr && L.map != nullptr, FM_E_UNSUPPORTED,
+                 "fft: row selection (mode %d) not available for this pass", L.map_mode);
+    ka.map = L.map;
+    void* args[] = {&ka};
+    FM_HIP(hipLaunchKernel(fn, dim3(unsigned(blocks)), wg, args, job_lds_bytes<R, LOGW>(), s));
+    FM_LAUNCHED();
+    return FM_OK;
+  }
   if (strided)
     hipLaunchKernelGGL((fft_kernel<R, true, LOGW>), dim3(unsigned(blocks)), wg, (job_lds_bytes<R, LOGW>()), s, ka);
   else if (xg && L.logn == LOGW)

@@ -357,6 +357,50 @@ def test_composites(gpu, prec):
 
 
 @pytest.mark.parametrize("prec", ["c64", "c128"])
+@pytest.mark.parametrize("kind,m,n,nsel,ncols", [
+    ("circulant", 8, 8, 3, 5),            # transforms of fewer than 16 points
+    ("circulant", 1024, 1024, 100, 7),    # one-wave single pass
+    ("circulant", 4096, 4096, 1000, 3),   # 4096-value single pass
+    ("circulant", 16384, 16384, 2048, 5),   # folded rows
+    ("circulant", 16384, 16384, 2048, 70),  # folded rows grouped per XCD
+    ("circulant", 65536, 65536, 4096, 2),   # separate strided passes
+    ("toeplitz", 3000, 2000, 333, 4),     # L = 8192
+    ("toeplitz", 700, 1500, 700, 3),      # every output row selected
+    ("toeplitz", 5000, 5000, 999, 2),     # L = 12288 = 4096 * 3: the two-step path
+])
+def test_selection_fused_into_convolution(gpu, prec, kind, m, n, nsel, ncols):
+    """S C: the selection applied in C's last pass (forward) or C^H's first
+    pass (adjoint) gives the same bits as the two steps S (C x) and
+    C^H (S^H y), matches the oracle, and accumulates in a Sum."""
+    rng = np.random.default_rng(m + 3 * n + nsel + ncols)
+    if kind == "circulant":
+        c = crandn(rng, n, NP[prec])
+        C = gpu.Circulant(to_dev(c))
+        ref = lambda x, adj: structured.circulant_apply_fft64(c, x, adj)  # noqa: E731
+    else:
+        col, row = crandn(rng, m, NP[prec]), crandn(rng, n, NP[prec])
+        C = gpu.Toeplitz(to_dev(col), to_dev(row))
+        ref = lambda x, adj: structured.toeplitz_apply_fft64(col, row, x, adj)  # noqa: E731
+    rows = np.sort(rng.choice(m, nsel, replace=False)).astype(np.int32)
+    S = gpu.SelectRows(m, to_dev(rows), torch_dt(prec))
+    A = gpu.Product(S, C)
+    x = crandn(rng, (ncols, n), NP[prec])
+    y = to_host(A @ to_dev(x))
+    assert np.array_equal(y, to_host(S @ (C @ to_dev(x)))), "forward differs from the two steps"
+    assert rel_err(y, ref(x, False)[:, rows]) <= TOL[prec]
+    u = crandn(rng, (ncols, nsel), NP[prec])
+    z = to_host(A.H @ to_dev(u))
+    assert np.array_equal(z, to_host(C.H @ (S.H @ to_dev(u)))), "adjoint differs from the two steps"
+    su = np.zeros((ncols, m), NP[prec])
+    su[:, rows] = u
+    assert rel_err(z, ref(su, True)) <= TOL[prec]
+    y2 = to_host(gpu.Sum(A, A) @ to_dev(x))
+    assert rel_err(y2, 2 * ref(x, False)[:, rows]) <= TOL[prec]
+    z2 = to_host(gpu.Sum(A, A).H @ to_dev(u))
+    assert rel_err(z2, 2 * ref(su, True)) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
 @pytest.mark.parametrize("n1,n2", [(1024, 64), (2048, 37), (4096, 5), (512, 3)])
 def test_long_transforms_along_a_strided_axis(gpu, prec, n1, n2):
     """Fourier(n1) along the slow axis of Kron(F_n1, F_n2): strided transforms
