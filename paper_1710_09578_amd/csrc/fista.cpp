@@ -108,7 +108,7 @@ fm_status plan_power(const fm_op_s* a, PowerPlan* p) {
   p->w = off;
   off += up(size_t(n) * 16);
   p->partial = off;
-  off += up(size_t(p->nparts) * 8);
+  off += up(size_t(2 * p->nparts) * 8);  // partial sums of ||w||^2, then of ||A v||^2
   p->scal = off;
   off += up(size_t(2 * kPowerChunk + 2) * 8);
   p->exec = off;
@@ -157,11 +157,14 @@ fm_status power_iteration(const fm_op_s* a, const void* v0, uint64_t seed, int m
       // iteration j of the chunk: ||A v||^2 -> scal[2j], ||A^H A v|| -> scal[2j+1]
       const int chunk = std::min(kPowerChunk, max_iters - it);
       for (int j = 0; j < chunk; ++j) {
+        double* part_w = partial;
+        double* part_a = partial + p.nparts;
         FM_TRY(exec(a, false, Elem::C128, bf, v, av, false, ws, s));
-        FM_TRY(launch_norm2(m, av, partial, p.nparts, scal + 2 * j, s));
+        FM_TRY(launch_norm2_partial(m, av, part_a, p.nparts, s));
         FM_TRY(exec(a, true, Elem::C128, ba, av, w, false, ws, s));
-        FM_TRY(launch_norm2(n, w, partial, p.nparts, scal + 2 * j + 1, s));
-        FM_TRY(launch_normalize(n, w, scal + 2 * j + 1, s));  // iterates past a stop are discarded
+        FM_TRY(launch_norm2_partial(n, w, part_w, p.nparts, s));
+        // both final sums and w / ||w|| in one launch (iterates past a stop are discarded)
+        FM_TRY(launch_normalize_final(n, w, p.nparts, part_w, part_a, scal + 2 * j + 1, scal + 2 * j, s));
         std::swap(v, w);
       }
       double h[2 * kPowerChunk];

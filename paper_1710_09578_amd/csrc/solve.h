@@ -55,6 +55,13 @@ fm_status launch_colmax(Elem e, int64_t rows, int64_t ncols, const void* g, int6
                         hipStream_t s);
 fm_status launch_norm2(int64_t n, const void* v, double* partial, int nparts, double* out, hipStream_t s);
 fm_status launch_normalize(int64_t n, void* v, const double* nrm2, hipStream_t s);
+// Partial sums of |v_i|^2 (complex128) into partial[0..nparts): the first
+// kernel of launch_norm2.
+fm_status launch_norm2_partial(int64_t n, const void* v, double* partial, int nparts, hipStream_t s);
+// w *= 1/||w|| with ||w||^2 summed from part_w as launch_norm2 sums it; also
+// stores that sum in *out_w and the sum of part_a in *out_a (complex128, n >= 1).
+fm_status launch_normalize_final(int64_t n, void* w, int nparts, const double* part_w, const double* part_a,
+                                 double* out_w, double* out_a, hipStream_t s);
 fm_status launch_start_vector(int64_t n, uint64_t seed, void* v, hipStream_t s);
 fm_status launch_fill_int(int64_t n, int* p, int v, hipStream_t s);
 fm_status launch_fill_double(int64_t n, double* p, double v, hipStream_t s);

@@ -160,6 +160,45 @@ __global__ __launch_bounds__(kTPB) void norm2_final_kernel(int nparts, const dou
   if (threadIdx.x == 0) *out = sm[0];
 }
 
+// The final sum of norm2_final_kernel, taken by a whole work-group (same
+// order, so the same value in every work-group that takes it).
+__device__ __forceinline__ double final_sum(int nparts, const double* partial, double* sm) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += kTPB) s += partial[i];
+  sm[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kTPB / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = sm[0];
+  __syncthreads();  // sm is reused by the caller
+  return r;
+}
+
+// Power-iteration step end: ||w||^2 from its partial sums, w *= 1/||w||, and
+// (work-group 0) both squared norms of the step stored: out_w = ||w||^2,
+// out_a = ||A v||^2 from its own partial sums. One launch in place of two
+// final reductions and the scaling; the values are those of
+// norm2_final_kernel and normalize_kernel.
+__global__ __launch_bounds__(kTPB) void normalize_final_kernel(int64_t n, c128* w, int nparts, const double* part_w,
+                                                               const double* part_a, double* out_w, double* out_a) {
+  __shared__ double sm[kTPB];
+  const double nw = final_sum(nparts, part_w, sm);
+  if (blockIdx.x == 0) {
+    const double na = final_sum(nparts, part_a, sm);
+    if (threadIdx.x == 0) {
+      *out_w = nw;
+      *out_a = na;
+    }
+  }
+  const int64_t i = int64_t(blockIdx.x) * kTPB + threadIdx.x;
+  if (i >= n) return;
+  const double f = 1.0 / sqrt(nw);
+  w[i].x *= f;
+  w[i].y *= f;
+}
+
 // v *= 1/sqrt(*nrm2)
 __global__ __launch_bounds__(kTPB) void normalize_kernel(int64_t n, c128* v, const double* nrm2) {
   const int64_t i = int64_t(blockIdx.x) * kTPB + threadIdx.x;
@@ -263,6 +302,21 @@ fm_status launch_norm2(int64_t n, const void* v, double* partial, int nparts, do
   hipLaunchKernelGGL(norm2_partial_kernel, dim3(unsigned(nparts)), dim3(kTPB), 0, s, n, (const c128*)v, partial);
   FM_LAUNCHED();
   hipLaunchKernelGGL(norm2_final_kernel, dim3(1), dim3(kTPB), 0, s, nparts, partial, out);
+  FM_LAUNCHED();
+  return FM_OK;
+}
+
+fm_status launch_norm2_partial(int64_t n, const void* v, double* partial, int nparts, hipStream_t s) {
+  FM_CHECK_ARG(nparts > 0 && nparts <= 65535, FM_E_INVALID, "norm2: %d partial sums", nparts);
+  hipLaunchKernelGGL(norm2_partial_kernel, dim3(unsigned(nparts)), dim3(kTPB), 0, s, n, (const c128*)v, partial);
+  FM_LAUNCHED();
+  return FM_OK;
+}
+
+fm_status launch_normalize_final(int64_t n, void* w, int nparts, const double* part_w, const double* part_a,
+                                 double* out_w, double* out_a, hipStream_t s) {
+  hipLaunchKernelGGL(normalize_final_kernel, dim3(unsigned(cdiv(n, kTPB))), dim3(kTPB), 0, s, n, (c128*)w, nparts,
+                     part_w, part_a, out_w, out_a);
   FM_LAUNCHED();
   return FM_OK;
 }
