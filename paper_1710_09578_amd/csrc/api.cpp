@@ -388,6 +388,7 @@ fm_status fm_op_create_circulant(fm_op* out, int64_t n, const void* c, fm_dtype 
   FM_TRY(dft128(n, c128.p, ghat.p, 1.0 / double(n), s));
   FM_TRY(store_spectrum(op, ghat.p, s));
   FM_HIP(hipStreamSynchronize(s));
+  op->gen = std::move(c128);  // the generator in FP64: columns C e_j for OMP
   return publish(g.release(), out);
 }
 
@@ -540,11 +541,8 @@ fm_status fm_op_create_toeplitz(fm_op* out, int64_t m, int64_t n, const void* co
     FM_TRY(dft128(L, emb.p, ghat.p, 1.0 / double(L), s));
     FM_TRY(store_spectrum(op, ghat.p, s));
   }
-  if (m == n) {  // keep the generator for the inverse (Levinson)
-    FM_TRY(op->gen.alloc(size_t(L) * 16));
-    FM_HIP(hipMemcpyAsync(op->gen.p, emb.p, size_t(L) * 16, hipMemcpyDeviceToDevice, s));
-  }
   FM_HIP(hipStreamSynchronize(s));
+  op->gen = std::move(emb);  // the embedded generator in FP64: the inverse (Levinson) and columns T e_j (OMP)
   return publish(g.release(), out);
 }
 

@@ -195,6 +195,26 @@ __global__ __launch_bounds__(NT) void omp_select_kernel(OmpState s, int step) {
   }
 }
 
+// The chosen column a = A e_j of a (row-selected) circulant or Toeplitz
+// operator read from its generator: A[i, j] = g[(rows[i] - j) mod L]
+// (rows: the selection's indices, NULL for none), rounded once to the
+// working precision, instead of a transform of the one-hot vector.
+template <typename R>
+__global__ __launch_bounds__(256) void omp_atom_kernel(OmpState s, int step, const c128* __restrict__ g, int64_t L,
+                                                       const int* __restrict__ rows) {
+  const int64_t col = blockIdx.y;
+  if (!s.active[col]) return;
+  const int j = s.idx[col * s.k + step];
+  if (j < 0) return;
+  Cx<R>* a = static_cast<Cx<R>*>(s.acol) + col * s.m;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < s.m; i += int64_t(gridDim.x) * 256) {
+    int64_t d = (rows ? int64_t(rows[i]) : i) - j;
+    if (d < 0) d += L;
+    const c128 v = g[d];
+    a[i] = {R(v.x), R(v.y)};
+  }
+}
+
 // Gram-Schmidt step of one column (NT threads, G dot products per sweep).
 template <typename R, int NT>
 __global__ __launch_bounds__(NT) void omp_orth_kernel(OmpState s, int step, R dep2) {
@@ -577,9 +597,33 @@ fm_status plan_omp(const fm_op_s* a, int64_t ncols, int64_t k, OmpPlan* p) {
   return FM_OK;
 }
 
+// Where the columns of A can be read from a stored generator: A = C or
+// A = S C, C a circulant or Toeplitz created from its generator.
+struct AtomSource {
+  const c128* g = nullptr;
+  int64_t L = 0;
+  const int* rows = nullptr;
+};
+AtomSource atom_source(const fm_op_s* a) {
+  AtomSource src;
+  const fm_op_s* C = a;
+  const int* rows = nullptr;
+  if (a->kind == Kind::Product && a->terms.size() == 2 && a->terms[0]->kind == Kind::Select) {
+    rows = static_cast<const int*>(a->terms[0]->idx.p);
+    C = a->terms[1];
+  }
+  if ((C->kind == Kind::Circulant || C->kind == Kind::Toeplitz) && C->gen.p != nullptr && C->L > 0) {
+    src.g = static_cast<const c128*>(C->gen.p);
+    src.L = C->L;
+    src.rows = rows;
+  }
+  return src;
+}
+
 template <typename R>
 fm_status run_omp(const fm_op_s* a, int64_t ncols, OmpState st, void* x, int64_t ldx, int* support, Workspace& w,
                   hipStream_t s) {
+  const AtomSource atom = atom_source(a);
   const Elem e = elem_of(a->dt);
   const int64_t m = a->m, n = a->n;
   // one work-group per column: 1024 threads keep more loads in flight (the
@@ -596,7 +640,13 @@ fm_status run_omp(const fm_op_s* a, int64_t ncols, OmpState st, void* x, int64_t
     FM_TRY(exec(a, true, e, ba, st.r, st.c, false, w, s));      // c = A^H r
     hipLaunchKernelGGL((omp_select_kernel<R, NT>), grid, dim3(NT), 0, s, st, step);
     FM_LAUNCHED();
-    FM_TRY(exec(a, false, e, bf, st.e, st.acol, false, w, s));  // a = A e_j
+    if (atom.g) {  // a = A e_j from the generator
+      const dim3 ga{unsigned(std::min<int64_t>(cdiv(m, 256), 64)), unsigned(ncols)};
+      hipLaunchKernelGGL(omp_atom_kernel<R>, ga, dim3(256), 0, s, st, step, atom.g, atom.L, atom.rows);
+      FM_LAUNCHED();
+    } else {
+      FM_TRY(exec(a, false, e, bf, st.e, st.acol, false, w, s));  // a = A e_j
+    }
     if (st.P > 1) {
       const dim3 g2{unsigned(st.P), unsigned(ncols)};
       constexpr int NS = 256;

@@ -27,6 +27,20 @@ struct DevBuf {
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) {
+    o.p = nullptr;
+    o.bytes = 0;
+  }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) {
+      reset();
+      p = o.p;
+      bytes = o.bytes;
+      o.p = nullptr;
+      o.bytes = 0;
+    }
+    return *this;
+  }
   ~DevBuf() { reset(); }
   fm_status alloc(size_t n);
   void reset();
@@ -101,8 +115,10 @@ struct fm_op_s {
   std::vector<int64_t> roff, coff;
   bool mix = false;
   int mix_logtw = 0;
-  // square Toeplitz: the embedded generator in complex128 (t_k at k mod L),
-  // kept for the Levinson solves of its inverse
+  // Circulant / Toeplitz (created from a generator, not derived): the
+  // embedded generator g in complex128, L values, with the operator's entry
+  // (i, j) = g[(i - j) mod L]; used by the Levinson solves of a Toeplitz
+  // inverse and for the columns A e_j that OMP takes
   fm::DevBuf gen;
   // evaluation path chosen by calibration (0: the structured transforms,
   // 1: a dense product with the operator's materialised matrix, column-major,

@@ -1,10 +1,12 @@
 """GPU parity of orthogonal matching pursuit (fm_omp) against the FP64 oracle.
 
 The greedy choice is an argmax taken in the kernel's precision, so the
-supports are compared exactly on problems whose correlations are well
-separated, and x is compared with the oracle's least-squares solution on the
-support the GPU chose (unique for a full-rank A_S), column by column
-(relative L2 <= 2e-5 complex64, <= 1e-12 complex128).
+selections are compared exactly over the steps where the oracle's two largest
+correlations are separated by more than that precision's error (every step of
+the true support here; see separated_steps), and x is compared with the
+oracle's least-squares solution on the support the GPU chose (unique for a
+full-rank A_S), column by column (relative L2 <= 2e-5 complex64, <= 1e-12
+complex128).
 """
 
 import numpy as np
@@ -37,20 +39,65 @@ def cs_problem(gpu, prec, n=1024, m=256, k=12, ncols=3, seed=0, sigma=1e-3):
     return A, a, b, xt
 
 
+# Unit roundoff of the working precision. A residual r = b - A x computed in
+# it carries an error of about u ||b||, i.e. u ||b|| / ||r|| relative to r:
+# small while the true support is being found, ~1e-4 in complex64 once r is
+# at noise level 1e-3. Where the oracle's two largest unchosen |A^H r| lie
+# closer than 64 times that (relative to the largest), either choice is a
+# correct OMP step in the working precision.
+UNIT = {"c64": 2.0 ** -24, "c128": 2.0 ** -53}
+
+
+def separated_steps(a, b, sup_ref, atoms, u):
+    """Leading steps of the oracle's run on one column whose choice is
+    separated by more than 64 u ||b|| / ||r|| (compared exactly); the rest
+    are checked for validity only."""
+    r = b.astype(np.complex128)
+    bn = np.linalg.norm(r)
+    chosen = []
+    for step in range(atoms):
+        c = np.abs(a.conj().T @ r)
+        c[chosen] = -1.0
+        top = np.sort(c)[::-1]
+        if top[0] - top[1] <= 64 * u * bn / np.linalg.norm(r) * top[0]:
+            return step
+        chosen.append(int(sup_ref[step]))
+        xs = np.linalg.lstsq(a[:, chosen], b, rcond=None)[0]
+        r = b - a[:, chosen] @ xs
+    return atoms
+
+
+def check_selections(a, b, sup, sup_ref, atoms_ref, xh, x_ref, prec, min_steps):
+    """Selections equal to the oracle's over its separated steps (at least
+    min_steps of them); x equal to the oracle's where the whole run is
+    separated; everywhere x is the least-squares solution on the GPU's own
+    support."""
+    for j in range(b.shape[0]):
+        t = separated_steps(a, b[j], sup_ref[j], int(atoms_ref[j]), UNIT[prec])
+        assert t >= min(min_steps, int(atoms_ref[j])), f"column {j}: the oracle's run is not separated at step {t}"
+        assert np.array_equal(sup[j][:t], sup_ref[j][:t]), (j, t, sup[j], sup_ref[j])
+        if t == atoms_ref[j]:
+            assert rel_err(xh[j:j + 1], x_ref[j:j + 1]) <= TOL[prec]
+        assert rel_err(xh[j], omp.least_squares_on(a, b[j], sup[j])) <= TOL[prec]
+
+
 @pytest.mark.parametrize("prec", ["c64", "c128"])
 @pytest.mark.parametrize("k", [1, 5, 12, 20])
 @pytest.mark.parametrize("m", [256, 768])
 def test_omp_matches_oracle(gpu, prec, k, m):
     """m = 256: one work-group per column for the Gram-Schmidt step; m = 768:
-    the step split over three work-groups per column."""
+    the step split over three work-groups per column. The selections are
+    compared with the oracle's over its separated steps (every step of the
+    true support, and those after it whose two largest correlations differ
+    by more than the working precision's error); a column whose run is
+    separated throughout gives the oracle's x."""
     A, a, b, _ = cs_problem(gpu, prec, m=m)
     x_ref, sup_ref, atoms_ref = omp.omp(a, b, k)
     x, sup, st = gpu.omp(A, to_dev(b), k)
     sup = to_host(sup)
-    assert np.array_equal(sup, sup_ref), (sup, sup_ref)
     assert [s["atoms"] for s in st] == list(atoms_ref) and all(s["status"] == 0 for s in st)
     xh = to_host(x)
-    assert rel_err(xh, x_ref) <= TOL[prec]
+    check_selections(a, b, sup, sup_ref, atoms_ref, xh, x_ref, prec, 12)  # 12: the true support
     for j in range(b.shape[0]):
         assert rel_err(xh[j], omp.least_squares_on(a, b[j], sup[j])) <= TOL[prec]
         res = np.linalg.norm(dense.apply(a, xh[j:j + 1])[0] - b[j])
@@ -108,9 +155,8 @@ def test_omp_column_counts(gpu, prec, ncols):
     A, a, b, _ = cs_problem(gpu, prec, n=1024, m=600, k=6, ncols=ncols, seed=9)
     x_ref, sup_ref, atoms_ref = omp.omp(a, b, 8)
     x, sup, st = gpu.omp(A, to_dev(b), 8)
-    assert np.array_equal(to_host(sup), sup_ref)
     assert [s["atoms"] for s in st] == list(atoms_ref)
-    assert rel_err(to_host(x), x_ref) <= TOL[prec]
+    check_selections(a, b, to_host(sup), sup_ref, atoms_ref, to_host(x), x_ref, prec, 6)  # 6: the true support
 
 
 @pytest.mark.parametrize("prec", ["c64", "c128"])
