@@ -6,7 +6,9 @@
 // Per column b (each column is one problem), k steps of
 //   c = A^H r                        (one backward transform of the block)
 //   j = argmax over unchosen i of |c_i|, first index on ties
-//   a = A e_j                        (one forward transform of a one-hot block)
+//   a = A e_j                        (read from the stored generator for A = C or
+//                                     S C, C a circulant or Toeplitz; otherwise one
+//                                     forward transform of a one-hot block)
 //   orthogonalise a against the basis Q of the chosen columns (classical
 //   Gram-Schmidt, applied twice), append q = a'/||a'|| to Q and the
 //   coefficients to the triangular factor R (A_S = Q R)
