@@ -1,7 +1,7 @@
 // Orthogonal matching pursuit: the greedy sparse-recovery method the paper
 // runs beside FISTA on the ultrasound model (section "Application to
 // Ultrasonic Nondestructive Testing"; OMP after Tropp and Gilbert), built
-// only on the operator's forward and backward transforms.
+// on the operator's transforms.
 //
 // Per column b (each column is one problem), k steps of
 //   c = A^H r                        (one backward transform of the block)
