@@ -92,6 +92,12 @@ struct OmpState {
   void* hbuf;
   int P;
   int64_t chunk;
+  // split argmax (SP > 1 work-groups per column, schunk indices each): per
+  // column and work-group the largest |c_i|^2 and its index
+  double* sbest;
+  int64_t* sidx;
+  int SP;
+  int64_t schunk;
 };
 
 template <typename R>
@@ -122,22 +128,18 @@ __global__ __launch_bounds__(256) void omp_init_kernel(OmpState s) {
   }
 }
 
-// Argmax of |c_i|^2 over unchosen i (first index on ties); moves the one-hot
-// entry of the column to it.
+// Largest |c_i|^2 over the unchosen i in [lo, hi) of one column and its index
+// (first index on ties; -1 when every value there is chosen or NaN), by the
+// whole work-group; the result is valid in thread 0.
 template <typename R, int NT>
-__global__ __launch_bounds__(NT) void omp_select_kernel(OmpState s, int step) {
-  __shared__ R bv[NT];
-  __shared__ int64_t bi[NT];
-  const int64_t col = blockIdx.x;
-  if (!s.active[col]) return;
-  const Cx<R>* c = static_cast<const Cx<R>*>(s.c) + col * s.n;
-  const unsigned char* sel = s.sel + col * s.n;
+__device__ __forceinline__ void argmax_range(const Cx<R>* c, const unsigned char* sel, int64_t lo, int64_t hi,
+                                             R* bv, int64_t* bi, R* best_out, int64_t* idx_out) {
   R best = R(-1);
   int64_t bj = -1;
   // strided order, 4 loads in flight: the first maximum of this thread wins
   constexpr int U = 4;
-  int64_t j0 = threadIdx.x;
-  for (; j0 + (U - 1) * NT < s.n; j0 += U * NT) {
+  int64_t j0 = lo + threadIdx.x;
+  for (; j0 + (U - 1) * NT < hi; j0 += U * NT) {
     Cx<R> v[U];
     unsigned char sl[U];
 #pragma unroll
@@ -154,7 +156,7 @@ __global__ __launch_bounds__(NT) void omp_select_kernel(OmpState s, int step) {
       }
     }
   }
-  for (int64_t j = j0; j < s.n; j += NT) {
+  for (int64_t j = j0; j < hi; j += NT) {
     if (sel[j]) continue;
     const Cx<R> v = c[j];
     const R mag = v.x * v.x + v.y * v.y;
@@ -179,22 +181,80 @@ __global__ __launch_bounds__(NT) void omp_select_kernel(OmpState s, int step) {
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    const int64_t j = bi[0];
-    Cx<R>* e = static_cast<Cx<R>*>(s.e) + col * s.n;
-    if (step > 0) {
-      const int prev = s.idx[col * s.k + step - 1];
-      if (prev >= 0) e[prev] = {R(0), R(0)};
-    }
-    if (j < 0) {  // every unchosen correlation is NaN (k <= n leaves one unchosen)
-      s.active[col] = 0;
-      s.status[col] = 1;
-      return;
-    }
-    s.idx[col * s.k + step] = int(j);
-    s.sel[col * s.n + j] = 1;
-    e[j] = {R(1), R(0)};
+  *best_out = bv[0];
+  *idx_out = bi[0];
+}
+
+// Records the chosen index j of a column (thread 0): the one-hot entry moves
+// to it, or the column stops (status 1) when there is none.
+template <typename R>
+__device__ __forceinline__ void record_choice(OmpState& s, int64_t col, int step, int64_t j) {
+  Cx<R>* e = static_cast<Cx<R>*>(s.e) + col * s.n;
+  if (step > 0) {
+    const int prev = s.idx[col * s.k + step - 1];
+    if (prev >= 0) e[prev] = {R(0), R(0)};
   }
+  if (j < 0) {  // every unchosen correlation is NaN (k <= n leaves one unchosen)
+    s.active[col] = 0;
+    s.status[col] = 1;
+    return;
+  }
+  s.idx[col * s.k + step] = int(j);
+  s.sel[col * s.n + j] = 1;
+  e[j] = {R(1), R(0)};
+}
+
+// Argmax of |c_i|^2 over unchosen i (first index on ties); moves the one-hot
+// entry of the column to it. One work-group per column.
+template <typename R, int NT>
+__global__ __launch_bounds__(NT) void omp_select_kernel(OmpState s, int step) {
+  __shared__ R bv[NT];
+  __shared__ int64_t bi[NT];
+  const int64_t col = blockIdx.x;
+  if (!s.active[col]) return;
+  R best;
+  int64_t j;
+  argmax_range<R, NT>(static_cast<const Cx<R>*>(s.c) + col * s.n, s.sel + col * s.n, 0, s.n, bv, bi, &best, &j);
+  if (threadIdx.x == 0) record_choice<R>(s, col, step, j);
+}
+
+// The same argmax split over SP work-groups per column (grid SP x ncols):
+// each takes its range of schunk indices.
+template <typename R, int NT>
+__global__ __launch_bounds__(NT) void omp_select_part_kernel(OmpState s) {
+  __shared__ R bv[NT];
+  __shared__ int64_t bi[NT];
+  const int64_t col = blockIdx.y;
+  if (!s.active[col]) return;
+  const int64_t lo = int64_t(blockIdx.x) * s.schunk;
+  const int64_t hi = lo + s.schunk < s.n ? lo + s.schunk : s.n;
+  R best;
+  int64_t j;
+  argmax_range<R, NT>(static_cast<const Cx<R>*>(s.c) + col * s.n, s.sel + col * s.n, lo, hi, bv, bi, &best, &j);
+  if (threadIdx.x == 0) {
+    s.sbest[col * s.SP + blockIdx.x] = double(best);
+    s.sidx[col * s.SP + blockIdx.x] = j;
+  }
+}
+
+// Combines the SP partial maxima of each column in range order (the larger
+// value, the smaller index on ties: the single work-group's choice) and
+// records it. One thread per column.
+template <typename R>
+__global__ __launch_bounds__(64) void omp_select_fin_kernel(OmpState s, int64_t ncols, int step) {
+  const int64_t col = int64_t(blockIdx.x) * 64 + threadIdx.x;
+  if (col >= ncols || !s.active[col]) return;
+  double best = -1.0;
+  int64_t j = -1;
+  for (int p = 0; p < s.SP; ++p) {
+    const double v = s.sbest[col * s.SP + p];
+    const int64_t i = s.sidx[col * s.SP + p];
+    if (i >= 0 && (j < 0 || v > best)) {
+      best = v;
+      j = i;
+    }
+  }
+  record_choice<R>(s, col, step, j);
 }
 
 // The chosen column a = A e_j of a (row-selected) circulant or Toeplitz
@@ -547,9 +607,19 @@ __global__ __launch_bounds__(256) void omp_finish_kernel(OmpState s, void* xout,
 }
 
 struct OmpPlan {
-  size_t r, c, e, acol, q, rf, z, idx, sel, bn, rn, act, nsel, status, part, hbuf, exec, total;
-  int P;
+  size_t r, c, e, acol, q, rf, z, idx, sel, bn, rn, act, nsel, status, part, hbuf, sbest, sidx, exec, total;
+  int P, SP;
 };
+
+// Work-groups per column of the argmax: with few columns one work-group
+// scanning all n indices is a long serial chain; spread it over ~256
+// work-groups in all, at least 4096 indices each, at most 16 per column.
+int select_split(int64_t ncols, int64_t n) {
+  if (ncols <= 0 || ncols >= 128) return 1;
+  int64_t p = std::min<int64_t>(256 / ncols, 16);
+  p = std::min<int64_t>(p, n / 4096);
+  return int(std::max<int64_t>(p, 1));
+}
 
 // Work-groups per column of the Gram-Schmidt step: enough to spread few
 // columns over the chip (~256 work-groups), at least 256 rows each, at most 16.
@@ -586,6 +656,9 @@ fm_status plan_omp(const fm_op_s* a, int64_t ncols, int64_t k, OmpPlan* p) {
   p->P = omp_split(ncols, m, k, es);
   take(&p->part, p->P > 1 ? size_t(ncols) * size_t(p->P) * size_t(k + 4) * es : 0);
   take(&p->hbuf, p->P > 1 ? size_t(ncols * k) * es : 0);
+  p->SP = select_split(ncols, n);
+  take(&p->sbest, p->SP > 1 ? size_t(ncols) * size_t(p->SP) * 8 : 0);
+  take(&p->sidx, p->SP > 1 ? size_t(ncols) * size_t(p->SP) * 8 : 0);
   p->exec = off;
   size_t ex = 0;
   for (int adj = 0; adj < 2; ++adj) {
@@ -640,7 +713,12 @@ fm_status run_omp(const fm_op_s* a, int64_t ncols, OmpState st, void* x, int64_t
   const Batch bf{ncols, 1, 1, n, n, m, m}, ba{ncols, 1, 1, m, m, n, n};
   for (int step = 0; step < int(st.k); ++step) {
     FM_TRY(exec(a, true, e, ba, st.r, st.c, false, w, s));      // c = A^H r
-    hipLaunchKernelGGL((omp_select_kernel<R, NT>), grid, dim3(NT), 0, s, st, step);
+    if (st.SP > 1) {
+      hipLaunchKernelGGL((omp_select_part_kernel<R, NT>), dim3(unsigned(st.SP), unsigned(ncols)), dim3(NT), 0, s, st);
+      hipLaunchKernelGGL(omp_select_fin_kernel<R>, dim3(unsigned(cdiv(ncols, 64))), dim3(64), 0, s, st, ncols, step);
+    } else {
+      hipLaunchKernelGGL((omp_select_kernel<R, NT>), grid, dim3(NT), 0, s, st, step);
+    }
     FM_LAUNCHED();
     if (atom.g) {  // a = A e_j from the generator
       const dim3 ga{unsigned(std::min<int64_t>(cdiv(m, 256), 64)), unsigned(ncols)};
@@ -747,6 +825,10 @@ fm_status fm_omp(fm_op a, int64_t ncols, const void* b, int64_t ldb, int32_t k, 
   st.chunk = cdiv(m, p.P);
   st.part = B + p.part;
   st.hbuf = B + p.hbuf;
+  st.SP = p.SP;
+  st.schunk = cdiv(n, p.SP);
+  st.sbest = reinterpret_cast<double*>(B + p.sbest);
+  st.sidx = reinterpret_cast<int64_t*>(B + p.sidx);
   Workspace w;
   w.base = B + p.exec;
   w.cap = p.total - p.exec;

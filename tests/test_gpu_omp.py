@@ -160,6 +160,21 @@ def test_omp_column_counts(gpu, prec, ncols):
 
 
 @pytest.mark.parametrize("prec", ["c64", "c128"])
+def test_omp_split_argmax(gpu, prec):
+    """n = 16384 with two columns: the argmax runs over four work-groups per
+    column and a combining launch (first index on ties across the ranges);
+    a duplicated column must pick the same atoms as its twin."""
+    A, a, b, _ = cs_problem(gpu, prec, n=16384, m=1024, k=8, ncols=2, seed=13)
+    b = np.concatenate([b, b[:1]])
+    x_ref, sup_ref, atoms_ref = omp.omp(a, b, 10)
+    x, sup, st = gpu.omp(A, to_dev(b), 10)
+    sup, xh = to_host(sup), to_host(x)
+    assert [s["atoms"] for s in st] == list(atoms_ref)
+    check_selections(a, b, sup, sup_ref, atoms_ref, xh, x_ref, prec, 8)
+    assert np.array_equal(sup[0], sup[2]) and np.array_equal(xh[0], xh[2])
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
 @pytest.mark.parametrize("m", [256, 768])
 def test_omp_zero_and_trivial_inputs(gpu, prec, m):
     A, a, b, _ = cs_problem(gpu, prec, m=m, ncols=2)
