@@ -457,6 +457,25 @@ def test_leading_dimension_and_views(gpu):
     ref = dense.apply(dense.circulant(c), to_host(x))
     assert rel_err(to_host(y[:, :256]), ref) <= TOL["c64"]
     assert np.all(to_host(y[:, 256:]) == 0)
+    # S C with the selection inside the transform (single pass and four-step)
+    for n, nsel in ((256, 40), (16384, 300)):
+        c = crandn(rng, n, np.complex64)
+        rows = np.sort(rng.choice(n, nsel, replace=False)).astype(np.int32)
+        A = gpu.Product(gpu.SelectRows(n, to_dev(rows)), gpu.Circulant(to_dev(c)))
+        big = to_dev(crandn(rng, (3, n + 17), np.complex64))
+        x = big[:, :n]
+        y = torch.zeros((3, nsel + 9), dtype=torch.complex64, device="cuda")
+        A.apply(x, out=y[:, :nsel])
+        ref = structured.circulant_apply_fft64(c, to_host(x))[:, rows]
+        assert rel_err(to_host(y[:, :nsel]), ref) <= TOL["c64"]
+        assert np.all(to_host(y[:, nsel:]) == 0)
+        u = big[:, :nsel]
+        z = torch.zeros((3, n + 5), dtype=torch.complex64, device="cuda")
+        A.apply(u, adjoint=True, out=z[:, :n])
+        su = np.zeros((3, n), np.complex64)
+        su[:, rows] = to_host(u)
+        assert rel_err(to_host(z[:, :n]), structured.circulant_apply_fft64(c, su, True)) <= TOL["c64"]
+        assert np.all(to_host(z[:, n:]) == 0)
 
 
 # ---------------------------------------------------------------- Kronecker workload at full size
