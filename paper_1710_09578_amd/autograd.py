@@ -116,17 +116,13 @@ class _Problem:
         r = x.shape[1]
         capi.fm_axpby(r, self.ncols, alpha, x, r, beta, y, r, out, r, self.dt, _stream())
 
-    def gradient(self, y, b, r, v, g, keep_v=True):
+    def gradient(self, y, b, r, v, g):
         """g = A^H (A y - b) through r = A y - b and v = S^H r (without a
-        selection v is r itself and r is not used). keep_v=False: v is not
-        formed (the library applies S^H inside C^H's first pass)."""
+        selection v is r itself and r is not used)."""
         if self.S is None:
             r = v
         self.A.apply(y, out=r)
         self.axpby(1.0, r, -1.0, b, r)
-        if self.S is not None and not keep_v:
-            self.A.apply(r, adjoint=True, out=g)
-            return
         if self.S is not None:
             self.S.apply(r, adjoint=True, out=v)
         self.C.apply(v, adjoint=True, out=g)
@@ -157,7 +153,7 @@ class _UnrolledFista(torch.autograd.Function):
         for k in range(iters):
             if k % checkpoint == 0:
                 ckpts.append((x.clone(), y.clone()))
-            P.gradient(y, bb, r, v, g, keep_v=False)
+            P.gradient(y, bb, r, v, g)
             P.step(y, g, x, xn, yn, None, lam, L, k, momentum)
             x, xn = xn, x
             y, yn = yn, y

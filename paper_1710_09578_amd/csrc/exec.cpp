@@ -149,20 +149,17 @@ fm_status exec_conv_mixed(const fm_op_s* op, bool adj, Elem e, const Batch& b, c
 
 // Cyclic convolution of length L with pad / crop (Circulant, Toeplitz):
 // y = crop(IFFT(spec .* FFT(pad(x)))), spec conj'ed for the adjoint.
-// imap / omap (at most one; contiguous vectors, power-of-two L): a row
-// selection's inverse map applied at the first pass's load (the input is
-// S^H x: position p reads row imap[p] of x, zero where -1) or at the last
-// pass's store (the output is S of the result: position p goes to row
-// omap[p] of y, nowhere where -1).
+// omap (contiguous vectors, power-of-two L): a row selection's inverse map
+// applied at the last pass's store (the output is S of the result: position
+// p goes to row omap[p] of y, nowhere where -1).
 fm_status exec_conv(const fm_op_s* op, bool adj, Elem e, const Batch& b, const void* x, void* y,
-                    bool acc, Workspace& ws, hipStream_t s, const int32_t* imap = nullptr,
-                    const int32_t* omap = nullptr) {
+                    bool acc, Workspace& ws, hipStream_t s, const int32_t* omap = nullptr) {
   const Split& sp = split(op, e);
   const int64_t L = op->L;
   const int64_t nin = in_rows(op, adj), nout = out_rows(op, adj);
   const void* spec = param(op, e);
-  FM_CHECK_ARG(!(imap && omap) && ((!imap && !omap) || (b.inner == 1 && b.outer == 1 && !sp.mixed())),
-               FM_E_UNSUPPORTED, "convolution: row selection fused only on contiguous vectors");
+  FM_CHECK_ARG(!omap || (b.inner == 1 && b.outer == 1 && !sp.mixed()), FM_E_UNSUPPORTED,
+               "convolution: row selection fused only on contiguous vectors");
   if (!sp.four_step()) {
     FftLaunch f;
     f.elem = e;
@@ -176,8 +173,7 @@ fm_status exec_conv(const fm_op_s* op, bool adj, Elem e, const Batch& b, const v
     f.spec = spec;
     f.spec_conj = adj;
     f.accumulate = acc;
-    f.map = imap ? imap : omap;
-    f.map_mode = imap ? 1 : omap ? 2 : 0;
+    f.omap = omap;
     LAUNCH(launch_fft(f, s));
     return FM_OK;
   }
@@ -207,8 +203,6 @@ fm_status exec_conv(const fm_op_s* op, bool adj, Elem e, const Batch& b, const v
     fr.tw_log = sp.logL;
     fr.tw_inv = 1;
     fr.fuse_n2 = int(n2);
-    fr.map = imap;
-    fr.map_mode = imap ? 1 : 0;
     LAUNCH(launch_fft(fr, s));
   } else {
     // step 1: forward length-n2 transforms at stride n1 of the zero-padded
@@ -223,8 +217,6 @@ fm_status exec_conv(const fm_op_s* op, bool adj, Elem e, const Batch& b, const v
   f1.in_limit = nin;
   f1.out_limit = L;
   f1.tw_log = sp.logL;
-  f1.map = imap;
-  f1.map_mode = imap ? 1 : 0;
   LAUNCH(launch_fft(f1, s));
   // step 2: contiguous length-n1 forward transform, spectral product (spectrum
   // stored in the same transposed order), inverse transform, twiddles W_L^-(n1 k2)
@@ -254,8 +246,7 @@ fm_status exec_conv(const fm_op_s* op, bool adj, Elem e, const Batch& b, const v
   f3.in_limit = L;
   f3.out_limit = nout;
   f3.accumulate = acc;
-  f3.map = omap;
-  f3.map_mode = omap ? 2 : 0;
+  f3.omap = omap;
   LAUNCH(launch_fft(f3, s));
   ws.release(mk);
   return FM_OK;
@@ -322,18 +313,20 @@ fm_status exec_mltoeplitz(const fm_op_s* op, bool adj, Elem e, const Batch& b, c
 fm_status exec_product(const fm_op_s* op, bool adj, Elem e, const Batch& b, const void* x, void* y,
                        bool acc, Workspace& ws, hipStream_t s) {
   const int k = int(op->terms.size());
-  // S C (S a row selection, C a circulant or Toeplitz of power-of-two length):
-  // S is applied inside C's last pass (forward, at the store) or C^H's first
-  // pass (adjoint, at the load), with S's inverse index map; no intermediate
-  // and no selection launch, the same values as the two steps
-  if (k == 2 && b.inner == 1 && b.outer == 1 && (e == Elem::C64 || e == Elem::C128)) {
+  // S C forward (S a row selection, C a circulant or Toeplitz of
+  // power-of-two length): S is applied inside C's last pass, at the store,
+  // with S's inverse index map; no intermediate and no gather launch, the
+  // same values as the two steps. (Reading S^H x through the map in C^H's
+  // first pass measured slower than the expand launch it saves: two
+  // dependent loads per value.)
+  if (k == 2 && !adj && b.inner == 1 && b.outer == 1 && (e == Elem::C64 || e == Elem::C128)) {
     const fm_op_s* S = op->terms[0];
     const fm_op_s* C = op->terms[1];
     if (S->kind == Kind::Select && (C->kind == Kind::Circulant || C->kind == Kind::Toeplitz) &&
         S->path.load(std::memory_order_acquire) == 0 && C->path.load(std::memory_order_acquire) == 0 &&
         !split(C, e).mixed() && S->inv.p != nullptr) {
       const int32_t* inv = static_cast<const int32_t*>(S->inv.p);
-      return exec_conv(C, adj, e, b, x, y, acc, ws, s, adj ? inv : nullptr, adj ? nullptr : inv);
+      return exec_conv(C, false, e, b, x, y, acc, ws, s, inv);
     }
   }
   // application order

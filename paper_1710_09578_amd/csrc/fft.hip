@@ -26,7 +26,7 @@ struct KArgs {
   int mode, spec_conj, tw_log, tw_inv, accumulate, logn, fuse_n2;
   int layout;  // contiguous: 0 transforms = columns, 1 packed (ncols*outer), 2 per column
   int64_t tiles;  // work-groups per column (layout 2) / per vector (strided)
-  const int* map;  // row selection at the load (MAP 1) or the store (MAP 2)
+  const int* omap;  // OMAP: a row selection's inverse index map for the store
 };
 
 // Store epilogue of a row selection applied to the result: position e of a
@@ -75,10 +75,10 @@ constexpr int kXcdCount = 8;  // work-group g runs on XCD g mod 8
 // loaded together with the input (the engine's PRETW), one dependent memory
 // round trip less per work-group, for launches too small to hide it (fewer
 // work-groups than CUs); more registers live, same arithmetic and bits.
-// MAP (run-time lengths only): 1 reads the input through a row selection's
-// inverse map, 2 stores the result through it (MapStoreEp): the selection of
-// a product S C or C^H S^H applied inside the transform's first / last pass.
-template <typename R, bool STRIDED, int LOGW, bool XG = false, int FIX = 0, bool PRE = false, int MAP = 0>
+// OMAP (run-time lengths only): the result is stored through a row
+// selection's inverse map (MapStoreEp): the selection of a product S C
+// applied inside the transform's last pass.
+template <typename R, bool STRIDED, int LOGW, bool XG = false, int FIX = 0, bool PRE = false, bool OMAP = false>
 __global__ __launch_bounds__(Geo<LOGW>::kThreads, (!PRE && (STRIDED || FIX > 0) && sizeof(R) == 4) ? 4 : 1) void fft_kernel(KArgs a) {
   extern __shared__ unsigned char smem_raw[];
   Cx<R>* lds = reinterpret_cast<Cx<R>*>(smem_raw);
@@ -174,16 +174,15 @@ __global__ __launch_bounds__(Geo<LOGW>::kThreads, (!PRE && (STRIDED || FIX > 0) 
   jb.twl = reinterpret_cast<const Cx<R>*>(a.twl);
   const Mode md{a.mode, a.spec_conj, a.tw_log, a.tw_inv, a.accumulate};
   const Cx<R>* tw = reinterpret_cast<const Cx<R>*>(a.tw);
-  if constexpr (MAP == 2) {
+  if constexpr (OMAP) {
     MapStoreEp<R> ep;
     ep.Y = ycol;
     ep.ystride = ystr;
-    ep.omap = a.map;
+    ep.omap = a.omap;
     ep.acc = a.accumulate;
     run_job<R, STRIDED, LOGW, (FIX > 0), MapStoreEp<R>, false, false, PRE>(jb, md, logn, lds, tw, &ep);
   } else {
-    if constexpr (MAP == 1) jb.imap = a.map;
-    run_job<R, STRIDED, LOGW, (FIX > 0), NoEp, MAP == 1, false, PRE>(jb, md, logn, lds, tw);
+    run_job<R, STRIDED, LOGW, (FIX > 0), NoEp, false, false, PRE>(jb, md, logn, lds, tw);
   }
 }
 
@@ -199,21 +198,14 @@ const void* fixed_kernel(int lg) {
     return fixed_kernel<R, LOGW, PRE, LG - 1>(lg);
   }
 }
-// Run-time-length kernels with a row selection at the load (mode 1) or the
-// store (mode 2); strided and row-grouped (XG) forms exist at 4096-value
-// work-groups, where the four-step passes run. NULL where there is none.
+// Run-time-length kernels that store through a row selection (contiguous,
+// and strided at 4096-value work-groups, where the four-step passes run);
+// NULL where there is none.
 template <typename R, int LOGW>
-const void* map_kernel(bool strided, bool xg, int mode) {
-  if (mode != 1 && mode != 2) return nullptr;
-  if (!strided && !xg)
-    return mode == 1 ? reinterpret_cast<const void*>(&fft_kernel<R, false, LOGW, false, 0, false, 1>)
-                     : reinterpret_cast<const void*>(&fft_kernel<R, false, LOGW, false, 0, false, 2>);
-  if constexpr (LOGW == 12) {
-    if (strided)
-      return mode == 1 ? reinterpret_cast<const void*>(&fft_kernel<R, true, LOGW, false, 0, false, 1>)
-                       : reinterpret_cast<const void*>(&fft_kernel<R, true, LOGW, false, 0, false, 2>);
-    if (mode == 1) return reinterpret_cast<const void*>(&fft_kernel<R, false, LOGW, true, 0, false, 1>);
-  }
+const void* omap_kernel(bool strided, bool xg) {
+  if (xg) return nullptr;
+  if (!strided) return reinterpret_cast<const void*>(&fft_kernel<R, false, LOGW, false, 0, false, true>);
+  if constexpr (LOGW == 12) return reinterpret_cast<const void*>(&fft_kernel<R, true, LOGW, false, 0, false, true>);
   return nullptr;
 }
 
@@ -261,17 +253,14 @@ fm_status launch_typed(const FftLaunch& L, KArgs ka, hipStream_t s) {
       (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     for (int lg = kFixMin; lg <= LOGW; ++lg)
       (void)hipFuncSetAttribute(fixed_kernel<R, LOGW>(lg), hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    for (const void* f : {map_kernel<R, LOGW>(false, false, 1), map_kernel<R, LOGW>(false, false, 2),
-                          map_kernel<R, LOGW>(true, false, 1), map_kernel<R, LOGW>(true, false, 2),
-                          map_kernel<R, LOGW>(false, true, 1)})
+    for (const void* f : {omap_kernel<R, LOGW>(false, false), omap_kernel<R, LOGW>(true, false)})
       if (f) (void)hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   });
   const dim3 wg(Geo<LOGW>::kThreads);
-  if (L.map_mode != 0) {
-    const void* fn = map_kernel<R, LOGW>(strided, xg, L.map_mode);
-    FM_CHECK_ARG(fn != nullptr && L.map != nullptr, FM_E_UNSUPPORTED,
-                 "fft: row selection (mode %d) not available for this pass", L.map_mode);
-    ka.map = L.map;
+  if (L.omap != nullptr) {
+    const void* fn = omap_kernel<R, LOGW>(strided, xg);
+    FM_CHECK_ARG(fn != nullptr, FM_E_UNSUPPORTED, "fft: row selection at the store not available for this pass");
+    ka.omap = L.omap;
     void* args[] = {&ka};
     FM_HIP(hipLaunchKernel(fn, dim3(unsigned(blocks)), wg, args, job_lds_bytes<R, LOGW>(), s));
     FM_LAUNCHED();

@@ -53,13 +53,10 @@ struct FftLaunch {
                            //      (L = 2^logn * fuse_n2, logn = 12; see xform.h)
   const void* twl = nullptr;  // table W_L^m (0 <= m < L) for a four-step length that is not a
                               // power of two; NULL: taken from the power-of-two tables (L = 2^tw_log)
-  // A row selection applied at the load or the store (map: n_in entries, a
-  // position's selected row or -1; inner == 1 and outer == 1 only):
-  //   map_mode 1: input position p is read at row map[p] of x's column (zero where map[p] < 0);
-  //   map_mode 2: result position p is stored (added) at row map[p] of y's column, not stored
-  //               where map[p] < 0.
-  const int32_t* map = nullptr;
-  int map_mode = 0;
+  // A row selection applied at the store: result position p is stored (added)
+  // at row omap[p] of y's column, and not stored where omap[p] < 0 (omap: a
+  // selection's inverse index map, one entry per result position).
+  const int32_t* omap = nullptr;
 };
 fm_status launch_fft(const FftLaunch& L, hipStream_t s);
 

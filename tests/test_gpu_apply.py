@@ -369,9 +369,9 @@ def test_composites(gpu, prec):
     ("toeplitz", 5000, 5000, 999, 2),     # L = 12288 = 4096 * 3: the two-step path
 ])
 def test_selection_fused_into_convolution(gpu, prec, kind, m, n, nsel, ncols):
-    """S C: the selection applied in C's last pass (forward) or C^H's first
-    pass (adjoint) gives the same bits as the two steps S (C x) and
-    C^H (S^H y), matches the oracle, and accumulates in a Sum."""
+    """S C: the selection applied in C's last pass (forward) gives the same
+    bits as the two steps S (C x); forward and adjoint match the oracle and
+    accumulate in a Sum."""
     rng = np.random.default_rng(m + 3 * n + nsel + ncols)
     if kind == "circulant":
         c = crandn(rng, n, NP[prec])
