@@ -191,6 +191,27 @@ __global__ __launch_bounds__(256) void expand_kernel(int64_t n_in, Batch b, cons
   }
 }
 
+// expand_kernel for complex64 contiguous vectors without accumulation, two
+// positions per thread and one 16-byte store (y 16-byte aligned, ldy even).
+__global__ __launch_bounds__(256) void expand_pair_kernel(int64_t n_in, Batch b, const int32_t* __restrict__ inv,
+                                                          const c64* __restrict__ x, c64* y) {
+  const int64_t f = 2 * (int64_t(blockIdx.x) * blockDim.x + threadIdx.x);
+  if (f >= n_in) return;
+  const bool two = f + 1 < n_in;
+  const int32_t k0 = inv[f];
+  const int32_t k1 = two ? inv[f + 1] : -1;
+  for (int64_t p = blockIdx.y; p < b.ncols; p += gridDim.y) {
+    const c64* xc = x + p * b.ldx;
+    c64* yc = y + p * b.ldy;
+    const c64 v0 = k0 >= 0 ? xc[k0] : c64{0.f, 0.f};
+    const c64 v1 = k1 >= 0 ? xc[k1] : c64{0.f, 0.f};
+    if (two)
+      *reinterpret_cast<float4*>(yc + f) = float4{v0.x, v0.y, v1.x, v1.y};
+    else
+      yc[f] = v0;
+  }
+}
+
 template <typename V>
 __global__ __launch_bounds__(256) void copy_kernel(int64_t flat_n, Batch b, const V* __restrict__ x, V* y,
                                                    int acc) {
@@ -550,6 +571,10 @@ fm_status launch_select(Elem e, int64_t n_in, int64_t m, const int32_t* idx, con
     dim3 g = vec_grid(b.ncols * b.outer, m * b.inner, 256);
     FM_ELEM_SWITCH(e, V, hipLaunchKernelGGL(gather_kernel<V>, g, dim3(256), 0, s, m, b, idx,
                                             (const V*)x, (V*)y, acc));
+  } else if (inv != nullptr && m > 0 && e == Elem::C64 && !acc && b.inner == 1 && b.outer == 1 &&
+             (reinterpret_cast<uintptr_t>(y) & 15) == 0 && (b.ldy & 1) == 0) {
+    dim3 g = vec_grid(b.ncols, cdiv(n_in, 2), 256);
+    hipLaunchKernelGGL(expand_pair_kernel, g, dim3(256), 0, s, n_in, b, inv, (const c64*)x, (c64*)y);
   } else if (inv != nullptr && m > 0) {
     dim3 g = vec_grid(b.ncols * b.outer, n_in * b.inner, 256);
     FM_ELEM_SWITCH(e, V, hipLaunchKernelGGL(expand_kernel<V>, g, dim3(256), 0, s, n_in, b, inv,
