@@ -112,7 +112,6 @@ __global__ __launch_bounds__(Geo<LOGW>::kThreads, (!PRE && (STRIDED || FIX > 0) 
     const int64_t i0 = it * tpw;
     jb.x = X + c * a.ldx + o * a.xvs + i0;
     jb.y = Y + c * a.ldy + o * a.yvs + i0;
-    jb.xcol = X + c * a.ldx + o * a.xvs;
     ycol = Y + c * a.ldy + o * a.yvs;
     ystr = 0;
     jb.xbstride = jb.ybstride = 1;
