@@ -160,6 +160,33 @@ def test_omp_column_counts(gpu, prec, ncols):
 
 
 @pytest.mark.parametrize("prec", ["c64", "c128"])
+@pytest.mark.parametrize("shape,select", [((600, 400), True), ((300, 500), False), ((5000, 5000), True)])
+def test_omp_toeplitz_columns_from_the_generator(gpu, prec, shape, select):
+    """OMP on T and S T with T a Toeplitz (power-of-two and 4096 * 3
+    embeddings): the chosen columns come from the stored embedded generator,
+    T[i, j] = g[(i - j) mod L]; selections and x against the oracle."""
+    rng = np.random.default_rng(sum(shape) + select)
+    mt, n = shape
+    col, row = crandn(rng, mt, NP[prec]), crandn(rng, n, NP[prec])
+    T = gpu.Toeplitz(to_dev(col), to_dev(row))
+    a = dense.toeplitz(col, row)
+    A = T
+    if select:
+        rows = np.sort(rng.choice(mt, mt // 3, replace=False)).astype(np.int32)
+        A = gpu.Product(gpu.SelectRows(mt, to_dev(rows), tdt(prec)), T)
+        a = dense.select_rows(mt, rows) @ a
+    k_true, k = 5, 7
+    xt = np.zeros((2, n), np.complex128)
+    for j in range(2):
+        xt[j, rng.choice(n, k_true, replace=False)] = np.sign(rng.standard_normal(k_true)) * (1 + rng.random(k_true))
+    b = (dense.apply(a, xt) + 1e-3 * crandn(rng, (2, a.shape[0]), np.complex128)).astype(NP[prec])
+    x_ref, sup_ref, atoms_ref = omp.omp(a, b, k)
+    x, sup, st = gpu.omp(A, to_dev(b), k)
+    assert [s["atoms"] for s in st] == list(atoms_ref)
+    check_selections(a, b, to_host(sup), sup_ref, atoms_ref, to_host(x), x_ref, prec, k_true)
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
 def test_omp_split_argmax(gpu, prec):
     """n = 16384 with two columns: the argmax runs over four work-groups per
     column and a combining launch (first index on ties across the ranges);
