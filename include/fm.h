@@ -352,7 +352,9 @@ fm_status fm_fista_workspace_size(fm_op a, int64_t ncols, const fm_fista_opts* o
  * output of `seed` scaled to [0,1) by its top 53 bits). Synchronises `stream`
  * once every 16 iterations (the stopping test is applied to every iteration
  * in order from a device history of the norms; iterations past the stop are
- * discarded). iters_out may be NULL. */
+ * discarded); the chunks of 16 after the first replay one HIP graph captured
+ * per call (direct launches under FM_FISTA_GRAPH=0; the same bits either way).
+ * iters_out may be NULL. */
 fm_status fm_power_iteration(fm_op a, const void* v0, uint64_t seed, int32_t max_iters, double tol,
                              double* L_out, int32_t* iters_out, void* stream);
 

@@ -91,6 +91,7 @@ fm_status plan_fista(const fm_op_s* a, int64_t ncols, int max_iters, FistaPlan* 
 // host applies the test to the history in order, so the estimate and the
 // iteration count are those of a check after every iteration.
 constexpr int kPowerChunk = 16;
+static_assert(kPowerChunk % 2 == 0, "a captured chunk leaves v and w in place");
 
 struct PowerPlan {
   size_t v, av, w, partial, scal, exec, total;
@@ -139,6 +140,8 @@ fm_status power_iteration(const fm_op_s* a, const void* v0, uint64_t seed, int m
   double* scal = reinterpret_cast<double*>(B + p.scal);
   const int64_t n = a->n, m = a->m;
   fm_status st = FM_OK;
+  hipGraphExec_t gexec = nullptr;  // one chunk of iterations, captured once
+  bool captured = false;
   auto run = [&]() -> fm_status {
     if (v0)
       FM_HIP(hipMemcpyAsync(v, v0, size_t(n) * 16, hipMemcpyDeviceToDevice, s));
@@ -153,19 +156,50 @@ fm_status power_iteration(const fm_op_s* a, const void* v0, uint64_t seed, int m
     double prev = 0.0, lk = 0.0;
     int it = 0;  // iterations whose test has been applied
     bool done = false;
-    while (!done && it < max_iters) {
-      // iteration j of the chunk: ||A v||^2 -> scal[2j], ||A^H A v|| -> scal[2j+1]
-      const int chunk = std::min(kPowerChunk, max_iters - it);
+    // iteration j of a chunk: ||A v||^2 -> scal[2j], ||A^H A v|| -> scal[2j+1]
+    auto launch_chunk = [&](int chunk, hipStream_t q) -> fm_status {
       for (int j = 0; j < chunk; ++j) {
         double* part_w = partial;
         double* part_a = partial + p.nparts;
-        FM_TRY(exec(a, false, Elem::C128, bf, v, av, false, ws, s));
-        FM_TRY(launch_norm2_partial(m, av, part_a, p.nparts, s));
-        FM_TRY(exec(a, true, Elem::C128, ba, av, w, false, ws, s));
-        FM_TRY(launch_norm2_partial(n, w, part_w, p.nparts, s));
+        FM_TRY(exec(a, false, Elem::C128, bf, v, av, false, ws, q));
+        FM_TRY(launch_norm2_partial(m, av, part_a, p.nparts, q));
+        FM_TRY(exec(a, true, Elem::C128, ba, av, w, false, ws, q));
+        FM_TRY(launch_norm2_partial(n, w, part_w, p.nparts, q));
         // both final sums and w / ||w|| in one launch (iterates past a stop are discarded)
-        FM_TRY(launch_normalize_final(n, w, p.nparts, part_w, part_a, scal + 2 * j + 1, scal + 2 * j, s));
+        FM_TRY(launch_normalize_final(n, w, p.nparts, part_w, part_a, scal + 2 * j + 1, scal + 2 * j, q));
         std::swap(v, w);
+      }
+      return FM_OK;
+    };
+    while (!done && it < max_iters) {
+      const int chunk = std::min(kPowerChunk, max_iters - it);
+      // full chunks after the first (which has set up whatever the launches
+      // create on first use) replay one captured graph: a chunk has an even
+      // number of iterations, so v and w are back in place at its end
+      if (it > 0 && chunk == kPowerChunk && !captured && solver_graphs_enabled()) {
+        captured = true;
+        hipStream_t cs = solver_capture_stream();
+        if (cs && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+          c128* const v_at = v;
+          c128* const w_at = w;
+          const size_t ws_at = ws.mark();
+          const fm_status sc = launch_chunk(chunk, cs);
+          v = v_at;  // also where the capture stopped part way
+          w = w_at;
+          ws.release(ws_at);
+          hipGraph_t g = nullptr;
+          const hipError_t ec = hipStreamEndCapture(cs, &g);
+          if (sc == FM_OK && ec == hipSuccess && g &&
+              hipGraphInstantiate(&gexec, g, nullptr, nullptr, 0) != hipSuccess)
+            gexec = nullptr;
+          if (g) (void)hipGraphDestroy(g);
+          (void)hipGetLastError();
+        }
+      }
+      if (it > 0 && chunk == kPowerChunk && gexec) {
+        FM_HIP(hipGraphLaunch(gexec, s));
+      } else {
+        FM_TRY(launch_chunk(chunk, s));
       }
       double h[2 * kPowerChunk];
       FM_HIP(hipMemcpyAsync(h, scal, size_t(2 * chunk) * 8, hipMemcpyDeviceToHost, s));
@@ -187,6 +221,10 @@ fm_status power_iteration(const fm_op_s* a, const void* v0, uint64_t seed, int m
     return FM_OK;
   };
   st = run();
+  if (gexec) {
+    (void)hipStreamSynchronize(s);  // the replays have finished before the graph goes
+    (void)hipGraphExecDestroy(gexec);
+  }
   cleanup();
   if (st == FM_OK) FM_HIP(hipStreamSynchronize(s));
   return st;

@@ -607,4 +607,7 @@ fm_status fista_fused_run(const FusedRun& run, hipStream_t s) {
   return run_typed<double>(run, s);
 }
 
+hipStream_t solver_capture_stream() { return capture_stream(); }
+bool solver_graphs_enabled() { return graph_chunk() > 0; }
+
 }  // namespace fm

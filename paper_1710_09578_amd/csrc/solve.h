@@ -108,4 +108,9 @@ struct FusedRun {
 // the stream at the end when the iterations were replayed from a graph.
 fm_status fista_fused_run(const FusedRun& run, hipStream_t s);
 
+// Stream (one per device, default priority) that solver graphs are captured
+// on, or NULL; and whether solver graphs are on (FM_FISTA_GRAPH != 0).
+hipStream_t solver_capture_stream();
+bool solver_graphs_enabled();
+
 }  // namespace fm

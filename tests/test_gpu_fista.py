@@ -69,6 +69,28 @@ def test_power_iteration_matches_oracle(gpu, kind):
     assert abs(L2 - L2_ref) <= 1e-12 * L2_ref
 
 
+@pytest.mark.parametrize("kind", ["toeplitz", "select_circulant"])
+def test_power_iteration_chunk_boundaries(gpu, kind):
+    """The estimate after exactly k iterations (tol 0) around the chunk
+    boundaries of 16: the first chunk launched directly, later full chunks
+    replayed from one captured graph, the remainder launched directly."""
+    rng = np.random.default_rng(19)
+    if kind == "toeplitz":
+        col, row = crandn(rng, 300), crandn(rng, 200)
+        A, a = gpu.Toeplitz(to_dev(col), to_dev(row)), dense.toeplitz(col, row)
+    else:
+        A, a, _ = cs_problem(gpu, "c64", seed=3)
+    v0 = crandn(rng, a.shape[1], np.complex128)
+    for k in (1, 15, 16, 17, 32, 33, 48, 63):
+        L_ref, it_ref = fista.power_iteration(a, v0, max_iters=k, tol=0.0)
+        L, it = gpu.power_iteration(A, to_dev(v0), max_iters=k, tol=0.0)
+        if it_ref == k:  # (the oracle stops early only where two estimates are equal)
+            assert it == k, (k, it)
+        assert abs(L - L_ref) <= 1e-12 * L_ref, (k, L, L_ref)
+        L2, _ = gpu.power_iteration(A, to_dev(v0), max_iters=k, tol=0.0)
+        assert L2 == L, k  # a second call, with its own graph, gives the same bits
+
+
 # ---------------------------------------------------------------- FISTA / ISTA
 @pytest.mark.parametrize("prec", ["c64", "c128"])
 @pytest.mark.parametrize("momentum", [True, False])
