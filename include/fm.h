@@ -334,11 +334,14 @@ typedef struct {
  * (size from fm_fista_workspace_size). Complex dtypes.
  * For A = C or A = S C (C a circulant or Toeplitz leaf, S a row selection) the
  * iteration runs in the convolution's own passes, with the residual and the
- * update in their loads and stores, replayed from HIP graphs of 10 iterations;
+ * update in their loads and stores, replayed from HIP graphs of 10 iterations
+ * (A = S C with one or two columns and a power-of-two C of length >= 65536:
+ * with 1024-point rows in the four-step split instead of 4096);
  * other operators run the general loop (products through fm_apply's executor,
  * then the update). Environment: FM_FISTA_FUSED=0 sends every operator through
  * the general loop; FM_FISTA_GRAPH=k captures k iterations per graph (0: direct
- * launches). Both forms give the same iterates up to rounding. */
+ * launches); FM_FISTA_NARROW=0 keeps 4096-point rows. All forms give the same
+ * iterates up to rounding. */
 fm_status fm_fista(fm_op a, int64_t ncols, const void* b, int64_t ldb, void* x, int64_t ldx,
                    const fm_fista_opts* opts, fm_fista_stat* stats, void* ws, size_t ws_bytes,
                    void* stream);

@@ -19,7 +19,7 @@ namespace {
 // Workspace layout of one solve (byte offsets), from one sizing pass.
 struct FistaPlan {
   size_t r, g, y, lam, active, status, iters, partial, exec, total;
-  size_t slot, pbase, beta, iter;  // fused solver only
+  size_t slot, pbase, beta, iter, nspec;  // fused solver only
   int64_t ntiles;
   int per_thread;
   FusedForm fused;
@@ -40,7 +40,7 @@ fm_status plan_fista(const fm_op_s* a, int64_t ncols, int max_iters, FistaPlan* 
   const Elem e = elem_of(a->dt);
   const size_t es = elem_bytes(e);
   const int64_t m = a->m, n = a->n;
-  p->fused = fused_enabled() ? fused_form(a) : FusedForm{};
+  p->fused = fused_enabled() ? fused_form(a, ncols) : FusedForm{};
   p->ntiles = update_tiles(n, &p->per_thread);
   size_t off = 0;
   p->r = off;
@@ -59,9 +59,9 @@ fm_status plan_fista(const fm_op_s* a, int64_t ncols, int max_iters, FistaPlan* 
   off += up(size_t(ncols) * 4);
   p->partial = off;
   int64_t nslot = p->ntiles;
-  if (p->fused.conv) nslot = std::max<int64_t>(nslot, fused_nslot(p->fused.conv, e));
+  if (p->fused.conv) nslot = std::max<int64_t>(nslot, fused_nslot(p->fused, e));
   off += up(size_t(2 * nslot * ncols) * 8);
-  p->slot = p->pbase = p->beta = p->iter = off;
+  p->slot = p->pbase = p->beta = p->iter = p->nspec = off;
   if (p->fused.conv) {
     p->slot = off;
     if (p->fused.conv->L > 4096) off += up(size_t(p->fused.conv->L * ncols) * es);
@@ -71,6 +71,8 @@ fm_status plan_fista(const fm_op_s* a, int64_t ncols, int max_iters, FistaPlan* 
     off += up(size_t(std::max(max_iters, 1)) * (es / 2));
     p->iter = off;
     off += up(4);
+    p->nspec = off;
+    if (p->fused.narrow) off += up(size_t(p->fused.conv->L) * es);
   }
   p->exec = off;
   size_t ex = 0;
@@ -349,6 +351,8 @@ fm_status fm_fista(fm_op a, int64_t ncols, const void* b, int64_t ldb, void* x, 
       run.e = e;
       run.conv = p.fused.conv;
       run.sel_map = p.fused.sel_map;
+      run.narrow = p.fused.narrow;
+      run.nspec = B + p.nspec;
       run.ncols = ncols;
       run.m = m;
       run.n = n;

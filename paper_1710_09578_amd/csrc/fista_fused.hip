@@ -13,7 +13,11 @@
 //             device iteration counter that selects the next momentum weight.
 // The passes and their work items are those of the batched stage kernel (the
 // same engine calls and epilogues), so a complex64 solve gives the same bits
-// as the same problem solved in a batch. The launches of a chunk of steady
+// as the same problem solved in a batch. A = S C (never a batch problem) with
+// one or two columns and a power-of-two length L >= 65536 takes 1024-point
+// rows instead (L = 1024 n2, one-wave work-groups, the spectrum reordered for
+// that split once per solve): a single column then spreads each pass over
+// n2 >= 64 work-groups instead of L / 4096. The launches of a chunk of steady
 // iterations (10 by default) are captured once per solve into a HIP graph and
 // replayed; the first iteration and a remainder shorter than a chunk are
 // launched directly.
@@ -36,7 +40,7 @@ using namespace xf;
 
 // FS31 / FS3U1: the last strided pass of one direction and the first strided
 // pass of the next in one work-group. Both cover the same column positions
-// (tile i0 .. i0 + 4096 / n2 of every strided transform), and a thread holds
+// (tile i0 .. i0 + n1 / n2 of every strided transform), and a thread holds
 // the same points of its transform in both, so the first pass's epilogue
 // keeps the values the second loads (S^H r after the residual, y after the
 // update) in registers: one launch and one read of them fewer, same bits.
@@ -125,8 +129,15 @@ __device__ __forceinline__ FistaEpT<R, CAP> update_ep(const FArgs<R>& a, int64_t
 
 // EPI: 0 slot pass, 1 residual store (forward's last pass), 2 update (adjoint's
 // last pass). IMAP: the input goes through imap; MAP: r is stored through omap.
-template <typename R, int KIND, int EPI, bool IMAP, bool MAP>
+// LOGW: log2 of the four-step row length n1 (12: 4096-point rows in
+// 256-thread work-groups; 10: 1024-point rows in one-wave work-groups, for the
+// separate power-of-two strided passes only).
+template <typename R, int KIND, int EPI, bool IMAP, bool MAP, int LOGW = 12>
 __global__ __launch_bounds__(256) void ff_kernel(FArgs<R> a) {
+  static_assert(LOGW == 12 || KIND == FK_FS1 || KIND == FK_FS2 || KIND == FK_FS31 || KIND == FK_FS3U1,
+                "shorter rows: separate power-of-two strided passes only");
+  constexpr int N1 = 1 << LOGW;
+  constexpr int NT = Geo<LOGW>::kThreads;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   Cx<R>* smem = reinterpret_cast<Cx<R>*>(smem_raw);
   if constexpr (KIND == FK_SINGLE) {
@@ -191,7 +202,7 @@ __global__ __launch_bounds__(256) void ff_kernel(FArgs<R> a) {
     // row k2 of the four-step split: transform, spectral product, inverse,
     // twiddles W_L^-(n1 k2), into the slot (ROWF forms the row from the input)
     const int k2 = blockIdx.x;
-    Cx<R>* row = w + (int64_t(k2) << 12);
+    Cx<R>* row = w + (int64_t(k2) << LOGW);
     Job<R> jb;
     jb.twl = a.twl;
     if constexpr (KIND == FK_ROWF) {
@@ -201,32 +212,32 @@ __global__ __launch_bounds__(256) void ff_kernel(FArgs<R> a) {
       jb.imap = a.imap;
     } else {
       jb.x = row;
-      jb.in_limit = 4096;
+      jb.in_limit = N1;
     }
     jb.y = row;
     jb.xbstride = jb.ybstride = 0;
     jb.inner = 1;
     jb.nvalid = 1;
-    jb.out_limit = 4096;
+    jb.out_limit = N1;
     jb.i0 = 0;
-    jb.S = a.spec + (int64_t(k2) << 12);
+    jb.S = a.spec + (int64_t(k2) << LOGW);
     jb.sbstride = 0;
     jb.q0 = k2;
     const Mode md{FFT_CONV, a.adj, a.logL, 1, 0};
     // rows are latency-bound launches of n2 work-groups per column: the
     // twiddle seeds go out with the input loads (PRETW)
-    run_job<R, false, 12, true, NoEp, KIND == FK_ROWF && IMAP, false, true>(jb, md, 12, smem, a.tw);
+    run_job<R, false, LOGW, true, NoEp, KIND == FK_ROWF && IMAP, false, true>(jb, md, LOGW, smem, a.tw);
     return;
   } else if constexpr (KIND == FK_FS31 || KIND == FK_FS3U1) {
     // the direction's inverse strided pass with its epilogue (capturing; its
     // operand loads issued first), then the next direction's forward strided
     // pass on the captured values
     const int lg = 31 - __builtin_clz(a.n2);
-    const int tpw = 1 << (12 - lg);
+    const int tpw = 1 << (LOGW - lg);
     const int i0 = int(blockIdx.x) * tpw;
     Job<R> jb;
     jb.xbstride = jb.ybstride = 1;
-    jb.inner = 4096;
+    jb.inner = N1;
     jb.nvalid = tpw;
     jb.i0 = i0;
     jb.S = nullptr;
@@ -245,27 +256,27 @@ __global__ __launch_bounds__(256) void ff_kernel(FArgs<R> a) {
     jf.out_limit = int(a.L);
     if constexpr (KIND == FK_FS31) {
       ResidualEpT<R, MAP, true> ep{a.b + c * a.ldb, 0, a.r + c * a.ldr, a.omap, 0};
-      run_job<R, true, 12, true, ResidualEpT<R, MAP, true>, false, false, false, true>(jb, mi, lg, smem, a.tw, &ep);
+      run_job<R, true, LOGW, true, ResidualEpT<R, MAP, true>, false, false, false, true>(jb, mi, lg, smem, a.tw, &ep);
       __syncthreads();  // every thread is past the first pass's LDS use
       jf.rin = ep.cap;
-      run_job<R, true, 12, true, NoEp, false, true>(jf, mf, lg, smem, a.tw);
+      run_job<R, true, LOGW, true, NoEp, false, true>(jf, mf, lg, smem, a.tw);
     } else {
       FistaEpT<R, true> ep = update_ep<R, true>(a, c, true, lg);
-      run_job<R, true, 12, true, FistaEpT<R, true>, false, false, false, true>(jb, mi, lg, smem, a.tw, &ep);
-      fista_partials<256>(ep, true, lg, tpw, int(blockIdx.x), smem);
+      run_job<R, true, LOGW, true, FistaEpT<R, true>, false, false, false, true>(jb, mi, lg, smem, a.tw, &ep);
+      fista_partials<NT>(ep, true, lg, tpw, int(blockIdx.x), smem);
       __syncthreads();  // the partial sums have left the LDS
       jf.rin = ep.cap;
-      run_job<R, true, 12, true, NoEp, false, true>(jf, mf, lg, smem, a.tw);
+      run_job<R, true, LOGW, true, NoEp, false, true>(jf, mf, lg, smem, a.tw);
     }
     return;
   } else if constexpr (KIND == FK_FS1 || KIND == FK_FS3) {
-    // strided 2^lg-point transforms at stride 4096 over 4096 / 2^lg positions
+    // strided 2^lg-point transforms at stride n1 over n1 / 2^lg positions
     const int lg = 31 - __builtin_clz(a.n2);
-    const int tpw = 1 << (12 - lg);
+    const int tpw = 1 << (LOGW - lg);
     const int i0 = int(blockIdx.x) * tpw;
     Job<R> jb;
     jb.xbstride = jb.ybstride = 1;
-    jb.inner = 4096;
+    jb.inner = N1;
     jb.nvalid = tpw;
     jb.i0 = i0;
     jb.S = nullptr;
@@ -280,7 +291,7 @@ __global__ __launch_bounds__(256) void ff_kernel(FArgs<R> a) {
       jb.in_limit = a.in_rows;
       jb.out_limit = int(a.L);
       const Mode md{FFT_FWD, 0, a.logL, 0, 0};
-      run_job<R, true, 12, true, NoEp, IMAP>(jb, md, lg, smem, a.tw);
+      run_job<R, true, LOGW, true, NoEp, IMAP>(jb, md, lg, smem, a.tw);
     } else {
       jb.x = w + i0;
       jb.y = (EPI == 2 ? a.yv + c * a.ldy : a.r + c * a.ldr) + i0;
@@ -289,11 +300,11 @@ __global__ __launch_bounds__(256) void ff_kernel(FArgs<R> a) {
       const Mode md{FFT_INV, 0, 0, 0, 0};
       if constexpr (EPI == 1) {
         ResidualEpT<R, MAP> ep{a.b + c * a.ldb, 0, a.r + c * a.ldr, a.omap, 0};
-        run_job<R, true, 12, true, ResidualEpT<R, MAP>, false, false, false, true>(jb, md, lg, smem, a.tw, &ep);
+        run_job<R, true, LOGW, true, ResidualEpT<R, MAP>, false, false, false, true>(jb, md, lg, smem, a.tw, &ep);
       } else {
         FistaEpT<R> ep = update_ep(a, c, true, lg);
-        run_job<R, true, 12, true, FistaEpT<R>, false, false, false, true>(jb, md, lg, smem, a.tw, &ep);
-        fista_partials<256>(ep, true, lg, tpw, int(blockIdx.x), smem);
+        run_job<R, true, LOGW, true, FistaEpT<R>, false, false, false, true>(jb, md, lg, smem, a.tw, &ep);
+        fista_partials<NT>(ep, true, lg, tpw, int(blockIdx.x), smem);
       }
     }
     return;
@@ -341,15 +352,15 @@ __global__ __launch_bounds__(256) void ff_pbase_kernel(int64_t ncols, int nslot,
   if (c < ncols) pbase[c] = c * nslot;
 }
 
-template <typename R, int KIND, int EPI, bool IMAP, bool MAP>
+template <typename R, int KIND, int EPI, bool IMAP, bool MAP, int LOGW = 12>
 fm_status launch_ff(dim3 grid, const FArgs<R>& a, hipStream_t s) {
-  auto fn = &ff_kernel<R, KIND, EPI, IMAP, MAP>;
+  auto fn = &ff_kernel<R, KIND, EPI, IMAP, MAP, LOGW>;
   static std::once_flag once;
   std::call_once(once, [fn] {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
                               160 * 1024);
   });
-  hipLaunchKernelGGL(fn, grid, dim3(256), (job_lds_bytes<R, 12>()), s, a);
+  hipLaunchKernelGGL(fn, grid, dim3(Geo<LOGW>::kThreads), (job_lds_bytes<R, LOGW>()), s, a);
   FM_LAUNCHED();
   return FM_OK;
 }
@@ -418,20 +429,21 @@ bool chained(const FArgs<R>& a, int fuse_max) {
 // from the second iteration on), FS2 (adjoint rows), FS3U1; the check of the
 // last iteration is a stop kernel after the loop (launch_stop_check). Other
 // forms: the direction's passes and a stop kernel.
-template <typename R>
+// LOGW 10 (1024-point rows) runs the chained form only.
+template <typename R, int LOGW = 12>
 fm_status launch_iteration(const FArgs<R>& fa, const FArgs<R>& aa, const FusedRun& run, int fuse_max, int nslot,
                            bool first, hipStream_t s) {
-  if (chained(fa, fuse_max)) {
+  if (LOGW != 12 || chained(fa, fuse_max)) {
     const dim3 grid(unsigned(fa.n2), unsigned(fa.ncols));  // n2 rows / n2 tiles per column
     FArgs<R> f = fa;
     f.check = f.bump = first ? 0 : 1;
-    FM_TRY((launch_ff<R, FK_FS2, 0, false, false>(grid, f, s)));
+    FM_TRY((launch_ff<R, FK_FS2, 0, false, false, LOGW>(grid, f, s)));
     if (run.sel_map)
-      FM_TRY((launch_ff<R, FK_FS31, 1, false, true>(grid, f, s)));
+      FM_TRY((launch_ff<R, FK_FS31, 1, false, true, LOGW>(grid, f, s)));
     else
-      FM_TRY((launch_ff<R, FK_FS31, 1, false, false>(grid, f, s)));
-    FM_TRY((launch_ff<R, FK_FS2, 0, false, false>(grid, aa, s)));
-    return launch_ff<R, FK_FS3U1, 2, false, false>(grid, aa, s);
+      FM_TRY((launch_ff<R, FK_FS31, 1, false, false, LOGW>(grid, f, s)));
+    FM_TRY((launch_ff<R, FK_FS2, 0, false, false, LOGW>(grid, aa, s)));
+    return launch_ff<R, FK_FS3U1, 2, false, false, LOGW>(grid, aa, s);
   } else if (run.sel_map) {
     FM_TRY((launch_direction<R, true>(fa, false, fuse_max, s)));
     FM_TRY((launch_direction<R, true>(aa, true, fuse_max, s)));
@@ -462,6 +474,33 @@ hipStream_t capture_stream() {
   std::lock_guard<std::mutex> lock(g_cap_mu);
   if (!g_cap[dev] && hipStreamCreateWithFlags(&g_cap[dev], hipStreamNonBlocking) != hipSuccess) g_cap[dev] = nullptr;
   return g_cap[dev];
+}
+
+template <typename R, int LOGW>
+fm_status iterate(const FArgs<R>& fa, const FArgs<R>& aa, const FusedRun& run, int fuse_max, int nslot,
+                  hipStream_t s);
+
+// The convolution's spectrum in the order of the split with 1024-point rows
+// (L = 1024 n2): row k2 holds the frequencies k2 + n2 k1, k1 = 0..1023, as
+// the row pass reads them (complex64: in pair order, values k and k + 1 of a
+// thread adjacent for one 16-byte load). Read from the complex128 copy, which
+// is stored for 4096-point rows (row k2' holds k2' + (L / 4096) k1'), and
+// rounded once, as the complex64 copy is: the same values, reordered.
+template <typename R>
+__global__ __launch_bounds__(256) void narrow_spectrum_kernel(int64_t L, const Cx<double>* __restrict__ p64,
+                                                              Cx<R>* out) {
+  const int64_t f = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (f >= L) return;
+  const int64_t n2 = L >> 10, n2w = L >> 12;
+  const int64_t k1 = f & 1023, k2 = f >> 10;
+  const int64_t g = k2 + n2 * k1;
+  const Cx<double> v = p64[g / n2w + 4096 * (g % n2w)];
+  int64_t o = f;
+  if constexpr (sizeof(R) == 4) {
+    const int64_t t = k1 & 63, k = k1 >> 6;  // position t + 64 k of the row's 64 threads
+    o = (k2 << 10) + 2 * (t + 64 * (k >> 1)) + (k & 1);
+  }
+  out[o] = Cx<R>{R(v.x), R(v.y)};
 }
 
 template <typename R>
@@ -500,7 +539,8 @@ fm_status run_typed(const FusedRun& run, hipStream_t s) {
   fa.momentum = run.momentum;
   fa.ncols = run.ncols;
   fa.check = fa.bump = 0;
-  fa.nslot = fused_nslot(C, sizeof(R) == 4 ? Elem::C64 : Elem::C128);
+  const int nslot = fused_nslot(FusedForm{C, run.sel_map, run.narrow}, e);
+  fa.nslot = nslot;
   fa.stop_tol = run.stop_tol;
   fa.active_w = run.active;
   fa.iters = run.iters;
@@ -522,17 +562,33 @@ fm_status run_typed(const FusedRun& run, hipStream_t s) {
   aa.out_rows = int(C->n);
   aa.imap = run.sel_map;
   aa.omap = nullptr;
-  const int nslot = fused_nslot(C, e);
+  if (run.narrow) {  // 1024-point rows: n2 = L / 1024, the spectrum in that split's order
+    fa.n2 = aa.n2 = int(C->L >> 10);
+    Cx<R>* ns = static_cast<Cx<R>*>(run.nspec);
+    hipLaunchKernelGGL(narrow_spectrum_kernel<R>, dim3(unsigned(cdiv(C->L, 256))), dim3(256), 0, s, C->L,
+                       static_cast<const Cx<double>*>(C->p64.p), ns);
+    FM_LAUNCHED();
+    fa.spec = aa.spec = ns;
+  }
   const int fuse_max = 1 << conv_max_fuse();
   hipLaunchKernelGGL(ff_pbase_kernel, dim3(unsigned(cdiv(run.ncols, 256))), dim3(256), 0, s, run.ncols, nslot,
                      run.pbase);
   FM_LAUNCHED();
   if (run.max_iters <= 0) return FM_OK;
-  const bool ch = chained(fa, fuse_max);
+  if (run.narrow) return iterate<R, 10>(fa, aa, run, fuse_max, nslot, s);
+  return iterate<R, 12>(fa, aa, run, fuse_max, nslot, s);
+}
+
+// The iterations: the chained form's first strided pass and first iteration
+// directly, then chunks replayed from a graph, then the remainder directly.
+template <typename R, int LOGW>
+fm_status iterate(const FArgs<R>& fa, const FArgs<R>& aa, const FusedRun& run, int fuse_max, int nslot,
+                  hipStream_t s) {
+  const bool ch = LOGW != 12 || chained(fa, fuse_max);
   int k = 0;
   if (ch) {  // the first forward strided pass and the first iteration (no check before it)
-    FM_TRY((launch_ff<R, FK_FS1, 0, false, false>(dim3(unsigned(fa.n2), unsigned(fa.ncols)), fa, s)));
-    FM_TRY(launch_iteration<R>(fa, aa, run, fuse_max, nslot, true, s));
+    FM_TRY((launch_ff<R, FK_FS1, 0, false, false, LOGW>(dim3(unsigned(fa.n2), unsigned(fa.ncols)), fa, s)));
+    FM_TRY((launch_iteration<R, LOGW>(fa, aa, run, fuse_max, nslot, true, s)));
     k = 1;
   }
   // `chunk` iterations captured once and replayed (0: direct launches)
@@ -541,7 +597,8 @@ fm_status run_typed(const FusedRun& run, hipStream_t s) {
   hipStream_t cs = chunk > 0 ? capture_stream() : nullptr;
   if (cs && hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
     fm_status st = FM_OK;
-    for (int j = 0; j < chunk && st == FM_OK; ++j) st = launch_iteration<R>(fa, aa, run, fuse_max, nslot, false, cs);
+    for (int j = 0; j < chunk && st == FM_OK; ++j)
+      st = launch_iteration<R, LOGW>(fa, aa, run, fuse_max, nslot, false, cs);
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(cs, &g);
     if (st == FM_OK && ec == hipSuccess && g) {
@@ -557,7 +614,7 @@ fm_status run_typed(const FusedRun& run, hipStream_t s) {
       st = FM_E_DEVICE;
     }
   }
-  for (; k < run.max_iters && st == FM_OK; ++k) st = launch_iteration<R>(fa, aa, run, fuse_max, nslot, false, s);
+  for (; k < run.max_iters && st == FM_OK; ++k) st = launch_iteration<R, LOGW>(fa, aa, run, fuse_max, nslot, false, s);
   if (ch && st == FM_OK) st = launch_stop_check(run, nslot, s);  // the last iteration's check
   if (exec) {
     (void)hipStreamSynchronize(s);  // the replays have finished before the graph goes
@@ -568,7 +625,16 @@ fm_status run_typed(const FusedRun& run, hipStream_t s) {
 
 }  // namespace
 
-FusedForm fused_form(const fm_op_s* a) {
+// 1024-point rows for S C (FM_FISTA_NARROW=0: never).
+bool narrow_enabled() {
+  static const bool v = [] {
+    const char* e = std::getenv("FM_FISTA_NARROW");
+    return !(e && e[0] == '0');
+  }();
+  return v;
+}
+
+FusedForm fused_form(const fm_op_s* a, int64_t ncols) {
   FusedForm f;
   auto conv_ok = [](const fm_op_s* c) {
     if (c->kind != Kind::Circulant && c->kind != Kind::Toeplitz) return false;
@@ -590,13 +656,20 @@ FusedForm fused_form(const fm_op_s* a) {
         S->dt == C->dt) {
       f.conv = C;
       f.sel_map = static_cast<const int*>(S->inv.p);
+      // a separate power-of-two strided pass, few columns: 1024-point rows
+      // (four times the work-groups per pass, one wave each)
+      const Split& s32 = C->s32;
+      const Split& s64 = C->s64;
+      f.narrow = narrow_enabled() && ncols <= kNarrowMaxCols && C->p64.p && s64.four_step() && !s64.mixed() &&
+                 s64.log1 == 12 && s32.log1 == 12 && s32.n2 == s64.n2 && s64.n2 >= 16 && C->L <= (int64_t(1) << 20);
     }
   }
   return f;
 }
 
-int fused_nslot(const fm_op_s* conv, Elem e) {
-  const Split& sp = e == Elem::C64 ? conv->s32 : conv->s64;
+int fused_nslot(const FusedForm& f, Elem e) {
+  if (f.narrow) return int(f.conv->L >> 10);
+  const Split& sp = e == Elem::C64 ? f.conv->s32 : f.conv->s64;
   if (!sp.four_step()) return 1;
   return sp.mixed() ? mixed_tiles(sp.n2) : sp.n2;
 }

@@ -74,15 +74,20 @@ fm_status launch_copy2d(Elem e, int64_t rows, int64_t ncols, const void* src, in
 struct FusedForm {
   const fm_op_s* conv = nullptr;  // NULL: A has another form
   const int* sel_map = nullptr;   // S's inverse index map (C's output row -> row of A, or -1), or NULL
+  bool narrow = false;            // A = S C solved with 1024-point rows (L = 1024 n2, n2 >= 64)
 };
-FusedForm fused_form(const fm_op_s* a);
+// Columns up to which A = S C takes 1024-point rows.
+constexpr int64_t kNarrowMaxCols = 2;
+FusedForm fused_form(const fm_op_s* a, int64_t ncols);
 // Partial-sum slots per column of the update pass (its work-groups per column).
-int fused_nslot(const fm_op_s* conv, Elem e);
+int fused_nslot(const FusedForm& f, Elem e);
 
 struct FusedRun {
   Elem e;
   const fm_op_s* conv;
   const int* sel_map;
+  bool narrow;            // 1024-point rows (FusedForm::narrow)
+  void* nspec;            // narrow: L values, the spectrum in that split's order (written here)
   int64_t ncols, m, n;    // A is m x n
   const void* b;
   int64_t ldb;

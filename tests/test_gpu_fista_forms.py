@@ -114,6 +114,36 @@ def test_circulant_ista_and_fista(gpu, prec, n):
         assert rel_err(to_host(x), x_ref) <= TOL[prec], (n, prec, momentum)
 
 
+@pytest.mark.parametrize("prec", ["c64", "c128"])
+@pytest.mark.parametrize("n,iters", [(65536, 30), (262144, 20), (1048576, 8)])
+def test_select_circulant_row_lengths(gpu, prec, n, iters):
+    """A = S C of power-of-two length L >= 65536: one or two columns run the
+    split with 1024-point rows (n2 = L / 1024 = 64 .. 1024), three columns
+    keep 4096-point rows. Both against the oracle, and each narrow column
+    against the same column of the three-column solve."""
+    rng = np.random.default_rng(n + 5)
+    c = crandn(rng, n, NP[prec])
+    rows = np.sort(rng.choice(n, n // 16, replace=False)).astype(np.int32)
+    ap, ad = structured.select_circulant_fft64(c.astype(np.complex128), rows)
+    xt = np.zeros((3, n), np.complex128)
+    for j in range(3):
+        xt[j, rng.choice(n, 64, replace=False)] = rng.standard_normal(64)
+    b = (ap(xt) + 1e-3 * crandn(rng, (3, rows.size), np.complex128)).astype(NP[prec])
+    L = float(np.max(np.abs(np.fft.fft(c.astype(np.complex128)))) ** 2)
+    lam = 0.05 * float(np.max(np.abs(ad(b.astype(np.complex128)))))
+    A = gpu.Product(gpu.SelectRows(n, to_dev(rows), tdt(prec)), gpu.Circulant(to_dev(c)))
+    x_ref, _ = fista.fista_op(ap, ad, n, b, lam, L, iters)
+    x3, _ = gpu.fista(A, to_dev(b), iters=iters, lam=lam, L=L)
+    x3 = to_host(x3)
+    assert rel_err(x3, x_ref) <= TOL[prec], (n, prec, "three columns")
+    for sl in (slice(0, 1), slice(1, 3)):
+        x1, st = gpu.fista(A, to_dev(np.ascontiguousarray(b[sl])), iters=iters, lam=lam, L=L)
+        assert all(s_["iters"] == iters and s_["status"] == 0 for s_ in st)
+        x1 = to_host(x1)
+        assert rel_err(x1, x_ref[sl]) <= TOL[prec], (n, prec, sl)
+        assert rel_err(x1, x3[sl]) <= TOL[prec], (n, prec, sl)
+
+
 def test_stop_counts_and_warm_start_fused(gpu):
     """Per-column stopping and a warm start on a four-step form (complex128:
     the stop decision is taken on values within 1e-12 of the oracle's)."""
