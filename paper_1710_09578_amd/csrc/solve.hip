@@ -110,22 +110,36 @@ __global__ __launch_bounds__(kTPB) void sub_kernel(int64_t rows, const void* b, 
   *rp = csub(*rp, bv);
 }
 
-// max_i |g[c, i]| per column (one work-group per column), times rel.
+// max_i |g[c, i]| per column (one work-group per column), times rel. The
+// maximum does not depend on the order, so a column's 1024 threads keep 8
+// independent loads in flight each: a single work-group on a long column is
+// bound by the loads it has in flight.
+constexpr int kColmaxTPB = 1024;
 template <typename R>
-__global__ __launch_bounds__(kTPB) void colmax_kernel(int64_t rows, const void* g, int64_t ldg, double rel,
-                                                      double* out) {
-  __shared__ double sm[kTPB];
+__global__ __launch_bounds__(kColmaxTPB) void colmax_kernel(int64_t rows, const void* g, int64_t ldg, double rel,
+                                                            double* out) {
+  __shared__ double sm[kColmaxTPB];
   const int64_t c = blockIdx.x;
   const Cx<R>* G = reinterpret_cast<const Cx<R>*>(g) + c * ldg;
   double m = 0.0;
-  for (int64_t i = threadIdx.x; i < rows; i += kTPB) {
-    const double re = G[i].x, im = G[i].y;
-    const double v = sqrt(re * re + im * im);
-    m = v > m ? v : m;
+  constexpr int kU = 8;
+  for (int64_t i0 = threadIdx.x; i0 < rows; i0 += int64_t(kU) * kColmaxTPB) {
+    Cx<R> v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t i = i0 + int64_t(u) * kColmaxTPB;
+      v[u] = i < rows ? G[i] : Cx<R>{R(0), R(0)};
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const double re = v[u].x, im = v[u].y;
+      const double a = sqrt(re * re + im * im);
+      m = a > m ? a : m;
+    }
   }
   sm[threadIdx.x] = m;
   __syncthreads();
-  for (int w = kTPB / 2; w > 0; w >>= 1) {
+  for (int w = kColmaxTPB / 2; w > 0; w >>= 1) {
     if (threadIdx.x < w) sm[threadIdx.x] = sm[threadIdx.x] > sm[threadIdx.x + w] ? sm[threadIdx.x] : sm[threadIdx.x + w];
     __syncthreads();
   }
@@ -291,9 +305,9 @@ fm_status launch_colmax(Elem e, int64_t rows, int64_t ncols, const void* g, int6
                         hipStream_t s) {
   if (ncols == 0) return FM_OK;
   if (e == Elem::C64)
-    hipLaunchKernelGGL(colmax_kernel<float>, dim3(unsigned(ncols)), dim3(kTPB), 0, s, rows, g, ldg, rel, out);
+    hipLaunchKernelGGL(colmax_kernel<float>, dim3(unsigned(ncols)), dim3(kColmaxTPB), 0, s, rows, g, ldg, rel, out);
   else
-    hipLaunchKernelGGL(colmax_kernel<double>, dim3(unsigned(ncols)), dim3(kTPB), 0, s, rows, g, ldg, rel, out);
+    hipLaunchKernelGGL(colmax_kernel<double>, dim3(unsigned(ncols)), dim3(kColmaxTPB), 0, s, rows, g, ldg, rel, out);
   FM_LAUNCHED();
   return FM_OK;
 }
