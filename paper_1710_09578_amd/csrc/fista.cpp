@@ -96,8 +96,9 @@ constexpr int kPowerChunk = 16;
 static_assert(kPowerChunk % 2 == 0, "a captured chunk leaves v and w in place");
 
 struct PowerPlan {
-  size_t v, av, w, partial, scal, exec, total;
+  size_t v, av, w, partial, scal, slot, nspec, zeros, exec, total;
   int nparts;
+  FusedForm fused;  // narrow: the products run through the solver's passes
 };
 
 fm_status plan_power(const fm_op_s* a, PowerPlan* p) {
@@ -114,6 +115,16 @@ fm_status plan_power(const fm_op_s* a, PowerPlan* p) {
   off += up(size_t(2 * p->nparts) * 8);  // partial sums of ||w||^2, then of ||A v||^2
   p->scal = off;
   off += up(size_t(2 * kPowerChunk + 2) * 8);
+  p->fused = fused_enabled() ? fused_form(a, 1) : FusedForm{};
+  p->slot = p->nspec = p->zeros = off;
+  if (p->fused.narrow) {
+    p->slot = off;
+    off += up(size_t(p->fused.conv->L) * 16);
+    p->nspec = off;
+    off += up(size_t(p->fused.conv->L) * 16);
+    p->zeros = off;
+    off += up(size_t(std::max(m, n)) * 16);
+  }
   p->exec = off;
   size_t ex = 0;
   for (int adj = 0; adj < 2; ++adj) {
@@ -158,14 +169,21 @@ fm_status power_iteration(const fm_op_s* a, const void* v0, uint64_t seed, int m
     double prev = 0.0, lk = 0.0;
     int it = 0;  // iterations whose test has been applied
     bool done = false;
+    const PowerForm pf{p.fused.conv, p.fused.sel_map, m, n, B + p.slot, B + p.nspec, B + p.zeros};
+    if (p.fused.narrow) FM_TRY(power_prepare(pf, s));
     // iteration j of a chunk: ||A v||^2 -> scal[2j], ||A^H A v|| -> scal[2j+1]
     auto launch_chunk = [&](int chunk, hipStream_t q) -> fm_status {
       for (int j = 0; j < chunk; ++j) {
         double* part_w = partial;
         double* part_a = partial + p.nparts;
-        FM_TRY(exec(a, false, Elem::C128, bf, v, av, false, ws, q));
-        FM_TRY(launch_norm2_partial(m, av, part_a, p.nparts, q));
-        FM_TRY(exec(a, true, Elem::C128, ba, av, w, false, ws, q));
+        if (p.fused.narrow) {
+          FM_TRY(power_product(pf, v, av, w, q));
+          FM_TRY(launch_norm2_partial(m, av, part_a, p.nparts, q));
+        } else {
+          FM_TRY(exec(a, false, Elem::C128, bf, v, av, false, ws, q));
+          FM_TRY(launch_norm2_partial(m, av, part_a, p.nparts, q));
+          FM_TRY(exec(a, true, Elem::C128, ba, av, w, false, ws, q));
+        }
         FM_TRY(launch_norm2_partial(n, w, part_w, p.nparts, q));
         // both final sums and w / ||w|| in one launch (iterates past a stop are discarded)
         FM_TRY(launch_normalize_final(n, w, p.nparts, part_w, part_a, scal + 2 * j + 1, scal + 2 * j, q));

@@ -134,7 +134,8 @@ __device__ __forceinline__ FistaEpT<R, CAP> update_ep(const FArgs<R>& a, int64_t
 // separate power-of-two strided passes only).
 template <typename R, int KIND, int EPI, bool IMAP, bool MAP, int LOGW = 12>
 __global__ __launch_bounds__(256) void ff_kernel(FArgs<R> a) {
-  static_assert(LOGW == 12 || KIND == FK_FS1 || KIND == FK_FS2 || KIND == FK_FS31 || KIND == FK_FS3U1,
+  static_assert(LOGW == 12 || KIND == FK_FS1 || KIND == FK_FS2 || KIND == FK_FS3 || KIND == FK_FS31 ||
+                    KIND == FK_FS3U1,
                 "shorter rows: separate power-of-two strided passes only");
   constexpr int N1 = 1 << LOGW;
   constexpr int NT = Geo<LOGW>::kThreads;
@@ -681,6 +682,60 @@ fm_status fista_fused_run(const FusedRun& run, hipStream_t s) {
 }
 
 hipStream_t solver_capture_stream() { return capture_stream(); }
+
+// w = A^H (A v) for the power iteration on A = S C in complex128, with the
+// solver's 1024-point-row passes: the forward's last pass stores A v through
+// the selection (b = 0 in the residual store: A v - 0 = A v exactly) and runs
+// the adjoint's first pass on the same values, the adjoint's last pass stores
+// w (again through the residual store with b = 0). Five launches instead of
+// the executor's seven.
+fm_status power_prepare(const PowerForm& p, hipStream_t s) {
+  const fm_op_s* C = p.conv;
+  hipLaunchKernelGGL(narrow_spectrum_kernel<double>, dim3(unsigned(cdiv(C->L, 256))), dim3(256), 0, s, C->L,
+                     static_cast<const Cx<double>*>(C->p64.p), static_cast<Cx<double>*>(p.nspec));
+  FM_LAUNCHED();
+  return launch_zero2d(Elem::C128, std::max(p.m, p.n), 1, p.zeros, std::max(p.m, p.n), s);
+}
+
+fm_status power_product(const PowerForm& p, const void* v, void* av, void* w, hipStream_t s) {
+  const fm_op_s* C = p.conv;
+  FArgs<double> fa{};
+  fa.slot = static_cast<Cx<double>*>(p.slot);
+  fa.spec = static_cast<const Cx<double>*>(p.nspec);
+  fa.tw = static_cast<const Cx<double>*>(twiddle_table(Elem::C128, 20));
+  FM_CHECK_ARG(fa.tw != nullptr, FM_E_DEVICE, "twiddle table unavailable: %s", last_error());
+  fa.L = C->L;
+  fa.logL = ilog2(C->L);
+  fa.n2 = int(C->L >> 10);
+  fa.twl = fa.tw + C->L;
+  fa.b = static_cast<const Cx<double>*>(p.zeros);
+  fa.ldb = 0;
+  fa.ncols = 1;
+  fa.check = fa.bump = 0;
+  FArgs<double> aa = fa;
+  fa.in = static_cast<const Cx<double>*>(v);
+  fa.ldin = p.n;
+  fa.adj = 0;
+  fa.in_rows = int(C->n);
+  fa.out_rows = int(C->m);
+  fa.omap = p.sel_map;
+  fa.r = static_cast<Cx<double>*>(av);
+  fa.ldr = p.m;
+  aa.in = static_cast<const Cx<double>*>(av);
+  aa.ldin = p.m;
+  aa.adj = 1;
+  aa.in_rows = int(C->m);
+  aa.out_rows = int(C->n);
+  aa.imap = p.sel_map;
+  aa.r = static_cast<Cx<double>*>(w);
+  aa.ldr = p.n;
+  const dim3 grid(unsigned(fa.n2), 1u);
+  FM_TRY((launch_ff<double, FK_FS1, 0, false, false, 10>(grid, fa, s)));
+  FM_TRY((launch_ff<double, FK_FS2, 0, false, false, 10>(grid, fa, s)));
+  FM_TRY((launch_ff<double, FK_FS31, 1, false, true, 10>(grid, fa, s)));
+  FM_TRY((launch_ff<double, FK_FS2, 0, false, false, 10>(grid, aa, s)));
+  return launch_ff<double, FK_FS3, 1, false, false, 10>(grid, aa, s);
+}
 bool solver_graphs_enabled() { return graph_chunk() > 0; }
 
 }  // namespace fm

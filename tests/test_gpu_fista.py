@@ -91,6 +91,42 @@ def test_power_iteration_chunk_boundaries(gpu, kind):
         assert L2 == L, k  # a second call, with its own graph, gives the same bits
 
 
+@pytest.mark.parametrize("kind", ["circulant_65536", "toeplitz_30000", "circulant_1048576"])
+def test_power_iteration_select_long(gpu, kind):
+    """Row-selected convolutions of power-of-two length L >= 65536, whose
+    products run through the solver's passes with 1024-point rows: the
+    estimate after exactly k iterations (tol 0) against the oracle's run
+    with FFT64 products from the same start vector."""
+    rng = np.random.default_rng(23)
+    if kind.startswith("circulant"):
+        n = int(kind.split("_")[1])
+        c = crandn(rng, n)
+        rows = np.sort(rng.choice(n, n // 16, replace=False)).astype(np.int32)
+        ap, ad = structured.select_circulant_fft64(c.astype(np.complex128), rows)
+        C = gpu.Circulant(to_dev(c))
+    else:
+        n = 30000
+        col, row = crandn(rng, n), crandn(rng, n)
+        rows = np.sort(rng.choice(n, n // 4, replace=False)).astype(np.int32)
+        t_ap = lambda v: structured.toeplitz_apply_fft64(col, row, v, L=65536)
+        t_ad = lambda v: structured.toeplitz_apply_fft64(col, row, v, True, L=65536)
+        ap = lambda v: t_ap(v)[:, rows]
+
+        def ad(u):
+            z = np.zeros((u.shape[0], n), np.complex128)
+            z[:, rows] = u
+            return t_ad(z)
+        C = gpu.Toeplitz(to_dev(col), to_dev(row))
+        assert C.transform_length == 65536
+    A = gpu.Product(gpu.SelectRows(n, to_dev(rows)), C)
+    v0 = crandn(rng, n, np.complex128)
+    for k in ((1, 17, 40) if n <= 65536 else (1, 5)):
+        L_ref, _ = fista.power_iteration_op(lambda v: ap(v[None])[0], lambda u: ad(u[None])[0], v0, k, 0.0)
+        L, it = gpu.power_iteration(A, to_dev(v0), max_iters=k, tol=0.0)
+        assert it == k
+        assert abs(L - L_ref) <= 1e-12 * L_ref, (kind, k, L, L_ref)
+
+
 # ---------------------------------------------------------------- FISTA / ISTA
 @pytest.mark.parametrize("prec", ["c64", "c128"])
 @pytest.mark.parametrize("momentum", [True, False])
