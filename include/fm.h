@@ -357,6 +357,9 @@ fm_status fm_fista_workspace_size(fm_op a, int64_t ncols, const fm_fista_opts* o
  * in order from a device history of the norms; iterations past the stop are
  * discarded); the chunks of 16 after the first replay one HIP graph captured
  * per call (direct launches under FM_FISTA_GRAPH=0; the same bits either way).
+ * For A = S C (C a circulant or Toeplitz of power-of-two length >= 65536, S a
+ * row selection) the products run through fm_fista's passes with 1024-point
+ * rows (FM_FISTA_FUSED=0 or FM_FISTA_NARROW=0: through fm_apply's executor).
  * iters_out may be NULL. */
 fm_status fm_power_iteration(fm_op a, const void* v0, uint64_t seed, int32_t max_iters, double tol,
                              double* L_out, int32_t* iters_out, void* stream);
