@@ -169,8 +169,8 @@ fm_status power_iteration(const fm_op_s* a, const void* v0, uint64_t seed, int m
     double prev = 0.0, lk = 0.0;
     int it = 0;  // iterations whose test has been applied
     bool done = false;
-    const PowerForm pf{p.fused.conv, p.fused.sel_map, m, n, B + p.slot, B + p.nspec, B + p.zeros};
-    if (p.fused.narrow) FM_TRY(power_prepare(pf, s));
+    const NarrowForm pf{p.fused.conv, p.fused.sel_map, m, n, B + p.slot, B + p.nspec, B + p.zeros};
+    if (p.fused.narrow) FM_TRY(narrow_prepare(pf, Elem::C128, s));
     // iteration j of a chunk: ||A v||^2 -> scal[2j], ||A^H A v|| -> scal[2j+1]
     auto launch_chunk = [&](int chunk, hipStream_t q) -> fm_status {
       for (int j = 0; j < chunk; ++j) {

@@ -683,35 +683,52 @@ fm_status fista_fused_run(const FusedRun& run, hipStream_t s) {
 
 hipStream_t solver_capture_stream() { return capture_stream(); }
 
-// w = A^H (A v) for the power iteration on A = S C in complex128, with the
-// solver's 1024-point-row passes: the forward's last pass stores A v through
-// the selection (b = 0 in the residual store: A v - 0 = A v exactly) and runs
-// the adjoint's first pass on the same values, the adjoint's last pass stores
-// w (again through the residual store with b = 0). Five launches instead of
-// the executor's seven.
-fm_status power_prepare(const PowerForm& p, hipStream_t s) {
+// w = A^H (A v) for the power iteration on A = S C (complex128) through the
+// solver's passes with 1024-point rows: the forward's last pass stores A v
+// through the selection and runs the adjoint's first pass on the same
+// values, and the adjoint's last pass stores w; both last passes use the
+// residual store with b = 0 (a value minus 0 is the value exactly). Five
+// launches instead of the executor's seven.
+fm_status narrow_prepare(const NarrowForm& p, Elem e, hipStream_t s) {
   const fm_op_s* C = p.conv;
-  hipLaunchKernelGGL(narrow_spectrum_kernel<double>, dim3(unsigned(cdiv(C->L, 256))), dim3(256), 0, s, C->L,
-                     static_cast<const Cx<double>*>(C->p64.p), static_cast<Cx<double>*>(p.nspec));
+  const dim3 g(unsigned(cdiv(C->L, 256)));
+  const Cx<double>* p64 = static_cast<const Cx<double>*>(C->p64.p);
+  if (e == Elem::C64)
+    hipLaunchKernelGGL(narrow_spectrum_kernel<float>, g, dim3(256), 0, s, C->L, p64, static_cast<Cx<float>*>(p.nspec));
+  else
+    hipLaunchKernelGGL(narrow_spectrum_kernel<double>, g, dim3(256), 0, s, C->L, p64,
+                       static_cast<Cx<double>*>(p.nspec));
   FM_LAUNCHED();
-  return launch_zero2d(Elem::C128, std::max(p.m, p.n), 1, p.zeros, std::max(p.m, p.n), s);
+  return launch_zero2d(e, std::max(p.m, p.n), 1, p.zeros, std::max(p.m, p.n), s);
 }
 
-fm_status power_product(const PowerForm& p, const void* v, void* av, void* w, hipStream_t s) {
+namespace {
+template <typename R>
+fm_status narrow_args(const NarrowForm& p, int64_t ncols, FArgs<R>* a) {
   const fm_op_s* C = p.conv;
-  FArgs<double> fa{};
-  fa.slot = static_cast<Cx<double>*>(p.slot);
-  fa.spec = static_cast<const Cx<double>*>(p.nspec);
-  fa.tw = static_cast<const Cx<double>*>(twiddle_table(Elem::C128, 20));
+  FArgs<R> fa{};
+  fa.slot = static_cast<Cx<R>*>(p.slot);
+  fa.spec = static_cast<const Cx<R>*>(p.nspec);
+  fa.tw = static_cast<const Cx<R>*>(twiddle_table(sizeof(R) == 4 ? Elem::C64 : Elem::C128, 20));
   FM_CHECK_ARG(fa.tw != nullptr, FM_E_DEVICE, "twiddle table unavailable: %s", last_error());
   fa.L = C->L;
   fa.logL = ilog2(C->L);
   fa.n2 = int(C->L >> 10);
   fa.twl = fa.tw + C->L;
-  fa.b = static_cast<const Cx<double>*>(p.zeros);
+  fa.b = static_cast<const Cx<R>*>(p.zeros);
   fa.ldb = 0;
-  fa.ncols = 1;
+  fa.ncols = ncols;
   fa.check = fa.bump = 0;
+  *a = fa;
+  return FM_OK;
+}
+
+}  // namespace
+
+fm_status power_product(const NarrowForm& p, const void* v, void* av, void* w, hipStream_t s) {
+  const fm_op_s* C = p.conv;
+  FArgs<double> fa;
+  FM_TRY(narrow_args<double>(p, 1, &fa));
   FArgs<double> aa = fa;
   fa.in = static_cast<const Cx<double>*>(v);
   fa.ldin = p.n;

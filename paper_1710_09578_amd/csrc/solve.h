@@ -118,18 +118,19 @@ fm_status fista_fused_run(const FusedRun& run, hipStream_t s);
 hipStream_t solver_capture_stream();
 bool solver_graphs_enabled();
 
-// Power-iteration products on A = S C through the solver's passes with
-// 1024-point rows (for A with fused_form(A, 1).narrow).
-struct PowerForm {
+// Products on A = S C through the solver's passes with 1024-point rows (for
+// A with fused_form(A, ncols).narrow), in the element type given to
+// narrow_prepare.
+struct NarrowForm {
   const fm_op_s* conv;
   const int* sel_map;
   int64_t m, n;  // A is m x n
-  void* slot;    // L complex128 values
-  void* nspec;   // L complex128 values: the spectrum in that split's order (written by power_prepare)
-  void* zeros;   // max(m, n) complex128 values (zeroed by power_prepare)
+  void* slot;    // L values per column
+  void* nspec;   // L values: the spectrum in that split's order (written by narrow_prepare)
+  void* zeros;   // max(m, n) values (zeroed by narrow_prepare)
 };
-fm_status power_prepare(const PowerForm& p, hipStream_t s);
-// av = A v (m values), w = A^H av (n values), complex128.
-fm_status power_product(const PowerForm& p, const void* v, void* av, void* w, hipStream_t s);
+fm_status narrow_prepare(const NarrowForm& p, Elem e, hipStream_t s);
+// Power iteration, complex128: av = A v (m values), w = A^H av (n values).
+fm_status power_product(const NarrowForm& p, const void* v, void* av, void* w, hipStream_t s);
 
 }  // namespace fm

@@ -187,6 +187,35 @@ def test_omp_toeplitz_columns_from_the_generator(gpu, prec, shape, select):
 
 
 @pytest.mark.parametrize("prec", ["c64", "c128"])
+@pytest.mark.parametrize("ncols", [1, 2])
+def test_omp_select_toeplitz_long_embedding(gpu, prec, ncols):
+    """S T with T a 60000 x 2000 Toeplitz (embedding L = 65536) and S 1500
+    of its rows: with one or two columns the correlations A^H r run with
+    1024-point rows. Selections and x against the oracle on the dense
+    selected rows, T[i, j] = col[i - j] (i >= j) or row[j - i]."""
+    rng = np.random.default_rng(41 + ncols)
+    mt, n = 60000, 2000
+    col, row = crandn(rng, mt, NP[prec]), crandn(rng, n, NP[prec])
+    row[0] = col[0]
+    T = gpu.Toeplitz(to_dev(col), to_dev(row))
+    assert T.transform_length == 65536
+    rows = np.sort(rng.choice(mt, 1500, replace=False)).astype(np.int32)
+    A = gpu.Product(gpu.SelectRows(mt, to_dev(rows), tdt(prec)), T)
+    d = rows.astype(np.int64)[:, None] - np.arange(n)[None, :]
+    a = np.where(d >= 0, col.astype(np.complex128)[np.clip(d, 0, None)],
+                 row.astype(np.complex128)[np.clip(-d, 0, None)])
+    k_true, k = 5, 7
+    xt = np.zeros((ncols, n), np.complex128)
+    for j in range(ncols):
+        xt[j, rng.choice(n, k_true, replace=False)] = np.sign(rng.standard_normal(k_true)) * (1 + rng.random(k_true))
+    b = (dense.apply(a, xt) + 1e-3 * crandn(rng, (ncols, a.shape[0]), np.complex128)).astype(NP[prec])
+    x_ref, sup_ref, atoms_ref = omp.omp(a, b, k)
+    x, sup, st = gpu.omp(A, to_dev(b), k)
+    assert [s["atoms"] for s in st] == list(atoms_ref)
+    check_selections(a, b, to_host(sup), sup_ref, atoms_ref, to_host(x), x_ref, prec, k_true)
+
+
+@pytest.mark.parametrize("prec", ["c64", "c128"])
 def test_omp_split_argmax(gpu, prec):
     """n = 16384 with two columns: the argmax runs over four work-groups per
     column and a combining launch (first index on ties across the ranges);
